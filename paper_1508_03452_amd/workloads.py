@@ -1,0 +1,204 @@
+"""Seeded synthetic initial conditions shaped like the paper's runs.
+
+This module only builds primitive fields (n, p, u, E, B, rho_c) and run
+parameters.  It holds none of the lattice Boltzmann arithmetic, so both the
+HIP library's callers and the oracle-based tests can use it.
+
+All arrays are float64 numpy arrays of shape (nz, ny, nx); cell centres are
+x_i = (i + 1/2 - N/2) dx in lattice units (dx = c = 1 unless stated).
+
+Workloads (Sec. IV of the paper; sizes and seeds are this project's):
+  alfven   -- small-amplitude Alfven wave on a periodic 256x4x4 box, ideal
+              limit (sigma = 1e6), initial E from ideal Ohm's law (Eq. Ohm_ideal).
+  sheet    -- self-similar resistive current sheet, 1024x4x4, x open,
+              p = 50, B_y = erf(x / 2) (the erf profile of Eq. Current_sheet at
+              the time where its width is two cells).
+  kh       -- Kelvin-Helmholtz-driven reconnection slab, 1024x2048x1, x
+              periodic, y open; tanh shear layer, antiparallel B_x, seeded
+              transverse velocity noise.
+  flare    -- 3-D flare-like box 256x256x512: quadrupole arcade plus a
+              flux rope (Sec. IV, stellar flare), stratified density,
+              seeded rope height, open faces.
+  random   -- smooth random periodic state for parity tests.
+"""
+from dataclasses import dataclass, field
+from math import erf, sqrt
+
+import numpy as np
+
+DEFAULT_PARAMS = dict(dx=1.0, c=1.0, mu0=1.0, tau=1.0, tau_h=0.5, alpha=0.1, Gamma=4.0 / 3.0, sigma=1.0,
+                      nu=27.0 ** 0.5)
+
+
+@dataclass
+class Workload:
+    name: str
+    shape: tuple           # (nx, ny, nz)
+    bc: tuple              # ((lo, hi),) * 3 with "periodic" / "open"
+    params: dict
+    fields: dict           # n, p, u (3), E (3), B (3), rho_c (array or None)
+    steps: int = 0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ncells(self):
+        nx, ny, nz = self.shape
+        return nx * ny * nz
+
+
+def _centres(n, dx=1.0):
+    return (np.arange(n, dtype=np.float64) + 0.5 - n / 2.0) * dx
+
+
+def _grid(shape, dx=1.0):
+    nx, ny, nz = shape
+    x = _centres(nx, dx)[None, None, :]
+    y = _centres(ny, dx)[None, :, None]
+    z = _centres(nz, dx)[:, None, None]
+    return x, y, z
+
+
+def _full(shape, v):
+    nx, ny, nz = shape
+    return np.full((nz, ny, nx), float(v))
+
+
+def _params(**kw):
+    d = dict(DEFAULT_PARAMS)
+    d.update(kw)
+    return d
+
+
+PERIODIC3 = (("periodic", "periodic"),) * 3
+
+
+def alfven(nx=256, ny=4, nz=4, amp=0.01, sigma=1e6, steps=500):
+    """Linear relativistic Alfven wave along a uniform B0 = 1 (n = p = 1)."""
+    shape = (nx, ny, nz)
+    x, _, _ = _grid(shape)
+    Gamma = 4.0 / 3.0
+    eps = 1.0 + 1.0 / (Gamma - 1.0)
+    vA = 1.0 / sqrt(eps + 1.0 + 1.0)           # B0^2 / (eps + p + B0^2), B0 = 1
+    s = np.broadcast_to(np.sin(2 * np.pi * (x + nx / 2.0) / nx), (nz, ny, nx)).copy()
+    By = amp * s
+    uy = -vA * amp * s
+    zero = _full(shape, 0.0)
+    u = (zero, uy, zero.copy())
+    B = (_full(shape, 1.0), By, zero.copy())
+    E = (zero.copy(), zero.copy(), uy.copy())   # E = -u x B with u = (0, u_y, 0), B = (1, B_y, 0)
+    fields = dict(n=_full(shape, 1.0), p=_full(shape, 1.0), u=u, E=E, B=B, rho_c=_full(shape, 0.0))
+    return Workload("alfven", shape, PERIODIC3, _params(sigma=sigma), fields, steps,
+                    meta=dict(vA=vA, amp=amp, k=2 * np.pi / nx))
+
+
+def sheet(nx=1024, ny=4, nz=4, sigma=100.0, p=50.0, steps=4000, width_cells=2.0):
+    """Resistive current sheet: B_y = erf(x / width), rest frame, E = 0."""
+    shape = (nx, ny, nz)
+    x, _, _ = _grid(shape)
+    t0 = sigma * (width_cells / 2.0) ** 2        # erf(x / (2 sqrt(t0 / sigma))) has that width
+    By = np.broadcast_to(np.vectorize(erf)(x / (2.0 * np.sqrt(t0 / sigma))), (nz, ny, nx)).copy()
+    zero = _full(shape, 0.0)
+    fields = dict(n=_full(shape, 1.0), p=_full(shape, p), u=(zero, zero.copy(), zero.copy()),
+                  E=(zero.copy(), zero.copy(), zero.copy()), B=(zero.copy(), By, zero.copy()),
+                  rho_c=zero.copy())
+    bc = (("open", "open"), ("periodic", "periodic"), ("periodic", "periodic"))
+    return Workload("sheet", shape, bc, _params(sigma=sigma), fields, steps, meta=dict(t0=t0))
+
+
+def kh(nx=1024, ny=2048, nz=1, v0=0.2, ratio=10.0, sigma=1e3, B0=0.1, noise=1e-3, seed=2015, a=1.0, b=10.0,
+       steps=20000):
+    """Kelvin-Helmholtz shear layer with an antiparallel field (Sec. IV, KH)."""
+    shape = (nx, ny, nz)
+    _, y, _ = _grid(shape)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    th = np.broadcast_to(np.tanh(y / a), (nz, ny, nx)).copy()
+    dn = 2.0 * (ratio - 1.0) / (ratio + 1.0)
+    n = 1.0 + 0.5 * dn * th
+    ux = v0 * th
+    uy = noise * rng.uniform(-1.0, 1.0, size=(nz, ny, nx)) * np.exp(-(y / b) ** 2)
+    zero = _full(shape, 0.0)
+    Bx = B0 * th
+    fields = dict(n=n, p=_full(shape, 1.0), u=(ux, uy, zero.copy()), E=(zero.copy(), zero.copy(), uy * Bx),
+                  B=(Bx, zero.copy(), zero.copy()), rho_c=zero.copy())
+    bc = (("periodic", "periodic"), ("open", "open"), ("periodic", "periodic"))
+    return Workload("kh", shape, bc, _params(sigma=sigma), fields, steps, meta=dict(v0=v0, ratio=ratio, B0=B0))
+
+
+def flare(nx=256, ny=256, nz=512, sigma=1e3, B0=0.06, seed=512, steps=10000, Lx=6.0, Lz=12.0):
+    """Flare-like 3-D box: quadrupole arcade + image current + flux rope.
+
+    Flux function psi = psi_b + psi_i + psi_l (Sec. IV, stellar flare) in the
+    x-z plane, B = curl(psi e_y), scaled so that max |B| = B0, with a
+    uniform-twist axial B_y inside the rope.  The rope height is drawn from
+    U[1.8, 2.2] with the seed.  Density n = max(0.05, exp(-z/2)), p = 1,
+    u = 0, E = 0.  Physical box [-Lx/2, Lx/2]^2 x [0, Lz].
+    """
+    shape = (nx, ny, nz)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = rng.uniform(1.8, 2.2)
+    r0, cb = 0.5, 0.2534
+    hphys = Lx / nx
+    xs = (np.arange(nx) + 0.5) * hphys - Lx / 2.0
+    zs = (np.arange(nz) + 0.5) * (Lz / nz)
+
+    def psi(X, Z):
+        pb = cb * np.log(((X + 0.3) ** 2 + (Z + 0.3) ** 2) * ((X - 0.3) ** 2 + (Z + 0.3) ** 2) /
+                         (((X + 1.5) ** 2 + (Z + 0.3) ** 2) * ((X - 1.5) ** 2 + (Z + 0.3) ** 2)))
+        pi_ = -r0 / 2.0 * np.log(X ** 2 + (Z + h) ** 2)
+        r = np.sqrt(X ** 2 + (Z - h) ** 2)
+        pl = np.where(r <= r0, r ** 2 / (2 * r0), r0 / 2 - r0 * np.log(r0) + r0 * np.log(np.maximum(r, 1e-300)))
+        return pb + pi_ + pl
+
+    X, Z = np.meshgrid(xs, zs, indexing="xy")        # (nz, nx)
+    d = 1e-4
+    # B = curl(psi e_y) = (-d psi/dz, 0, d psi/dx)
+    bx = -(psi(X, Z + d) - psi(X, Z - d)) / (2 * d)
+    bz = (psi(X + d, Z) - psi(X - d, Z)) / (2 * d)
+    bmax = np.sqrt(bx ** 2 + bz ** 2).max()
+    scale = B0 / bmax
+    r = np.sqrt(X ** 2 + (Z - h) ** 2)
+    by = np.where(r <= r0, scale * np.sqrt(np.maximum(2.0 * (1.0 - r ** 2 / r0 ** 2), 0.0)), 0.0)
+    Bx = np.broadcast_to((bx * scale)[:, None, :], (nz, ny, nx)).copy()
+    Bz = np.broadcast_to((bz * scale)[:, None, :], (nz, ny, nx)).copy()
+    By = np.broadcast_to(by[:, None, :], (nz, ny, nx)).copy()
+    n = np.broadcast_to(np.maximum(0.05, np.exp(-zs / 2.0))[:, None, None], (nz, ny, nx)).copy()
+    zero = _full(shape, 0.0)
+    fields = dict(n=n, p=_full(shape, 1.0), u=(zero, zero.copy(), zero.copy()),
+                  E=(zero.copy(), zero.copy(), zero.copy()), B=(Bx, By, Bz), rho_c=zero.copy())
+    bc = (("open", "open"),) * 3
+    return Workload("flare", shape, bc, _params(sigma=sigma), fields, steps, meta=dict(h=h, B0=B0))
+
+
+def random_state(shape=(8, 8, 8), seed=0, vmax=0.3, amp=0.05, Bmag=0.3, Emag=0.05, sigma=10.0, modes=3,
+                 bc=PERIODIC3, **params):
+    """Smooth random state: a few random Fourier modes per field."""
+    nx, ny, nz = shape
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x, y, z = _grid(shape)
+    X = (x + nx / 2.0) / nx
+    Y = (y + ny / 2.0) / ny
+    Z = (z + nz / 2.0) / nz
+
+    def smooth(scale):
+        f = np.zeros((nz, ny, nx))
+        for _ in range(modes):
+            k = rng.integers(0, 3, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            f = f + rng.uniform(-1, 1) * np.cos(2 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z) + ph)
+        return scale * f / modes
+
+    n = 1.0 + smooth(amp * 4)
+    p = 1.0 + smooth(amp * 4)
+    u = [smooth(vmax) for _ in range(3)]
+    B = [smooth(Bmag) + (Bmag if a == 0 else 0.0) for a in range(3)]
+    E = [smooth(Emag) for _ in range(3)]
+    fields = dict(n=n, p=p, u=tuple(u), E=tuple(E), B=tuple(B), rho_c=smooth(0.01))
+    return Workload("random", tuple(shape), bc, _params(sigma=sigma, **params), fields, 0)
+
+
+CONFIGS = {
+    "alfven": alfven,
+    "sheet": sheet,
+    "kh": kh,
+    "flare": flare,
+}

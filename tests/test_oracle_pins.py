@@ -1,0 +1,400 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+None of these re-type the oracle's formulas: they check its outputs against
+continuum definitions (Eqs. EM_Fluid, EM_EM components, Ohm, Density_cons),
+library routines (numpy eig / solve), closed-form wave speeds, printed values
+(tests/golden), symmetries and conservation laws.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1508_03452_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+ETA = np.diag([1.0, -1.0, -1.0, -1.0])
+
+
+def t_fluid(eps, p, beta):
+    """T_fluid^{mu nu} = (eps + p) U U / c^2 - p eta (Eq. EM_Fluid), in units of the (c, u) components."""
+    gam = 1.0 / np.sqrt(1.0 - beta @ beta)
+    U = gam * np.r_[1.0, beta]
+    return (eps + p) * np.outer(U, U) - p * ETA
+
+
+def t_em(E, B, c=1.0, mu0=1.0):
+    """T_EM components listed above Eq. Dis_fun_EM."""
+    eps0 = 1.0 / (mu0 * c * c)
+    T = np.zeros((4, 4))
+    U = 0.5 * (E @ E + c * c * B @ B)
+    T[0, 0] = eps0 * U
+    T[0, 1:] = T[1:, 0] = np.cross(E, B) / (mu0 * c)
+    T[1:, 1:] = eps0 * (-np.outer(E, E) - c * c * np.outer(B, B) + U * np.eye(3))
+    return T
+
+
+def rand_state(rng, vmax=0.6):
+    n = rng.uniform(0.3, 3.0)
+    p = rng.uniform(0.05, 5.0)
+    d = rng.normal(size=3)
+    beta = d / np.linalg.norm(d) * rng.uniform(0, vmax)
+    E = rng.uniform(-0.5, 0.5, 3)
+    B = rng.uniform(-0.7, 0.7, 3)
+    return n, p, beta, E, B
+
+
+# --------------------------------------------------------------- lattice ---
+
+def test_d3q19_set_and_weights():
+    L = oracle.lattice()
+    vecs = {tuple(v) for v in L["e"]}
+    expect = {(0, 0, 0)}
+    for a in range(3):
+        for s in (1, -1):
+            v = [0, 0, 0]
+            v[a] = s
+            expect.add(tuple(v))
+    for a in range(3):
+        for b in range(a + 1, 3):
+            for s in (1, -1):
+                for t in (1, -1):
+                    v = [0, 0, 0]
+                    v[a], v[b] = s, t
+                    expect.add(tuple(v))
+    assert vecs == expect and len(L["e"]) == 19
+    assert abs(L["w"].sum() - 1.0) < 1e-14
+    assert abs(L["wp"].sum() - 1.0) < 1e-14
+    # the f weights do not depend on nu (Sec. III weights)
+    for nu in (1.7, 2.2795, 4.0, 7.3):
+        assert np.allclose(oracle.lattice(nu=nu)["w"], L["w"], rtol=0, atol=1e-14)
+    # at the default nu every mass weight is positive
+    assert (L["wp"] > 0).all()
+
+
+def test_d3q13_geometry():
+    for c in (0.5 ** 0.5, 1.0, 2.5):
+        L = oracle.lattice(c=c)
+        v, e, b, s = L["v"], L["ee"], L["bb"], L["s"]
+        assert np.allclose(np.linalg.norm(v, axis=1), 2 * c)
+        assert np.allclose(np.einsum("ka,ka->k", v, e), 0, atol=1e-14)       # e perpendicular to v
+        assert np.allclose(np.einsum("ka,ka->k", v, b), 0, atol=1e-14)
+        assert np.allclose(np.einsum("ka,ka->k", e, b), 0, atol=1e-14)       # b normal to the plane of v, e
+        # 12 distinct velocities pointing at cube edge centres, each used by two populations
+        offs = {tuple(x) for x in s}
+        assert len(offs) == 12 and all(sorted(map(abs, o)) == [0, 1, 1] for o in offs)
+        # 13 distinct electric and 7 distinct magnetic vectors with the null vector (Sec. III)
+        assert len({tuple(np.round(x, 12)) for x in e}) + 1 == 13
+        assert len({tuple(np.round(x, 12)) for x in b}) + 1 == 7
+
+
+# ----------------------------------------------------------- equilibria ---
+
+@pytest.mark.parametrize("c", [1.0, 2.5])
+def test_f_equilibrium_moments_are_total_tensor(c):
+    """Moments of f_eq reproduce T_fluid + T_EM (Eqs. El_total, EM_Fluid, EM components)."""
+    rng = np.random.default_rng(7)
+    L = oracle.lattice(c=c)
+    xi = L["xi"]
+    worst = 0.0
+    for _ in range(200):
+        n, p, beta, E, B = rand_state(rng)
+        E = E * c
+        eps = n * c * c + p / (4.0 / 3.0 - 1.0)
+        f, _ = oracle.equilibria(eps, p, n, beta, E, B, c=c)
+        T = np.einsum("im,in,i->mn", xi, xi, f)
+        ref = t_fluid(eps, p, beta) + t_em(E, B, c=c)
+        worst = max(worst, np.abs(T - ref).max() / np.abs(ref).max())
+    assert worst < 5e-15
+
+
+def test_g_equilibrium_moments_are_number_current():
+    """N^mu = sum xi^mu g_eq = n U^mu / c (Eq. Density_cons, Eq. Hupp)."""
+    rng = np.random.default_rng(8)
+    for nu in (27 ** 0.5, 4.5):
+        xi = oracle.lattice(nu=nu)["xi"]
+        for _ in range(100):
+            n, p, beta, E, B = rand_state(rng)
+            _, g = oracle.equilibria(n + 3 * p, p, n, beta, E, B, nu=nu)
+            gam = 1 / np.sqrt(1 - beta @ beta)
+            N = xi.T @ g
+            assert np.allclose(N, n * gam * np.r_[1.0, beta], rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("c", [0.5 ** 0.5, 1.0, 2.5])
+def test_h_equilibrium_moments(c):
+    """Eqs. Cal_E, Cal_B, Cal_rhoc at equilibrium, and the charge flux sum h v = J."""
+    rng = np.random.default_rng(9)
+    L = oracle.lattice(c=c)
+    for _ in range(50):
+        J, E, B = rng.normal(size=3), rng.normal(size=3), rng.normal(size=3)
+        rho = rng.normal()
+        h = oracle.h_equilibrium(J, E, B, rho, c=c)
+        hk = h[:24]
+        assert np.allclose(hk @ L["ee"], E, atol=1e-13)
+        assert np.allclose(hk @ L["bb"], B, atol=1e-13)
+        assert abs(h[24] + hk.sum() - rho) < 1e-13
+        assert np.allclose(hk @ L["v"], J, atol=1e-13)
+
+
+# ------------------------------------------------------------- recovery ---
+
+def test_recovery_matches_lapack_eigenpair():
+    """The Landau-frame velocity is the eigenvector of the largest eigenvalue of T_fl^mu_nu."""
+    rng = np.random.default_rng(10)
+    for _ in range(200):
+        n, p, beta, E, B = rand_state(rng, vmax=0.8)
+        eps = n + 3 * p
+        Tfl = t_fluid(eps, p, beta)
+        Tfl = Tfl + 0.02 * p * np.diag(rng.uniform(-1, 1, 4))        # non-equilibrium part
+        Tfl = 0.5 * (Tfl + Tfl.T)
+        T = Tfl + t_em(E, B)
+        gam = 1 / np.sqrt(1 - beta @ beta)
+        r = oracle.recover(T, n * gam, E, B)
+        w, V = np.linalg.eig(Tfl @ ETA)
+        k = np.argmax(w.real)
+        vec = V[:, k].real / V[0, k].real
+        assert abs(r["eps"] - w[k].real) < 1e-12 * abs(w[k].real)
+        assert np.allclose(r["beta"], vec[1:], atol=2e-13)
+
+
+def test_recovery_round_trip_perfect_fluid():
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        n, p, beta, E, B = rand_state(rng, vmax=0.9)
+        eps = n + 3 * p
+        gam = 1 / np.sqrt(1 - beta @ beta)
+        T = t_fluid(eps, p, beta) + t_em(E, B)
+        r = oracle.recover(T, n * gam, E, B)
+        assert abs(r["eps"] - eps) < 1e-12 * eps
+        assert abs(r["n"] - n) < 1e-11 * n
+        assert abs(r["p"] - p) < 1e-11 * max(p, eps)
+        assert np.allclose(r["beta"], beta, atol=1e-12)
+
+
+# ------------------------------------------------------------ Ohm solve ---
+
+def _ohm_J(E, u, B, rho, sigma, c=1.0):
+    gam = 1 / np.sqrt(1 - u @ u / c ** 2)
+    return sigma * gam * (E + np.cross(u, B) - (E @ u) * u / c ** 2) + rho * u
+
+
+def test_ohm_solve_matches_linear_solve():
+    """E = E' - (dt/2) mu0 c^2 J(E) (Eq. Ex_force with Eq. Ohm) solved by numpy on the affine map."""
+    rng = np.random.default_rng(12)
+    for sigma in (0.0, 0.3, 10.0, 1e3, 1e7):
+        for _ in range(30):
+            c = 1.0
+            dt = 1 / np.sqrt(2)
+            q = 0.5 * dt
+            u = rng.normal(size=3)
+            u *= rng.uniform(0, 0.95) / np.linalg.norm(u)
+            B, Ep = rng.normal(size=3), rng.normal(size=3)
+            rho = rng.normal() * 0.1
+            F = lambda E: E + q * _ohm_J(E, u, B, rho, sigma)
+            b0 = F(np.zeros(3))
+            A = np.column_stack([F(np.eye(3)[k]) - b0 for k in range(3)])
+            E_ref = np.linalg.solve(A, Ep - b0)
+            E, J = oracle.ohm(Ep, B, u, rho, sigma=sigma)
+            assert np.allclose(E, E_ref, rtol=1e-12, atol=1e-14 * max(1, np.abs(Ep).max()))
+            assert np.allclose(J, _ohm_J(E, u, B, rho, sigma), rtol=1e-9, atol=1e-9)
+
+
+def test_ohm_limits():
+    rng = np.random.default_rng(13)
+    u = np.array([0.3, -0.2, 0.1])
+    B, Ep = rng.normal(size=3), rng.normal(size=3)
+    E, _ = oracle.ohm(Ep, B, u, 0.0, sigma=1e12)
+    assert np.allclose(E, -np.cross(u, B), atol=1e-9)                 # Eq. Ohm_ideal
+    E, J = oracle.ohm(Ep, B, np.zeros(3), 0.0, sigma=5.0)
+    assert np.allclose(J, 5.0 * E, rtol=1e-14)                        # rest frame J = sigma E
+    assert np.allclose(E, Ep / (1 + 0.5 / np.sqrt(2) * 5.0), rtol=1e-14)
+
+
+# ------------------------------------------------- whole-step invariants ---
+
+def _run(w, steps, **over):
+    params = dict(w.params)
+    params.update(over)
+    o = oracle.Oracle(w.shape, w.bc, **params)
+    o.init(w.fields)
+    if steps:
+        o.step(steps)
+    return o
+
+
+def test_uniform_state_is_steady():
+    shape = (6, 5, 4)
+    nz, ny, nx = shape[2], shape[1], shape[0]
+    g = (nz, ny, nx)
+    u = (0.2, -0.1, 0.05)
+    B = (0.3, 0.1, -0.2)
+    E = tuple(-np.cross(u, B))
+    f = dict(n=np.full(g, 1.3), p=np.full(g, 0.7), u=tuple(np.full(g, x) for x in u),
+             E=tuple(np.full(g, x) for x in E), B=tuple(np.full(g, x) for x in B), rho_c=np.zeros(g))
+    for bc in (W.PERIODIC3, (("open", "open"),) * 3):
+        o = oracle.Oracle(shape, bc, sigma=50.0)
+        o.init(f)
+        o.step(20)
+        m = o.moments()
+        assert m["n_failed"] == 0
+        for k, v in (("n", 1.3), ("p", 0.7), ("ux", u[0]), ("uy", u[1]), ("Bx", B[0]), ("Ez", E[2])):
+            assert np.abs(m[k] - v).max() < 1e-12, k
+
+
+def test_conservation_on_periodic_box():
+    """Number, energy-momentum and charge are conserved to round-off (Eqs. Density_cons,
+    Energy_momentum_cons, Current_cons); the collision conserves T^{0 nu} exactly."""
+    w = W.random_state(shape=(10, 8, 6), seed=3, vmax=0.05, Bmag=0.3, Emag=0.05, sigma=10.0)
+    o = _run(w, 0)
+    d0 = o.diagnostics()
+    o.step(30)
+    d1 = o.diagnostics()
+    assert d1["n_failed"] == 0
+    assert abs(d1["energy"] - d0["energy"]) < 1e-13 * d0["energy"]
+    assert abs(d1["mass"] - d0["mass"]) < 1e-13 * d0["mass"]
+    assert np.abs(d1["momentum"] - d0["momentum"]).max() < 1e-13 * d0["energy"]
+    assert abs(d1["charge"] - d0["charge"]) < 1e-13 * w.ncells
+
+
+def _phase_speed(o, key, nx, steps, every):
+    def ph():
+        F = np.fft.rfft(o.moments()[key].mean(axis=(0, 1)))
+        return np.angle(F[1])
+    prev = ph()
+    unw = 0.0
+    for _ in range(steps // every):
+        o.step(every)
+        cur = ph()
+        d = -(cur - prev)
+        unw += (d + np.pi) % (2 * np.pi) - np.pi
+        prev = cur
+    k = 2 * np.pi / nx
+    return unw / (k * steps / np.sqrt(2))
+
+
+def _wave_fields(nx, kind, a=1e-4, B0=1.0):
+    g = (1, 1, nx)
+    x = (np.arange(nx) + 0.5)[None, None, :]
+    s = np.sin(2 * np.pi * x / nx) * np.ones(g)
+    z = np.zeros(g)
+    one = np.ones(g)
+    if kind == "light":
+        return dict(n=one, p=one, u=(z, z, z), E=(z, z, -a * s), B=(z, a * s, z), rho_c=z), 1.0
+    if kind == "sound":
+        Gam, eps = 4 / 3, 4.0
+        cs = np.sqrt(Gam * 1.0 / (eps + 1.0))
+        dp = a * s
+        de = dp / Gam + dp / (Gam - 1)          # isentropic: dn = n dp / (Gamma p)
+        return dict(n=one + dp / Gam, p=one + dp, u=(cs * de / (eps + 1.0), z, z), E=(z, z, z), B=(z, z, z),
+                    rho_c=z), cs
+    vA = B0 / np.sqrt(5.0 + B0 ** 2)            # B0^2 / (eps + p + B0^2), n = p = 1
+    uy = -vA * a * s
+    return dict(n=one, p=one, u=(z, uy, z), E=(z, z, uy * B0), B=(B0 * one, a * B0 * s, z), rho_c=z), vA
+
+
+@pytest.mark.parametrize("kind,tol", [("light", 1e-3), ("sound", 2e-3), ("alfven", 1e-2)])
+def test_linear_wave_speeds(kind, tol):
+    """Vacuum light (c), relativistic sound sqrt(Gamma p / (eps + p)) and Alfven B0 / sqrt(eps + p + B0^2)."""
+    nx = 128
+    f, v = _wave_fields(nx, kind)
+    o = oracle.Oracle((nx, 1, 1), None, sigma=1e6 if kind == "alfven" else 0.0)
+    o.init(f)
+    key = "p" if kind == "sound" else "By"
+    speed = _phase_speed(o, key, nx, 400, 50)
+    assert abs(speed / v - 1) < tol, (speed, v)
+
+
+def test_alfven_worked_value_and_eos_convention():
+    """The paper's printed v_A = 0.40785 follows from its formula only if eps includes the rest mass
+    (Eq. EOS); the oracle's eps for n = p = 1 must be that value."""
+    gold = json.load(open(os.path.join(GOLD, "alfven_worked_value.json")))
+    f, _ = _wave_fields(8, "alfven", a=0.0)
+    o = oracle.Oracle((8, 1, 1), None, Gamma=gold["Gamma"])
+    o.init(f)
+    eps = float(o.moments()["eps"].mean())
+    p, B0, eta = gold["p"], gold["B0"], gold["eta_A"]
+    den = eps + p + B0 ** 2 * (1 + eta ** 2)
+    vA2 = 2 * B0 ** 2 / den / (1 + np.sqrt(1 - (2 * eta * B0 ** 2 / den) ** 2))
+    assert round(np.sqrt(vA2), gold["printed_digits"]) == gold["v_A"]
+
+
+def test_current_sheet_follows_erf_diffusion():
+    """Resistive diffusion of a current sheet, Eq. Current_sheet (erf profile, rest frame)."""
+    from math import erf
+    sigma, nx, steps = 100.0, 512, 1500
+    w = W.sheet(nx=nx, ny=1, nz=1, sigma=sigma, steps=steps)
+    o = _run(w, steps)
+    m = o.moments()
+    x = np.arange(nx) + 0.5 - nx / 2
+    t = w.meta["t0"] + steps / np.sqrt(2)
+    ref = np.array([erf(v / (2 * np.sqrt(t / sigma))) for v in x])
+    sel = np.abs(x) < 128
+    err = np.sqrt(np.mean((m["By"][0, 0] - ref)[sel] ** 2))
+    assert err < 5e-3
+
+
+def _permute(fields, perm):
+    """Cyclic axis permutation: new axis a is old axis perm[a]; arrays are (z, y, x)."""
+    out = {}
+    tr = tuple(2 - perm[2 - k] for k in range(3))
+    for k in ("n", "p", "rho_c"):
+        out[k] = np.ascontiguousarray(np.transpose(fields[k], tr))
+    for k in ("u", "E", "B"):
+        out[k] = tuple(np.ascontiguousarray(np.transpose(fields[k][perm[a]], tr)) for a in range(3))
+    return out
+
+
+def test_axis_permutation_symmetry():
+    """The D3Q19 and D3Q13 sets are invariant under a cyclic relabelling of the axes."""
+    w = W.random_state(shape=(6, 7, 8), seed=5, vmax=0.05, Bmag=0.2, Emag=0.03, sigma=5.0)
+    perm = (1, 2, 0)
+    o1 = _run(w, 8)
+    m1 = o1.moments()
+    fp = _permute(w.fields, perm)
+    nx, ny, nz = w.shape
+    shp = (w.shape[perm[0]], w.shape[perm[1]], w.shape[perm[2]])
+    o2 = oracle.Oracle(shp, None, **w.params)
+    o2.init(fp)
+    o2.step(8)
+    m2 = o2.moments()
+    tr = tuple(2 - perm[2 - k] for k in range(3))
+    for k in ("n", "p"):
+        assert np.abs(np.transpose(m1[k], tr) - m2[k]).max() < 1e-12
+    for base in ("u", "E", "B", "J"):
+        for a in range(3):
+            src = np.transpose(m1[base + "xyz"[perm[a]]], tr)
+            assert np.abs(src - m2[base + "xyz"[a]]).max() < 1e-12, base
+
+
+def test_mirror_symmetry():
+    """x -> -x: polar vectors flip their x component, the axial B flips y and z."""
+    w = W.random_state(shape=(8, 6, 5), seed=6, vmax=0.05, Bmag=0.2, Emag=0.03, sigma=5.0)
+    o1 = _run(w, 8)
+    m1 = o1.moments()
+    f = w.fields
+    fl = lambda a: np.ascontiguousarray(a[:, :, ::-1])
+    fm = dict(n=fl(f["n"]), p=fl(f["p"]), rho_c=fl(f["rho_c"]),
+              u=(-fl(f["u"][0]), fl(f["u"][1]), fl(f["u"][2])),
+              E=(-fl(f["E"][0]), fl(f["E"][1]), fl(f["E"][2])),
+              B=(fl(f["B"][0]), -fl(f["B"][1]), -fl(f["B"][2])))
+    o2 = oracle.Oracle(w.shape, None, **w.params)
+    o2.init(fm)
+    o2.step(8)
+    m2 = o2.moments()
+    sign = dict(n=1, p=1, ux=-1, uy=1, uz=1, Ex=-1, Ey=1, Ez=1, Bx=1, By=-1, Bz=-1, Jx=-1, Jy=1, Jz=1)
+    for k, s in sign.items():
+        assert np.abs(s * m1[k][:, :, ::-1] - m2[k]).max() < 1e-12, k
+
+
+def test_checkpoint_equivalence():
+    w = W.random_state(shape=(6, 5, 4), seed=2, vmax=0.05, Bmag=0.2, Emag=0.02)
+    a = _run(w, 10)
+    b = _run(w, 5)
+    st = b.get_state()
+    c = oracle.Oracle(w.shape, w.bc, **w.params)
+    c.set_state(st)
+    c.step(5)
+    assert np.array_equal(a.get_state(), c.get_state())
