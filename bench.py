@@ -1,0 +1,143 @@
+"""Throughput of the fused resistive-RMHD lattice Boltzmann step on one MI355X.
+
+Prints ONE JSON line.  A step is one launch of the fused kernel (transport,
+moments, recovery, Ohm-coupled E and J, collisions, stores) over the whole
+grid; the workload is the 3-D flare-like box 256x256x512 (synthetic initial
+fields, see paper_1508_03452_amd/workloads.py).  Timing: W untimed warm-up
+steps, then K steps bracketed by synchronisations, with HIP events recorded
+on the stream the kernels are launched on.
+
+roofline: algorithmic HBM bytes of one step (read + write of the 66 state
+values per cell) divided by the measured average step duration, against the
+MI355X HBM peak of 8 TB/s.  traffic: HBM bytes per step from rocprofv3
+FETCH_SIZE / WRITE_SIZE counters (profiles/), scaled by the copy-kernel
+calibration factor, or null when not measured for this kernel version.
+
+cpu_baseline: the oracle (plain single-threaded FP64 C) on a bounded sample
+of the same workload, timed on this host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS + % HBM peak, plain FP64 vs mixed+learned form at stated error"
+KERNEL_SOURCES = ("paper_1508_03452_amd/csrc/rmhdlb_kernels.hip", "paper_1508_03452_amd/csrc/rmhdlb_device.h")
+# HBM GB per launch of k_fused_step from rocprofv3 FETCH_SIZE + WRITE_SIZE
+# (scaled by the copy-kernel calibration), keyed by (workload, storage, hash
+# of the kernel sources): a changed kernel reports null until re-measured.
+MEASURED_TRAFFIC = {
+    ("flare", "f64", "c66a3a8f73d6"): 59.36,   # profiles/fused_step_f64_flare256x256x512.md
+}
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="flare", choices=["flare", "kh"])
+    ap.add_argument("--storage", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(budget_s):
+    """Oracle on a 64x64x32 instance of the flare generator for as many steps as fit the budget."""
+    import oracle
+    from paper_1508_03452_amd import workloads as W
+    w = W.flare(nx=64, ny=64, nz=32, Lz=3.0)
+    o = oracle.Oracle(w.shape, w.bc, **w.params)
+    o.init(w.fields)
+    o.step(1)  # first-touch
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        o.step(2)
+        steps += 2
+    el = time.perf_counter() - t0
+    return {"value": w.ncells * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"flare generator at 64x64x32 ({w.ncells} cells), {steps} steps, {el:.1f} s, "
+                      f"single-threaded FP64 C oracle on {os.cpu_count()} visible host cores"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described in DESIGN.md, not implemented)"}))
+        sys.exit(2)
+    import torch
+    from paper_1508_03452_amd import workloads as W
+    from paper_1508_03452_amd.rmhdlb import Solver
+    torch.cuda.set_device(0)
+    w = W.flare() if args.workload == "flare" else W.kh()
+    stream = torch.cuda.current_stream()
+    s = Solver(w.shape, w.bc, storage=args.storage, stream=stream, **w.params)
+    s.init_fields(w.fields)
+    del w.fields
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    s.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    m = s.moments(fields=())
+    d = m["diag"]
+    ncell = w.ncells
+    mlups = ncell / (ms * 1e-3) / 1e6
+    bytes_per_value = 8 if args.storage == "f64" else 4
+    alg_bytes = 2 * 66 * bytes_per_value * ncell
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    traffic = MEASURED_TRAFFIC.get((args.workload, args.storage, kernel_hash()))
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": (f"flare-like 3-D box {w.shape[0]}x{w.shape[1]}x{w.shape[2]}, sigma=1e3, open faces"
+                                if args.workload == "flare" else
+                                f"KH shear layer {w.shape[0]}x{w.shape[1]}x{w.shape[2]}, v0=0.2, ratio 10, sigma=1e3"),
+                   "storage": args.storage, "cells": ncell, "recovery": "plain Newton",
+                   "wall_s_timed": round(wall, 3), "failed_cells": d["n_failed"],
+                   "mean_newton_iters": round(d["mean_iters"], 3)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_fused_step", "alg_bytes_per_launch": alg_bytes,
+                     "traffic_unit": "GB per launch", "kernel_sources_hash": kernel_hash()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,158 @@
+/*
+ * rmhdlb.h -- C ABI of the MI355X (gfx950) lattice Boltzmann solver for
+ * resistive relativistic magnetohydrodynamics (Mohseni, Mendoza, Succi,
+ * Herrmann, arXiv:1508.03452, Sec. III).
+ *
+ * One time step per cell: transport of the post-collision fluid
+ * distributions f (D3Q19, energy-momentum) and g (D3Q19, number) with
+ * minmod-limited fluxes and the bulk-viscosity term (Eq. rlb), streaming of
+ * the D3Q13 Maxwell distributions h (Eq. LB_Maxwell), the moments (Eqs.
+ * Cal_E, Cal_B, Cal_rhoc), the Landau-frame recovery of eps, u, n, p
+ * (Sec. III, "Coupling between fluid and electromagnetic fields"), the
+ * force-corrected E with the Ohm current (Eqs. Ex_force, Ohm), and the
+ * collisions towards f_eq (Eq. Dis_fun_EM), g_eq (Eq. Hupp) and h_eq
+ * (Eq. Maxwell-eq).  All of it runs in one fused kernel per step.
+ *
+ * Conventions for every entry point:
+ *  - Return value: RMHDLB_OK (0) or a negative error code; no exception
+ *    crosses the ABI.  rmhdlb_strerror() names a code.
+ *  - Arrays: contiguous FP64, nx*ny*nz values, x fastest, then y, then z.
+ *    Field pointers are DEVICE pointers on the context's device unless an
+ *    entry point says otherwise.  Inputs are borrowed for the call only.
+ *  - Units: the paper's numerical units with mu0 = 1 by default; dt is fixed
+ *    by dx/dt = sqrt(2) c (Sec. III, end of the coupling subsection).
+ *  - Streams: all work is queued on the HIP stream given to rmhdlb_create
+ *    (NULL = the default stream).  Only rmhdlb_moments and the state copy
+ *    calls synchronise (that stream).
+ *  - A context is used by one host thread at a time; contexts are
+ *    independent.
+ */
+#ifndef RMHDLB_H
+#define RMHDLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RMHDLB_OK = 0,
+    RMHDLB_EINVAL = -1,      /* invalid argument or parameter */
+    RMHDLB_ENOMEM = -2,      /* device allocation failed */
+    RMHDLB_EDEVICE = -3,     /* HIP runtime or launch error */
+    RMHDLB_ERECOVERY = -4,   /* primitive recovery failed in some cell (state holds NaN there) */
+    RMHDLB_EUNSUPPORTED = -5 /* parameter value outside what the method supports */
+};
+
+enum { RMHDLB_BC_PERIODIC = 0, RMHDLB_BC_OPEN = 1 };
+
+/* Storage of the distributions between steps.  F64 is the plain path. */
+enum { RMHDLB_STORE_F64 = 0, RMHDLB_STORE_F32 = 1 };
+
+typedef struct {
+    int32_t nx, ny, nz;          /* cells per axis, each >= 1 */
+    int32_t bc_lo[3], bc_hi[3];  /* face types per axis (periodic on both faces or open on both) */
+    double dx;                   /* cell size (> 0) */
+    double c;                    /* light speed (> 0); dt = dx / (sqrt(2) c) */
+    double mu0;                  /* permeability (> 0); eps0 = 1 / (mu0 c^2) */
+    double tau;                  /* fluid relaxation time in units of dt (> 0; the paper uses 1) */
+    double tau_h;                /* Maxwell relaxation time; only 1/2 is supported (Eq. Ex_force) */
+    double alpha;                /* bulk-viscosity constant, lambda_i = alpha dx (>= 0; the paper uses 0.1) */
+    double Gamma;                /* adiabatic index of p = (Gamma - 1)(eps - n c^2), Eq. EOS (> 1) */
+    double sigma;                /* conductivity of Eq. Ohm (>= 0) */
+    double nu;                   /* lattice nu = c / c_s (> 0); sqrt(27) makes every g weight positive */
+    int32_t storage;             /* RMHDLB_STORE_* */
+    int32_t reserved[7];         /* must be zero */
+} rmhdlb_params;
+
+/* Initial primitive fields (Sec. IV): number density n, pressure p,
+ * velocity u, electric field E, magnetic field B, charge density rho_c
+ * (rho_c may be NULL: then eps0 div E by central differences, Eq. Gauss_E). */
+typedef struct {
+    const double *n, *p;
+    const double *u[3], *E[3], *B[3];
+    const double *rho_c;
+} rmhdlb_fields_in;
+
+/* Primitive fields of the current state; any pointer may be NULL. */
+typedef struct {
+    double *n, *p, *eps;
+    double *u[3], *E[3], *B[3], *J[3];
+    double *rho_c;
+} rmhdlb_fields_out;
+
+/* Global diagnostics of the current state (sums over cells, FP64). */
+typedef struct {
+    double energy;       /* sum of T^00 (fluid + field, the moment of f) */
+    double mass;         /* sum of N^0 */
+    double momentum[3];  /* sum of T^0a */
+    double em_energy;    /* sum of eps0 (E^2 + c^2 B^2) / 2 */
+    double max_divB;     /* max over cells of |div B| by central differences */
+    double charge;       /* sum of rho_c (Eq. Cal_rhoc) */
+    double mean_iters;   /* mean Newton iterations of the recovery */
+    int64_t n_failed;    /* cells whose recovery failed */
+    int64_t step;        /* steps taken since rmhdlb_init_fields */
+} rmhdlb_diag;
+
+typedef struct rmhdlb_ctx rmhdlb_ctx; /* opaque, owned by the library */
+
+/* Create a solver.  Validates *params (RMHDLB_EINVAL; tau_h != 1/2 gives
+ * RMHDLB_EUNSUPPORTED), allocates the two state buffers on the current HIP
+ * device (RMHDLB_ENOMEM) and keeps `hip_stream` (a hipStream_t, may be NULL).
+ * On success *out owns the device memory until rmhdlb_destroy; on failure
+ * *out is NULL and nothing stays allocated. */
+int rmhdlb_create(const rmhdlb_params *params, void *hip_stream, rmhdlb_ctx **out);
+
+/* Set the state from primitive fields (device pointers, see rmhdlb_fields_in).
+ * The stored state is post-collision: f and g are the equilibria of the given
+ * fields (f_eq of Eq. Dis_fun_EM, g_eq of Eq. Hupp), the Maxwell
+ * populations are laid out so that the first streaming delivers h_eq of
+ * (J0, E0 + (dt/2) mu0 c^2 J0, B0) with J0 from Eq. Ohm, and the rest
+ * population holds rho_c.  Returns RMHDLB_EINVAL for NULL pointers; physically
+ * invalid inputs (|u| >= c, n <= 0, p < 0) surface as failed cells at the
+ * next rmhdlb_moments.  Resets the step counter. */
+int rmhdlb_init_fields(rmhdlb_ctx *ctx, const rmhdlb_fields_in *in);
+
+/* Queue nsteps >= 0 fused time steps on the context's stream and return
+ * without waiting.  Only launch errors are reported here (RMHDLB_EDEVICE);
+ * recovery failures are deferred to rmhdlb_moments. */
+int rmhdlb_step(rmhdlb_ctx *ctx, int64_t nsteps);
+
+/* Primitive fields of the current state (what the next step computes first:
+ * transport, moments, recovery, E and J), written to the non-NULL device
+ * pointers of *out, and the global diagnostics written to *diag (host
+ * memory).  Either may be NULL.  Synchronises the stream.  Returns
+ * RMHDLB_ERECOVERY when some cell failed its recovery (its primitives are
+ * NaN; diag->n_failed counts them). */
+int rmhdlb_moments(rmhdlb_ctx *ctx, rmhdlb_fields_out *out, rmhdlb_diag *diag);
+
+/* Release the context and its device memory.  NULL is accepted. */
+int rmhdlb_destroy(rmhdlb_ctx *ctx);
+
+/* Static text for an error code. */
+const char *rmhdlb_strerror(int code);
+
+/* Number of FP64 values of the raw state: 66 * nx*ny*nz (F[19], G[19],
+ * h*[24 moving + 1 rest], E_prev[3], each nx*ny*nz values, post-collision). */
+int64_t rmhdlb_state_len(const rmhdlb_ctx *ctx);
+
+/* Copy the raw state to / from a DEVICE buffer of rmhdlb_state_len FP64
+ * values in the layout above (checkpoint and restart; FP32 storage is
+ * widened or rounded).  Synchronise the stream. */
+int rmhdlb_get_state(rmhdlb_ctx *ctx, double *dst);
+int rmhdlb_set_state(rmhdlb_ctx *ctx, const double *src);
+
+/* The lattice tables the library uses (host memory, no device work):
+ * e19[19*3] D3Q19 unit vectors and w19[19] weights in state order; for the
+ * 24 moving Maxwell populations in state order the lattice offsets
+ * s24[24*3] (v_k dt / dx), ehat24[24*3] (e_k = c ehat_k / sqrt 2) and
+ * bhat24[24*3] (b_k = bhat_k).  Sec. III, Eq. cellconfigs1 and the D3Q13
+ * definitions. */
+int rmhdlb_lattice_tables(int32_t *e19, double *w19, int32_t *s24, int32_t *ehat24, int32_t *bhat24);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,265 @@
+// rmhdlb_api.hip -- implementation of the C ABI declared in include/rmhdlb.h.
+//
+// Owns parameter validation, the two device state buffers and the scratch
+// memory, the per-run constants and the launch sequence.  No host
+// synchronisation except in rmhdlb_moments and the state copies.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "rmhdlb.h"
+#include "rmhdlb_internal.h"
+
+using rmhd::Consts;
+
+struct rmhdlb_ctx {
+    rmhdlb_params P;
+    hipStream_t stream;
+    Consts K;
+    size_t elem;       // bytes per stored value
+    void* buf[2];      // state buffers, NSTATE * stride values each
+    int cur;
+    double* scratch;   // 6 N doubles: initial J0 and E'0, then B of the moments pass
+    double* part;      // per-tile partial diagnostics
+    double* part2;     // per-tile max |div B|
+    double* result;    // NPART + 1 reduced values
+    int64_t step;
+};
+
+namespace {
+
+int validate(const rmhdlb_params* P) {
+    if (!P) return RMHDLB_EINVAL;
+    if (P->nx < 1 || P->ny < 1 || P->nz < 1) return RMHDLB_EINVAL;
+    const int64_t N = (int64_t)P->nx * P->ny * P->nz;
+    if (N > 2147483647LL / 2) return RMHDLB_EINVAL;  // cell indices are 32-bit
+    for (int a = 0; a < 3; ++a) {
+        if ((P->bc_lo[a] != RMHDLB_BC_PERIODIC && P->bc_lo[a] != RMHDLB_BC_OPEN) ||
+            (P->bc_hi[a] != RMHDLB_BC_PERIODIC && P->bc_hi[a] != RMHDLB_BC_OPEN))
+            return RMHDLB_EINVAL;
+        if ((P->bc_lo[a] == RMHDLB_BC_PERIODIC) != (P->bc_hi[a] == RMHDLB_BC_PERIODIC)) return RMHDLB_EINVAL;
+    }
+    if (!(P->dx > 0) || !(P->c > 0) || !(P->mu0 > 0) || !(P->tau > 0) || !(P->alpha >= 0) || !(P->Gamma > 1) ||
+        !(P->sigma >= 0) || !(P->nu > 0) || !isfinite(P->sigma) || !isfinite(P->alpha))
+        return RMHDLB_EINVAL;
+    if (P->storage != RMHDLB_STORE_F64 && P->storage != RMHDLB_STORE_F32) return RMHDLB_EINVAL;
+    for (int k = 0; k < 7; ++k)
+        if (P->reserved[k] != 0) return RMHDLB_EINVAL;
+    if (P->tau_h != 0.5) return RMHDLB_EUNSUPPORTED;  // the force form of Eq. Ex_force needs tau_h = 1/2
+    return RMHDLB_OK;
+}
+
+Consts make_consts(const rmhdlb_params* P) {
+    Consts K;
+    memset(&K, 0, sizeof(K));
+    K.nx = P->nx;
+    K.ny = P->ny;
+    K.nz = P->nz;
+    for (int a = 0; a < 3; ++a) K.per[a] = P->bc_lo[a] == RMHDLB_BC_PERIODIC ? 1 : 0;
+    K.N = (int64_t)P->nx * P->ny * P->nz;
+    K.stride = (K.N + 63) / 64 * 64;
+    const double dt = P->dx / (sqrt(2.0) * P->c);  // dx / dt = sqrt(2) c
+    K.c = P->c;
+    K.dx = P->dx;
+    K.eps0 = 1.0 / (P->mu0 * P->c * P->c);
+    K.cour = rmhd::KAPPA * P->c * dt / P->dx;
+    K.kv = P->alpha * P->c * dt / P->dx;
+    K.inv_tau = 1.0 / P->tau;
+    const double ct_c0 = sqrt(27.0) / P->nu, ca = sqrt(19.0) / P->nu;
+    K.wg = (P->nu / ct_c0) / P->tau;
+    K.q = 0.5 * dt * P->mu0 * P->c * P->c;
+    K.sigma = P->sigma;
+    K.gm1 = P->Gamma - 1.0;
+    K.wp[0] = 0.1;
+    K.wp[1] = 0.3 - 1.0 / (6.0 * ca * ca);
+    K.wp[2] = 1.0 / (12.0 * ca * ca) - 3.0 / 40.0;
+    K.gc1 = ct_c0 * 3.0 * ca;
+    K.gc2 = ct_c0 * 4.5 * ca * ca;
+    K.gc3 = ct_c0 * 1.5;
+    K.inv_2dx = 0.5 / P->dx;
+    return K;
+}
+
+void release(rmhdlb_ctx* C) {
+    if (!C) return;
+    for (int b = 0; b < 2; ++b)
+        if (C->buf[b]) (void)hipFree(C->buf[b]);
+    if (C->scratch) (void)hipFree(C->scratch);
+    if (C->part) (void)hipFree(C->part);
+    if (C->part2) (void)hipFree(C->part2);
+    if (C->result) (void)hipFree(C->result);
+    delete C;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rmhdlb_strerror(int code) {
+    switch (code) {
+        case RMHDLB_OK: return "ok";
+        case RMHDLB_EINVAL: return "invalid argument";
+        case RMHDLB_ENOMEM: return "device allocation failed";
+        case RMHDLB_EDEVICE: return "HIP runtime or launch error";
+        case RMHDLB_ERECOVERY: return "primitive recovery failed in some cells";
+        case RMHDLB_EUNSUPPORTED: return "unsupported parameter value";
+        default: return "unknown error";
+    }
+}
+
+int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** out) {
+    if (!out) return RMHDLB_EINVAL;
+    *out = nullptr;
+    const int v = validate(params);
+    if (v != RMHDLB_OK) return v;
+    rmhdlb_ctx* C = new (std::nothrow) rmhdlb_ctx();
+    if (!C) return RMHDLB_ENOMEM;
+    C->P = *params;
+    C->stream = (hipStream_t)hip_stream;
+    C->K = make_consts(params);
+    C->elem = params->storage == RMHDLB_STORE_F64 ? sizeof(double) : sizeof(float);
+    const size_t bytes = (size_t)rmhd::NSTATE * (size_t)C->K.stride * C->elem;
+    const int nt = rmhd::num_tiles(C->K);
+    bool ok = true;
+    for (int b = 0; b < 2 && ok; ++b) ok = hipMalloc(&C->buf[b], bytes) == hipSuccess;
+    ok = ok && hipMalloc((void**)&C->scratch, sizeof(double) * 6 * (size_t)C->K.N) == hipSuccess;
+    ok = ok && hipMalloc((void**)&C->part, sizeof(double) * rmhd::NPART * (size_t)nt) == hipSuccess;
+    ok = ok && hipMalloc((void**)&C->part2, sizeof(double) * (size_t)nt) == hipSuccess;
+    ok = ok && hipMalloc((void**)&C->result, sizeof(double) * (rmhd::NPART + 1)) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        release(C);
+        return RMHDLB_ENOMEM;
+    }
+    C->cur = 0;
+    C->step = 0;
+    *out = C;
+    return RMHDLB_OK;
+}
+
+int rmhdlb_destroy(rmhdlb_ctx* ctx) {
+    if (!ctx) return RMHDLB_OK;
+    (void)hipStreamSynchronize(ctx->stream);
+    release(ctx);
+    return RMHDLB_OK;
+}
+
+int rmhdlb_init_fields(rmhdlb_ctx* C, const rmhdlb_fields_in* in) {
+    if (!C || !in || !in->n || !in->p) return RMHDLB_EINVAL;
+    rmhd::InPtrs ip;
+    ip.n = in->n;
+    ip.p = in->p;
+    for (int a = 0; a < 3; ++a) {
+        if (!in->u[a] || !in->E[a] || !in->B[a]) return RMHDLB_EINVAL;
+        ip.u[a] = in->u[a];
+        ip.E[a] = in->E[a];
+        ip.B[a] = in->B[a];
+    }
+    ip.rho_c = in->rho_c;
+    C->cur = 0;
+    hipError_t e = C->elem == sizeof(double)
+                       ? rmhd::launch_init<double>(ip, C->K, C->scratch, C->buf[0], C->stream)
+                       : rmhd::launch_init<float>(ip, C->K, C->scratch, C->buf[0], C->stream);
+    if (e != hipSuccess) return RMHDLB_EDEVICE;
+    C->step = 0;
+    return RMHDLB_OK;
+}
+
+int rmhdlb_step(rmhdlb_ctx* C, int64_t nsteps) {
+    if (!C || nsteps < 0) return RMHDLB_EINVAL;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        hipError_t e = C->elem == sizeof(double)
+                           ? rmhd::launch_step<double>(C->buf[C->cur], C->buf[1 - C->cur], C->K, C->stream)
+                           : rmhd::launch_step<float>(C->buf[C->cur], C->buf[1 - C->cur], C->K, C->stream);
+        if (e != hipSuccess) return RMHDLB_EDEVICE;
+        C->cur = 1 - C->cur;
+        C->step++;
+    }
+    return RMHDLB_OK;
+}
+
+int rmhdlb_moments(rmhdlb_ctx* C, rmhdlb_fields_out* out, rmhdlb_diag* diag) {
+    if (!C) return RMHDLB_EINVAL;
+    rmhd::OutPtrs op;
+    memset(&op, 0, sizeof(op));
+    if (out) {
+        op.n = out->n;
+        op.p = out->p;
+        op.eps = out->eps;
+        for (int a = 0; a < 3; ++a) {
+            op.u[a] = out->u[a];
+            op.E[a] = out->E[a];
+            op.B[a] = out->B[a];
+            op.J[a] = out->J[a];
+        }
+        op.rho_c = out->rho_c;
+    }
+    hipError_t e = C->elem == sizeof(double)
+                       ? rmhd::launch_moments<double>(C->buf[C->cur], C->K, op, C->scratch, C->part, C->part2,
+                                                      C->result, C->stream)
+                       : rmhd::launch_moments<float>(C->buf[C->cur], C->K, op, C->scratch, C->part, C->part2,
+                                                     C->result, C->stream);
+    if (e != hipSuccess) return RMHDLB_EDEVICE;
+    double r[rmhd::NPART + 1];
+    if (hipMemcpyAsync(r, C->result, sizeof(r), hipMemcpyDeviceToHost, C->stream) != hipSuccess)
+        return RMHDLB_EDEVICE;
+    if (hipStreamSynchronize(C->stream) != hipSuccess) return RMHDLB_EDEVICE;
+    const int64_t failed = (int64_t)llround(r[8]);
+    if (diag) {
+        diag->energy = r[0];
+        diag->mass = r[1];
+        diag->momentum[0] = r[2];
+        diag->momentum[1] = r[3];
+        diag->momentum[2] = r[4];
+        diag->em_energy = r[5];
+        diag->charge = r[6];
+        diag->mean_iters = r[7] / (double)C->K.N;
+        diag->n_failed = failed;
+        diag->max_divB = r[rmhd::NPART];
+        diag->step = C->step;
+    }
+    return failed ? RMHDLB_ERECOVERY : RMHDLB_OK;
+}
+
+int64_t rmhdlb_state_len(const rmhdlb_ctx* C) { return C ? (int64_t)rmhd::NSTATE * C->K.N : -1; }
+
+int rmhdlb_get_state(rmhdlb_ctx* C, double* dst) {
+    if (!C || !dst) return RMHDLB_EINVAL;
+    hipError_t e = C->elem == sizeof(double) ? rmhd::launch_export<double>(C->buf[C->cur], dst, C->K, C->stream)
+                                             : rmhd::launch_export<float>(C->buf[C->cur], dst, C->K, C->stream);
+    if (e != hipSuccess || hipStreamSynchronize(C->stream) != hipSuccess) return RMHDLB_EDEVICE;
+    return RMHDLB_OK;
+}
+
+int rmhdlb_set_state(rmhdlb_ctx* C, const double* src) {
+    if (!C || !src) return RMHDLB_EINVAL;
+    hipError_t e = C->elem == sizeof(double) ? rmhd::launch_import<double>(src, C->buf[C->cur], C->K, C->stream)
+                                             : rmhd::launch_import<float>(src, C->buf[C->cur], C->K, C->stream);
+    if (e != hipSuccess || hipStreamSynchronize(C->stream) != hipSuccess) return RMHDLB_EDEVICE;
+    return RMHDLB_OK;
+}
+
+int rmhdlb_lattice_tables(int32_t* e19, double* w19, int32_t* s24, int32_t* ehat24, int32_t* bhat24) {
+    if (!e19 || !w19 || !s24 || !ehat24 || !bhat24) return RMHDLB_EINVAL;
+    for (int i = 0; i < rmhd::Q; ++i) {
+        e19[3 * i] = rmhd::EX[i];
+        e19[3 * i + 1] = rmhd::EY[i];
+        e19[3 * i + 2] = rmhd::EZ[i];
+        w19[i] = rmhd::weight(i);
+    }
+    for (int k = 0; k < rmhd::QH; ++k) {
+        s24[3 * k] = rmhd::SX[k];
+        s24[3 * k + 1] = rmhd::SY[k];
+        s24[3 * k + 2] = rmhd::SZ[k];
+        ehat24[3 * k] = rmhd::EHX[k];
+        ehat24[3 * k + 1] = rmhd::EHY[k];
+        ehat24[3 * k + 2] = rmhd::EHZ[k];
+        bhat24[3 * k] = rmhd::BHX[k];
+        bhat24[3 * k + 1] = rmhd::BHY[k];
+        bhat24[3 * k + 2] = rmhd::BHZ[k];
+    }
+    return RMHDLB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// rmhdlb_device.h -- device-side lattice tables and per-cell physics of the
+// resistive relativistic MHD lattice Boltzmann step (arXiv:1508.03452,
+// Sec. III), written for gfx950 in FP64 arithmetic.
+//
+// The fluid distributions are held in the normalised, nu-free variables
+// F = (c_t/c_0)^2 f and G = (c_t/c_0) g, for which the moments are
+// T^00 = sum F, T^0a = kappa sum e^a F, T^ab = kappa^2 sum e^a e^b F and
+// N^0 = sum G, with kappa = c_0 c_a / c_t = sqrt(19/27).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rmhd {
+
+// ---------------------------------------------------------------- lattices
+
+constexpr int Q = 19;   // D3Q19 (Eq. cellconfigs1)
+constexpr int QH = 24;  // moving D3Q13 Maxwell populations; index 24 is the rest one
+constexpr int NSTATE = Q + Q + QH + 1 + 3;  // F, G, h*, E_prev
+
+// Interface order of the D3Q19 directions: rest, +-x, +-y, +-z, then the
+// face diagonals in the xy, xz and yz planes.
+constexpr int EX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int EY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int EZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+// D3Q19 weights: they do not depend on nu (Sec. III): -44/361, 99/722, 9/361.
+__host__ __device__ constexpr double weight(int i) {
+    return i == 0 ? -44.0 / 361.0 : (i <= 6 ? 99.0 / 722.0 : 9.0 / 361.0);
+}
+
+// D3Q13 Maxwell lattice, population k = 8 p + 2 i + j (plane p = xy, xz, yz;
+// direction i; auxiliary pair j).  v_k dt = (SX, SY, SZ) dx, i.e. v_k =
+// sqrt(2) c s_k; e_k = (c / sqrt 2) ehat_k; b_k = bhat_k.  The pair j = 1 has
+// the opposite e and b of j = 0.
+constexpr int SX[QH] = {1, 1, -1, -1, -1, -1, 1, 1, 1, 1, -1, -1, -1, -1, 1, 1, 0, 0, 0, 0, 0, 0, 0, 0};
+constexpr int SY[QH] = {1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, -1, -1, -1, -1, 1, 1};
+constexpr int SZ[QH] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, -1, -1, -1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
+constexpr int EHX[QH] = {1, -1, 1, -1, -1, 1, -1, 1, 1, -1, 1, -1, -1, 1, -1, 1, 0, 0, 0, 0, 0, 0, 0, 0};
+constexpr int EHY[QH] = {-1, 1, 1, -1, 1, -1, -1, 1, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, -1, 1};
+constexpr int EHZ[QH] = {0, 0, 0, 0, 0, 0, 0, 0, -1, 1, 1, -1, 1, -1, -1, 1, -1, 1, 1, -1, 1, -1, -1, 1};
+constexpr int BHX[QH] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1, 1, -1, 1, -1, 1, -1, 1};
+constexpr int BHY[QH] = {0, 0, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 0, 0, 0, 0};
+constexpr int BHZ[QH] = {-1, 1, -1, 1, -1, 1, -1, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+
+// Offsets of the state arrays (each `stride` values long).
+constexpr int OFF_F = 0, OFF_G = Q, OFF_H = 2 * Q, OFF_E = 2 * Q + QH + 1;
+
+// --------------------------------------------------------------- constants
+
+struct Consts {
+    int nx, ny, nz;
+    int per[3];          // 1 = periodic axis, 0 = open
+    int64_t N;           // cells
+    int64_t stride;      // values per state array (N rounded up)
+    double c, dx, eps0;
+    double cour;         // Courant number along a link: kappa c dt / dx
+    double kv;           // bulk-viscosity coefficient alpha c dt / dx
+    double inv_tau;      // 1 / tau (tau in units of dt)
+    double wg;           // rate of the g collision, (c_0 nu / c_t) / tau
+    double q;            // (dt / 2) mu0 c^2
+    double sigma, gm1;   // conductivity, Gamma - 1
+    double wp[3];        // g weights (rest, axis, diagonal)
+    double gc1, gc2, gc3;  // (c_t/c_0) * (3 c_a, 9/2 c_a^2, 3/2) of the g equilibrium
+    double inv_2dx;
+};
+
+constexpr double KAPPA = 0.83887049280786108;   // sqrt(19/27)
+constexpr double KAPPA2 = 19.0 / 27.0;
+constexpr double SQRT19_3 = 2.5166114784235836; // sqrt(19/3)
+constexpr double INV_SQRT2 = 0.70710678118654752;
+
+// ------------------------------------------------------------- primitives
+
+__device__ __forceinline__ double minmod(double a, double b) {
+    if (a * b <= 0.0) return 0.0;
+    return fabs(a) < fabs(b) ? a : b;
+}
+
+// Solve (Pi + lam I) y = S for the symmetric 3x3 Pi (xx, yy, zz, xy, xz, yz)
+// by cofactors.
+__device__ __forceinline__ void solve_shifted(const double Pi[6], double lam, const double S[3], double y[3]) {
+    const double a = Pi[0] + lam, b = Pi[1] + lam, c = Pi[2] + lam;
+    const double d = Pi[3], e = Pi[4], f = Pi[5];
+    const double c00 = b * c - f * f, c01 = e * f - d * c, c02 = d * f - e * b;
+    const double c11 = a * c - e * e, c12 = d * e - a * f, c22 = a * b - d * d;
+    const double inv = 1.0 / (a * c00 + d * c01 + e * c02);
+    y[0] = (c00 * S[0] + c01 * S[1] + c02 * S[2]) * inv;
+    y[1] = (c01 * S[0] + c11 * S[1] + c12 * S[2]) * inv;
+    y[2] = (c02 * S[0] + c12 * S[1] + c22 * S[2]) * inv;
+}
+
+// Landau-frame recovery.  The fluid tensor T_fl = T - T_EM has the timelike
+// eigenvector (1, beta) with eigenvalue eps: (Pi + eps I) beta = S and
+// eps = E_f - S.beta.  Eliminating beta gives the secular equation
+// phi(lam) = lam - E_f + S^T (Pi + lam I)^-1 S = 0, increasing and convex for
+// lam above its root (phi' = 1 - |beta|^2 = 1/gamma^2 there), so Newton from
+// lam = E_f (where phi = S^T A^-1 S >= 0) decreases monotonically to it.
+// Every Newton step is applied (so lam carries no one-sided bias from the
+// monotone approach) until the step is at the rounding floor; beta is then
+// solved at the final lam.  Returns the number of Newton steps.
+__device__ __forceinline__ int recover(double Ef, const double S[3], const double Pi[6], double& lam,
+                                       double beta[3]) {
+    lam = Ef;
+    int it = 0;
+    while (it < 60) {
+        solve_shifted(Pi, lam, S, beta);
+        const double phi = lam - Ef + (S[0] * beta[0] + S[1] * beta[1] + S[2] * beta[2]);
+        const double dphi = 1.0 - (beta[0] * beta[0] + beta[1] * beta[1] + beta[2] * beta[2]);
+        const double d = phi / dphi;
+        ++it;
+        if (d == 0.0) return it;  // beta already solved at lam
+        lam -= d;
+        if (!(fabs(d) > 4.5e-16 * fabs(lam))) break;
+    }
+    solve_shifted(Pi, lam, S, beta);
+    return it;
+}
+
+}  // namespace rmhd

@@ -1,0 +1,103 @@
+// rmhdlb_internal.h -- declarations shared by the kernels and the C ABI
+// implementation of the HIP library (not part of the public interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rmhdlb_device.h"
+
+namespace rmhd {
+
+constexpr int NPART = 9;  // partial diagnostics per block (see k_moments)
+constexpr int RED_WAVES = 4;
+
+struct InPtrs {
+    const double *n, *p;
+    const double *u[3], *E[3], *B[3];
+    const double* rho_c;
+};
+
+struct OutPtrs {
+    double *n, *p, *eps;
+    double *u[3], *E[3], *B[3], *J[3];
+    double* rho_c;
+};
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
+// Deterministic block sums of W values per thread: butterfly within each
+// 64-wide wavefront, then the 4 wavefront results in fixed order.  Thread j
+// (j < W) writes sum j to out[j].
+template <int W>
+__device__ __forceinline__ void block_sum(const double (&v)[W], double* __restrict__ out) {
+    __shared__ double sh[W][RED_WAVES];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const double s = wave_sum(v[j]);
+        if (lane == 0) sh[j][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < W) {
+        const int j = threadIdx.x;
+        out[j] = ((sh[j][0] + sh[j][1]) + (sh[j][2] + sh[j][3]));
+    }
+}
+
+__device__ __forceinline__ void block_max1(double v, double* __restrict__ out) {
+    __shared__ double sh[RED_WAVES];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double m = wave_max(v);
+    if (lane == 0) sh[wave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+__device__ __forceinline__ double block_sum_value(double v) {
+    __shared__ double sh[RED_WAVES];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double s = wave_sum(v);
+    if (lane == 0) sh[wave] = s;
+    __syncthreads();
+    const double r = ((sh[0] + sh[1]) + (sh[2] + sh[3]));
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double block_max_value(double v) {
+    __shared__ double sh[RED_WAVES];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double m = wave_max(v);
+    if (lane == 0) sh[wave] = m;
+    __syncthreads();
+    const double r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    __syncthreads();
+    return r;
+}
+
+int num_tiles(const Consts& K);
+
+template <typename T>
+hipError_t launch_step(const void* src, void* dst, const Consts& K, hipStream_t s);
+template <typename T>
+hipError_t launch_moments(const void* src, const Consts& K, const OutPtrs& out, double* Bscr, double* part,
+                          double* part2, double* result, hipStream_t s);
+template <typename T>
+hipError_t launch_init(const InPtrs& in, const Consts& K, double* scr, void* dst, hipStream_t s);
+template <typename T>
+hipError_t launch_export(const void* src, double* dst, const Consts& K, hipStream_t s);
+template <typename T>
+hipError_t launch_import(const double* src, void* dst, const Consts& K, hipStream_t s);
+
+}  // namespace rmhd

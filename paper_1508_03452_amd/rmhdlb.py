@@ -1,0 +1,224 @@
+"""Thin ctypes binding of the C ABI in include/rmhdlb.h.
+
+Argument marshalling only: every step of the method runs in the HIP library
+(librmhdlb.so).  PyTorch provides device memory and the stream.  If the
+library is missing this module raises; there is no other code path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librmhdlb.so")
+
+RMHDLB_OK, RMHDLB_EINVAL, RMHDLB_ENOMEM, RMHDLB_EDEVICE, RMHDLB_ERECOVERY, RMHDLB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+BC = {"periodic": 0, "open": 1}
+STORAGE = {"f64": 0, "f32": 1}
+OUT_FIELDS = ("n", "p", "eps", "ux", "uy", "uz", "Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho_c")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class rmhdlb_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("bc_lo", ctypes.c_int32 * 3), ("bc_hi", ctypes.c_int32 * 3),
+        ("dx", ctypes.c_double), ("c", ctypes.c_double), ("mu0", ctypes.c_double),
+        ("tau", ctypes.c_double), ("tau_h", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("Gamma", ctypes.c_double), ("sigma", ctypes.c_double), ("nu", ctypes.c_double),
+        ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class rmhdlb_fields_in(ctypes.Structure):
+    _fields_ = [("n", _dp), ("p", _dp), ("u", _dp * 3), ("E", _dp * 3), ("B", _dp * 3), ("rho_c", _dp)]
+
+
+class rmhdlb_fields_out(ctypes.Structure):
+    _fields_ = [("n", _dp), ("p", _dp), ("eps", _dp), ("u", _dp * 3), ("E", _dp * 3), ("B", _dp * 3),
+                ("J", _dp * 3), ("rho_c", _dp)]
+
+
+class rmhdlb_diag(ctypes.Structure):
+    _fields_ = [("energy", ctypes.c_double), ("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3),
+                ("em_energy", ctypes.c_double), ("max_divB", ctypes.c_double), ("charge", ctypes.c_double),
+                ("mean_iters", ctypes.c_double), ("n_failed", ctypes.c_int64), ("step", ctypes.c_int64)]
+
+
+SYMBOLS = ("rmhdlb_create", "rmhdlb_init_fields", "rmhdlb_step", "rmhdlb_moments", "rmhdlb_destroy",
+           "rmhdlb_strerror", "rmhdlb_state_len", "rmhdlb_get_state", "rmhdlb_set_state", "rmhdlb_lattice_tables")
+
+_LIB = None
+
+
+def load():
+    """Load librmhdlb.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1508_03452_amd/build.py "
+                           "(there is no fallback implementation)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    L.rmhdlb_create.argtypes = [ctypes.POINTER(rmhdlb_params), vp, ctypes.POINTER(vp)]
+    L.rmhdlb_init_fields.argtypes = [vp, ctypes.POINTER(rmhdlb_fields_in)]
+    L.rmhdlb_step.argtypes = [vp, ctypes.c_int64]
+    L.rmhdlb_moments.argtypes = [vp, ctypes.POINTER(rmhdlb_fields_out), ctypes.POINTER(rmhdlb_diag)]
+    L.rmhdlb_destroy.argtypes = [vp]
+    L.rmhdlb_strerror.argtypes = [ctypes.c_int]
+    L.rmhdlb_strerror.restype = ctypes.c_char_p
+    L.rmhdlb_state_len.argtypes = [vp]
+    L.rmhdlb_state_len.restype = ctypes.c_int64
+    L.rmhdlb_get_state.argtypes = [vp, _dp]
+    L.rmhdlb_set_state.argtypes = [vp, _dp]
+    ip = ctypes.POINTER(ctypes.c_int32)
+    L.rmhdlb_lattice_tables.argtypes = [ip, _dp, ip, ip, ip]
+    _LIB = L
+    return L
+
+
+def strerror(code):
+    return load().rmhdlb_strerror(int(code)).decode()
+
+
+class RmhdlbError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+def _check(code, what, allow=()):
+    if code != RMHDLB_OK and code not in allow:
+        raise RmhdlbError(code, what)
+    return code
+
+
+def make_params(shape, bc=None, storage="f64", **kw):
+    from .workloads import DEFAULT_PARAMS
+    d = dict(DEFAULT_PARAMS)
+    d.update(kw)
+    P = rmhdlb_params()
+    P.nx, P.ny, P.nz = (int(v) for v in shape)
+    bc = bc or (("periodic", "periodic"),) * 3
+    for a in range(3):
+        P.bc_lo[a] = BC[bc[a][0]]
+        P.bc_hi[a] = BC[bc[a][1]]
+    for k in ("dx", "c", "mu0", "tau", "tau_h", "alpha", "Gamma", "sigma", "nu"):
+        setattr(P, k, float(d[k]))
+    P.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    return P
+
+
+def lattice_tables():
+    L = load()
+    e = np.zeros(57, dtype=np.int32)
+    w = np.zeros(19)
+    s, eh, bh = (np.zeros(72, dtype=np.int32) for _ in range(3))
+    ip = ctypes.POINTER(ctypes.c_int32)
+    _check(L.rmhdlb_lattice_tables(e.ctypes.data_as(ip), w.ctypes.data_as(_dp), s.ctypes.data_as(ip),
+                                   eh.ctypes.data_as(ip), bh.ctypes.data_as(ip)), "rmhdlb_lattice_tables")
+    return dict(e=e.reshape(19, 3), w=w, s=s.reshape(24, 3), ehat=eh.reshape(24, 3), bhat=bh.reshape(24, 3))
+
+
+def _dptr(t):
+    """Device pointer of a contiguous float64 torch tensor."""
+    import torch
+    assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+    return ctypes.cast(ctypes.c_void_p(t.data_ptr()), _dp)
+
+
+class Solver:
+    """One rmhdlb context on the current torch device and stream.  shape = (nx, ny, nz)."""
+
+    def __init__(self, shape, bc=None, storage="f64", stream=None, **params):
+        import torch
+        self.torch = torch
+        self.shape = tuple(int(v) for v in shape)
+        nx, ny, nz = self.shape
+        self.grid = (nz, ny, nx)
+        self.P = make_params(self.shape, bc, storage, **params)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._h = ctypes.c_void_p()
+        _check(load().rmhdlb_create(ctypes.byref(self.P), ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.byref(self._h)), "rmhdlb_create")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().rmhdlb_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a):
+        torch = self.torch
+        if isinstance(a, torch.Tensor):
+            t = a.to(device="cuda", dtype=torch.float64)
+        else:
+            t = torch.from_numpy(np.array(np.broadcast_to(np.asarray(a, dtype=np.float64), self.grid)))
+            t = t.to("cuda")
+        return t.reshape(self.grid).contiguous()
+
+    def init_fields(self, fields):
+        """fields: n, p, u (3), E (3), B (3), rho_c (None => Gauss) as numpy arrays or tensors."""
+        keep = {k: self._dev(fields[k]) for k in ("n", "p")}
+        fin = rmhdlb_fields_in()
+        fin.n, fin.p = _dptr(keep["n"]), _dptr(keep["p"])
+        for k in ("u", "E", "B"):
+            ts = [self._dev(x) for x in fields[k]]
+            keep[k] = ts
+            setattr(fin, k, (_dp * 3)(*[_dptr(t) for t in ts]))
+        if fields.get("rho_c") is not None:
+            keep["rho_c"] = self._dev(fields["rho_c"])
+            fin.rho_c = _dptr(keep["rho_c"])
+        else:
+            fin.rho_c = _dp()
+        _check(load().rmhdlb_init_fields(self._h, ctypes.byref(fin)), "rmhdlb_init_fields")
+        self.stream.synchronize()   # inputs are borrowed only for the call
+        return self
+
+    def step(self, nsteps=1):
+        _check(load().rmhdlb_step(self._h, int(nsteps)), "rmhdlb_step")
+
+    def moments(self, fields=OUT_FIELDS, diag=True):
+        """Primitive fields as cuda tensors (nz, ny, nx) plus a diagnostics dict."""
+        torch = self.torch
+        outs = {k: torch.empty(self.grid, dtype=torch.float64, device="cuda") for k in fields}
+        fo = rmhdlb_fields_out()
+        get = lambda k: _dptr(outs[k]) if k in outs else _dp()
+        fo.n, fo.p, fo.eps, fo.rho_c = get("n"), get("p"), get("eps"), get("rho_c")
+        for base in ("u", "E", "B", "J"):
+            setattr(fo, base, (_dp * 3)(*[get(base + a) for a in "xyz"]))
+        d = rmhdlb_diag()
+        rc = _check(load().rmhdlb_moments(self._h, ctypes.byref(fo), ctypes.byref(d)), "rmhdlb_moments",
+                    allow=(RMHDLB_ERECOVERY,))
+        res = dict(outs)
+        if diag:
+            res["diag"] = dict(energy=d.energy, mass=d.mass, momentum=np.array(list(d.momentum)),
+                               em_energy=d.em_energy, max_divB=d.max_divB, charge=d.charge,
+                               mean_iters=d.mean_iters, n_failed=int(d.n_failed), step=int(d.step))
+        res["rc"] = rc
+        return res
+
+    def state_len(self):
+        return int(load().rmhdlb_state_len(self._h))
+
+    def get_state(self):
+        t = self.torch.empty(self.state_len(), dtype=self.torch.float64, device="cuda")
+        _check(load().rmhdlb_get_state(self._h, _dptr(t)), "rmhdlb_get_state")
+        return t.reshape((66,) + self.grid)
+
+    def set_state(self, state):
+        t = self._dev_flat(state)
+        _check(load().rmhdlb_set_state(self._h, _dptr(t)), "rmhdlb_set_state")
+
+    def _dev_flat(self, a):
+        torch = self.torch
+        if isinstance(a, torch.Tensor):
+            return a.to(device="cuda", dtype=torch.float64).reshape(-1).contiguous()
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).to("cuda")

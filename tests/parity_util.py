@@ -1,0 +1,63 @@
+"""Helpers for comparing the HIP library with the oracle (test infrastructure)."""
+import numpy as np
+
+import oracle
+
+VEC = ("u", "E", "B", "J")
+
+
+def field_errors(ref, got, scale_B):
+    """Per-field error: max |got - ref| / max(max |ref|, floor).  Floors: c for
+    velocities, the field scale for E, B, J (their natural size in the run)."""
+    errs = {}
+    for k, r in ref.items():
+        if k not in got or k in ("n_failed",):
+            continue
+        g = got[k]
+        if k[0] == "u" and len(k) == 2:
+            floor = 1.0
+        elif (k[0] in "EBJ" and len(k) == 2) or k == "rho_c":
+            floor = scale_B             # rho_c ~ eps0 div E ~ eps0 c |B| / dx
+        else:
+            floor = 1e-300
+        den = max(np.abs(r).max(), floor)
+        errs[k] = float(np.abs(g - r).max() / den)
+    return errs
+
+
+def state_errors(ref, got):
+    """Per-group error of the raw state (F, G, h*, E_prev), relative to each group's max."""
+    groups = dict(F=slice(0, 19), G=slice(19, 38), h=slice(38, 63), E=slice(63, 66))
+    out = {}
+    for k, s in groups.items():
+        r, g = ref[s], got[s]
+        out[k] = float(np.abs(g - r).max() / max(np.abs(r).max(), 1e-300))
+    return out
+
+
+def run_oracle(w, steps):
+    o = oracle.Oracle(w.shape, w.bc, **w.params)
+    o.init(w.fields)
+    if steps:
+        o.step(steps)
+    return o
+
+
+def run_gpu(w, steps, storage="f64"):
+    from paper_1508_03452_amd.rmhdlb import Solver
+    s = Solver(w.shape, w.bc, storage=storage, **w.params)
+    s.init_fields(w.fields)
+    if steps:
+        s.step(steps)
+    return s
+
+
+def gpu_moments_np(s):
+    m = s.moments()
+    out = {k: v.cpu().numpy() for k, v in m.items() if hasattr(v, "cpu")}
+    out["diag"] = m["diag"]
+    return out
+
+
+def field_scale(w):
+    return max(max(np.abs(b).max() for b in w.fields["B"]), 1e-3)

@@ -1,0 +1,77 @@
+"""CPU checks of the HIP library: it loads, exports every declared entry
+point, validates parameters before touching the device, and its lattice
+tables are the D3Q19 / D3Q13 sets of the paper (checked against the oracle's
+tables, which it builds from the paper's trigonometric definitions)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1508_03452_amd import rmhdlb as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "rmhdlb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rmhdlb_\w+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    L = R.load()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(R.SYMBOLS)
+
+
+def test_strerror():
+    assert R.strerror(0) == "ok"
+    assert "recovery" in R.strerror(R.RMHDLB_ERECOVERY)
+
+
+def test_tables_match_paper_lattices():
+    t = R.lattice_tables()
+    o = oracle.lattice(c=1.0)
+    assert np.array_equal(t["e"], o["e"])
+    assert np.allclose(t["w"], o["w"], atol=1e-15)
+    assert np.array_equal(t["s"], o["s"])
+    assert np.allclose(t["ehat"] / np.sqrt(2.0), o["ee"], atol=1e-15)   # e_k = c ehat_k / sqrt 2 at c = 1
+    assert np.array_equal(t["bhat"], np.round(o["bb"]).astype(int))
+
+
+def _create(**kw):
+    P = R.make_params((8, 8, 8), **kw)
+    h = ctypes.c_void_p()
+    return R.load().rmhdlb_create(ctypes.byref(P), None, ctypes.byref(h)), h
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(tau_h=0.4), R.RMHDLB_EUNSUPPORTED),
+    (dict(tau=0.0), R.RMHDLB_EINVAL),
+    (dict(Gamma=1.0), R.RMHDLB_EINVAL),
+    (dict(sigma=-1.0), R.RMHDLB_EINVAL),
+    (dict(c=0.0), R.RMHDLB_EINVAL),
+    (dict(storage=7), R.RMHDLB_EINVAL),
+])
+def test_parameter_validation_without_device(kw, code):
+    rc, h = _create(**kw)
+    assert rc == code and not h.value
+
+
+def test_mixed_periodic_axis_rejected():
+    P = R.make_params((8, 8, 8), bc=(("periodic", "open"), ("periodic", "periodic"), ("periodic", "periodic")))
+    h = ctypes.c_void_p()
+    assert R.load().rmhdlb_create(ctypes.byref(P), None, ctypes.byref(h)) == R.RMHDLB_EINVAL
+
+
+def test_null_arguments():
+    L = R.load()
+    assert L.rmhdlb_step(None, 1) == R.RMHDLB_EINVAL
+    assert L.rmhdlb_destroy(None) == 0
+    assert L.rmhdlb_state_len(None) == -1
