@@ -4,6 +4,7 @@
 // memory, the per-run constants and the launch sequence.  No host
 // synchronisation except in rmhdlb_moments and the state copies.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -25,6 +26,7 @@ struct rmhdlb_ctx {
     double* part2;     // per-tile max |div B|
     double* result;    // NPART + 1 reduced values
     int64_t step;
+    rmhd::StepTuning tune;
 };
 
 namespace {
@@ -134,6 +136,14 @@ int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** ou
     }
     C->cur = 0;
     C->step = 0;
+    // Launch shape: z-planes per block, non-temporal stores, two lanes per
+    // cell; overridable through RMHDLB_ZB / RMHDLB_NT / RMHDLB_PAIR for sweeps.
+    C->tune.zb = 4;
+    C->tune.nt_store = 1;
+    C->tune.pair = 1;
+    if (const char* v = getenv("RMHDLB_ZB")) C->tune.zb = atoi(v) > 0 ? atoi(v) : 1;
+    if (const char* v = getenv("RMHDLB_NT")) C->tune.nt_store = atoi(v) != 0;
+    if (const char* v = getenv("RMHDLB_PAIR")) C->tune.pair = atoi(v) != 0;
     *out = C;
     return RMHDLB_OK;
 }
@@ -170,8 +180,8 @@ int rmhdlb_step(rmhdlb_ctx* C, int64_t nsteps) {
     if (!C || nsteps < 0) return RMHDLB_EINVAL;
     for (int64_t s = 0; s < nsteps; ++s) {
         hipError_t e = C->elem == sizeof(double)
-                           ? rmhd::launch_step<double>(C->buf[C->cur], C->buf[1 - C->cur], C->K, C->stream)
-                           : rmhd::launch_step<float>(C->buf[C->cur], C->buf[1 - C->cur], C->K, C->stream);
+                           ? rmhd::launch_step<double>(C->buf[C->cur], C->buf[1 - C->cur], C->K, C->tune, C->stream)
+                           : rmhd::launch_step<float>(C->buf[C->cur], C->buf[1 - C->cur], C->K, C->tune, C->stream);
         if (e != hipSuccess) return RMHDLB_EDEVICE;
         C->cur = 1 - C->cur;
         C->step++;

@@ -88,8 +88,16 @@ __device__ __forceinline__ double block_max_value(double v) {
 
 int num_tiles(const Consts& K);
 
+// Launch shape of the fused step: z-planes walked per block (1 = one tile
+// per block), non-temporal stores of the next state, lanes per cell.
+struct StepTuning {
+    int zb;
+    int nt_store;
+    int pair;  // 1 = two lanes per cell (k_fused_step_pair)
+};
+
 template <typename T>
-hipError_t launch_step(const void* src, void* dst, const Consts& K, hipStream_t s);
+hipError_t launch_step(const void* src, void* dst, const Consts& K, const StepTuning& tune, hipStream_t s);
 template <typename T>
 hipError_t launch_moments(const void* src, const Consts& K, const OutPtrs& out, double* Bscr, double* part,
                           double* part2, double* result, hipStream_t s);
