@@ -32,7 +32,9 @@ KERNEL_SOURCES = ("paper_1508_03452_amd/csrc/rmhdlb_kernels.hip", "paper_1508_03
 # (scaled by the copy-kernel calibration), keyed by (workload, storage, hash
 # of the kernel sources): a changed kernel reports null until re-measured.
 MEASURED_TRAFFIC = {
-    ("flare", "f64", "c66a3a8f73d6"): 59.36,   # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "5cf44b93893a"): 62.08,   # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f32", "5cf44b93893a"): 26.22,   # profiles/fused_step_f32_flare256x256x512.md
+    ("flare", "f16", "5cf44b93893a"): 13.23,   # profiles/fused_step_f16_flare256x256x512.md
 }
 
 
@@ -51,7 +53,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="flare", choices=["flare", "kh"])
-    ap.add_argument("--storage", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--storage", default="f64", choices=["f64", "f32", "f16"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
@@ -106,8 +108,9 @@ def main():
     d = m["diag"]
     ncell = w.ncells
     mlups = ncell / (ms * 1e-3) / 1e6
-    bytes_per_value = 8 if args.storage == "f64" else 4
-    alg_bytes = 2 * 66 * bytes_per_value * ncell
+    # read + write of the stored state: 63 distribution values + 3 E_prev values per cell
+    dist_b, e_b = {"f64": (8, 8), "f32": (4, 4), "f16": (2, 4)}[args.storage]
+    alg_bytes = 2 * (63 * dist_b + 3 * e_b) * ncell
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     traffic = MEASURED_TRAFFIC.get((args.workload, args.storage, kernel_hash()))
     out = {
@@ -121,12 +124,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.storage,
+        "dtype": "f64" if args.storage == "f64" else f"{args.storage} storage, f32 arithmetic",
         "data": "synthetic",
         "config": {"workload": (f"flare-like 3-D box {w.shape[0]}x{w.shape[1]}x{w.shape[2]}, sigma=1e3, open faces"
                                 if args.workload == "flare" else
                                 f"KH shear layer {w.shape[0]}x{w.shape[1]}x{w.shape[2]}, v0=0.2, ratio 10, sigma=1e3"),
                    "storage": args.storage, "cells": ncell, "recovery": "plain Newton",
+                   "arithmetic": "f64" if args.storage == "f64" else "f32 (recovery and Ohm solve in f64)",
                    "wall_s_timed": round(wall, 3), "failed_cells": d["n_failed"],
                    "mean_newton_iters": round(d["mean_iters"], 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

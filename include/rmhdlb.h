@@ -48,8 +48,13 @@ enum {
 
 enum { RMHDLB_BC_PERIODIC = 0, RMHDLB_BC_OPEN = 1 };
 
-/* Storage of the distributions between steps.  F64 is the plain path. */
-enum { RMHDLB_STORE_F64 = 0, RMHDLB_STORE_F32 = 1 };
+/* Storage of the state between steps.  F64 is the plain path.  F32 and F16
+ * store f and g as deviations from w_i E_ref and w'_i N_ref (references: the
+ * means of eps and n over the initial fields), h in the same type and E_prev
+ * in FP32; the step then runs in FP32 arithmetic with the recovery and the
+ * Ohm solve in FP64.  rmhdlb_get_state / set_state always use the FP64,
+ * unshifted layout. */
+enum { RMHDLB_STORE_F64 = 0, RMHDLB_STORE_F32 = 1, RMHDLB_STORE_F16 = 2 };
 
 typedef struct {
     int32_t nx, ny, nz;          /* cells per axis, each >= 1 */

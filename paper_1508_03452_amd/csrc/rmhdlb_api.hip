@@ -18,8 +18,9 @@ struct rmhdlb_ctx {
     rmhdlb_params P;
     hipStream_t stream;
     Consts K;
-    size_t elem;       // bytes per stored value
-    void* buf[2];      // state buffers, NSTATE * stride values each
+    int storage;       // RMHDLB_STORE_*
+    void* buf[2];      // state buffers (distributions, then E_prev)
+    rmhd::StateBuf sb[2];
     int cur;
     double* scratch;   // 6 N doubles: initial J0 and E'0, then B of the moments pass
     double* part;      // per-tile partial diagnostics
@@ -28,6 +29,12 @@ struct rmhdlb_ctx {
     int64_t step;
     rmhd::StepTuning tune;
 };
+
+// Dispatch on the storage type of a context.
+#define RMHD_DISPATCH(C, CALL)                                       \
+    ((C)->storage == RMHDLB_STORE_F64 ? rmhd::CALL<double>           \
+     : (C)->storage == RMHDLB_STORE_F32 ? rmhd::CALL<float>          \
+                                         : rmhd::CALL<_Float16>)
 
 namespace {
 
@@ -45,7 +52,8 @@ int validate(const rmhdlb_params* P) {
     if (!(P->dx > 0) || !(P->c > 0) || !(P->mu0 > 0) || !(P->tau > 0) || !(P->alpha >= 0) || !(P->Gamma > 1) ||
         !(P->sigma >= 0) || !(P->nu > 0) || !isfinite(P->sigma) || !isfinite(P->alpha))
         return RMHDLB_EINVAL;
-    if (P->storage != RMHDLB_STORE_F64 && P->storage != RMHDLB_STORE_F32) return RMHDLB_EINVAL;
+    if (P->storage != RMHDLB_STORE_F64 && P->storage != RMHDLB_STORE_F32 && P->storage != RMHDLB_STORE_F16)
+        return RMHDLB_EINVAL;
     for (int k = 0; k < 7; ++k)
         if (P->reserved[k] != 0) return RMHDLB_EINVAL;
     if (P->tau_h != 0.5) return RMHDLB_EUNSUPPORTED;  // the force form of Eq. Ex_force needs tau_h = 1/2
@@ -81,6 +89,34 @@ Consts make_consts(const rmhdlb_params* P) {
     K.gc3 = ct_c0 * 1.5;
     K.inv_2dx = 0.5 / P->dx;
     return K;
+}
+
+size_t dist_elem(int storage) {
+    return storage == RMHDLB_STORE_F64 ? 8 : (storage == RMHDLB_STORE_F32 ? 4 : 2);
+}
+size_t efield_elem(int storage) { return storage == RMHDLB_STORE_F64 ? 8 : 4; }
+size_t efield_offset(int storage, int64_t stride) {
+    const size_t b = (size_t)(rmhd::NSTATE - 3) * (size_t)stride * dist_elem(storage);
+    return (b + 255) / 256 * 256;
+}
+size_t buffer_bytes(int storage, int64_t stride) {
+    return efield_offset(storage, stride) + 3 * (size_t)stride * efield_elem(storage);
+}
+
+// Shifts of the stored f and g: w_i E_ref and w'_i N_ref rounded to the
+// arithmetic type (FP32 on the mixed paths), and their exact sums.
+void set_shifts(Consts& K, int storage, double eref, double nref) {
+    for (int c = 0; c < 3; ++c) K.fsh[c] = K.gsh[c] = 0.0;
+    K.fs0 = K.fsaa = K.gs0 = 0.0;
+    if (storage == RMHDLB_STORE_F64) return;
+    const double w[3] = {rmhd::weight(0), rmhd::weight(1), rmhd::weight(7)};
+    for (int c = 0; c < 3; ++c) {
+        K.fsh[c] = (double)(float)(w[c] * eref);
+        K.gsh[c] = (double)(float)(K.wp[c] * nref);
+    }
+    K.fs0 = K.fsh[0] + 6.0 * K.fsh[1] + 12.0 * K.fsh[2];
+    K.fsaa = 2.0 * K.fsh[1] + 8.0 * K.fsh[2];
+    K.gs0 = K.gsh[0] + 6.0 * K.gsh[1] + 12.0 * K.gsh[2];
 }
 
 void release(rmhdlb_ctx* C) {
@@ -120,13 +156,21 @@ int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** ou
     C->P = *params;
     C->stream = (hipStream_t)hip_stream;
     C->K = make_consts(params);
-    C->elem = params->storage == RMHDLB_STORE_F64 ? sizeof(double) : sizeof(float);
-    const size_t bytes = (size_t)rmhd::NSTATE * (size_t)C->K.stride * C->elem;
+    C->storage = params->storage;
+    const size_t bytes = buffer_bytes(C->storage, C->K.stride);
     const int nt = rmhd::num_tiles(C->K);
+    const size_t nred = (size_t)((C->K.N + 255) / 256);  // blocks of the init-reference reduction
     bool ok = true;
-    for (int b = 0; b < 2 && ok; ++b) ok = hipMalloc(&C->buf[b], bytes) == hipSuccess;
+    for (int b = 0; b < 2 && ok; ++b) {
+        ok = hipMalloc(&C->buf[b], bytes) == hipSuccess;
+        if (ok) {
+            C->sb[b].dist = C->buf[b];
+            C->sb[b].efield = (char*)C->buf[b] + efield_offset(C->storage, C->K.stride);
+        }
+    }
     ok = ok && hipMalloc((void**)&C->scratch, sizeof(double) * 6 * (size_t)C->K.N) == hipSuccess;
-    ok = ok && hipMalloc((void**)&C->part, sizeof(double) * rmhd::NPART * (size_t)nt) == hipSuccess;
+    ok = ok && hipMalloc((void**)&C->part, sizeof(double) * (size_t)(rmhd::NPART * (size_t)nt > 2 * nred
+                                                                       ? rmhd::NPART * (size_t)nt : 2 * nred)) == hipSuccess;
     ok = ok && hipMalloc((void**)&C->part2, sizeof(double) * (size_t)nt) == hipSuccess;
     ok = ok && hipMalloc((void**)&C->result, sizeof(double) * (rmhd::NPART + 1)) == hipSuccess;
     if (!ok) {
@@ -136,14 +180,12 @@ int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** ou
     }
     C->cur = 0;
     C->step = 0;
-    // Launch shape: z-planes per block, non-temporal stores, two lanes per
-    // cell; overridable through RMHDLB_ZB / RMHDLB_NT / RMHDLB_PAIR for sweeps.
+    // Launch shape: z-planes per block and non-temporal stores; overridable
+    // through RMHDLB_ZB / RMHDLB_NT for tuning sweeps.
     C->tune.zb = 4;
     C->tune.nt_store = 1;
-    C->tune.pair = 1;
     if (const char* v = getenv("RMHDLB_ZB")) C->tune.zb = atoi(v) > 0 ? atoi(v) : 1;
     if (const char* v = getenv("RMHDLB_NT")) C->tune.nt_store = atoi(v) != 0;
-    if (const char* v = getenv("RMHDLB_PAIR")) C->tune.pair = atoi(v) != 0;
     *out = C;
     return RMHDLB_OK;
 }
@@ -168,9 +210,18 @@ int rmhdlb_init_fields(rmhdlb_ctx* C, const rmhdlb_fields_in* in) {
     }
     ip.rho_c = in->rho_c;
     C->cur = 0;
-    hipError_t e = C->elem == sizeof(double)
-                       ? rmhd::launch_init<double>(ip, C->K, C->scratch, C->buf[0], C->stream)
-                       : rmhd::launch_init<float>(ip, C->K, C->scratch, C->buf[0], C->stream);
+    if (C->storage != RMHDLB_STORE_F64) {
+        // references of the stored deviations: means of eps and n over the initial fields
+        if (rmhd::launch_init_ref(ip, C->K, C->part, C->result, C->stream) != hipSuccess) return RMHDLB_EDEVICE;
+        double r[2];
+        if (hipMemcpyAsync(r, C->result, sizeof(r), hipMemcpyDeviceToHost, C->stream) != hipSuccess ||
+            hipStreamSynchronize(C->stream) != hipSuccess)
+            return RMHDLB_EDEVICE;
+        set_shifts(C->K, C->storage, r[0] / (double)C->K.N, r[1] / (double)C->K.N);
+    } else {
+        set_shifts(C->K, C->storage, 0.0, 0.0);
+    }
+    hipError_t e = RMHD_DISPATCH(C, launch_init)(ip, C->K, C->scratch, C->sb[0], C->stream);
     if (e != hipSuccess) return RMHDLB_EDEVICE;
     C->step = 0;
     return RMHDLB_OK;
@@ -179,9 +230,7 @@ int rmhdlb_init_fields(rmhdlb_ctx* C, const rmhdlb_fields_in* in) {
 int rmhdlb_step(rmhdlb_ctx* C, int64_t nsteps) {
     if (!C || nsteps < 0) return RMHDLB_EINVAL;
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = C->elem == sizeof(double)
-                           ? rmhd::launch_step<double>(C->buf[C->cur], C->buf[1 - C->cur], C->K, C->tune, C->stream)
-                           : rmhd::launch_step<float>(C->buf[C->cur], C->buf[1 - C->cur], C->K, C->tune, C->stream);
+        hipError_t e = RMHD_DISPATCH(C, launch_step)(C->sb[C->cur], C->sb[1 - C->cur], C->K, C->tune, C->stream);
         if (e != hipSuccess) return RMHDLB_EDEVICE;
         C->cur = 1 - C->cur;
         C->step++;
@@ -205,11 +254,8 @@ int rmhdlb_moments(rmhdlb_ctx* C, rmhdlb_fields_out* out, rmhdlb_diag* diag) {
         }
         op.rho_c = out->rho_c;
     }
-    hipError_t e = C->elem == sizeof(double)
-                       ? rmhd::launch_moments<double>(C->buf[C->cur], C->K, op, C->scratch, C->part, C->part2,
-                                                      C->result, C->stream)
-                       : rmhd::launch_moments<float>(C->buf[C->cur], C->K, op, C->scratch, C->part, C->part2,
-                                                     C->result, C->stream);
+    hipError_t e = RMHD_DISPATCH(C, launch_moments)(C->sb[C->cur], C->K, op, C->scratch, C->part, C->part2,
+                                                    C->result, C->stream);
     if (e != hipSuccess) return RMHDLB_EDEVICE;
     double r[rmhd::NPART + 1];
     if (hipMemcpyAsync(r, C->result, sizeof(r), hipMemcpyDeviceToHost, C->stream) != hipSuccess)
@@ -236,16 +282,14 @@ int64_t rmhdlb_state_len(const rmhdlb_ctx* C) { return C ? (int64_t)rmhd::NSTATE
 
 int rmhdlb_get_state(rmhdlb_ctx* C, double* dst) {
     if (!C || !dst) return RMHDLB_EINVAL;
-    hipError_t e = C->elem == sizeof(double) ? rmhd::launch_export<double>(C->buf[C->cur], dst, C->K, C->stream)
-                                             : rmhd::launch_export<float>(C->buf[C->cur], dst, C->K, C->stream);
+    hipError_t e = RMHD_DISPATCH(C, launch_export)(C->sb[C->cur], dst, C->K, C->stream);
     if (e != hipSuccess || hipStreamSynchronize(C->stream) != hipSuccess) return RMHDLB_EDEVICE;
     return RMHDLB_OK;
 }
 
 int rmhdlb_set_state(rmhdlb_ctx* C, const double* src) {
     if (!C || !src) return RMHDLB_EINVAL;
-    hipError_t e = C->elem == sizeof(double) ? rmhd::launch_import<double>(src, C->buf[C->cur], C->K, C->stream)
-                                             : rmhd::launch_import<float>(src, C->buf[C->cur], C->K, C->stream);
+    hipError_t e = RMHD_DISPATCH(C, launch_import)(src, C->sb[C->cur], C->K, C->stream);
     if (e != hipSuccess || hipStreamSynchronize(C->stream) != hipSuccess) return RMHDLB_EDEVICE;
     return RMHDLB_OK;
 }

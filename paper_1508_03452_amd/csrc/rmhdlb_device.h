@@ -44,7 +44,8 @@ constexpr int BHX[QH] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1, 1, 
 constexpr int BHY[QH] = {0, 0, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 0, 0, 0, 0};
 constexpr int BHZ[QH] = {-1, 1, -1, 1, -1, 1, -1, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 
-// Offsets of the state arrays (each `stride` values long).
+// Offsets of the state arrays (each `stride` values long); E_prev (OFF_E..)
+// lives in its own block of the buffer.
 constexpr int OFF_F = 0, OFF_G = Q, OFF_H = 2 * Q, OFF_E = 2 * Q + QH + 1;
 
 // --------------------------------------------------------------- constants
@@ -64,6 +65,12 @@ struct Consts {
     double wp[3];        // g weights (rest, axis, diagonal)
     double gc1, gc2, gc3;  // (c_t/c_0) * (3 c_a, 9/2 c_a^2, 3/2) of the g equilibrium
     double inv_2dx;
+    // Stored f, g are deviations from these per-class shifts (rest, axis,
+    // diagonal): w_i E_ref and w'_i N_ref rounded to the step's arithmetic
+    // type, all 0 on the plain FP64 path.  fs0 = sum_i fsh_i, fsaa = the sum
+    // over the directions with e^a != 0 (any axis a), gs0 = sum_i gsh_i.
+    double fsh[3], gsh[3];
+    double fs0, fsaa, gs0;
 };
 
 constexpr double KAPPA = 0.83887049280786108;   // sqrt(19/27)
@@ -73,8 +80,9 @@ constexpr double INV_SQRT2 = 0.70710678118654752;
 
 // ------------------------------------------------------------- primitives
 
-__device__ __forceinline__ double minmod(double a, double b) {
-    if (a * b <= 0.0) return 0.0;
+template <typename V>
+__device__ __forceinline__ V minmod(V a, V b) {
+    if (a * b <= V(0)) return V(0);
     return fabs(a) < fabs(b) ? a : b;
 }
 

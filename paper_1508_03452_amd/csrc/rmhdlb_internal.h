@@ -88,24 +88,51 @@ __device__ __forceinline__ double block_max_value(double v) {
 
 int num_tiles(const Consts& K);
 
-// Launch shape of the fused step: z-planes walked per block (1 = one tile
-// per block), non-temporal stores of the next state, lanes per cell.
+// Launch shape of the fused step: z-planes walked per block and non-temporal
+// stores of the next state.
 struct StepTuning {
     int zb;
     int nt_store;
-    int pair;  // 1 = two lanes per cell (k_fused_step_pair)
 };
 
-template <typename T>
-hipError_t launch_step(const void* src, void* dst, const Consts& K, const StepTuning& tune, hipStream_t s);
-template <typename T>
-hipError_t launch_moments(const void* src, const Consts& K, const OutPtrs& out, double* Bscr, double* part,
+// Device pointers of one state buffer: the 63 distribution arrays and the 3
+// E_prev arrays (each `stride` values long).
+struct StateBuf {
+    void* dist;
+    void* efield;
+};
+
+// Storage type -> (E_prev storage type, arithmetic type of the step).
+template <typename TS>
+struct StoreTypes;
+template <>
+struct StoreTypes<double> {
+    using E = double;
+    using V = double;
+};
+template <>
+struct StoreTypes<float> {
+    using E = float;
+    using V = float;
+};
+template <>
+struct StoreTypes<_Float16> {
+    using E = float;
+    using V = float;
+};
+
+template <typename TS>
+hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K, const StepTuning& tune,
+                       hipStream_t s);
+template <typename TS>
+hipError_t launch_moments(const StateBuf& src, const Consts& K, const OutPtrs& out, double* Bscr, double* part,
                           double* part2, double* result, hipStream_t s);
-template <typename T>
-hipError_t launch_init(const InPtrs& in, const Consts& K, double* scr, void* dst, hipStream_t s);
-template <typename T>
-hipError_t launch_export(const void* src, double* dst, const Consts& K, hipStream_t s);
-template <typename T>
-hipError_t launch_import(const double* src, void* dst, const Consts& K, hipStream_t s);
+hipError_t launch_init_ref(const InPtrs& in, const Consts& K, double* part, double* result, hipStream_t s);
+template <typename TS>
+hipError_t launch_init(const InPtrs& in, const Consts& K, double* scr, const StateBuf& dst, hipStream_t s);
+template <typename TS>
+hipError_t launch_export(const StateBuf& src, double* dst, const Consts& K, hipStream_t s);
+template <typename TS>
+hipError_t launch_import(const double* src, const StateBuf& dst, const Consts& K, hipStream_t s);
 
 }  // namespace rmhd

@@ -1,14 +1,14 @@
 // rmhdlb_kernels.hip -- gfx950 kernels of the resistive relativistic MHD
 // lattice Boltzmann step (arXiv:1508.03452, Sec. III).
 //
-// Layout in HBM: structure of arrays, one array per population, x fastest:
-//   state[a * stride + cell], a = F[0..18], G[0..18], h*[0..24], E_prev[0..2],
-// two such buffers (read one, write the other).  The stored state is
-// post-collision.  One thread owns one cell; a 64 x 4 tile of cells is one
-// workgroup (one wavefront per x-row of 64, so every load of an array row is
-// one coalesced 512-byte FP64 segment).  Tiles are handed out so that each of
-// the 8 XCDs works on a contiguous slab of the grid and the stencil
-// neighbours of its tiles stay in that XCD's L2.
+// Layout in HBM: structure of arrays, one array per population, x fastest.
+// A state buffer holds the 63 distribution arrays (F[0..18], G[0..18],
+// h*[0..24]) of storage type TS, then (256-byte aligned) the 3 E_prev arrays
+// of type TE (TS, or FP32 when TS is FP16); two buffers, read one and write
+// the other.  The stored state is post-collision.  On the FP32 and FP16
+// storage paths F and G are stored as deviations from w_i E_ref and
+// w'_i N_ref (references from the initial fields) and the step runs in FP32
+// arithmetic, with the recovery and the Ohm solve in FP64.
 #include "rmhdlb_device.h"
 #include "rmhdlb_internal.h"
 
@@ -21,15 +21,24 @@ __device__ __forceinline__ double ld(const T* __restrict__ p, int64_t i) {
     return static_cast<double>(p[i]);
 }
 
+template <typename V, typename T>
+__device__ __forceinline__ V ldv(const T* __restrict__ p, int64_t i) {
+    return static_cast<V>(p[i]);
+}
+
 // Stores of the next state are never read again in this step: the
 // non-temporal hint keeps them from evicting the stencil lines from L2.
-template <bool NT, typename T>
-__device__ __forceinline__ void st(T* __restrict__ p, double v) {
+template <bool NT, typename T, typename V>
+__device__ __forceinline__ void st(T* __restrict__ p, V v) {
     if constexpr (NT)
         __builtin_nontemporal_store(static_cast<T>(v), p);
     else
         *p = static_cast<T>(v);
 }
+
+// Shift of the stored f, g of direction i (0 on the plain FP64 path).
+__device__ __forceinline__ double fshift(const Consts& K, int i) { return K.fsh[i == 0 ? 0 : (i <= 6 ? 1 : 2)]; }
+__device__ __forceinline__ double gshift(const Consts& K, int i) { return K.gsh[i == 0 ? 0 : (i <= 6 ? 1 : 2)]; }
 
 // Neighbour offsets of one cell along one axis for displacements -2..+2,
 // with periodic wrap or (open face) a copy of the first interior cell.
@@ -143,16 +152,19 @@ __device__ __forceinline__ void solve_cell(const Consts& K, CellSol& M) {
 // minmod-MUSCL flux difference, plus the 7-point bulk-viscosity Laplacian
 // for i != 0; g without viscosity.  Then the streaming of h, the moments,
 // the recovery and E, J.
-template <typename T>
-__device__ __forceinline__ void macroscopic(const T* __restrict__ src, const Consts& K, int cell, const Nbr& nb,
-                                            Macro& M) {
+// One thread per cell, FP64 arithmetic (moments and diagnostics pass).  The
+// shift of a stored array is constant in space, so it transports to itself
+// and is added back after the transport.
+template <typename TS, typename TE>
+__device__ __forceinline__ void macroscopic(const TS* __restrict__ src, const TE* __restrict__ esrc, const Consts& K,
+                                            int cell, const Nbr& nb, Macro& M) {
     M.T00 = 0.0;
     M.N0 = 0.0;
     double t0x = 0, t0y = 0, t0z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const T* __restrict__ fa = src + (int64_t)(OFF_F + i) * K.stride + cell;
-        const T* __restrict__ ga = src + (int64_t)(OFF_G + i) * K.stride + cell;
+        const TS* __restrict__ fa = src + (int64_t)(OFF_F + i) * K.stride + cell;
+        const TS* __restrict__ ga = src + (int64_t)(OFF_G + i) * K.stride + cell;
         const double f0 = ld(fa, 0), g0 = ld(ga, 0);
         double fv = f0, gv = g0;
         if (i != 0) {
@@ -174,6 +186,8 @@ __device__ __forceinline__ void macroscopic(const T* __restrict__ src, const Con
                 gv = g0 - K.cour * (face_p - face_m);
             }
         }
+        fv += fshift(K, i);
+        gv += gshift(K, i);
         M.F[i] = fv;
         M.G[i] = gv;
         M.T00 += fv;
@@ -202,7 +216,7 @@ __device__ __forceinline__ void macroscopic(const T* __restrict__ src, const Con
     double ehx = 0, ehy = 0, ehz = 0, bx = 0, by = 0, bz = 0, hs = 0;
 #pragma unroll
     for (int k = 0; k < QH; ++k) {
-        const T* __restrict__ ha = src + (int64_t)(OFF_H + k) * K.stride + cell;
+        const TS* __restrict__ ha = src + (int64_t)(OFF_H + k) * K.stride + cell;
         const double h = ld(ha, nb.at(-SX[k], -SY[k], -SZ[k]));
         M.H[k] = h;
         hs += h;
@@ -224,9 +238,9 @@ __device__ __forceinline__ void macroscopic(const T* __restrict__ src, const Con
     M.rho = M.H[QH] + hs;
 
     // previous E and its Gauss charge
-    const T* __restrict__ e0 = src + (int64_t)(OFF_E + 0) * K.stride + cell;
-    const T* __restrict__ e1 = src + (int64_t)(OFF_E + 1) * K.stride + cell;
-    const T* __restrict__ e2 = src + (int64_t)(OFF_E + 2) * K.stride + cell;
+    const TE* __restrict__ e0 = esrc + cell;
+    const TE* __restrict__ e1 = esrc + K.stride + cell;
+    const TE* __restrict__ e2 = esrc + 2 * K.stride + cell;
     M.Ep[0] = ld(e0, 0);
     M.Ep[1] = ld(e1, 0);
     M.Ep[2] = ld(e2, 0);
@@ -241,67 +255,73 @@ __device__ __forceinline__ void macroscopic(const T* __restrict__ src, const Con
 // the corrections that make its moments T_fluid + T_EM: the delta_i0
 // coefficient 361 (3p - eps) / (33 (p + eps)), the minus sign of the
 // (E.c_i)^2 term, the y-z cross terms, and c on the (B x E).c_i term.
-struct FeqCell {
-    double P34, A1, Bc, g2, beta[3], b2, eps0;
-    double X, BxE[3], E[3], cB[3];
+// The per-cell setup runs in FP64; the per-direction evaluation in V (FP64 on
+// the plain path, FP32 on the mixed-storage paths).
+template <typename V>
+struct FeqCellT {
+    V P34, A1, Bc, g2, beta[3], b2, eps0;
+    V X, BxE[3], E[3], cB[3];
     __device__ __forceinline__ void setup(double eps, double p, double gam, const double bta[3], const double Ev[3],
                                           const double Bv[3], double c, double e0) {
-        P34 = 0.75 * (eps + p);
-        A1 = 1.0 + (3.0 * p - eps) / (p + eps);
-        Bc = 361.0 * (3.0 * p - eps) / (33.0 * (p + eps));
-        g2 = gam * gam;
-        b2 = bta[0] * bta[0] + bta[1] * bta[1] + bta[2] * bta[2];
+        P34 = (V)(0.75 * (eps + p));
+        A1 = (V)(1.0 + (3.0 * p - eps) / (p + eps));
+        Bc = (V)(361.0 * (3.0 * p - eps) / (33.0 * (p + eps)));
+        g2 = (V)(gam * gam);
+        b2 = (V)(bta[0] * bta[0] + bta[1] * bta[1] + bta[2] * bta[2]);
+        double cb[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            beta[a] = bta[a];
-            E[a] = Ev[a];
-            cB[a] = c * Bv[a];
+            beta[a] = (V)bta[a];
+            E[a] = (V)Ev[a];
+            cb[a] = c * Bv[a];
+            cB[a] = (V)cb[a];
         }
-        X = cB[0] * cB[0] + cB[1] * cB[1] + cB[2] * cB[2] + E[0] * E[0] + E[1] * E[1] + E[2] * E[2];
+        X = (V)(cb[0] * cb[0] + cb[1] * cb[1] + cb[2] * cb[2] + Ev[0] * Ev[0] + Ev[1] * Ev[1] + Ev[2] * Ev[2]);
         // c (B x E)
-        BxE[0] = cB[1] * E[2] - cB[2] * E[1];
-        BxE[1] = cB[2] * E[0] - cB[0] * E[2];
-        BxE[2] = cB[0] * E[1] - cB[1] * E[0];
-        eps0 = e0;
+        BxE[0] = (V)(cb[1] * Ev[2] - cb[2] * Ev[1]);
+        BxE[1] = (V)(cb[2] * Ev[0] - cb[0] * Ev[2]);
+        BxE[2] = (V)(cb[0] * Ev[1] - cb[1] * Ev[0]);
+        eps0 = (V)e0;
     }
     template <int I>
-    __device__ __forceinline__ double eq() const {
+    __device__ __forceinline__ V eq() const {
         constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
-        const double eb = ex * beta[0] + ey * beta[1] + ez * beta[2];
-        const double cross = (ex * ey) * beta[0] * beta[1] + (ex * ez) * beta[0] * beta[2] + (ey * ez) * beta[1] * beta[2];
-        const double diag = (ex * ex) * beta[0] * beta[0] + (ey * ey) * beta[1] * beta[1] + (ez * ez) * beta[2] * beta[2];
-        double fluid = A1 + 19.0 * g2 * cross + 4.0 * KAPPA * g2 * eb + (4.0 / 15.0) * g2 * (19.0 * diag - 4.0 * b2);
+        const V eb = ex * beta[0] + ey * beta[1] + ez * beta[2];
+        const V cross = (ex * ey) * beta[0] * beta[1] + (ex * ez) * beta[0] * beta[2] + (ey * ez) * beta[1] * beta[2];
+        const V diag = (ex * ex) * beta[0] * beta[0] + (ey * ey) * beta[1] * beta[1] + (ez * ez) * beta[2] * beta[2];
+        V fluid = A1 + V(19) * g2 * cross + V(4 * KAPPA) * g2 * eb + V(4.0 / 15.0) * g2 * (V(19) * diag - V(4) * b2);
         if (I == 0) fluid += Bc;
-        const double Be = ex * cB[0] + ey * cB[1] + ez * cB[2];
-        const double Ee = ex * E[0] + ey * E[1] + ez * E[2];
-        const double BxEe = ex * BxE[0] + ey * BxE[1] + ez * BxE[2];
-        const double crossEB = (ex * ey) * (E[0] * E[1] + cB[0] * cB[1]) + (ex * ez) * (E[0] * E[2] + cB[0] * cB[2]) +
-                               (ey * ez) * (E[1] * E[2] + cB[1] * cB[2]);
-        const double em = 2.3 * X - SQRT19_3 * BxEe - 3.8 * (Be * Be + Ee * Ee) - 6.65 * crossEB;
-        return weight(I) * (P34 * fluid + eps0 * em);
+        const V Be = ex * cB[0] + ey * cB[1] + ez * cB[2];
+        const V Ee = ex * E[0] + ey * E[1] + ez * E[2];
+        const V BxEe = ex * BxE[0] + ey * BxE[1] + ez * BxE[2];
+        const V crossEB = (ex * ey) * (E[0] * E[1] + cB[0] * cB[1]) + (ex * ez) * (E[0] * E[2] + cB[0] * cB[2]) +
+                          (ey * ez) * (E[1] * E[2] + cB[1] * cB[2]);
+        const V em = V(2.3) * X - V(SQRT19_3) * BxEe - V(3.8) * (Be * Be + Ee * Ee) - V(6.65) * crossEB;
+        return V(weight(I)) * (P34 * fluid + eps0 * em);
     }
 };
+using FeqCell = FeqCellT<double>;
 
 // f_eq of direction sgn * e_I (sgn = +-1): the odd terms change sign, the
 // weight is that of e_I.
-template <int I>
-__device__ __forceinline__ double feq_signed(const FeqCell& f, double sgn) {
+template <int I, typename V>
+__device__ __forceinline__ V feq_signed(const FeqCellT<V>& f, V sgn) {
     constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
-    const double eb = sgn * (ex * f.beta[0] + ey * f.beta[1] + ez * f.beta[2]);
-    const double cross =
+    const V eb = sgn * (ex * f.beta[0] + ey * f.beta[1] + ez * f.beta[2]);
+    const V cross =
         (ex * ey) * f.beta[0] * f.beta[1] + (ex * ez) * f.beta[0] * f.beta[2] + (ey * ez) * f.beta[1] * f.beta[2];
-    const double diag = (ex * ex) * f.beta[0] * f.beta[0] + (ey * ey) * f.beta[1] * f.beta[1] +
-                        (ez * ez) * f.beta[2] * f.beta[2];
-    const double fluid =
-        f.A1 + 19.0 * f.g2 * cross + 4.0 * KAPPA * f.g2 * eb + (4.0 / 15.0) * f.g2 * (19.0 * diag - 4.0 * f.b2);
-    const double Be = ex * f.cB[0] + ey * f.cB[1] + ez * f.cB[2];
-    const double Ee = ex * f.E[0] + ey * f.E[1] + ez * f.E[2];
-    const double BxEe = sgn * (ex * f.BxE[0] + ey * f.BxE[1] + ez * f.BxE[2]);
-    const double crossEB = (ex * ey) * (f.E[0] * f.E[1] + f.cB[0] * f.cB[1]) +
-                           (ex * ez) * (f.E[0] * f.E[2] + f.cB[0] * f.cB[2]) +
-                           (ey * ez) * (f.E[1] * f.E[2] + f.cB[1] * f.cB[2]);
-    const double em = 2.3 * f.X - SQRT19_3 * BxEe - 3.8 * (Be * Be + Ee * Ee) - 6.65 * crossEB;
-    return weight(I) * (f.P34 * fluid + f.eps0 * em);
+    const V diag = (ex * ex) * f.beta[0] * f.beta[0] + (ey * ey) * f.beta[1] * f.beta[1] +
+                   (ez * ez) * f.beta[2] * f.beta[2];
+    const V fluid =
+        f.A1 + V(19) * f.g2 * cross + V(4 * KAPPA) * f.g2 * eb + V(4.0 / 15.0) * f.g2 * (V(19) * diag - V(4) * f.b2);
+    const V Be = ex * f.cB[0] + ey * f.cB[1] + ez * f.cB[2];
+    const V Ee = ex * f.E[0] + ey * f.E[1] + ez * f.E[2];
+    const V BxEe = sgn * (ex * f.BxE[0] + ey * f.BxE[1] + ez * f.BxE[2]);
+    const V crossEB = (ex * ey) * (f.E[0] * f.E[1] + f.cB[0] * f.cB[1]) +
+                      (ex * ez) * (f.E[0] * f.E[2] + f.cB[0] * f.cB[2]) +
+                      (ey * ez) * (f.E[1] * f.E[2] + f.cB[1] * f.cB[2]);
+    const V em = V(2.3) * f.X - V(SQRT19_3) * BxEe - V(3.8) * (Be * Be + Ee * Ee) - V(6.65) * crossEB;
+    return V(weight(I)) * (f.P34 * fluid + f.eps0 * em);
 }
 
 template <int I, typename Fn>
@@ -310,40 +330,6 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
         fn(std::integral_constant<int, I>{});
         static_for<I + 1>(fn);
     }
-}
-
-// Collisions and the stores of one cell (second half of the step).
-template <bool NT, typename T>
-__device__ __forceinline__ void collide_store(T* __restrict__ dst, const Consts& K, int cell, const Macro& M) {
-    FeqCell fe;
-    // Reading of the coupling: f_eq carries T_EM of the same pair (E_prev, B)
-    // that the recovery subtracted, so the collision conserves T^{0 nu}.
-    fe.setup(M.eps, M.p, M.gam, M.beta, M.Ep, M.B, K.c, K.eps0);
-    const double rate = M.gam * K.inv_tau;
-    static_for<0>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        const double eb = EX[i] * M.beta[0] + EY[i] * M.beta[1] + EZ[i] * M.beta[2];
-        const double om = rate * (1.0 - KAPPA * eb);  // Anderson-Witting: gamma (1 - kappa e.beta) / tau
-        const double feq = fe.eq<i>();
-        st<NT>(dst + (int64_t)(OFF_F + i) * K.stride + cell, M.F[i] - om * (M.F[i] - feq));
-        // g: Eq. Hupp equilibrium, collision with g(t + dt) in closed form
-        const double wpi = i == 0 ? K.wp[0] : (i <= 6 ? K.wp[1] : K.wp[2]);
-        const double geq = wpi * M.n * M.gam * (1.0 + K.gc1 * eb + K.gc2 * eb * eb - K.gc3 * fe.b2);
-        st<NT>(dst + (int64_t)(OFF_G + i) * K.stride + cell, (M.G[i] + K.wg * geq) / (1.0 + K.wg));
-    });
-    // h_eq of Eq. Maxwell-eq with the current coefficient 1/(32 c^2):
-    // v.J / (32 c^2) = s.J / (16 sqrt2 c), E.e / (8 c^2) = ehat.E / (8 sqrt2 c), B.b / 8 = bhat.B / 8
-    const double cj = 1.0 / (16.0 * 1.4142135623730951 * K.c), ce = 1.0 / (8.0 * 1.4142135623730951 * K.c);
-#pragma unroll
-    for (int k = 0; k < QH; ++k) {
-        const double heq = cj * (SX[k] * M.J[0] + SY[k] * M.J[1] + SZ[k] * M.J[2]) +
-                           ce * (EHX[k] * M.E[0] + EHY[k] * M.E[1] + EHZ[k] * M.E[2]) +
-                           0.125 * (BHX[k] * M.B[0] + BHY[k] * M.B[1] + BHZ[k] * M.B[2]);
-        st<NT>(dst + (int64_t)(OFF_H + k) * K.stride + cell, 2.0 * heq - M.H[k]);  // tau_h = 1/2
-    }
-    st<NT>(dst + (int64_t)(OFF_H + QH) * K.stride + cell, 2.0 * M.rho - M.H[QH]);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) st<NT>(dst + (int64_t)(OFF_E + a) * K.stride + cell, M.E[a]);
 }
 
 // ---------------------------------------------------- two lanes per cell
@@ -356,27 +342,50 @@ __device__ __forceinline__ void collide_store(T* __restrict__ dst, const Consts&
 // populations f_0, g_0; lane 1 owns h_rest.  Partial moments are summed over
 // the pair with one xor-1 shuffle each, and both lanes then run the recovery
 // and the Ohm solve on identical inputs.
+//
+// f and g are handled as stored deviations d (the shift is 0 on the plain
+// path): the transport is linear and the shift is uniform, so the transported
+// value is shift + transport(d); the moments add the exact sums of the shifts;
+// the collisions write the new deviations directly.
 constexpr int PX = 64, PY = 2, PTPB = 2 * PX * PY;
+#ifndef RMHDLB_WAVES
+#define RMHDLB_WAVES 2  // waves per SIMD the fused kernel is compiled for
+#endif
+// f/g slots whose loads may be in flight together, per arithmetic width
+#ifndef RMHDLB_GROUP_F64
+#define RMHDLB_GROUP_F64 2
+#endif
+#ifndef RMHDLB_GROUP_F32
+#define RMHDLB_GROUP_F32 2
+#endif
+template <typename V>
+constexpr int pin_group() {
+    return sizeof(V) == 8 ? RMHDLB_GROUP_F64 : RMHDLB_GROUP_F32;
+}
 
-__device__ __forceinline__ double pair_sum(double v) { return v + __shfl_xor(v, 1, 64); }
+template <typename V>
+__device__ __forceinline__ V pair_sum(V v) {
+    return v + __shfl_xor(v, 1, 64);
+}
 
-template <bool NT, typename T>
-__device__ __forceinline__ void pair_cell(const T* __restrict__ src, T* __restrict__ dst, const Consts& K, int cell,
-                                          const Nbr& nb, int h) {
-    const double sgn = h ? -1.0 : 1.0;
+template <bool NT, typename TS, typename TE, typename V>
+__device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* __restrict__ se, TS* __restrict__ dd,
+                                          TE* __restrict__ de, const Consts& K, int cell, const Nbr& nb, int h) {
+    const V sgn = h ? V(-1) : V(1);
     const int64_t S = K.stride;
     // Array bases stay uniform (scalar registers); the lane's choice between
     // the two arrays of a pair is folded into its 32-bit element index.
     const int hc = cell + (h ? (int)S : 0);
-    double Fv[10], Gv[10], Hv[13];
-    double t00 = 0, t0x = 0, t0y = 0, t0z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0, n0 = 0;
+    const V cour = (V)K.cour, kv = (V)K.kv;
+    V Fv[10], Gv[10], Hv[13];
+    V t00 = 0, t0x = 0, t0y = 0, t0z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0, n0 = 0;
     // slot 0: f_0, g_0 (lane 0) and h_rest (lane 1)
     {
-        const double a = ld(src + (h ? (int64_t)(OFF_H + QH) : (int64_t)OFF_F) * S + cell, 0);
-        const double g = ld(src + (int64_t)OFF_G * S + cell, 0);
-        Fv[0] = h ? 0.0 : a;
-        Gv[0] = h ? 0.0 : g;
-        Hv[12] = h ? a : 0.0;
+        const V a = ldv<V>(sd, (h ? (int64_t)(OFF_H + QH) : (int64_t)OFF_F) * S + cell);
+        const V g = ldv<V>(sd, (int64_t)OFF_G * S + cell);
+        Fv[0] = h ? V(0) : a;
+        Gv[0] = h ? V(0) : g;
+        Hv[12] = h ? a : V(0);
         t00 = Fv[0];
         n0 = Gv[0];
     }
@@ -390,25 +399,28 @@ __device__ __forceinline__ void pair_cell(const T* __restrict__ src, T* __restri
             const int om2 = h ? nb.at(2 * ex, 2 * ey, 2 * ez) : nb.at(-2 * ex, -2 * ey, -2 * ez);
             const int om1 = h ? nb.at(ex, ey, ez) : nb.at(-ex, -ey, -ez);
             const int op1 = h ? nb.at(-ex, -ey, -ez) : nb.at(ex, ey, ez);
-            const T* __restrict__ fa = src + (int64_t)(OFF_F + i0) * S;
-            const T* __restrict__ ga = src + (int64_t)(OFF_G + i0) * S;
-            const double f0 = ld(fa, hc), fm2 = ld(fa, hc + om2), fm1 = ld(fa, hc + om1), fp1 = ld(fa, hc + op1);
-            const double lap = (ld(fa, hc + lap_xp) + ld(fa, hc + lap_xm)) + (ld(fa, hc + lap_yp) + ld(fa, hc + lap_ym)) +
-                               (ld(fa, hc + lap_zp) + ld(fa, hc + lap_zm)) - 6.0 * f0;
-            const double fv = f0 - K.cour * ((f0 + 0.5 * minmod(f0 - fm1, fp1 - f0)) -
-                                             (fm1 + 0.5 * minmod(fm1 - fm2, f0 - fm1))) + K.kv * lap;
-            const double g0 = ld(ga, hc), gm2 = ld(ga, hc + om2), gm1 = ld(ga, hc + om1), gp1 = ld(ga, hc + op1);
-            const double gv = g0 - K.cour * ((g0 + 0.5 * minmod(g0 - gm1, gp1 - g0)) -
-                                             (gm1 + 0.5 * minmod(gm1 - gm2, g0 - gm1)));
+            const TS* __restrict__ fa = sd + (int64_t)(OFF_F + i0) * S;
+            const TS* __restrict__ ga = sd + (int64_t)(OFF_G + i0) * S;
+            const V f0 = ldv<V>(fa, hc), fm2 = ldv<V>(fa, hc + om2), fm1 = ldv<V>(fa, hc + om1),
+                    fp1 = ldv<V>(fa, hc + op1);
+            const V lap = (ldv<V>(fa, hc + lap_xp) + ldv<V>(fa, hc + lap_xm)) +
+                          (ldv<V>(fa, hc + lap_yp) + ldv<V>(fa, hc + lap_ym)) +
+                          (ldv<V>(fa, hc + lap_zp) + ldv<V>(fa, hc + lap_zm)) - V(6) * f0;
+            const V fv = f0 - cour * ((f0 + V(0.5) * minmod(f0 - fm1, fp1 - f0)) -
+                                      (fm1 + V(0.5) * minmod(fm1 - fm2, f0 - fm1))) + kv * lap;
+            const V g0 = ldv<V>(ga, hc), gm2 = ldv<V>(ga, hc + om2), gm1 = ldv<V>(ga, hc + om1),
+                    gp1 = ldv<V>(ga, hc + op1);
+            const V gv = g0 - cour * ((g0 + V(0.5) * minmod(g0 - gm1, gp1 - g0)) -
+                                      (gm1 + V(0.5) * minmod(gm1 - gm2, g0 - gm1)));
             Fv[s] = fv;
             Gv[s] = gv;
             // Keep each slot's arithmetic next to its loads: without this the
             // scheduler sinks all of it below every load of the cell, and the
             // ~150 load destinations in flight cost a wave its occupancy.
-            asm volatile("" : "+v"(Fv[s]), "+v"(Gv[s])::"memory");
+            if constexpr (s % pin_group<V>() == 0 || s == 9) asm volatile("" : "+v"(Fv[s]), "+v"(Gv[s])::"memory");
             t00 += fv;
             n0 += gv;
-            const double sf = sgn * fv;
+            const V sf = sgn * fv;
             if (ex) t0x += ex * sf;
             if (ey) t0y += ey * sf;
             if (ez) t0z += ez * sf;
@@ -420,14 +432,14 @@ __device__ __forceinline__ void pair_cell(const T* __restrict__ src, T* __restri
             if (ey * ez) tyz += (ey * ez) * fv;
         }
     });
-    double ehx = 0, ehy = 0, ehz = 0, bx = 0, by = 0, bz = 0, hs = 0;
+    V ehx = 0, ehy = 0, ehz = 0, bx = 0, by = 0, bz = 0, hs = 0;
 #pragma unroll
     for (int m = 0; m < 12; ++m) {
         const int k0 = 2 * m;
-        const double v = ld(src + (int64_t)(OFF_H + k0) * S, hc + nb.at(-SX[k0], -SY[k0], -SZ[k0]));
+        const V v = ldv<V>(sd + (int64_t)(OFF_H + k0) * S, hc + nb.at(-SX[k0], -SY[k0], -SZ[k0]));
         Hv[m] = v;
         hs += v;
-        const double sv = sgn * v;
+        const V sv = sgn * v;
         if (EHX[k0]) ehx += EHX[k0] * sv;
         if (EHY[k0]) ehy += EHY[k0] * sv;
         if (EHZ[k0]) ehz += EHZ[k0] * sv;
@@ -437,110 +449,100 @@ __device__ __forceinline__ void pair_cell(const T* __restrict__ src, T* __restri
     }
     CellSol M;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) M.Ep[a] = ld(src + (int64_t)(OFF_E + a) * S + cell, 0);
+    for (int a = 0; a < 3; ++a) M.Ep[a] = ld(se + (int64_t)a * S + cell, 0);
     // Gauss charge: lane 0 takes E_x(x+-1), E_y(y+1); lane 1 E_y(y-1), E_z(z+-1)
     double gpart;
     {
-        const T* ex_ = src + (int64_t)(OFF_E + 0) * S + cell;
-        const T* ey_ = src + (int64_t)(OFF_E + 1) * S + cell;
-        const T* ez_ = src + (int64_t)(OFF_E + 2) * S + cell;
+        const TE* ex_ = se + cell;
+        const TE* ey_ = se + S + cell;
+        const TE* ez_ = se + 2 * S + cell;
         const double a = h ? -ld(ey_, lap_ym) : ld(ex_, lap_xp);
         const double b = h ? ld(ez_, lap_zp) : -ld(ex_, lap_xm);
         const double c = h ? -ld(ez_, lap_zm) : ld(ey_, lap_yp);
         gpart = (a + b) + c;
     }
-    M.T00 = pair_sum(t00);
-    M.N0 = pair_sum(n0);
-    M.T0[0] = KAPPA * pair_sum(t0x);
-    M.T0[1] = KAPPA * pair_sum(t0y);
-    M.T0[2] = KAPPA * pair_sum(t0z);
-    M.Tab[0] = KAPPA2 * pair_sum(txx);
-    M.Tab[1] = KAPPA2 * pair_sum(tyy);
-    M.Tab[2] = KAPPA2 * pair_sum(tzz);
-    M.Tab[3] = KAPPA2 * pair_sum(txy);
-    M.Tab[4] = KAPPA2 * pair_sum(txz);
-    M.Tab[5] = KAPPA2 * pair_sum(tyz);
+    M.T00 = K.fs0 + (double)pair_sum(t00);
+    M.N0 = K.gs0 + (double)pair_sum(n0);
+    M.T0[0] = KAPPA * (double)pair_sum(t0x);
+    M.T0[1] = KAPPA * (double)pair_sum(t0y);
+    M.T0[2] = KAPPA * (double)pair_sum(t0z);
+    M.Tab[0] = KAPPA2 * (K.fsaa + (double)pair_sum(txx));
+    M.Tab[1] = KAPPA2 * (K.fsaa + (double)pair_sum(tyy));
+    M.Tab[2] = KAPPA2 * (K.fsaa + (double)pair_sum(tzz));
+    M.Tab[3] = KAPPA2 * (double)pair_sum(txy);
+    M.Tab[4] = KAPPA2 * (double)pair_sum(txz);
+    M.Tab[5] = KAPPA2 * (double)pair_sum(tyz);
     const double ec = K.c * INV_SQRT2;
-    M.Epr[0] = ec * pair_sum(ehx);
-    M.Epr[1] = ec * pair_sum(ehy);
-    M.Epr[2] = ec * pair_sum(ehz);
-    M.B[0] = pair_sum(bx);
-    M.B[1] = pair_sum(by);
-    M.B[2] = pair_sum(bz);
-    M.rho = pair_sum(Hv[12] + hs);
+    M.Epr[0] = ec * (double)pair_sum(ehx);
+    M.Epr[1] = ec * (double)pair_sum(ehy);
+    M.Epr[2] = ec * (double)pair_sum(ehz);
+    M.B[0] = (double)pair_sum(bx);
+    M.B[1] = (double)pair_sum(by);
+    M.B[2] = (double)pair_sum(bz);
+    M.rho = (double)pair_sum(Hv[12] + hs);
     M.rho_g = K.eps0 * K.inv_2dx * pair_sum(gpart);
     solve_cell(K, M);
 
-    // collisions and stores
-    FeqCell fe;
+    // collisions and stores (new deviations)
+    FeqCellT<V> fe;
     fe.setup(M.eps, M.p, M.gam, M.beta, M.Ep, M.B, K.c, K.eps0);
-    const double rate = M.gam * K.inv_tau;
-    const double inv1wg = 1.0 / (1.0 + K.wg);
+    const V rate = (V)(M.gam * K.inv_tau);
+    const V wg = (V)K.wg, inv1wg = (V)(1.0 / (1.0 + K.wg));
+    const V ng = (V)(M.n * M.gam);
+    const V gc1 = (V)K.gc1, gc2 = (V)K.gc2, gc3b2 = (V)(K.gc3 * (M.beta[0] * M.beta[0] + M.beta[1] * M.beta[1] +
+                                                              M.beta[2] * M.beta[2]));
+    const V bx_ = (V)M.beta[0], by_ = (V)M.beta[1], bz_ = (V)M.beta[2];
     if (h == 0) {
-        const double feq0 = fe.eq<0>();
-        st<NT>(dst + (int64_t)OFF_F * S + cell, Fv[0] - rate * (Fv[0] - feq0));
-        const double geq0 = K.wp[0] * M.n * M.gam * (1.0 - K.gc3 * fe.b2);
-        st<NT>(dst + (int64_t)OFF_G * S + cell, (Gv[0] + K.wg * geq0) * inv1wg);
+        const V q0 = (V)K.fsh[0] - fe.template eq<0>();
+        st<NT>(dd + (int64_t)OFF_F * S + cell, Fv[0] - rate * (Fv[0] + q0));
+        const V geq0 = (V)K.wp[0] * ng * (V(1) - gc3b2);
+        st<NT>(dd + (int64_t)OFF_G * S + cell, (Gv[0] + wg * (geq0 - (V)K.gsh[0])) * inv1wg);
     } else {
-        st<NT>(dst + (int64_t)(OFF_H + QH) * S + cell, 2.0 * M.rho - Hv[12]);
+        st<NT>(dd + (int64_t)(OFF_H + QH) * S + cell, (V)(2.0 * M.rho) - Hv[12]);
     }
     static_for<1>([&](auto ic) {
         constexpr int s = decltype(ic)::value;
         if constexpr (s <= 9) {
             constexpr int i0 = 2 * s - 1;
-            const double eb = sgn * (EX[i0] * M.beta[0] + EY[i0] * M.beta[1] + EZ[i0] * M.beta[2]);
-            const double om = rate * (1.0 - KAPPA * eb);
-            const double feq = feq_signed<i0>(fe, sgn);
-            st<NT>(dst + (int64_t)(OFF_F + i0) * S + hc, Fv[s] - om * (Fv[s] - feq));
-            const double wpi = i0 <= 6 ? K.wp[1] : K.wp[2];
-            const double geq = wpi * M.n * M.gam * (1.0 + K.gc1 * eb + K.gc2 * eb * eb - K.gc3 * fe.b2);
-            st<NT>(dst + (int64_t)(OFF_G + i0) * S + hc, (Gv[s] + K.wg * geq) * inv1wg);
+            constexpr int cls = i0 <= 6 ? 1 : 2;
+            const V eb = sgn * (EX[i0] * bx_ + EY[i0] * by_ + EZ[i0] * bz_);
+            const V om = rate * (V(1) - V(KAPPA) * eb);
+            const V q = (V)K.fsh[cls] - feq_signed<i0>(fe, sgn);
+            st<NT>(dd + (int64_t)(OFF_F + i0) * S + hc, Fv[s] - om * (Fv[s] + q));
+            const V geq = (V)K.wp[cls] * ng * (V(1) + gc1 * eb + gc2 * eb * eb - gc3b2);
+            st<NT>(dd + (int64_t)(OFF_G + i0) * S + hc, (Gv[s] + wg * (geq - (V)K.gsh[cls])) * inv1wg);
         }
     });
-    const double cj = 1.0 / (16.0 * 1.4142135623730951 * K.c), ce = 1.0 / (8.0 * 1.4142135623730951 * K.c);
+    const V cj = (V)(1.0 / (16.0 * 1.4142135623730951 * K.c)), ce = (V)(1.0 / (8.0 * 1.4142135623730951 * K.c));
+    const V J0 = (V)M.J[0], J1 = (V)M.J[1], J2 = (V)M.J[2];
+    const V E0 = (V)M.E[0], E1 = (V)M.E[1], E2 = (V)M.E[2];
+    const V B0 = (V)M.B[0], B1 = (V)M.B[1], B2 = (V)M.B[2];
 #pragma unroll
     for (int m = 0; m < 12; ++m) {
         const int k0 = 2 * m;
-        const double heq = cj * (SX[k0] * M.J[0] + SY[k0] * M.J[1] + SZ[k0] * M.J[2]) +
-                           sgn * (ce * (EHX[k0] * M.E[0] + EHY[k0] * M.E[1] + EHZ[k0] * M.E[2]) +
-                                  0.125 * (BHX[k0] * M.B[0] + BHY[k0] * M.B[1] + BHZ[k0] * M.B[2]));
-        st<NT>(dst + (int64_t)(OFF_H + k0) * S + hc, 2.0 * heq - Hv[m]);
+        const V heq = cj * (SX[k0] * J0 + SY[k0] * J1 + SZ[k0] * J2) +
+                      sgn * (ce * (EHX[k0] * E0 + EHY[k0] * E1 + EHZ[k0] * E2) +
+                             V(0.125) * (BHX[k0] * B0 + BHY[k0] * B1 + BHZ[k0] * B2));
+        st<NT>(dd + (int64_t)(OFF_H + k0) * S + hc, V(2) * heq - Hv[m]);
     }
     if (h == 0) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) st<NT>(dst + (int64_t)(OFF_E + a) * S + cell, M.E[a]);
+        for (int a = 0; a < 3; ++a) st<NT>(de + (int64_t)a * S + cell, M.E[a]);
     }
 }
 
 // ------------------------------------------------------------------ kernels
 
-// One block owns a 64 x 4 column tile and walks zb consecutive z-planes.
-// Blocks are numbered column-fastest within a z-chunk, and XCD k receives the
-// contiguous block range [k P, (k + 1) P): the columns one XCD runs at the same
-// time are neighbours marching through the same planes, so the y-halo and the
-// z-neighbour planes of the stencil are shared in that XCD's L2.
-template <bool NT, typename T>
-__global__ __launch_bounds__(TPB) void k_fused_step(const T* __restrict__ src, T* __restrict__ dst, Consts K,
-                                                    int tiles_x, int ncol, int zb, int nblk) {
-    const int b = tile_of_block(nblk);
-    if (b >= nblk) return;
-    const int col = b % ncol, zc = b / ncol;
-    const int tx = col % tiles_x, ty = col / tiles_x;
-    const int x = tx * TX + (threadIdx.x % TX), y = ty * TY + (threadIdx.x / TX);
-    if (x >= K.nx || y >= K.ny) return;
-    const int z0 = zc * zb, z1 = min(K.nz, z0 + zb);
-    for (int z = z0; z < z1; ++z) {
-        const int cell = x + K.nx * (y + K.ny * z);
-        const Nbr nb = make_nbr(K, x, y, z);
-        Macro M;
-        macroscopic(src, K, cell, nb, M);
-        collide_store<NT>(dst, K, cell, M);
-    }
-}
-
-template <bool NT, typename T>
-__global__ __launch_bounds__(PTPB, 2) void k_fused_step_pair(const T* __restrict__ src, T* __restrict__ dst, Consts K,
-                                                          int tiles_x, int ncol, int zb, int nblk) {
+// One block owns a 64 x 2 column of cells (two lanes per cell) and walks zb
+// consecutive z-planes.  Blocks are numbered column-fastest within a z-chunk
+// and XCD k receives the contiguous block range [k P, (k + 1) P): the columns
+// one XCD runs at the same time are neighbours marching through the same
+// planes, so the y-halo and the z-neighbour planes of the stencil meet in
+// that XCD's L2.
+template <bool NT, typename TS, typename TE, typename V>
+__global__ __launch_bounds__(PTPB, RMHDLB_WAVES) void k_fused_step(const TS* __restrict__ sd, const TE* __restrict__ se,
+                                                        TS* __restrict__ dd, TE* __restrict__ de, Consts K,
+                                                        int tiles_x, int ncol, int zb, int nblk) {
     const int b = tile_of_block(nblk);
     if (b >= nblk) return;
     const int col = b % ncol, zc = b / ncol;
@@ -552,16 +554,16 @@ __global__ __launch_bounds__(PTPB, 2) void k_fused_step_pair(const T* __restrict
     for (int z = z0; z < z1; ++z) {
         const int cell = x + K.nx * (y + K.ny * z);
         const Nbr nb = make_nbr(K, x, y, z);
-        pair_cell<NT>(src, dst, K, cell, nb, h);
+        pair_cell<NT, TS, TE, V>(sd, se, dd, de, K, cell, nb, h);
     }
 }
 
 // Primitives of the current state and per-block partial diagnostics:
 // part[blk * NPART + j], j = T00, N0, T0x, T0y, T0z, em energy, rho, iters, failed.
-template <typename T>
-__global__ __launch_bounds__(TPB) void k_moments(const T* __restrict__ src, Consts K, int tiles_x, int tiles_y,
-                                                 int ntiles, OutPtrs out, double* __restrict__ Bscratch,
-                                                 double* __restrict__ part) {
+template <typename TS, typename TE>
+__global__ __launch_bounds__(TPB) void k_moments(const TS* __restrict__ src, const TE* __restrict__ esrc, Consts K,
+                                                 int tiles_x, int tiles_y, int ntiles, OutPtrs out,
+                                                 double* __restrict__ Bscratch, double* __restrict__ part) {
     const int tile = tile_of_block(ntiles);
     if (tile >= ntiles) return;
     const int tx = tile % tiles_x, rest = tile / tiles_x;
@@ -572,7 +574,7 @@ __global__ __launch_bounds__(TPB) void k_moments(const T* __restrict__ src, Cons
         const int cell = x + K.nx * (y + K.ny * z);
         const Nbr nb = make_nbr(K, x, y, z);
         Macro M;
-        macroscopic(src, K, cell, nb, M);
+        macroscopic(src, esrc, K, cell, nb, M);
         const double c = K.c;
         if (out.n) out.n[cell] = M.n;
         if (out.p) out.p[cell] = M.p;
@@ -628,7 +630,7 @@ __global__ __launch_bounds__(TPB) void k_divb(const double* __restrict__ Bs, Con
 __global__ __launch_bounds__(TPB) void k_reduce(const double* __restrict__ part, int nblk, int width, int is_max,
                                                 double* __restrict__ out) {
     for (int j = 0; j < width; ++j) {
-        double acc = is_max ? 0.0 : 0.0;
+        double acc = 0.0;
         for (int b = threadIdx.x; b < nblk; b += TPB) {
             const double v = part[(int64_t)b * width + j];
             acc = is_max ? fmax(acc, v) : acc + v;
@@ -637,6 +639,18 @@ __global__ __launch_bounds__(TPB) void k_reduce(const double* __restrict__ part,
         if (threadIdx.x == 0) out[j] = r;
         __syncthreads();
     }
+}
+
+// Sums of eps = n c^2 + p / (Gamma - 1) and n over the initial fields (the
+// references of the stored deviations).
+__global__ __launch_bounds__(TPB) void k_init_ref(InPtrs in, Consts K, double* __restrict__ part) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (i < K.N) {
+        v[0] = in.n[i] * K.c * K.c + in.p[i] / K.gm1;
+        v[1] = in.n[i];
+    }
+    block_sum<2>(v, part + (int64_t)blockIdx.x * 2);
 }
 
 // Initial state, pass 1: J0 from Eq. Ohm with the Gauss charge of E0, and
@@ -674,11 +688,12 @@ __global__ __launch_bounds__(TPB) void k_init_current(InPtrs in, Consts K, int t
     }
 }
 
-// Initial state, pass 2: f* = f_eq, g* = g_eq, h*_k(x) = h_eq-form at x + s_k,
-// h*_rest = rho_c, E_prev = E0.
-template <typename T>
+// Initial state, pass 2: f* = f_eq, g* = g_eq (stored minus their shifts),
+// h*_k(x) = h_eq-form at x + s_k, h*_rest = rho_c, E_prev = E0.
+template <typename TS, typename TE>
 __global__ __launch_bounds__(TPB) void k_init_state(InPtrs in, Consts K, int tiles_x, int tiles_y, int ntiles,
-                                                    const double* __restrict__ scr, T* __restrict__ dst) {
+                                                    const double* __restrict__ scr, TS* __restrict__ dst,
+                                                    TE* __restrict__ edst) {
     const int tile = tile_of_block(ntiles);
     if (tile >= ntiles) return;
     const int tx = tile % tiles_x, rest = tile / tiles_x;
@@ -688,28 +703,27 @@ __global__ __launch_bounds__(TPB) void k_init_state(InPtrs in, Consts K, int til
     const int cell = x + K.nx * (y + K.ny * z);
     const Nbr nb = make_nbr(K, x, y, z);
     const double c = K.c, c2 = c * c;
-    Macro M;
-    double u[3];
+    double u[3], Ep[3], Bv[3], beta[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         u[a] = in.u[a][cell];
-        M.Ep[a] = in.E[a][cell];
-        M.B[a] = in.B[a][cell];
-        M.beta[a] = u[a] / c;
+        Ep[a] = in.E[a][cell];
+        Bv[a] = in.B[a][cell];
+        beta[a] = u[a] / c;
     }
     const double n = in.n[cell], p = in.p[cell];
-    const double b2 = M.beta[0] * M.beta[0] + M.beta[1] * M.beta[1] + M.beta[2] * M.beta[2];
+    const double b2 = beta[0] * beta[0] + beta[1] * beta[1] + beta[2] * beta[2];
     const double gam = 1.0 / sqrt(1.0 - b2);
     const double eps = n * c2 + p / K.gm1;
     FeqCell fe;
-    fe.setup(eps, p, gam, M.beta, M.Ep, M.B, c, K.eps0);
+    fe.setup(eps, p, gam, beta, Ep, Bv, c, K.eps0);
     static_for<0>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        const double eb = EX[i] * M.beta[0] + EY[i] * M.beta[1] + EZ[i] * M.beta[2];
-        dst[(int64_t)(OFF_F + i) * K.stride + cell] = static_cast<T>(fe.eq<i>());
+        const double eb = EX[i] * beta[0] + EY[i] * beta[1] + EZ[i] * beta[2];
+        dst[(int64_t)(OFF_F + i) * K.stride + cell] = static_cast<TS>(fe.template eq<i>() - fshift(K, i));
         const double wpi = i == 0 ? K.wp[0] : (i <= 6 ? K.wp[1] : K.wp[2]);
         dst[(int64_t)(OFF_G + i) * K.stride + cell] =
-            static_cast<T>(wpi * n * gam * (1.0 + K.gc1 * eb + K.gc2 * eb * eb - K.gc3 * b2));
+            static_cast<TS>(wpi * n * gam * (1.0 + K.gc1 * eb + K.gc2 * eb * eb - K.gc3 * b2) - gshift(K, i));
     });
     const double cj = 1.0 / (16.0 * 1.4142135623730951 * c), ce = 1.0 / (8.0 * 1.4142135623730951 * c);
 #pragma unroll
@@ -719,7 +733,7 @@ __global__ __launch_bounds__(TPB) void k_init_state(InPtrs in, Consts K, int til
         const double P0 = scr[3 * K.N + t], P1 = scr[4 * K.N + t], P2 = scr[5 * K.N + t];
         const double heq = cj * (SX[k] * J0 + SY[k] * J1 + SZ[k] * J2) + ce * (EHX[k] * P0 + EHY[k] * P1 + EHZ[k] * P2) +
                            0.125 * (BHX[k] * in.B[0][t] + BHY[k] * in.B[1][t] + BHZ[k] * in.B[2][t]);
-        dst[(int64_t)(OFF_H + k) * K.stride + cell] = static_cast<T>(heq);
+        dst[(int64_t)(OFF_H + k) * K.stride + cell] = static_cast<TS>(heq);
     }
     double rho;
     if (in.rho_c) {
@@ -730,26 +744,44 @@ __global__ __launch_bounds__(TPB) void k_init_state(InPtrs in, Consts K, int til
                (in.E[1][cell + nb.at(0, 1, 0)] - in.E[1][cell + nb.at(0, -1, 0)]) +
                (in.E[2][cell + nb.at(0, 0, 1)] - in.E[2][cell + nb.at(0, 0, -1)]));
     }
-    dst[(int64_t)(OFF_H + QH) * K.stride + cell] = static_cast<T>(rho);
+    dst[(int64_t)(OFF_H + QH) * K.stride + cell] = static_cast<TS>(rho);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) dst[(int64_t)(OFF_E + a) * K.stride + cell] = static_cast<T>(M.Ep[a]);
+    for (int a = 0; a < 3; ++a) edst[(int64_t)a * K.stride + cell] = static_cast<TE>(Ep[a]);
 }
 
-// Raw state conversion to / from the FP64 interface layout.
-template <typename T>
-__global__ void k_export(const T* __restrict__ s, double* __restrict__ d, int64_t N, int64_t stride) {
+// Raw state conversion to / from the FP64 interface layout (shifts added back).
+template <typename TS, typename TE>
+__global__ void k_export(const TS* __restrict__ s, const TE* __restrict__ se, double* __restrict__ d, Consts K) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N * NSTATE) return;
-    const int64_t a = i / N, cell = i - a * N;
-    d[i] = static_cast<double>(s[a * stride + cell]);
+    if (i >= K.N * NSTATE) return;
+    const int64_t a = i / K.N, cell = i - a * K.N;
+    if (a < OFF_E) {
+        double v = static_cast<double>(s[a * K.stride + cell]);
+        if (a < OFF_G)
+            v += fshift(K, (int)a);
+        else if (a < OFF_H)
+            v += gshift(K, (int)(a - OFF_G));
+        d[i] = v;
+    } else {
+        d[i] = static_cast<double>(se[(a - OFF_E) * K.stride + cell]);
+    }
 }
 
-template <typename T>
-__global__ void k_import(const double* __restrict__ s, T* __restrict__ d, int64_t N, int64_t stride) {
+template <typename TS, typename TE>
+__global__ void k_import(const double* __restrict__ s, TS* __restrict__ d, TE* __restrict__ de, Consts K) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N * NSTATE) return;
-    const int64_t a = i / N, cell = i - a * N;
-    d[a * stride + cell] = static_cast<T>(s[i]);
+    if (i >= K.N * NSTATE) return;
+    const int64_t a = i / K.N, cell = i - a * K.N;
+    if (a < OFF_E) {
+        double v = s[i];
+        if (a < OFF_G)
+            v -= fshift(K, (int)a);
+        else if (a < OFF_H)
+            v -= gshift(K, (int)(a - OFF_G));
+        d[a * K.stride + cell] = static_cast<TS>(v);
+    } else {
+        de[(a - OFF_E) * K.stride + cell] = static_cast<TE>(s[i]);
+    }
 }
 
 // ------------------------------------------------------------ host launchers
@@ -767,80 +799,90 @@ int num_tiles(const Consts& K) {
     return n;
 }
 
-template <typename T>
-hipError_t launch_step(const void* src, void* dst, const Consts& K, const StepTuning& tune, hipStream_t s) {
-    const int tiles_x = (K.nx + TX - 1) / TX, tiles_y = (K.ny + TY - 1) / TY;
+template <typename TS>
+hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K, const StepTuning& tune,
+                       hipStream_t s) {
+    using TE = typename StoreTypes<TS>::E;
+    using V = typename StoreTypes<TS>::V;
     const int zb = tune.zb > 0 ? (tune.zb < K.nz ? tune.zb : K.nz) : 1;
-    const int ncol = tiles_x * tiles_y, nblk = ncol * ((K.nz + zb - 1) / zb);
-    const int grid = ((nblk + 7) / 8) * 8;
-    if (tune.pair) {
-        const int ptx = (K.nx + PX - 1) / PX, pcol = ptx * ((K.ny + PY - 1) / PY);
-        const int pblk = pcol * ((K.nz + zb - 1) / zb), pgrid = ((pblk + 7) / 8) * 8;
-        if (tune.nt_store)
-            hipLaunchKernelGGL((k_fused_step_pair<true, T>), dim3(pgrid), dim3(PTPB), 0, s, (const T*)src, (T*)dst, K,
-                               ptx, pcol, zb, pblk);
-        else
-            hipLaunchKernelGGL((k_fused_step_pair<false, T>), dim3(pgrid), dim3(PTPB), 0, s, (const T*)src, (T*)dst,
-                               K, ptx, pcol, zb, pblk);
-        return hipGetLastError();
-    }
+    const int ptx = (K.nx + PX - 1) / PX, pcol = ptx * ((K.ny + PY - 1) / PY);
+    const int pblk = pcol * ((K.nz + zb - 1) / zb), pgrid = ((pblk + 7) / 8) * 8;
+    const TS* sd = (const TS*)src.dist;
+    const TE* se = (const TE*)src.efield;
+    TS* dd = (TS*)dst.dist;
+    TE* de = (TE*)dst.efield;
     if (tune.nt_store)
-        hipLaunchKernelGGL((k_fused_step<true, T>), dim3(grid), dim3(TPB), 0, s, (const T*)src, (T*)dst, K, tiles_x,
-                           ncol, zb, nblk);
+        hipLaunchKernelGGL((k_fused_step<true, TS, TE, V>), dim3(pgrid), dim3(PTPB), 0, s, sd, se, dd, de, K, ptx,
+                           pcol, zb, pblk);
     else
-        hipLaunchKernelGGL((k_fused_step<false, T>), dim3(grid), dim3(TPB), 0, s, (const T*)src, (T*)dst, K, tiles_x,
-                           ncol, zb, nblk);
+        hipLaunchKernelGGL((k_fused_step<false, TS, TE, V>), dim3(pgrid), dim3(PTPB), 0, s, sd, se, dd, de, K, ptx,
+                           pcol, zb, pblk);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_moments(const void* src, const Consts& K, const OutPtrs& out, double* Bscr, double* part,
+template <typename TS>
+hipError_t launch_moments(const StateBuf& src, const Consts& K, const OutPtrs& out, double* Bscr, double* part,
                           double* part2, double* result, hipStream_t s) {
+    using TE = typename StoreTypes<TS>::E;
     int tx, ty, nt, nb;
     grid_of(K, tx, ty, nt, nb);
-    hipLaunchKernelGGL(k_moments<T>, dim3(nb), dim3(TPB), 0, s, (const T*)src, K, tx, ty, nt, out, Bscr, part);
+    hipLaunchKernelGGL((k_moments<TS, TE>), dim3(nb), dim3(TPB), 0, s, (const TS*)src.dist,
+                       (const TE*)src.efield, K, tx, ty, nt, out, Bscr, part);
     hipLaunchKernelGGL(k_divb, dim3(nb), dim3(TPB), 0, s, (const double*)Bscr, K, tx, ty, nt, part2);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, s, (const double*)part, nt, NPART, 0, result);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, s, (const double*)part2, nt, 1, 1, result + NPART);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_init(const InPtrs& in, const Consts& K, double* scr, void* dst, hipStream_t s) {
+hipError_t launch_init_ref(const InPtrs& in, const Consts& K, double* part, double* result, hipStream_t s) {
+    const int nblk = (int)((K.N + TPB - 1) / TPB);
+    hipLaunchKernelGGL(k_init_ref, dim3(nblk), dim3(TPB), 0, s, in, K, part);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, s, (const double*)part, nblk, 2, 0, result);
+    return hipGetLastError();
+}
+
+template <typename TS>
+hipError_t launch_init(const InPtrs& in, const Consts& K, double* scr, const StateBuf& dst, hipStream_t s) {
+    using TE = typename StoreTypes<TS>::E;
     int tx, ty, nt, nb;
     grid_of(K, tx, ty, nt, nb);
     hipLaunchKernelGGL(k_init_current, dim3(nb), dim3(TPB), 0, s, in, K, tx, ty, nt, scr);
-    hipLaunchKernelGGL(k_init_state<T>, dim3(nb), dim3(TPB), 0, s, in, K, tx, ty, nt, (const double*)scr, (T*)dst);
+    hipLaunchKernelGGL((k_init_state<TS, TE>), dim3(nb), dim3(TPB), 0, s, in, K, tx, ty, nt, (const double*)scr,
+                       (TS*)dst.dist, (TE*)dst.efield);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_export(const void* src, double* dst, const Consts& K, hipStream_t s) {
+template <typename TS>
+hipError_t launch_export(const StateBuf& src, double* dst, const Consts& K, hipStream_t s) {
+    using TE = typename StoreTypes<TS>::E;
     const int64_t total = K.N * NSTATE;
     const int64_t blocks = (total + 255) / 256;
-    hipLaunchKernelGGL(k_export<T>, dim3((unsigned)blocks), dim3(256), 0, s, (const T*)src, dst, K.N, K.stride);
+    hipLaunchKernelGGL((k_export<TS, TE>), dim3((unsigned)blocks), dim3(256), 0, s, (const TS*)src.dist,
+                       (const TE*)src.efield, dst, K);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_import(const double* src, void* dst, const Consts& K, hipStream_t s) {
+template <typename TS>
+hipError_t launch_import(const double* src, const StateBuf& dst, const Consts& K, hipStream_t s) {
+    using TE = typename StoreTypes<TS>::E;
     const int64_t total = K.N * NSTATE;
     const int64_t blocks = (total + 255) / 256;
-    hipLaunchKernelGGL(k_import<T>, dim3((unsigned)blocks), dim3(256), 0, s, src, (T*)dst, K.N, K.stride);
+    hipLaunchKernelGGL((k_import<TS, TE>), dim3((unsigned)blocks), dim3(256), 0, s, src, (TS*)dst.dist,
+                       (TE*)dst.efield, K);
     return hipGetLastError();
 }
 
-template hipError_t launch_step<double>(const void*, void*, const Consts&, const StepTuning&, hipStream_t);
-template hipError_t launch_step<float>(const void*, void*, const Consts&, const StepTuning&, hipStream_t);
-template hipError_t launch_moments<double>(const void*, const Consts&, const OutPtrs&, double*, double*, double*,
-                                           double*, hipStream_t);
-template hipError_t launch_moments<float>(const void*, const Consts&, const OutPtrs&, double*, double*, double*,
-                                          double*, hipStream_t);
-template hipError_t launch_init<double>(const InPtrs&, const Consts&, double*, void*, hipStream_t);
-template hipError_t launch_init<float>(const InPtrs&, const Consts&, double*, void*, hipStream_t);
-template hipError_t launch_export<double>(const void*, double*, const Consts&, hipStream_t);
-template hipError_t launch_export<float>(const void*, double*, const Consts&, hipStream_t);
-template hipError_t launch_import<double>(const double*, void*, const Consts&, hipStream_t);
-template hipError_t launch_import<float>(const double*, void*, const Consts&, hipStream_t);
+#define RMHD_INSTANTIATE(TS)                                                                                          \
+    template hipError_t launch_step<TS>(const StateBuf&, const StateBuf&, const Consts&, const StepTuning&,           \
+                                        hipStream_t);                                                                 \
+    template hipError_t launch_moments<TS>(const StateBuf&, const Consts&, const OutPtrs&, double*, double*, double*, \
+                                           double*, hipStream_t);                                                     \
+    template hipError_t launch_init<TS>(const InPtrs&, const Consts&, double*, const StateBuf&, hipStream_t);         \
+    template hipError_t launch_export<TS>(const StateBuf&, double*, const Consts&, hipStream_t);                      \
+    template hipError_t launch_import<TS>(const double*, const StateBuf&, const Consts&, hipStream_t);
+
+RMHD_INSTANTIATE(double)
+RMHD_INSTANTIATE(float)
+RMHD_INSTANTIATE(_Float16)
 
 }  // namespace rmhd

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "librmhdlb.so")
 
 RMHDLB_OK, RMHDLB_EINVAL, RMHDLB_ENOMEM, RMHDLB_EDEVICE, RMHDLB_ERECOVERY, RMHDLB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 BC = {"periodic": 0, "open": 1}
-STORAGE = {"f64": 0, "f32": 1}
+STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 OUT_FIELDS = ("n", "p", "eps", "ux", "uy", "uz", "Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho_c")
 
 _dp = ctypes.POINTER(ctypes.c_double)
