@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
 FIELDS_OUT = ("n", "p", "eps", "ux", "uy", "uz", "Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho_c")
-BC = {"periodic": 0, "open": 1}
+BC = {"periodic": 0, "open": 1, "driven": 2}
 
 
 class _Params(ctypes.Structure):
@@ -32,6 +32,7 @@ class _Params(ctypes.Structure):
         ("tau", ctypes.c_double), ("tau_h", ctypes.c_double),
         ("alpha", ctypes.c_double), ("Gamma", ctypes.c_double), ("sigma", ctypes.c_double),
         ("nu", ctypes.c_double),
+        ("divb_fix", ctypes.c_int32), ("null_band", ctypes.c_int32),
     ]
 
 
@@ -62,6 +63,7 @@ def lib():
         L.rmhdlb_oracle_h_equilibrium.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, ctypes.c_double, dp]
         L.rmhdlb_oracle_recover.argtypes = [ctypes.POINTER(_Params), dp, ctypes.c_double, dp, dp, dp]
         L.rmhdlb_oracle_ohm.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, ctypes.c_double, dp, dp]
+        L.rmhdlb_oracle_set_driven.argtypes = [ctypes.c_void_p, dp, dp, dp * 3, dp * 3]
         _LIB = L
     return _LIB
 
@@ -75,11 +77,11 @@ def _vec(x):
 
 
 DEFAULTS = dict(dx=1.0, c=1.0, mu0=1.0, tau=1.0, tau_h=0.5, alpha=0.1, Gamma=4.0 / 3.0, sigma=1.0,
-                nu=27.0 ** 0.5)
+                nu=27.0 ** 0.5, divb_fix=1, null_band=64)
 
 
 def make_params(shape=(1, 1, 1), bc=None, **kw):
-    """shape = (nx, ny, nz); bc = ((lo, hi) per axis) with 'periodic'/'open'."""
+    """shape = (nx, ny, nz); bc = ((lo, hi) per axis) with 'periodic'/'open' ('driven' on the low z face)."""
     d = dict(DEFAULTS)
     d.update(kw)
     P = _Params()
@@ -90,6 +92,8 @@ def make_params(shape=(1, 1, 1), bc=None, **kw):
         P.bc_hi[a] = BC[bc[a][1]]
     for k in ("dx", "c", "mu0", "tau", "tau_h", "alpha", "Gamma", "sigma", "nu"):
         setattr(P, k, float(d[k]))
+    P.divb_fix = int(d["divb_fix"])
+    P.null_band = int(d["null_band"])
     return P
 
 
@@ -151,10 +155,26 @@ class Oracle:
         return outs
 
     def diagnostics(self):
-        d = np.empty(10)
+        d = np.empty(13)
         lib().rmhdlb_oracle_diagnostics(self._h, _ptr(d))
         return dict(energy=d[0], mass=d[1], momentum=d[2:5].copy(), em_energy=d[5], max_divB=d[6], charge=d[7],
-                    n_failed=int(d[8]), mean_iters=d[9])
+                    n_failed=int(d[8]), mean_iters=d[9], recon_rate=d[10], null_index=int(d[11]), B0=d[12])
+
+    def set_driven(self, face):
+        """Prescribed fields of the driven low-z face: n, p, u (3-tuple), B (3-tuple), each (ny, nx)."""
+        nx, ny, _ = self.shape
+        keep = []
+
+        def arr(a):
+            a = np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (ny, nx)))
+            keep.append(a)
+            return _ptr(a)
+        dp = ctypes.POINTER(ctypes.c_double)
+        u = (dp * 3)(*[arr(x) for x in face["u"]])
+        B = (dp * 3)(*[arr(x) for x in face["B"]])
+        rc = lib().rmhdlb_oracle_set_driven(self._h, arr(face["n"]), arr(face["p"]), u, B)
+        if rc != 0:
+            raise ValueError(f"oracle set_driven failed ({rc})")
 
     def get_state(self):
         n = lib().rmhdlb_oracle_state_len(self._h)

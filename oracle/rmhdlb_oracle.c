@@ -31,6 +31,7 @@
 
 #define BC_PERIODIC 0
 #define BC_OPEN 1
+#define BC_DRIVEN 2 /* low face of z only: fixed ghost planes (Reading R23) */
 
 #define Q19 19
 #define QH 24 /* moving Maxwell populations; index 24 is the rest population */
@@ -43,6 +44,8 @@ typedef struct {
     double tau;   /* fluid relaxation time in units of dt (Reading R3) */
     double tau_h; /* Maxwell relaxation time, must be 1/2 (Eq. Ex_force) */
     double alpha, Gamma, sigma, nu;
+    int32_t divb_fix;  /* normal-B adjustment on open faces (Reading R22) */
+    int32_t null_band; /* half-width in y-cells of the null-point search band (< 1: 64) */
 } orc_params;
 
 /* ---------------------------------------------------------------- lattice */
@@ -145,6 +148,12 @@ typedef struct {
     orc_macro *mac;   /* macroscopic fields of the current step */
     long step;
     long n_failed;    /* failed recoveries in the last macroscopic pass */
+    /* driven low-z face (Reading R23): two ghost planes below z = 0 of
+     * post-collision f, g, h* and of E, fixed in time; [q][layer][y][x] */
+    double *gf, *gg, *gh, *gE;
+    double *Bt;       /* B of Eq. Cal_B from the streamed h of every cell, 3 arrays of N */
+    double *Ez0;      /* initial E^z, for the reconnection rate */
+    double B0;        /* max |B| of the initial fields */
 } orc_ctx;
 
 static inline long cell_index(const orc_ctx *C, int x, int y, int z)
@@ -159,7 +168,7 @@ static inline int map_coord(int x, int n, int lo, int hi)
 {
     if (x < 0) {
         if (lo == BC_PERIODIC) return ((x % n) + n) % n;
-        return 0;
+        return 0; /* open; a driven face's ghost planes are read through value_at */
     }
     if (x >= n) {
         if (hi == BC_PERIODIC) return x % n;
@@ -175,6 +184,29 @@ static inline long nb_index(const orc_ctx *C, int x, int y, int z)
     y = map_coord(y, P->ny, P->bc_lo[1], P->bc_hi[1]);
     z = map_coord(z, P->nz, P->bc_lo[2], P->bc_hi[2]);
     return cell_index(C, x, y, z);
+}
+
+/* Reading R23: with a driven low-z face, z = -1 and z = -2 are ghost planes
+ * whose post-collision populations and E are fixed (the equilibrium of the
+ * prescribed face fields).  Value of array q of a distribution set at a
+ * lattice point that may lie in a ghost plane: `arr` holds the interior
+ * (nq arrays of N), `ghost` the two ghost planes of the same arrays. */
+static inline int driven_ghost(const orc_ctx *C, int z)
+{
+    return C->P.bc_lo[2] == BC_DRIVEN && z < 0;
+}
+
+static inline double value_at(const orc_ctx *C, const double *arr, const double *ghost, int q, int x, int y, int z)
+{
+    const orc_params *P = &C->P;
+    if (ghost && driven_ghost(C, z)) {
+        int xx = map_coord(x, P->nx, P->bc_lo[0], P->bc_hi[0]);
+        int yy = map_coord(y, P->ny, P->bc_lo[1], P->bc_hi[1]);
+        int layer = -z - 1; /* z = -1 -> 0, z = -2 -> 1 */
+        long plane = (long)P->nx * P->ny;
+        return ghost[((long)q * 2 + layer) * plane + xx + (long)P->nx * yy];
+    }
+    return arr[(long)q * C->N + nb_index(C, x, y, z)];
 }
 
 /* ------------------------------------------------------------ physics bits */
@@ -393,16 +425,16 @@ static inline double minmod(double a, double b)
  * is the printed axis-wise difference; for the face diagonals the axis-wise
  * unsplit form has C_x + C_y = 1.19 > 1 and is unstable.
  * Returns the flux difference (dt/dx)(c_0/c_t) [h(x + e_i/2) - h(x - e_i/2)]. */
-static double advection(const orc_ctx *C, const double *fq, int i, int x, int y, int z)
+static double advection(const orc_ctx *C, const double *arr, const double *ghost, int i, int x, int y, int z)
 {
     const orc_lattice *L = &C->L;
     if (i == 0) return 0.0;
     const int *e = L->e[i];
     double cour = (1.0 / L->ct_c0) * L->ca * C->P.c * C->dt / C->P.dx;
-    double fm2 = fq[nb_index(C, x - 2 * e[0], y - 2 * e[1], z - 2 * e[2])];
-    double fm1 = fq[nb_index(C, x - e[0], y - e[1], z - e[2])];
-    double f0 = fq[cell_index(C, x, y, z)];
-    double fp1 = fq[nb_index(C, x + e[0], y + e[1], z + e[2])];
+    double fm2 = value_at(C, arr, ghost, i, x - 2 * e[0], y - 2 * e[1], z - 2 * e[2]);
+    double fm1 = value_at(C, arr, ghost, i, x - e[0], y - e[1], z - e[2]);
+    double f0 = value_at(C, arr, ghost, i, x, y, z);
+    double fp1 = value_at(C, arr, ghost, i, x + e[0], y + e[1], z + e[2]);
     double face_plus = f0 + 0.5 * minmod(f0 - fm1, fp1 - f0);     /* face x + e_i/2, upwind cell x */
     double face_minus = fm1 + 0.5 * minmod(fm1 - fm2, f0 - fm1);  /* face x - e_i/2, upwind cell x - e_i */
     return cour * (face_plus - face_minus);
@@ -410,28 +442,81 @@ static double advection(const orc_ctx *C, const double *fq, int i, int x, int y,
 
 /* Reading R5: the bulk-viscosity term is lambda_i times the 7-point central
  * Laplacian of f_i itself. */
-static double laplacian(const orc_ctx *C, const double *fq, int x, int y, int z)
+static double laplacian(const orc_ctx *C, const double *arr, const double *ghost, int i, int x, int y, int z)
 {
-    double c0 = fq[cell_index(C, x, y, z)];
+    double c0 = value_at(C, arr, ghost, i, x, y, z);
     double s = 0.0;
-    s += fq[nb_index(C, x + 1, y, z)] + fq[nb_index(C, x - 1, y, z)] - 2.0 * c0;
-    s += fq[nb_index(C, x, y + 1, z)] + fq[nb_index(C, x, y - 1, z)] - 2.0 * c0;
-    s += fq[nb_index(C, x, y, z + 1)] + fq[nb_index(C, x, y, z - 1)] - 2.0 * c0;
+    s += value_at(C, arr, ghost, i, x + 1, y, z) + value_at(C, arr, ghost, i, x - 1, y, z) - 2.0 * c0;
+    s += value_at(C, arr, ghost, i, x, y + 1, z) + value_at(C, arr, ghost, i, x, y - 1, z) - 2.0 * c0;
+    s += value_at(C, arr, ghost, i, x, y, z + 1) + value_at(C, arr, ghost, i, x, y, z - 1) - 2.0 * c0;
     return s;
 }
 
 /* ------------------------------------------------------------ macroscopic */
 
 /* eps0 div E by central differences over the neighbours (boundary mapping
- * as for the distributions); E is stored as three arrays of N values. */
-static double gauss_charge(const orc_ctx *C, const double *E, int x, int y, int z)
+ * as for the distributions); E is stored as three arrays of N values, and
+ * `ghost` holds E in the ghost planes of a driven face (NULL: none). */
+static double gauss_charge(const orc_ctx *C, const double *E, const double *ghost, int x, int y, int z)
 {
-    const long N = C->N;
-    double dv = (E[0 * N + nb_index(C, x + 1, y, z)] - E[0 * N + nb_index(C, x - 1, y, z)] +
-                 E[1 * N + nb_index(C, x, y + 1, z)] - E[1 * N + nb_index(C, x, y - 1, z)] +
-                 E[2 * N + nb_index(C, x, y, z + 1)] - E[2 * N + nb_index(C, x, y, z - 1)]) /
+    double dv = (value_at(C, E, ghost, 0, x + 1, y, z) - value_at(C, E, ghost, 0, x - 1, y, z) +
+                 value_at(C, E, ghost, 1, x, y + 1, z) - value_at(C, E, ghost, 1, x, y - 1, z) +
+                 value_at(C, E, ghost, 2, x, y, z + 1) - value_at(C, E, ghost, 2, x, y, z - 1)) /
                 (2.0 * C->P.dx);
     return C->eps0 * dv;
+}
+
+/* Derivative along `axis` of a field X (N values) at a cell: central
+ * differences, periodic wrap on periodic axes; on the faces of a
+ * non-periodic axis the one-sided difference towards the interior; zero on
+ * an axis of one cell.  This is the divergence operator of the normal-B
+ * adjustment and of the max |div B| diagnostic. */
+static double axis_derivative(const orc_ctx *C, const double *X, int axis, int x, int y, int z)
+{
+    const orc_params *P = &C->P;
+    const int n = axis == 0 ? P->nx : (axis == 1 ? P->ny : P->nz);
+    const int v = axis == 0 ? x : (axis == 1 ? y : z);
+    const int ex = axis == 0, ey = axis == 1, ez = axis == 2;
+    if (n == 1) return 0.0;
+    const int periodic = P->bc_lo[axis] == BC_PERIODIC;
+    const double here = X[cell_index(C, x, y, z)];
+    if (!periodic && v == 0) return (X[cell_index(C, x + ex, y + ey, z + ez)] - here) / P->dx;
+    if (!periodic && v == n - 1) return (here - X[cell_index(C, x - ex, y - ey, z - ez)]) / P->dx;
+    return (X[nb_index(C, x + ex, y + ey, z + ez)] - X[nb_index(C, x - ex, y - ey, z - ez)]) / (2.0 * P->dx);
+}
+
+/* Reading R22 (the divergence-free adjustment on open faces, Sec. IV, KH
+ * set-up): in a cell on an open face of axis a (with at least two cells
+ * along a), the normal component of B is replaced by the value that makes
+ * the discrete divergence zero there, using the streamed B of the inner
+ * neighbour and the tangential derivatives of the streamed B:
+ *   low face:  B_a(x) = B_a(x + e_a) + dx sum_{b != a} d_b B_b
+ *   high face: B_a(x) = B_a(x - e_a) - dx sum_{b != a} d_b B_b.
+ * Every other component (and every interior cell) keeps the streamed value.
+ * Fills B with the cell's B for this step. */
+static void divb_fixed_B(const orc_ctx *C, int x, int y, int z, double B[3])
+{
+    const orc_params *P = &C->P;
+    const long N = C->N;
+    const long id = cell_index(C, x, y, z);
+    for (int a = 0; a < 3; a++) B[a] = C->Bt[(long)a * N + id];
+    if (!P->divb_fix) return;
+    const int dims[3] = {P->nx, P->ny, P->nz}, pos[3] = {x, y, z};
+    for (int a = 0; a < 3; a++) {
+        const int n = dims[a];
+        if (n < 2) continue;
+        const int low = pos[a] == 0 && P->bc_lo[a] == BC_OPEN;
+        const int high = pos[a] == n - 1 && P->bc_hi[a] == BC_OPEN;
+        if (!low && !high) continue;
+        double dt_sum = 0.0;
+        for (int b = 0; b < 3; b++)
+            if (b != a) dt_sum += axis_derivative(C, C->Bt + (long)b * N, b, x, y, z);
+        const int ex = a == 0, ey = a == 1, ez = a == 2;
+        if (low)
+            B[a] = C->Bt[(long)a * N + cell_index(C, x + ex, y + ey, z + ez)] + P->dx * dt_sum;
+        else
+            B[a] = C->Bt[(long)a * N + cell_index(C, x - ex, y - ey, z - ez)] - P->dx * dt_sum;
+    }
 }
 
 /* The first half of one step at one cell: transport f and g, stream h, take
@@ -445,13 +530,13 @@ static double gauss_charge(const orc_ctx *C, const double *E, int x, int y, int 
  * form amplifies the grid-scale non-equilibrium mode by 1 - omega - 2C, with
  * C = sqrt(19/54) the Courant number, so it is unstable at the paper's
  * tau = 1; the printed f(t + dt) in the collision is not conservative.) */
-static void macroscopic_cell(orc_ctx *C, int x, int y, int z, orc_macro *m, double *hp)
+static void macroscopic_cell(orc_ctx *C, int x, int y, int z, orc_macro *m, const double *hp)
 {
     const orc_lattice *L = &C->L;
     const orc_params *P = &C->P;
     const long N = C->N;
     const long id = cell_index(C, x, y, z);
-    const double *fs = C->f[C->cur], *gs = C->g[C->cur], *hs = C->hs[C->cur];
+    const double *fs = C->f[C->cur], *gs = C->g[C->cur];
     const double *Ep = C->Ep[C->cur];
     const double c = P->c;
     /* Reading R5: lambda_i = alpha dx for i != 0 times the 7-point Laplacian,
@@ -463,16 +548,11 @@ static void macroscopic_cell(orc_ctx *C, int x, int y, int z, orc_macro *m, doub
 
     /* transport (left-hand side and bulk-viscosity term of Eq. rlb) */
     for (int i = 0; i < Q19; i++) {
-        const double *fi = fs + (long)i * N, *gi = gs + (long)i * N;
-        double val = fi[id] - advection(C, fi, i, x, y, z);
-        if (i != 0) val += kv * laplacian(C, fi, x, y, z);
+        double val = fs[(long)i * N + id] - advection(C, fs, C->gf, i, x, y, z);
+        if (i != 0) val += kv * laplacian(C, fs, C->gf, i, x, y, z);
         f[(long)i * N + id] = val;
-        g[(long)i * N + id] = gi[id] - advection(C, gi, i, x, y, z);
+        g[(long)i * N + id] = gs[(long)i * N + id] - advection(C, gs, C->gg, i, x, y, z);
     }
-
-    /* stream: h_k(x, t) = h*_k(x - v_k dt, t - dt), Eq. LB_Maxwell */
-    for (int k = 0; k < QH; k++) hp[k] = hs[(long)k * N + nb_index(C, x - L->s[k][0], y - L->s[k][1], z - L->s[k][2])];
-    hp[QH] = hs[(long)QH * N + id];
 
     /* T^{mu nu} = sum_i xi^mu_i xi^nu_i f_i and N^0 = sum_i xi^0_i g_i */
     for (int mu = 0; mu < 4; mu++)
@@ -485,15 +565,14 @@ static void macroscopic_cell(orc_ctx *C, int x, int y, int z, orc_macro *m, doub
     for (int i = 0; i < Q19; i++) N0 += L->xi[i][0] * g[(long)i * N + id];
     m->N0 = N0;
 
-    /* Eqs. Cal_E, Cal_B, Cal_rhoc */
-    double Epr[3] = {0, 0, 0}, B[3] = {0, 0, 0}, rhoc = hp[QH];
+    /* Eqs. Cal_E, Cal_rhoc from the streamed h; B of Eq. Cal_B was taken by
+     * the streaming pass, with the normal component adjusted on open faces */
+    double Epr[3] = {0, 0, 0}, B[3], rhoc = hp[QH];
     for (int k = 0; k < QH; k++) {
-        for (int a = 0; a < 3; a++) {
-            Epr[a] += hp[k] * L->ee[k][a];
-            B[a] += hp[k] * L->bb[k][a];
-        }
+        for (int a = 0; a < 3; a++) Epr[a] += hp[k] * L->ee[k][a];
         rhoc += hp[k];
     }
+    divb_fixed_B(C, x, y, z, B);
 
     /* Fluid tensor T_fl = T - T_EM.  Reading R10: E is the previous step's
      * (the current one needs the velocity through Ohm's law, Eq. Ex_force);
@@ -538,13 +617,37 @@ static void macroscopic_cell(orc_ctx *C, int x, int y, int z, orc_macro *m, doub
      * differences.  With the populations' charge (Eq. Cal_rhoc) the
      * non-dissipative D3Q13 charge flux makes the convection current
      * unstable in any moving fluid. */
-    double rho_gauss = gauss_charge(C, Ep, x, y, z);
+    double rho_gauss = gauss_charge(C, Ep, C->gE, x, y, z);
     ohm_solve(C, Epr, B, u, rho_gauss, m->E, m->J);
+}
+
+/* Stream h of every cell (Eq. LB_Maxwell: h_k(x, t) = h*_k(x - v_k dt, t - dt),
+ * the rest population in place) and take B of Eq. Cal_B from it. */
+static void stream_pass(orc_ctx *C)
+{
+    const orc_lattice *L = &C->L;
+    const long N = C->N;
+    const double *hs = C->hs[C->cur];
+    for (int z = 0; z < C->P.nz; z++)
+        for (int y = 0; y < C->P.ny; y++)
+            for (int x = 0; x < C->P.nx; x++) {
+                long id = cell_index(C, x, y, z);
+                double *hp = &C->hpull[id * (QH + 1)];
+                for (int k = 0; k < QH; k++)
+                    hp[k] = value_at(C, hs, C->gh, k, x - L->s[k][0], y - L->s[k][1], z - L->s[k][2]);
+                hp[QH] = hs[(long)QH * N + id];
+                for (int a = 0; a < 3; a++) {
+                    double b = 0.0;
+                    for (int k = 0; k < QH; k++) b += hp[k] * L->bb[k][a];
+                    C->Bt[(long)a * N + id] = b;
+                }
+            }
 }
 
 static void macroscopic_pass(orc_ctx *C)
 {
     long nf = 0;
+    stream_pass(C);
     for (int z = 0; z < C->P.nz; z++)
         for (int y = 0; y < C->P.ny; y++)
             for (int x = 0; x < C->P.nx; x++) {
@@ -621,11 +724,11 @@ ORC_API int rmhdlb_oracle_create(const orc_params *P, void **out)
         !(P->nu > 0) || !(P->alpha >= 0))
         return ORC_EINVAL;
     for (int a = 0; a < 3; a++) {
-        if ((P->bc_lo[a] != BC_PERIODIC && P->bc_lo[a] != BC_OPEN) ||
-            (P->bc_hi[a] != BC_PERIODIC && P->bc_hi[a] != BC_OPEN))
-            return ORC_EINVAL;
+        int lo_ok = P->bc_lo[a] == BC_PERIODIC || P->bc_lo[a] == BC_OPEN || (a == 2 && P->bc_lo[a] == BC_DRIVEN);
+        if (!lo_ok || (P->bc_hi[a] != BC_PERIODIC && P->bc_hi[a] != BC_OPEN)) return ORC_EINVAL;
         if ((P->bc_lo[a] == BC_PERIODIC) != (P->bc_hi[a] == BC_PERIODIC)) return ORC_EINVAL;
     }
+    if (P->divb_fix != 0 && P->divb_fix != 1) return ORC_EINVAL;
     if (P->tau_h != 0.5) return ORC_EUNSUPPORTED; /* Eq. Ex_force holds for tau_h = 1/2 */
     orc_ctx *C = (orc_ctx *)calloc(1, sizeof(orc_ctx));
     if (!C) return ORC_ENOMEM;
@@ -644,7 +747,17 @@ ORC_API int rmhdlb_oracle_create(const orc_params *P, void **out)
     C->gtr = (double *)calloc((size_t)Q19 * C->N, sizeof(double));
     C->hpull = (double *)calloc((size_t)(QH + 1) * C->N, sizeof(double));
     C->mac = (orc_macro *)calloc((size_t)C->N, sizeof(orc_macro));
-    int ok = C->hpull && C->mac && C->ftr && C->gtr;
+    C->Bt = (double *)calloc((size_t)3 * C->N, sizeof(double));
+    C->Ez0 = (double *)calloc((size_t)C->N, sizeof(double));
+    int ok = C->hpull && C->mac && C->ftr && C->gtr && C->Bt && C->Ez0;
+    if (P->bc_lo[2] == BC_DRIVEN) {
+        const size_t plane2 = (size_t)2 * P->nx * P->ny;
+        C->gf = (double *)calloc(Q19 * plane2, sizeof(double));
+        C->gg = (double *)calloc(Q19 * plane2, sizeof(double));
+        C->gh = (double *)calloc((QH + 1) * plane2, sizeof(double));
+        C->gE = (double *)calloc(3 * plane2, sizeof(double));
+        ok = ok && C->gf && C->gg && C->gh && C->gE;
+    }
     for (int b = 0; b < 2; b++) ok = ok && C->f[b] && C->g[b] && C->hs[b] && C->Ep[b];
     if (!ok) {
         for (int b = 0; b < 2; b++) {
@@ -657,6 +770,12 @@ ORC_API int rmhdlb_oracle_create(const orc_params *P, void **out)
         free(C->gtr);
         free(C->hpull);
         free(C->mac);
+        free(C->Bt);
+        free(C->Ez0);
+        free(C->gf);
+        free(C->gg);
+        free(C->gh);
+        free(C->gE);
         free(C);
         return ORC_ENOMEM;
     }
@@ -678,7 +797,65 @@ ORC_API void rmhdlb_oracle_destroy(void *ctx)
     free(C->gtr);
     free(C->hpull);
     free(C->mac);
+    free(C->Bt);
+    free(C->Ez0);
+    free(C->gf);
+    free(C->gg);
+    free(C->gh);
+    free(C->gE);
     free(C);
+}
+
+/* Reading R23: the ghost planes of a driven low-z face hold the
+ * post-collision state of a fully relaxed cell with the prescribed fields:
+ * f_eq and g_eq of (n, p, u, E = -u x B, B), h* = h_eq of (J, E + (dt/2)
+ * mu0 c^2 J, B) with J of Eq. Ohm at zero charge (h* = h_eq is the fixed
+ * point of the tau_h = 1/2 collision), and E.  Both ghost planes take the
+ * same values; arrays are nx*ny values of the face, x fastest.  Returns
+ * ORC_EINVAL for |u| >= c, n <= 0 or p < 0. */
+static int fill_ghosts(orc_ctx *C, const double *n, const double *p, const double *const u[3],
+                       const double *const B[3])
+{
+    const orc_params *P = &C->P;
+    const long plane = (long)P->nx * P->ny;
+    const double c = P->c;
+    const double q = 0.5 * C->dt * P->mu0 * c * c;
+    for (long xy = 0; xy < plane; xy++) {
+        double uu[3] = {u[0][xy], u[1][xy], u[2][xy]}, BB[3] = {B[0][xy], B[1][xy], B[2][xy]};
+        double u2 = uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2];
+        if (!(u2 < c * c) || !(n[xy] > 0) || !(p[xy] >= 0)) return ORC_EINVAL;
+        double EE[3] = {-(uu[1] * BB[2] - uu[2] * BB[1]), -(uu[2] * BB[0] - uu[0] * BB[2]),
+                        -(uu[0] * BB[1] - uu[1] * BB[0])};
+        double beta[3] = {uu[0] / c, uu[1] / c, uu[2] / c};
+        double eps = n[xy] * c * c + p[xy] / (P->Gamma - 1.0);
+        double feq[Q19], geq[Q19], heq[QH + 1], JJ[3], Epr[3];
+        f_equilibrium(C, eps, p[xy], beta, EE, BB, feq);
+        g_equilibrium(C, n[xy], beta, geq);
+        ohm_current(C, EE, uu, BB, 0.0, JJ);
+        for (int a = 0; a < 3; a++) Epr[a] = EE[a] + q * JJ[a];
+        h_equilibrium(C, JJ, Epr, BB, 0.0, heq);
+        for (int layer = 0; layer < 2; layer++) {
+            for (int i = 0; i < Q19; i++) {
+                C->gf[((long)i * 2 + layer) * plane + xy] = feq[i];
+                C->gg[((long)i * 2 + layer) * plane + xy] = geq[i];
+            }
+            for (int k = 0; k <= QH; k++) C->gh[((long)k * 2 + layer) * plane + xy] = heq[k];
+            for (int a = 0; a < 3; a++) C->gE[((long)a * 2 + layer) * plane + xy] = EE[a];
+        }
+    }
+    return ORC_OK;
+}
+
+/* Prescribed fields of a driven low-z face (Reading R23): n, p, u[3], B[3],
+ * each nx*ny values.  Replaces the ghost planes set by rmhdlb_oracle_init. */
+ORC_API int rmhdlb_oracle_set_driven(void *ctx, const double *n, const double *p, const double *const u[3],
+                                     const double *const B[3])
+{
+    orc_ctx *C = (orc_ctx *)ctx;
+    if (!C || !n || !p || C->P.bc_lo[2] != BC_DRIVEN) return ORC_EINVAL;
+    for (int a = 0; a < 3; a++)
+        if (!u[a] || !B[a]) return ORC_EINVAL;
+    return fill_ghosts(C, n, p, u, B);
 }
 
 /* Initial state from primitive fields, each an array of nx*ny*nz doubles in
@@ -737,7 +914,7 @@ ORC_API int rmhdlb_oracle_init(void *ctx, const double *n, const double *p, cons
                 double u2 = uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2];
                 if (!(u2 < c * c) || !(n[id] > 0) || !(p[id] >= 0)) bad = 1;
                 double JJ[3];
-                ohm_current(C, EE, uu, BB, gauss_charge(C, E0, x, y, z), JJ);
+                ohm_current(C, EE, uu, BB, gauss_charge(C, E0, NULL, x, y, z), JJ);
                 for (int a = 0; a < 3; a++) J[(long)a * N + id] = JJ[a];
             }
     free(E0);
@@ -779,6 +956,16 @@ ORC_API int rmhdlb_oracle_init(void *ctx, const double *n, const double *p, cons
             }
     free(rhoc);
     free(J);
+    /* reference values of the reconnection-rate diagnostic */
+    double b2max = 0.0;
+    for (long id = 0; id < N; id++) {
+        C->Ez0[id] = E[2][id];
+        double b2 = fma(B[0][id], B[0][id], fma(B[1][id], B[1][id], B[2][id] * B[2][id]));
+        if (b2 > b2max) b2max = b2;
+    }
+    C->B0 = sqrt(b2max);
+    /* a driven face starts from the fields of its first interior plane */
+    if (P->bc_lo[2] == BC_DRIVEN && fill_ghosts(C, n, p, u, B) != ORC_OK) return ORC_EINVAL;
     C->step = 0;
     return ORC_OK;
 }
@@ -829,9 +1016,16 @@ ORC_API int rmhdlb_oracle_charge(void *ctx, double *rhoc)
 
 /* Global diagnostics of the current state, sums in long double:
  * d[0] = sum T^00, d[1] = sum N^0, d[2..4] = sum T^0a, d[5] = sum eps0 (E^2 + c^2 B^2)/2,
- * d[6] = max |div B| (central differences), d[7] = sum rho_c, d[8] = failed cells,
- * d[9] = mean power-method iterations. */
-ORC_API int rmhdlb_oracle_diagnostics(void *ctx, double d[10])
+ * d[6] = max |div B| (the derivative operator of axis_derivative), d[7] = sum rho_c,
+ * d[8] = failed cells, d[9] = mean power-method iterations,
+ * d[10] = reconnection rate, d[11] = null-point cell index, d[12] = B0.
+ *
+ * Reconnection rate (Sec. IV, KH reconnection; Reading R21): the null point
+ * is the cell of least B_x^2 + B_y^2 (evaluated as fma(B_x, B_x, B_y B_y))
+ * among the rows whose centre lies within null_band cells of y = 0, first in
+ * x-fastest order on ties; R = (E^z - E^z_0) / B0 there, with E^z_0 the
+ * initial E^z of that cell and B0 the largest |B| of the initial fields. */
+ORC_API int rmhdlb_oracle_diagnostics(void *ctx, double d[13])
 {
     orc_ctx *C = (orc_ctx *)ctx;
     if (!C || !d) return ORC_EINVAL;
@@ -840,7 +1034,15 @@ ORC_API int rmhdlb_oracle_diagnostics(void *ctx, double d[10])
     double maxdiv = 0.0;
     long double its = 0;
     const orc_params *P = &C->P;
+    const long N = C->N;
     const double c = P->c;
+    double *Bm = (double *)malloc(sizeof(double) * 3 * N);
+    if (!Bm) return ORC_ENOMEM;
+    for (long id = 0; id < N; id++)
+        for (int a = 0; a < 3; a++) Bm[(long)a * N + id] = C->mac[id].B[a];
+    const int band = P->null_band >= 1 ? P->null_band : 64;
+    double best = INFINITY;
+    long null_id = -1;
     for (int z = 0; z < P->nz; z++)
         for (int y = 0; y < P->ny; y++)
             for (int x = 0; x < P->nx; x++) {
@@ -854,17 +1056,27 @@ ORC_API int rmhdlb_oracle_diagnostics(void *ctx, double d[10])
                 s[5] += 0.5 * C->eps0 * (E2 + c * c * B2);
                 s[6] += m->rhoc;
                 its += m->iters;
-                double dv = (C->mac[nb_index(C, x + 1, y, z)].B[0] - C->mac[nb_index(C, x - 1, y, z)].B[0] +
-                             C->mac[nb_index(C, x, y + 1, z)].B[1] - C->mac[nb_index(C, x, y - 1, z)].B[1] +
-                             C->mac[nb_index(C, x, y, z + 1)].B[2] - C->mac[nb_index(C, x, y, z - 1)].B[2]) /
-                            (2.0 * P->dx);
+                double dv = 0.0;
+                for (int a = 0; a < 3; a++) dv += axis_derivative(C, Bm + (long)a * N, a, x, y, z);
                 if (fabs(dv) > maxdiv) maxdiv = fabs(dv);
+                /* |y_j| <= band with cell centres y_j = j + 1/2 - ny/2 */
+                if (labs(2L * y + 1 - P->ny) <= 2L * band) {
+                    double key = fma(m->B[0], m->B[0], m->B[1] * m->B[1]);
+                    if (key < best) {
+                        best = key;
+                        null_id = id;
+                    }
+                }
             }
+    free(Bm);
     for (int k = 0; k < 6; k++) d[k] = (double)s[k];
     d[6] = maxdiv;
     d[7] = (double)s[6];
     d[8] = (double)C->n_failed;
-    d[9] = (double)(its / (long double)C->N);
+    d[9] = (double)(its / (long double)N);
+    d[10] = null_id >= 0 ? (C->mac[null_id].E[2] - C->Ez0[null_id]) / C->B0 : NAN;
+    d[11] = (double)null_id;
+    d[12] = C->B0;
     return ORC_OK;
 }
 

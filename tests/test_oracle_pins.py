@@ -398,3 +398,169 @@ def test_checkpoint_equivalence():
     c.set_state(st)
     c.step(5)
     assert np.array_equal(a.get_state(), c.get_state())
+
+
+# ------------------------------------------- open, driven faces (Sec. IV) ---
+
+def _face_divergence(m, bc, dx=1.0):
+    """Discrete div B of the reported B with central differences inside and
+    one-sided differences on the faces of non-periodic axes (numpy, (z, y, x))."""
+    B = (m["Bx"], m["By"], m["Bz"])
+    div = np.zeros_like(B[0])
+    for a, ax in ((0, 2), (1, 1), (2, 0)):
+        X = B[a]
+        n = X.shape[ax]
+        if n == 1:
+            continue
+        if bc[a][0] == "periodic":
+            d = (np.roll(X, -1, ax) - np.roll(X, 1, ax)) / (2 * dx)
+        else:
+            d = np.empty_like(X)
+            sl = [slice(None)] * 3
+            def take(i):
+                s = list(sl)
+                s[ax] = i
+                return X[tuple(s)]
+            def put(i, v):
+                s = list(sl)
+                s[ax] = i
+                d[tuple(s)] = v
+            put(slice(1, n - 1), (take(slice(2, n)) - take(slice(0, n - 2))) / (2 * dx))
+            put(0, (take(1) - take(0)) / dx)
+            put(n - 1, (take(n - 1) - take(n - 2)) / dx)
+        div += d
+    return div
+
+
+def test_divb_fix_makes_open_faces_divergence_free():
+    """Sec. IV (KH set-up): on open faces the normal B is adjusted so that div B = 0 there.
+    Checked on face cells away from edges, at the initial state and after 6 steps; the
+    interior of the initial state is untouched, and without the adjustment the face
+    divergence is O(|B| k), so the check is not vacuous."""
+    bc = (("open", "open"), ("open", "open"), ("periodic", "periodic"))
+    w = W.random_state(shape=(12, 10, 4), seed=11, vmax=0.1, Bmag=0.3, Emag=0.03, sigma=5.0, bc=bc)
+    # face cells at least two cells from another open face (next to an edge the
+    # tangential difference reaches the neighbouring face's adjusted value)
+    face = np.zeros((4, 10, 12), bool)
+    face[:, 2:-2, 0] = face[:, 2:-2, -1] = True
+    face[:, 0, 2:-2] = face[:, -1, 2:-2] = True
+    inner = np.zeros_like(face)
+    inner[:, 1:-1, 1:-1] = True
+    for steps in (0, 6):
+        on = _run(w, steps, divb_fix=1).moments()
+        off = _run(w, steps, divb_fix=0).moments()
+        assert on["n_failed"] == 0 and off["n_failed"] == 0
+        d_on = np.abs(_face_divergence(on, bc))[face].max()
+        d_off = np.abs(_face_divergence(off, bc))[face].max()
+        assert d_on < 1e-14, (steps, d_on)
+        assert d_off > 1e-3, (steps, d_off)
+        if steps == 0:
+            for k in ("n", "p", "ux", "Ex", "Bx", "By", "Bz", "Jz"):
+                assert np.array_equal(on[k][inner], off[k][inner]), k
+
+
+def _uniform_fields(shape, n, p, u, B):
+    nx, ny, nz = shape
+    g = (nz, ny, nx)
+    E = tuple(-np.cross(u, B))
+    return dict(n=np.full(g, n), p=np.full(g, p), u=tuple(np.full(g, x) for x in u),
+                E=tuple(np.full(g, x) for x in E), B=tuple(np.full(g, x) for x in B), rho_c=np.zeros(g))
+
+
+DRIVEN_BC = (("periodic", "periodic"), ("periodic", "periodic"), ("driven", "open"))
+
+
+def test_driven_face_in_equilibrium_with_the_interior_is_steady():
+    """A driven face whose prescribed fields equal a uniform interior state keeps it uniform."""
+    shape = (5, 4, 6)
+    u, B = (0.15, -0.05, 0.1), (0.2, 0.1, -0.3)
+    o = oracle.Oracle(shape, DRIVEN_BC, sigma=20.0)
+    o.init(_uniform_fields(shape, 1.2, 0.8, u, B))
+    o.step(25)
+    m = o.moments()
+    assert m["n_failed"] == 0
+    for k, v in (("n", 1.2), ("p", 0.8), ("ux", u[0]), ("uz", u[2]), ("By", B[1]), ("Ey", -np.cross(u, B)[1])):
+        assert np.abs(m[k] - v).max() < 1e-12, k
+
+
+def test_driven_face_drags_the_fluid_and_is_mirror_symmetric():
+    """A face driven at u_x = +-v0 under a fluid at rest injects x-momentum that decays
+    away from the face; driving at -v0 gives the mirror image."""
+    shape, v0 = (4, 4, 12), 0.2
+    res = {}
+    for sgn in (1.0, -1.0):
+        o = oracle.Oracle(shape, DRIVEN_BC, sigma=20.0)
+        o.init(_uniform_fields(shape, 1.0, 1.0, (0.0, 0.0, 0.0), (0.0, 0.0, 0.05)))
+        face = dict(n=1.0, p=1.0, u=(sgn * v0, 0.0, 0.0), B=(0.0, 0.0, 0.05))
+        o.set_driven(face)
+        px = []
+        for _ in range(4):
+            o.step(10)
+            px.append(o.diagnostics()["momentum"][0])
+        res[sgn] = (o.moments(), px)
+    m, px = res[1.0]
+    assert m["n_failed"] == 0
+    prof = m["ux"].mean(axis=(1, 2))
+    assert 0 < prof[0] < v0 and prof[0] > prof[2] > prof[5] > 0
+    assert all(b > a for a, b in zip(px, px[1:])) and px[0] > 0
+    mm, pxm = res[-1.0]
+    assert np.abs(mm["ux"] + m["ux"]).max() < 1e-13
+    assert np.abs(np.array(pxm) + np.array(px)).max() < 1e-12 * abs(px[-1])
+
+
+def test_driven_face_rejects_superluminal_fields():
+    o = oracle.Oracle((3, 3, 3), DRIVEN_BC)
+    o.init(_uniform_fields((3, 3, 3), 1.0, 1.0, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0)))
+    with pytest.raises(ValueError):
+        o.set_driven(dict(n=1.0, p=1.0, u=(1.0, 0.0, 0.0), B=(0.0, 0.0, 0.0)))
+
+
+# ------------------------------------------ reconnection rate (Sec. IV, KH) ---
+
+def test_reconnection_rate_of_a_resistive_sheet_is_the_diffusion_field():
+    """For a resting current sheet B_y = B0 erf(x / (2 sqrt(T / sigma))) the out-of-plane field
+    at the null is E_z = J_z / sigma = (dB_y/dx) / sigma (Eq. Ohm at rest, Ampere's law), so
+    R = (E_z - 0) / B0 follows 1 / sqrt(pi sigma T) e^{-x^2 sigma / 4T} at the null's centre."""
+    sigma, nx, steps = 10.0, 256, 200
+    w = W.sheet(nx=nx, ny=1, nz=1, sigma=sigma, steps=steps)
+    o = _run(w, steps)
+    d = o.diagnostics()
+    T = w.meta["t0"] + steps / np.sqrt(2)
+    x_null = d["null_index"] + 0.5 - nx / 2
+    assert abs(x_null) == 0.5
+    ref = np.exp(-x_null ** 2 * sigma / (4 * T)) / np.sqrt(np.pi * sigma * T)
+    assert abs(d["B0"] - 1.0) < 1e-15
+    assert abs(d["recon_rate"] - ref) < 0.03 * ref, (d["recon_rate"], ref)
+
+
+def test_null_point_is_a_band_argmin():
+    """The null is the least B_x^2 + B_y^2 of the band of rows around y = 0 (checked against
+    numpy's minimum), R is Delta E_z / B0 there, and B0 = max |B| of the initial fields."""
+    w = W.kh(nx=16, ny=40, v0=0.2, ratio=10.0, sigma=100.0, noise=1e-2)
+    o = _run(w, 0, null_band=5)
+    d = o.diagnostics()
+    assert abs(d["B0"] - 0.1 * np.tanh(19.5)) < 1e-16
+    o.step(30)
+    d = o.diagnostics()
+    m = o.moments()
+    key = m["Bx"] ** 2 + m["By"] ** 2
+    y = np.arange(40) + 0.5 - 20
+    band = np.abs(y) <= 5
+    sub = key[0][band]
+    zi, yi, xi = np.unravel_index(d["null_index"], (1, 40, 16))
+    assert band[yi]
+    assert key[0, yi, xi] <= sub.min() * (1 + 1e-15)
+    ref = (m["Ez"][0, yi, xi] - w.fields["E"][2][0, yi, xi]) / d["B0"]
+    assert abs(d["recon_rate"] - ref) <= 1e-15 * max(abs(ref), 1e-300)
+
+
+def test_null_point_ties_go_to_the_lowest_index():
+    """With B = 0 everywhere every band cell ties; the null is the band's first cell
+    (rows with |y| <= 3 of 10 start at row 2), and R is undefined without a field (B0 = 0)."""
+    shape = (6, 10, 2)
+    o = oracle.Oracle(shape, W.PERIODIC3, null_band=3)
+    o.init(_uniform_fields(shape, 1.0, 1.0, (0.1, 0.0, 0.0), (0.0, 0.0, 0.0)))
+    o.step(2)
+    d = o.diagnostics()
+    assert d["null_index"] == 2 * 6
+    assert np.isnan(d["recon_rate"]) and d["B0"] == 0.0
