@@ -66,6 +66,7 @@ def cpu_baseline(budget_s):
     w = W.flare(nx=64, ny=64, nz=32, Lz=3.0)
     o = oracle.Oracle(w.shape, w.bc, **w.params)
     o.init(w.fields)
+    o.set_driven(w.driven)
     o.step(1)  # first-touch
     steps = 0
     t0 = time.perf_counter()
@@ -92,6 +93,8 @@ def main():
     stream = torch.cuda.current_stream()
     s = Solver(w.shape, w.bc, storage=args.storage, stream=stream, **w.params)
     s.init_fields(w.fields)
+    if w.driven is not None:
+        s.set_driven_face(w.driven)
     del w.fields
     s.step(args.warmup)
     torch.cuda.synchronize()
@@ -126,7 +129,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.storage == "f64" else f"{args.storage} storage, f32 arithmetic",
         "data": "synthetic",
-        "config": {"workload": (f"flare-like 3-D box {w.shape[0]}x{w.shape[1]}x{w.shape[2]}, sigma=1e3, open faces"
+        "config": {"workload": (f"flare-like 3-D box {w.shape[0]}x{w.shape[1]}x{w.shape[2]}, sigma=1e3, "
+                                f"driven shearing bottom face, open faces elsewhere"
                                 if args.workload == "flare" else
                                 f"KH shear layer {w.shape[0]}x{w.shape[1]}x{w.shape[2]}, v0=0.2, ratio 10, sigma=1e3"),
                    "storage": args.storage, "cells": ncell, "recovery": "plain Newton",

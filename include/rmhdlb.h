@@ -46,7 +46,14 @@ enum {
     RMHDLB_EUNSUPPORTED = -5 /* parameter value outside what the method supports */
 };
 
-enum { RMHDLB_BC_PERIODIC = 0, RMHDLB_BC_OPEN = 1 };
+/* Face types.  Periodic pairs both faces of an axis.  Open: the ghosts are
+ * copies of the first interior cell along the face normal (Sec. IV, Alfven
+ * test), and with divb_fix the normal B of a face cell is adjusted so that
+ * div B vanishes there (Sec. IV, KH set-up).  Driven (low face of z only,
+ * the high z face then open): two ghost planes below z = 0 hold the fixed
+ * post-collision state of prescribed face fields (rmhdlb_set_driven_face),
+ * an equilibrium boundary of this library's own (not in the paper). */
+enum { RMHDLB_BC_PERIODIC = 0, RMHDLB_BC_OPEN = 1, RMHDLB_BC_DRIVEN = 2 };
 
 /* Storage of the state between steps.  F64 is the plain path.  F32 and F16
  * store f and g as deviations from w_i E_ref and w'_i N_ref (references: the
@@ -69,7 +76,10 @@ typedef struct {
     double sigma;                /* conductivity of Eq. Ohm (>= 0) */
     double nu;                   /* lattice nu = c / c_s (> 0); sqrt(27) makes every g weight positive */
     int32_t storage;             /* RMHDLB_STORE_* */
-    int32_t reserved[7];         /* must be zero */
+    int32_t divb_fix;            /* 1: adjust the normal B on open faces so div B = 0 there; 0: off */
+    int32_t null_band;           /* reconnection-rate null search: rows with |y| <= null_band cells
+                                    (cell centres y_j = j + 1/2 - ny/2); < 1 selects 64 */
+    int32_t reserved[5];         /* must be zero */
 } rmhdlb_params;
 
 /* Initial primitive fields (Sec. IV): number density n, pressure p,
@@ -88,18 +98,33 @@ typedef struct {
     double *rho_c;
 } rmhdlb_fields_out;
 
-/* Global diagnostics of the current state (sums over cells, FP64). */
+/* Global diagnostics of the current state (sums over cells, FP64, in a
+ * fixed order: per-block trees, then the blocks in order). */
 typedef struct {
     double energy;       /* sum of T^00 (fluid + field, the moment of f) */
     double mass;         /* sum of N^0 */
     double momentum[3];  /* sum of T^0a */
     double em_energy;    /* sum of eps0 (E^2 + c^2 B^2) / 2 */
-    double max_divB;     /* max over cells of |div B| by central differences */
+    double max_divB;     /* max over cells of |div B|: central differences, one-sided on the faces of
+                            non-periodic axes */
     double charge;       /* sum of rho_c (Eq. Cal_rhoc) */
     double mean_iters;   /* mean Newton iterations of the recovery */
+    double recon_rate;   /* R = (E^z - E^z_0) / B0 at the null point (Sec. IV, KH reconnection): the
+                            null is the cell of least B_x^2 + B_y^2 in the null_band rows (first cell in
+                            x-fastest order on ties), E^z_0 its initial E^z, B0 = max |B| of the
+                            initial fields; NaN when B0 = 0 */
+    double B0;           /* max |B| of the initial fields */
+    int64_t null_index;  /* linear cell index of the null point (-1: none) */
+    int64_t newton_hist[16]; /* cells by Newton iterations of the recovery (last bin: 15 or more) */
     int64_t n_failed;    /* cells whose recovery failed */
     int64_t step;        /* steps taken since rmhdlb_init_fields */
 } rmhdlb_diag;
+
+/* Prescribed fields of a driven face: nx*ny DEVICE values each, x fastest. */
+typedef struct {
+    const double *n, *p;
+    const double *u[3], *B[3];
+} rmhdlb_face_in;
 
 typedef struct rmhdlb_ctx rmhdlb_ctx; /* opaque, owned by the library */
 
@@ -133,6 +158,18 @@ int rmhdlb_step(rmhdlb_ctx *ctx, int64_t nsteps);
  * NaN; diag->n_failed counts them). */
 int rmhdlb_moments(rmhdlb_ctx *ctx, rmhdlb_fields_out *out, rmhdlb_diag *diag);
 
+/* Driven low-z face (bc_lo[2] = RMHDLB_BC_DRIVEN): set the fields whose
+ * relaxed state fills the two ghost planes below z = 0.  Each ghost cell
+ * holds f_eq and g_eq of (n, p, u, E = -u x B, B) and h* = h_eq of (J, E +
+ * (dt/2) mu0 c^2 J, B) with J of Eq. Ohm at zero charge, and E_prev = E;
+ * the step never writes them.  rmhdlb_init_fields fills them from the
+ * z = 0 plane of its fields; call this afterwards to prescribe others (the
+ * state and the step counter are kept).  Returns RMHDLB_EINVAL, with the
+ * ghost planes unchanged, for a context without a driven face, NULL
+ * pointers, or any face cell with |u| >= c, n <= 0 or p < 0 (checked on the
+ * device; this call synchronises the stream). */
+int rmhdlb_set_driven_face(rmhdlb_ctx *ctx, const rmhdlb_face_in *face);
+
 /* Release the context and its device memory.  NULL is accepted. */
 int rmhdlb_destroy(rmhdlb_ctx *ctx);
 
@@ -146,6 +183,8 @@ int64_t rmhdlb_state_len(const rmhdlb_ctx *ctx);
 /* Copy the raw state to / from a DEVICE buffer of rmhdlb_state_len FP64
  * values in the layout above (checkpoint and restart; FP32 storage is
  * widened or rounded).  Synchronise the stream. */
+/* The ghost planes of a driven face are configuration, not state: they
+ * come from rmhdlb_init_fields / rmhdlb_set_driven_face and are not copied. */
 int rmhdlb_get_state(rmhdlb_ctx *ctx, double *dst);
 int rmhdlb_set_state(rmhdlb_ctx *ctx, const double *src);
 

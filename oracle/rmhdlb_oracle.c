@@ -487,12 +487,18 @@ static double axis_derivative(const orc_ctx *C, const double *X, int axis, int x
 
 /* Reading R22 (the divergence-free adjustment on open faces, Sec. IV, KH
  * set-up): in a cell on an open face of axis a (with at least two cells
- * along a), the normal component of B is replaced by the value that makes
- * the discrete divergence zero there, using the streamed B of the inner
- * neighbour and the tangential derivatives of the streamed B:
+ * along a) and on no face of another non-periodic axis, the normal
+ * component of B is replaced by the value that makes the discrete
+ * divergence zero there, using the streamed B of the inner neighbour and the
+ * tangential derivatives of the streamed B:
  *   low face:  B_a(x) = B_a(x + e_a) + dx sum_{b != a} d_b B_b
  *   high face: B_a(x) = B_a(x - e_a) - dx sum_{b != a} d_b B_b.
- * Every other component (and every interior cell) keeps the streamed value.
+ * Every other component (and every interior, edge or corner cell) keeps the
+ * streamed value.  The adjusted B is the cell's B in the fluid coupling
+ * (recovery, Ohm's law, f_eq); the Maxwell populations relax towards h_eq of
+ * the streamed B (see collision_pass).  Edge cells are left alone because
+ * their two adjustments assume each other's unadjusted value; with them the
+ * fields grew at the corners of a box open on every face.
  * Fills B with the cell's B for this step. */
 static void divb_fixed_B(const orc_ctx *C, int x, int y, int z, double B[3])
 {
@@ -508,6 +514,11 @@ static void divb_fixed_B(const orc_ctx *C, int x, int y, int z, double B[3])
         const int low = pos[a] == 0 && P->bc_lo[a] == BC_OPEN;
         const int high = pos[a] == n - 1 && P->bc_hi[a] == BC_OPEN;
         if (!low && !high) continue;
+        int edge = 0;
+        for (int b = 0; b < 3; b++)
+            if (b != a && dims[b] >= 2 && P->bc_lo[b] != BC_PERIODIC && (pos[b] == 0 || pos[b] == dims[b] - 1))
+                edge = 1;
+        if (edge) continue;
         double dt_sum = 0.0;
         for (int b = 0; b < 3; b++)
             if (b != a) dt_sum += axis_derivative(C, C->Bt + (long)b * N, b, x, y, z);
@@ -686,7 +697,13 @@ static void collision_pass(orc_ctx *C)
                 for (int a = 0; a < 3; a++) Eprev[a] = C->Ep[C->cur][(long)a * N + id];
                 f_equilibrium(C, m->eps, m->p, m->beta, Eprev, m->B, feq);
                 g_equilibrium(C, m->n, m->beta, geq);
-                h_equilibrium(C, m->J, m->E, m->B, m->rhoc, heq);
+                /* Reading R22: the Maxwell populations relax towards h_eq of the
+                 * streamed B.  With tau_h = 1/2 the collision reflects h about h_eq,
+                 * so an adjusted B in h_eq would enter the populations twice over
+                 * each step; that feedback made open boxes unstable (measured). */
+                double Bstream[3];
+                for (int a = 0; a < 3; a++) Bstream[a] = C->Bt[(long)a * N + id];
+                h_equilibrium(C, m->J, m->E, Bstream, m->rhoc, heq);
                 /* chi^mu = gamma nu (1, beta) */
                 double chi[4] = {m->gam * L->nu, m->gam * L->nu * m->beta[0], m->gam * L->nu * m->beta[1],
                                  m->gam * L->nu * m->beta[2]};

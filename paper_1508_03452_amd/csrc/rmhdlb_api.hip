@@ -7,12 +7,16 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 #include "rmhdlb.h"
 #include "rmhdlb_internal.h"
 
 using rmhd::Consts;
+
+// Reduced diagnostics: NPART sums, max |div B|, R, null cell, B0.
+constexpr int RESULT_LEN = rmhd::NPART + 4;
 
 struct rmhdlb_ctx {
     rmhdlb_params P;
@@ -22,10 +26,14 @@ struct rmhdlb_ctx {
     void* buf[2];      // state buffers (distributions, then E_prev)
     rmhd::StateBuf sb[2];
     int cur;
-    double* scratch;   // 6 N doubles: initial J0 and E'0, then B of the moments pass
+    double* scratch;   // 6 N doubles: initial J0 and E'0, then B and E^z of the moments pass
     double* part;      // per-tile partial diagnostics
     double* part2;     // per-tile max |div B|
-    double* result;    // NPART + 1 reduced values
+    double* nullp;     // per-tile null-point candidates (key, cell)
+    double* faceB;     // adjusted normal B of the open-face cells
+    double* ez0;       // initial E^z (reconnection rate)
+    double* aux;       // aux[0] = max |B| of the initial fields
+    double* result;    // NPART sums, max |div B|, R, null cell, B0
     int64_t step;
     rmhd::StepTuning tune;
 };
@@ -44,21 +52,26 @@ int validate(const rmhdlb_params* P) {
     const int64_t N = (int64_t)P->nx * P->ny * P->nz;
     if (N > 2147483647LL / 2) return RMHDLB_EINVAL;  // cell indices are 32-bit
     for (int a = 0; a < 3; ++a) {
-        if ((P->bc_lo[a] != RMHDLB_BC_PERIODIC && P->bc_lo[a] != RMHDLB_BC_OPEN) ||
-            (P->bc_hi[a] != RMHDLB_BC_PERIODIC && P->bc_hi[a] != RMHDLB_BC_OPEN))
-            return RMHDLB_EINVAL;
+        const bool lo_ok = P->bc_lo[a] == RMHDLB_BC_PERIODIC || P->bc_lo[a] == RMHDLB_BC_OPEN ||
+                           (a == 2 && P->bc_lo[a] == RMHDLB_BC_DRIVEN);
+        if (!lo_ok || (P->bc_hi[a] != RMHDLB_BC_PERIODIC && P->bc_hi[a] != RMHDLB_BC_OPEN)) return RMHDLB_EINVAL;
         if ((P->bc_lo[a] == RMHDLB_BC_PERIODIC) != (P->bc_hi[a] == RMHDLB_BC_PERIODIC)) return RMHDLB_EINVAL;
     }
+    if (P->divb_fix != 0 && P->divb_fix != 1) return RMHDLB_EINVAL;
     if (!(P->dx > 0) || !(P->c > 0) || !(P->mu0 > 0) || !(P->tau > 0) || !(P->alpha >= 0) || !(P->Gamma > 1) ||
         !(P->sigma >= 0) || !(P->nu > 0) || !isfinite(P->sigma) || !isfinite(P->alpha))
         return RMHDLB_EINVAL;
     if (P->storage != RMHDLB_STORE_F64 && P->storage != RMHDLB_STORE_F32 && P->storage != RMHDLB_STORE_F16)
         return RMHDLB_EINVAL;
-    for (int k = 0; k < 7; ++k)
+    for (int k = 0; k < 5; ++k)
         if (P->reserved[k] != 0) return RMHDLB_EINVAL;
     if (P->tau_h != 0.5) return RMHDLB_EUNSUPPORTED;  // the force form of Eq. Ex_force needs tau_h = 1/2
     return RMHDLB_OK;
 }
+
+// Elements in front of cell 0 of every state array: the two ghost planes of
+// a driven low-z face, rounded up so that cell 0 stays 64-element aligned.
+int64_t ghost_cells(const Consts& K) { return K.drv ? ((int64_t)2 * K.nx * K.ny + 63) / 64 * 64 : 0; }
 
 Consts make_consts(const rmhdlb_params* P) {
     Consts K;
@@ -67,8 +80,21 @@ Consts make_consts(const rmhdlb_params* P) {
     K.ny = P->ny;
     K.nz = P->nz;
     for (int a = 0; a < 3; ++a) K.per[a] = P->bc_lo[a] == RMHDLB_BC_PERIODIC ? 1 : 0;
+    K.drv = P->bc_lo[2] == RMHDLB_BC_DRIVEN;
+    const int dims[3] = {P->nx, P->ny, P->nz};
+    int any_open = 0;
+    for (int a = 0; a < 3; ++a) {
+        K.open_lo[a] = P->divb_fix && dims[a] >= 2 && P->bc_lo[a] == RMHDLB_BC_OPEN;
+        K.open_hi[a] = P->divb_fix && dims[a] >= 2 && P->bc_hi[a] == RMHDLB_BC_OPEN;
+        any_open |= K.open_lo[a] | K.open_hi[a];
+    }
+    K.divb = any_open;
+    K.band = P->null_band >= 1 ? P->null_band : 64;
+    const int64_t fsz[3] = {(int64_t)P->ny * P->nz, (int64_t)P->nx * P->nz, (int64_t)P->nx * P->ny};
+    K.fo[0] = 0;
+    for (int f = 0; f < 6; ++f) K.fo[f + 1] = K.fo[f] + fsz[f >> 1];
     K.N = (int64_t)P->nx * P->ny * P->nz;
-    K.stride = (K.N + 63) / 64 * 64;
+    K.stride = (ghost_cells(K) + K.N + 63) / 64 * 64;
     const double dt = P->dx / (sqrt(2.0) * P->c);  // dx / dt = sqrt(2) c
     K.c = P->c;
     K.dx = P->dx;
@@ -126,6 +152,10 @@ void release(rmhdlb_ctx* C) {
     if (C->scratch) (void)hipFree(C->scratch);
     if (C->part) (void)hipFree(C->part);
     if (C->part2) (void)hipFree(C->part2);
+    if (C->nullp) (void)hipFree(C->nullp);
+    if (C->faceB) (void)hipFree(C->faceB);
+    if (C->ez0) (void)hipFree(C->ez0);
+    if (C->aux) (void)hipFree(C->aux);
     if (C->result) (void)hipFree(C->result);
     delete C;
 }
@@ -161,18 +191,24 @@ int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** ou
     const int nt = rmhd::num_tiles(C->K);
     const size_t nred = (size_t)((C->K.N + 255) / 256);  // blocks of the init-reference reduction
     bool ok = true;
+    const int64_t g0 = ghost_cells(C->K);
     for (int b = 0; b < 2 && ok; ++b) {
-        ok = hipMalloc(&C->buf[b], bytes) == hipSuccess;
+        // zeroed once so that ghost planes and padding hold defined values
+        ok = hipMalloc(&C->buf[b], bytes) == hipSuccess && hipMemset(C->buf[b], 0, bytes) == hipSuccess;
         if (ok) {
-            C->sb[b].dist = C->buf[b];
-            C->sb[b].efield = (char*)C->buf[b] + efield_offset(C->storage, C->K.stride);
+            C->sb[b].dist = (char*)C->buf[b] + g0 * dist_elem(C->storage);
+            C->sb[b].efield = (char*)C->buf[b] + efield_offset(C->storage, C->K.stride) + g0 * efield_elem(C->storage);
         }
     }
+    const size_t npart = std::max(std::max((size_t)rmhd::NPART * nt, 2 * nred), (size_t)C->K.nx * C->K.ny);
     ok = ok && hipMalloc((void**)&C->scratch, sizeof(double) * 6 * (size_t)C->K.N) == hipSuccess;
-    ok = ok && hipMalloc((void**)&C->part, sizeof(double) * (size_t)(rmhd::NPART * (size_t)nt > 2 * nred
-                                                                       ? rmhd::NPART * (size_t)nt : 2 * nred)) == hipSuccess;
-    ok = ok && hipMalloc((void**)&C->part2, sizeof(double) * (size_t)nt) == hipSuccess;
-    ok = ok && hipMalloc((void**)&C->result, sizeof(double) * (rmhd::NPART + 1)) == hipSuccess;
+    ok = ok && hipMalloc((void**)&C->part, sizeof(double) * npart) == hipSuccess;
+    ok = ok && hipMalloc((void**)&C->part2, sizeof(double) * std::max((size_t)nt, nred)) == hipSuccess;
+    ok = ok && hipMalloc((void**)&C->nullp, sizeof(double) * 2 * (size_t)nt) == hipSuccess;
+    ok = ok && hipMalloc((void**)&C->faceB, sizeof(double) * (size_t)std::max<int64_t>(C->K.fo[6], 1)) == hipSuccess;
+    ok = ok && hipMalloc((void**)&C->ez0, sizeof(double) * (size_t)C->K.N) == hipSuccess;
+    ok = ok && hipMalloc((void**)&C->aux, sizeof(double) * 4) == hipSuccess;
+    ok = ok && hipMalloc((void**)&C->result, sizeof(double) * RESULT_LEN) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         release(C);
@@ -223,14 +259,53 @@ int rmhdlb_init_fields(rmhdlb_ctx* C, const rmhdlb_fields_in* in) {
     }
     hipError_t e = RMHD_DISPATCH(C, launch_init)(ip, C->K, C->scratch, C->sb[0], C->stream);
     if (e != hipSuccess) return RMHDLB_EDEVICE;
+    // references of the reconnection rate: E^z_0 and B0 = max |B|
+    if (hipMemcpyAsync(C->ez0, in->E[2], sizeof(double) * (size_t)C->K.N, hipMemcpyDeviceToDevice, C->stream) !=
+            hipSuccess ||
+        rmhd::launch_init_bmax(ip, C->K, C->part2, C->aux, C->stream) != hipSuccess)
+        return RMHDLB_EDEVICE;
+    // a driven face starts from the fields of the first interior plane
+    if (C->K.drv) {
+        rmhd::FacePtrs fp;
+        fp.n = in->n;
+        fp.p = in->p;
+        for (int a = 0; a < 3; ++a) {
+            fp.u[a] = in->u[a];
+            fp.B[a] = in->B[a];
+        }
+        for (int b = 0; b < 2; ++b)
+            if (RMHD_DISPATCH(C, launch_ghost)(fp, C->K, C->sb[b], C->stream) != hipSuccess) return RMHDLB_EDEVICE;
+    }
     C->step = 0;
+    return RMHDLB_OK;
+}
+
+int rmhdlb_set_driven_face(rmhdlb_ctx* C, const rmhdlb_face_in* face) {
+    if (!C || !face || !face->n || !face->p || !C->K.drv) return RMHDLB_EINVAL;
+    rmhd::FacePtrs fp;
+    fp.n = face->n;
+    fp.p = face->p;
+    for (int a = 0; a < 3; ++a) {
+        if (!face->u[a] || !face->B[a]) return RMHDLB_EINVAL;
+        fp.u[a] = face->u[a];
+        fp.B[a] = face->B[a];
+    }
+    double bad = 0.0;
+    if (rmhd::launch_face_check(fp, C->K, C->part, C->result, C->stream) != hipSuccess ||
+        hipMemcpyAsync(&bad, C->result, sizeof(double), hipMemcpyDeviceToHost, C->stream) != hipSuccess ||
+        hipStreamSynchronize(C->stream) != hipSuccess)
+        return RMHDLB_EDEVICE;
+    if (bad != 0.0) return RMHDLB_EINVAL;
+    for (int b = 0; b < 2; ++b)
+        if (RMHD_DISPATCH(C, launch_ghost)(fp, C->K, C->sb[b], C->stream) != hipSuccess) return RMHDLB_EDEVICE;
     return RMHDLB_OK;
 }
 
 int rmhdlb_step(rmhdlb_ctx* C, int64_t nsteps) {
     if (!C || nsteps < 0) return RMHDLB_EINVAL;
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = RMHD_DISPATCH(C, launch_step)(C->sb[C->cur], C->sb[1 - C->cur], C->K, C->tune, C->stream);
+        hipError_t e =
+            RMHD_DISPATCH(C, launch_step)(C->sb[C->cur], C->sb[1 - C->cur], C->K, C->tune, C->faceB, C->stream);
         if (e != hipSuccess) return RMHDLB_EDEVICE;
         C->cur = 1 - C->cur;
         C->step++;
@@ -254,10 +329,18 @@ int rmhdlb_moments(rmhdlb_ctx* C, rmhdlb_fields_out* out, rmhdlb_diag* diag) {
         }
         op.rho_c = out->rho_c;
     }
-    hipError_t e = RMHD_DISPATCH(C, launch_moments)(C->sb[C->cur], C->K, op, C->scratch, C->part, C->part2,
-                                                    C->result, C->stream);
+    rmhd::DiagBufs D;
+    D.faceB = C->faceB;
+    D.scratch = C->scratch;
+    D.part = C->part;
+    D.part2 = C->part2;
+    D.nullp = C->nullp;
+    D.ez0 = C->ez0;
+    D.b0 = C->aux;
+    D.result = C->result;
+    hipError_t e = RMHD_DISPATCH(C, launch_moments)(C->sb[C->cur], C->K, op, D, C->stream);
     if (e != hipSuccess) return RMHDLB_EDEVICE;
-    double r[rmhd::NPART + 1];
+    double r[RESULT_LEN];
     if (hipMemcpyAsync(r, C->result, sizeof(r), hipMemcpyDeviceToHost, C->stream) != hipSuccess)
         return RMHDLB_EDEVICE;
     if (hipStreamSynchronize(C->stream) != hipSuccess) return RMHDLB_EDEVICE;
@@ -271,8 +354,12 @@ int rmhdlb_moments(rmhdlb_ctx* C, rmhdlb_fields_out* out, rmhdlb_diag* diag) {
         diag->em_energy = r[5];
         diag->charge = r[6];
         diag->mean_iters = r[7] / (double)C->K.N;
+        for (int k = 0; k < 16; ++k) diag->newton_hist[k] = (int64_t)llround(r[9 + k]);
         diag->n_failed = failed;
         diag->max_divB = r[rmhd::NPART];
+        diag->recon_rate = r[rmhd::NPART + 1];
+        diag->null_index = (int64_t)llround(r[rmhd::NPART + 2]);
+        diag->B0 = r[rmhd::NPART + 3];
         diag->step = C->step;
     }
     return failed ? RMHDLB_ERECOVERY : RMHDLB_OK;

@@ -52,9 +52,14 @@ constexpr int OFF_F = 0, OFF_G = Q, OFF_H = 2 * Q, OFF_E = 2 * Q + QH + 1;
 
 struct Consts {
     int nx, ny, nz;
-    int per[3];          // 1 = periodic axis, 0 = open
+    int per[3];          // 1 = periodic axis, 0 = open or driven
+    int drv;             // 1: driven low z face, ghost planes z = -1, -2 stored below the interior
+    int divb;            // 1: the normal B of open-face cells is adjusted so that div B = 0 there
+    int open_lo[3], open_hi[3];  // face takes the div B adjustment (open, with at least 2 cells on the axis)
+    int band;            // half-width in rows of the reconnection null search band
+    int64_t fo[7];       // offsets of the six face arrays of adjusted normal B (x lo, x hi, y lo, ...), fo[6] = total
     int64_t N;           // cells
-    int64_t stride;      // values per state array (N rounded up)
+    int64_t stride;      // values per state array (ghost planes + N, rounded up)
     double c, dx, eps0;
     double cour;         // Courant number along a link: kappa c dt / dx
     double kv;           // bulk-viscosity coefficient alpha c dt / dx

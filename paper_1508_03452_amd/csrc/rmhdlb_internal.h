@@ -9,13 +9,19 @@
 
 namespace rmhd {
 
-constexpr int NPART = 9;  // partial diagnostics per block (see k_moments)
+constexpr int NPART = 25;  // partial diagnostic sums per block: 9 (see k_moments) + 16 Newton bins
 constexpr int RED_WAVES = 4;
 
 struct InPtrs {
     const double *n, *p;
     const double *u[3], *E[3], *B[3];
     const double* rho_c;
+};
+
+// Prescribed fields of a driven face (nx * ny values each).
+struct FacePtrs {
+    const double *n, *p;
+    const double *u[3], *B[3];
 };
 
 struct OutPtrs {
@@ -121,12 +127,28 @@ struct StoreTypes<_Float16> {
     using V = float;
 };
 
+// Device buffers of the diagnostics pass.
+struct DiagBufs {
+    double* faceB;    // adjusted normal B of the open-face cells (Consts::fo layout)
+    double* scratch;  // 4 N: B of every cell, then E^z
+    double* part;     // NPART per tile
+    double* part2;    // max |div B| per tile
+    double* nullp;    // (key, cell) per tile
+    const double* ez0;  // initial E^z
+    const double* b0;   // max |B| of the initial fields
+    double* result;   // NPART sums, max |div B|, R, null cell, B0
+};
+
 template <typename TS>
 hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K, const StepTuning& tune,
-                       hipStream_t s);
+                       double* faceB, hipStream_t s);
 template <typename TS>
-hipError_t launch_moments(const StateBuf& src, const Consts& K, const OutPtrs& out, double* Bscr, double* part,
-                          double* part2, double* result, hipStream_t s);
+hipError_t launch_moments(const StateBuf& src, const Consts& K, const OutPtrs& out, const DiagBufs& D,
+                          hipStream_t s);
+hipError_t launch_init_bmax(const InPtrs& in, const Consts& K, double* part, double* b0, hipStream_t s);
+hipError_t launch_face_check(const FacePtrs& in, const Consts& K, double* part, double* result, hipStream_t s);
+template <typename TS>
+hipError_t launch_ghost(const FacePtrs& in, const Consts& K, const StateBuf& dst, hipStream_t s);
 hipError_t launch_init_ref(const InPtrs& in, const Consts& K, double* part, double* result, hipStream_t s);
 template <typename TS>
 hipError_t launch_init(const InPtrs& in, const Consts& K, double* scr, const StateBuf& dst, hipStream_t s);

@@ -41,9 +41,10 @@ __device__ __forceinline__ double fshift(const Consts& K, int i) { return K.fsh[
 __device__ __forceinline__ double gshift(const Consts& K, int i) { return K.gsh[i == 0 ? 0 : (i <= 6 ? 1 : 2)]; }
 
 // Neighbour offsets of one cell along one axis for displacements -2..+2,
-// with periodic wrap or (open face) a copy of the first interior cell.
-__device__ __forceinline__ int map_coord(int v, int n, int periodic) {
-    if (v < 0) return periodic ? (v + n >= 0 ? v + n : v + 2 * n) : 0;
+// with periodic wrap or (open face) a copy of the first interior cell; with
+// keep_low the coordinates -1, -2 stay (the ghost planes of a driven face).
+__device__ __forceinline__ int map_coord(int v, int n, int periodic, int keep_low) {
+    if (v < 0) return periodic ? (v + n >= 0 ? v + n : v + 2 * n) : (keep_low ? v : 0);
     if (v >= n) return periodic ? (v - n < n ? v - n : v - 2 * n) : n - 1;
     return v;
 }
@@ -53,16 +54,67 @@ struct Nbr {
     __device__ __forceinline__ int at(int dx, int dy, int dz) const { return ox[dx + 2] + oy[dy + 2] + oz[dz + 2]; }
 };
 
+// STATE: offsets into the state arrays, which hold the ghost planes of a
+// driven face below z = 0; otherwise offsets into plain N-cell field arrays
+// (a driven face then acts as open).
+template <bool STATE>
 __device__ __forceinline__ Nbr make_nbr(const Consts& K, int x, int y, int z) {
     Nbr n;
     const int sy = K.nx, sz = K.nx * K.ny;
 #pragma unroll
     for (int d = -2; d <= 2; ++d) {
-        n.ox[d + 2] = map_coord(x + d, K.nx, K.per[0]) - x;
-        n.oy[d + 2] = (map_coord(y + d, K.ny, K.per[1]) - y) * sy;
-        n.oz[d + 2] = (map_coord(z + d, K.nz, K.per[2]) - z) * sz;
+        n.ox[d + 2] = map_coord(x + d, K.nx, K.per[0], 0) - x;
+        n.oy[d + 2] = (map_coord(y + d, K.ny, K.per[1], 0) - y) * sy;
+        n.oz[d + 2] = (map_coord(z + d, K.nz, K.per[2], STATE ? K.drv : 0) - z) * sz;
     }
     return n;
+}
+
+// Derivative along `axis` of a quantity X(x, y, z) at a cell: central
+// differences (periodic wrap on periodic axes), one-sided towards the
+// interior on the faces of a non-periodic axis, zero on an axis of one cell.
+// The divergence operator of the normal-B adjustment and of max |div B|.
+template <typename Fn>
+__device__ __forceinline__ double axis_derivative(const Consts& K, int axis, int x, int y, int z, Fn&& X) {
+    const int n = axis == 0 ? K.nx : (axis == 1 ? K.ny : K.nz);
+    const int v = axis == 0 ? x : (axis == 1 ? y : z);
+    const int ex = axis == 0, ey = axis == 1, ez = axis == 2;
+    if (n == 1) return 0.0;
+    if (!K.per[axis] && v == 0) return (X(x + ex, y + ey, z + ez) - X(x, y, z)) / K.dx;
+    if (!K.per[axis] && v == n - 1) return (X(x, y, z) - X(x - ex, y - ey, z - ez)) / K.dx;
+    const int wp = map_coord(v + 1, n, K.per[axis], 0) - v, wm = map_coord(v - 1, n, K.per[axis], 0) - v;
+    return (X(x + ex * wp, y + ey * wp, z + ez * wp) - X(x + ex * wm, y + ey * wm, z + ez * wm)) / (2.0 * K.dx);
+}
+
+// Index of a face cell in the adjusted-normal-B arrays (face f = 2 axis + high).
+__device__ __forceinline__ int64_t face_slot(const Consts& K, int f, int x, int y, int z) {
+    const int a = f >> 1;
+    const int64_t j = a == 0 ? y + (int64_t)K.ny * z : (a == 1 ? x + (int64_t)K.nx * z : x + (int64_t)K.nx * y);
+    return K.fo[f] + j;
+}
+
+// Whether a cell lies on a face of a non-periodic axis other than `a` (an
+// edge or corner cell when it also lies on a face of `a`).
+__device__ __forceinline__ bool on_other_face(const Consts& K, int a, int x, int y, int z) {
+    const int pos[3] = {x, y, z}, dims[3] = {K.nx, K.ny, K.nz};
+    bool e = false;
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+        if (b != a && dims[b] >= 2 && !K.per[b] && (pos[b] == 0 || pos[b] == dims[b] - 1)) e = true;
+    return e;
+}
+
+// Normal-B adjustment of an open-face cell (Sec. IV, KH set-up): on a face
+// cell that is not an edge or corner cell, replace the normal component by
+// the value the face pass computed.
+__device__ __forceinline__ void apply_face_b(const Consts& K, const double* __restrict__ faceB, int x, int y, int z,
+                                             double B[3]) {
+    const int pos[3] = {x, y, z}, dims[3] = {K.nx, K.ny, K.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool lo = pos[a] == 0 && K.open_lo[a], hi = pos[a] == dims[a] - 1 && K.open_hi[a];
+        if ((lo || hi) && !on_other_face(K, a, x, y, z)) B[a] = faceB[face_slot(K, lo ? 2 * a : 2 * a + 1, x, y, z)];
+    }
 }
 
 // Tile index with XCD-aware placement: block b runs on XCD b % 8, so XCD k is
@@ -156,8 +208,9 @@ __device__ __forceinline__ void solve_cell(const Consts& K, CellSol& M) {
 // shift of a stored array is constant in space, so it transports to itself
 // and is added back after the transport.
 template <typename TS, typename TE>
-__device__ __forceinline__ void macroscopic(const TS* __restrict__ src, const TE* __restrict__ esrc, const Consts& K,
-                                            int cell, const Nbr& nb, Macro& M) {
+__device__ __forceinline__ void macroscopic(const TS* __restrict__ src, const TE* __restrict__ esrc,
+                                            const double* __restrict__ faceB, const Consts& K, int cell,
+                                            const Nbr& nb, int x, int y, int z, Macro& M) {
     M.T00 = 0.0;
     M.N0 = 0.0;
     double t0x = 0, t0y = 0, t0z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
@@ -248,6 +301,7 @@ __device__ __forceinline__ void macroscopic(const TS* __restrict__ src, const TE
               ((ld(e0, nb.at(1, 0, 0)) - ld(e0, nb.at(-1, 0, 0))) + (ld(e1, nb.at(0, 1, 0)) - ld(e1, nb.at(0, -1, 0))) +
                (ld(e2, nb.at(0, 0, 1)) - ld(e2, nb.at(0, 0, -1))));
 
+    if (K.divb) apply_face_b(K, faceB, x, y, z, M.B);
     solve_cell(K, M);
 }
 
@@ -370,7 +424,8 @@ __device__ __forceinline__ V pair_sum(V v) {
 
 template <bool NT, typename TS, typename TE, typename V>
 __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* __restrict__ se, TS* __restrict__ dd,
-                                          TE* __restrict__ de, const Consts& K, int cell, const Nbr& nb, int h) {
+                                          TE* __restrict__ de, const double* __restrict__ faceB, const Consts& K,
+                                          int cell, const Nbr& nb, int h, int x, int y, int z) {
     const V sgn = h ? V(-1) : V(1);
     const int64_t S = K.stride;
     // Array bases stay uniform (scalar registers); the lane's choice between
@@ -479,8 +534,20 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
     M.B[0] = (double)pair_sum(bx);
     M.B[1] = (double)pair_sum(by);
     M.B[2] = (double)pair_sum(bz);
+    // The Maxwell populations relax towards h_eq of the streamed B (an
+    // adjusted face B enters only the fluid coupling): take its B part,
+    // B . b_k / 8, into h* = 2 h_eq - h now, while the streamed B is at hand.
+    {
+        const V sb0 = (V)M.B[0], sb1 = (V)M.B[1], sb2 = (V)M.B[2];
+#pragma unroll
+        for (int m = 0; m < 12; ++m) {
+            const int k0 = 2 * m;
+            Hv[m] -= V(0.25) * sgn * (BHX[k0] * sb0 + BHY[k0] * sb1 + BHZ[k0] * sb2);
+        }
+    }
     M.rho = (double)pair_sum(Hv[12] + hs);
     M.rho_g = K.eps0 * K.inv_2dx * pair_sum(gpart);
+    if (K.divb) apply_face_b(K, faceB, x, y, z, M.B);
     solve_cell(K, M);
 
     // collisions and stores (new deviations)
@@ -516,13 +583,10 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
     const V cj = (V)(1.0 / (16.0 * 1.4142135623730951 * K.c)), ce = (V)(1.0 / (8.0 * 1.4142135623730951 * K.c));
     const V J0 = (V)M.J[0], J1 = (V)M.J[1], J2 = (V)M.J[2];
     const V E0 = (V)M.E[0], E1 = (V)M.E[1], E2 = (V)M.E[2];
-    const V B0 = (V)M.B[0], B1 = (V)M.B[1], B2 = (V)M.B[2];
 #pragma unroll
     for (int m = 0; m < 12; ++m) {
         const int k0 = 2 * m;
-        const V heq = cj * (SX[k0] * J0 + SY[k0] * J1 + SZ[k0] * J2) +
-                      sgn * (ce * (EHX[k0] * E0 + EHY[k0] * E1 + EHZ[k0] * E2) +
-                             V(0.125) * (BHX[k0] * B0 + BHY[k0] * B1 + BHZ[k0] * B2));
+        const V heq = cj * (SX[k0] * J0 + SY[k0] * J1 + SZ[k0] * J2) + sgn * ce * (EHX[k0] * E0 + EHY[k0] * E1 + EHZ[k0] * E2);
         st<NT>(dd + (int64_t)(OFF_H + k0) * S + hc, V(2) * heq - Hv[m]);
     }
     if (h == 0) {
@@ -541,7 +605,8 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
 // that XCD's L2.
 template <bool NT, typename TS, typename TE, typename V>
 __global__ __launch_bounds__(PTPB, RMHDLB_WAVES) void k_fused_step(const TS* __restrict__ sd, const TE* __restrict__ se,
-                                                        TS* __restrict__ dd, TE* __restrict__ de, Consts K,
+                                                        TS* __restrict__ dd, TE* __restrict__ de,
+                                                        const double* __restrict__ faceB, Consts K,
                                                         int tiles_x, int ncol, int zb, int nblk) {
     const int b = tile_of_block(nblk);
     if (b >= nblk) return;
@@ -553,28 +618,117 @@ __global__ __launch_bounds__(PTPB, RMHDLB_WAVES) void k_fused_step(const TS* __r
     const int z0 = zc * zb, z1 = min(K.nz, z0 + zb);
     for (int z = z0; z < z1; ++z) {
         const int cell = x + K.nx * (y + K.ny * z);
-        const Nbr nb = make_nbr(K, x, y, z);
-        pair_cell<NT, TS, TE, V>(sd, se, dd, de, K, cell, nb, h);
+        const Nbr nb = make_nbr<true>(K, x, y, z);
+        pair_cell<NT, TS, TE, V>(sd, se, dd, de, faceB, K, cell, nb, h, x, y, z);
     }
 }
 
+// B of Eq. Cal_B at a cell from the streamed h (population order, FP64).
+template <typename TS>
+__device__ __forceinline__ double streamed_B(const TS* __restrict__ src, const Consts& K, int comp, int x, int y,
+                                             int z) {
+    const Nbr nb = make_nbr<true>(K, x, y, z);
+    const int cell = x + K.nx * (y + K.ny * z);
+    double b = 0.0;
+#pragma unroll
+    for (int k = 0; k < QH; ++k) {
+        const int bk = comp == 0 ? BHX[k] : (comp == 1 ? BHY[k] : BHZ[k]);
+        if (bk) b += bk * ld(src + (int64_t)(OFF_H + k) * K.stride + cell, nb.at(-SX[k], -SY[k], -SZ[k]));
+    }
+    return b;
+}
+
+// Normal B of the open-face cells for this step (Sec. IV, KH set-up): in a
+// cell on an open face of axis a (not an edge or corner cell) the discrete
+// divergence is made zero with
+// the streamed B of the inner neighbour and the tangential derivatives of
+// the streamed B:  low face  B_a = B_a(x + e_a) + dx sum_{b != a} d_b B_b,
+//                  high face B_a = B_a(x - e_a) - dx sum_{b != a} d_b B_b.
+// One thread per face cell over the six faces; inactive faces return.
+template <typename TS>
+__global__ __launch_bounds__(256) void k_face_b(const TS* __restrict__ src, Consts K, double* __restrict__ faceB) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= K.fo[6]) return;
+    int f = 0;
+    while (f < 5 && i >= K.fo[f + 1]) ++f;
+    const int a = f >> 1, high = f & 1;
+    if (!(high ? K.open_hi[a] : K.open_lo[a])) return;
+    const int64_t j = i - K.fo[f];
+    int x, y, z;
+    if (a == 0) {
+        y = (int)(j % K.ny);
+        z = (int)(j / K.ny);
+        x = high ? K.nx - 1 : 0;
+    } else if (a == 1) {
+        x = (int)(j % K.nx);
+        z = (int)(j / K.nx);
+        y = high ? K.ny - 1 : 0;
+    } else {
+        x = (int)(j % K.nx);
+        y = (int)(j / K.nx);
+        z = high ? K.nz - 1 : 0;
+    }
+    if (on_other_face(K, a, x, y, z)) return;  // edge and corner cells keep the streamed B
+    double dsum = 0.0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+        if (b != a)
+            dsum += axis_derivative(K, b, x, y, z, [&](int xx, int yy, int zz) { return streamed_B(src, K, b, xx, yy, zz); });
+    const int s = high ? -1 : 1;
+    const double inner = streamed_B(src, K, a, x + s * (a == 0), y + s * (a == 1), z + s * (a == 2));
+    faceB[i] = high ? inner - K.dx * dsum : inner + K.dx * dsum;
+}
+
+// Deterministic (key, index) minimum, ties to the lower index; NaN keys never win.
+__device__ __forceinline__ void argmin_merge(double& k, double& i, double k2, double i2) {
+    if (k2 < k || (k2 == k && i2 < i)) {
+        k = k2;
+        i = i2;
+    }
+}
+
+__device__ __forceinline__ void block_argmin(double k, double i, double* __restrict__ out) {
+    __shared__ double shk[RED_WAVES], shi[RED_WAVES];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) argmin_merge(k, i, __shfl_xor(k, o, 64), __shfl_xor(i, o, 64));
+    if (lane == 0) {
+        shk[wave] = k;
+        shi[wave] = i;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double bk = shk[0], bi = shi[0];
+        for (int w = 1; w < RED_WAVES; ++w) argmin_merge(bk, bi, shk[w], shi[w]);
+        out[0] = bk;
+        out[1] = bi;
+    }
+}
+
+constexpr double NO_INDEX = 9.0e15;  // larger than any cell index, exact in FP64
+
 // Primitives of the current state and per-block partial diagnostics:
-// part[blk * NPART + j], j = T00, N0, T0x, T0y, T0z, em energy, rho, iters, failed.
+// part[blk * NPART + j], j = T00, N0, T0x, T0y, T0z, em energy, rho, iters,
+// failed, then 16 Newton-iteration bins; null-search partials (least
+// B_x^2 + B_y^2 in the band and its cell) in nullp[2 blk ..]; B and E^z of
+// every cell into scratch (4 arrays of N).
 template <typename TS, typename TE>
-__global__ __launch_bounds__(TPB) void k_moments(const TS* __restrict__ src, const TE* __restrict__ esrc, Consts K,
-                                                 int tiles_x, int tiles_y, int ntiles, OutPtrs out,
-                                                 double* __restrict__ Bscratch, double* __restrict__ part) {
+__global__ __launch_bounds__(TPB) void k_moments(const TS* __restrict__ src, const TE* __restrict__ esrc,
+                                                 const double* __restrict__ faceB, Consts K, int tiles_x,
+                                                 int tiles_y, int ntiles, OutPtrs out, double* __restrict__ scratch,
+                                                 double* __restrict__ part, double* __restrict__ nullp) {
     const int tile = tile_of_block(ntiles);
     if (tile >= ntiles) return;
     const int tx = tile % tiles_x, rest = tile / tiles_x;
     const int ty = rest % tiles_y, z = rest / tiles_y;
     const int x = tx * TX + (threadIdx.x % TX), y = ty * TY + (threadIdx.x / TX);
     double v[NPART] = {0};
+    double key = __builtin_inf(), idx = NO_INDEX;
     if (x < K.nx && y < K.ny) {
         const int cell = x + K.nx * (y + K.ny * z);
-        const Nbr nb = make_nbr(K, x, y, z);
+        const Nbr nb = make_nbr<true>(K, x, y, z);
         Macro M;
-        macroscopic(src, esrc, K, cell, nb, M);
+        macroscopic(src, esrc, faceB, K, cell, nb, x, y, z, M);
         const double c = K.c;
         if (out.n) out.n[cell] = M.n;
         if (out.p) out.p[cell] = M.p;
@@ -585,8 +739,9 @@ __global__ __launch_bounds__(TPB) void k_moments(const TS* __restrict__ src, con
             if (out.E[a]) out.E[a][cell] = M.E[a];
             if (out.B[a]) out.B[a][cell] = M.B[a];
             if (out.J[a]) out.J[a][cell] = M.J[a];
-            Bscratch[(int64_t)a * K.N + cell] = M.B[a];
+            scratch[(int64_t)a * K.N + cell] = M.B[a];
         }
+        scratch[3 * K.N + cell] = M.E[2];
         if (out.rho_c) out.rho_c[cell] = M.rho;
         v[0] = M.T00;
         v[1] = M.N0;
@@ -599,11 +754,25 @@ __global__ __launch_bounds__(TPB) void k_moments(const TS* __restrict__ src, con
         v[6] = M.rho;
         v[7] = M.iters;
         v[8] = M.ok ? 0.0 : 1.0;
+        const int bin = M.iters < 15 ? (M.iters > 0 ? M.iters : 0) : 15;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[9 + k] = bin == k ? 1.0 : 0.0;
+        // |y_j| <= band with cell centres y_j = j + 1/2 - ny/2
+        const int dy = 2 * y + 1 - K.ny;
+        if ((dy < 0 ? -dy : dy) <= 2 * K.band) {
+            const double kb = fma(M.B[0], M.B[0], M.B[1] * M.B[1]);
+            if (kb == kb) {
+                key = kb;
+                idx = (double)cell;
+            }
+        }
     }
     block_sum<NPART>(v, part + (int64_t)tile * NPART);
+    block_argmin(key, idx, nullp + 2 * (int64_t)tile);
 }
 
-// max |div B| per block from the B field written by k_moments.
+// max |div B| per block from the B written by k_moments (the derivative
+// operator of the normal-B adjustment).
 __global__ __launch_bounds__(TPB) void k_divb(const double* __restrict__ Bs, Consts K, int tiles_x, int tiles_y,
                                               int ntiles, double* __restrict__ part) {
     const int tile = tile_of_block(ntiles);
@@ -613,17 +782,34 @@ __global__ __launch_bounds__(TPB) void k_divb(const double* __restrict__ Bs, Con
     const int x = tx * TX + (threadIdx.x % TX), y = ty * TY + (threadIdx.x / TX);
     double v[1] = {0.0};
     if (x < K.nx && y < K.ny) {
-        const int cell = x + K.nx * (y + K.ny * z);
-        const Nbr nb = make_nbr(K, x, y, z);
-        const double* b0 = Bs + cell;
-        const double* b1 = Bs + K.N + cell;
-        const double* b2 = Bs + 2 * K.N + cell;
-        const double dv = ((b0[nb.at(1, 0, 0)] - b0[nb.at(-1, 0, 0)]) + (b1[nb.at(0, 1, 0)] - b1[nb.at(0, -1, 0)]) +
-                           (b2[nb.at(0, 0, 1)] - b2[nb.at(0, 0, -1)])) *
-                          K.inv_2dx;
+        double dv = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double* Ba = Bs + (int64_t)a * K.N;
+            dv += axis_derivative(K, a, x, y, z, [&](int xx, int yy, int zz) { return Ba[xx + K.nx * (yy + K.ny * zz)]; });
+        }
         v[0] = fabs(dv);
     }
     block_max1(v[0], part + tile);
+}
+
+// Null point over the per-block partials, then R = (E^z - E^z_0) / B0 there.
+// out[0] = R, out[1] = null cell (-1: none), out[2] = B0.
+__global__ __launch_bounds__(TPB) void k_null_reduce(const double* __restrict__ nullp, int nblk,
+                                                     const double* __restrict__ ez, const double* __restrict__ ez0,
+                                                     const double* __restrict__ b0, double* __restrict__ out) {
+    __shared__ double res[2];
+    double k = __builtin_inf(), i = NO_INDEX;
+    for (int b = threadIdx.x; b < nblk; b += TPB) argmin_merge(k, i, nullp[2 * (int64_t)b], nullp[2 * (int64_t)b + 1]);
+    block_argmin(k, i, res);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const bool found = res[1] < NO_INDEX;
+        const int64_t c = found ? (int64_t)res[1] : -1;
+        out[0] = found ? (ez[c] - ez0[c]) / b0[0] : __builtin_nan("");
+        out[1] = (double)c;
+        out[2] = b0[0];
+    }
 }
 
 // Fixed-order reduction of the per-block partials by one block.
@@ -653,6 +839,87 @@ __global__ __launch_bounds__(TPB) void k_init_ref(InPtrs in, Consts K, double* _
     block_sum<2>(v, part + (int64_t)blockIdx.x * 2);
 }
 
+// Largest B^2 of the initial fields (as fma(B_x, B_x, fma(B_y, B_y, B_z B_z))), per block.
+__global__ __launch_bounds__(TPB) void k_init_bmax(InPtrs in, Consts K, double* __restrict__ part) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    double v = 0.0;
+    if (i < K.N) v = fma(in.B[0][i], in.B[0][i], fma(in.B[1][i], in.B[1][i], in.B[2][i] * in.B[2][i]));
+    block_max1(v, part + blockIdx.x);
+}
+
+__global__ void k_sqrt1(double* __restrict__ v) {
+    if (threadIdx.x == 0) v[0] = sqrt(v[0]);
+}
+
+// Face cells with |u| >= c, n <= 0 or p < 0, per block.
+__global__ __launch_bounds__(TPB) void k_face_check(FacePtrs in, Consts K, double* __restrict__ part) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    double bad[1] = {0.0};
+    if (i < (int64_t)K.nx * K.ny) {
+        const double u2 = in.u[0][i] * in.u[0][i] + in.u[1][i] * in.u[1][i] + in.u[2][i] * in.u[2][i];
+        bad[0] = (u2 < K.c * K.c && in.n[i] > 0.0 && in.p[i] >= 0.0) ? 0.0 : 1.0;
+    }
+    block_sum<1>(bad, part + blockIdx.x);
+}
+
+// Ghost planes of a driven low-z face: the post-collision state of a fully
+// relaxed cell with the prescribed fields -- f_eq and g_eq of (n, p, u,
+// E = -u x B, B) (stored minus their shifts), h* = h_eq of (J, E + q J, B)
+// with J of Eq. Ohm at zero charge (h* = h_eq is the fixed point of the
+// tau_h = 1/2 collision), rest h* = 0 and E_prev = E; both planes the same.
+// dd, de point at cell 0 of the state buffer; the planes sit just below it.
+template <typename TS, typename TE>
+__global__ __launch_bounds__(TPB) void k_init_ghost(FacePtrs in, Consts K, TS* __restrict__ dd, TE* __restrict__ de) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    const int64_t plane = (int64_t)K.nx * K.ny;
+    if (i >= plane) return;
+    const double c = K.c, c2 = c * c;
+    double u[3], Bv[3], beta[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        u[a] = in.u[a][i];
+        Bv[a] = in.B[a][i];
+        beta[a] = u[a] / c;
+    }
+    const double E[3] = {-(u[1] * Bv[2] - u[2] * Bv[1]), -(u[2] * Bv[0] - u[0] * Bv[2]), -(u[0] * Bv[1] - u[1] * Bv[0])};
+    const double n = in.n[i], p = in.p[i];
+    const double b2 = beta[0] * beta[0] + beta[1] * beta[1] + beta[2] * beta[2];
+    const double gam = 1.0 / sqrt(1.0 - b2);
+    const double eps = n * c2 + p / K.gm1;
+    const double uxB[3] = {u[1] * Bv[2] - u[2] * Bv[1], u[2] * Bv[0] - u[0] * Bv[2], u[0] * Bv[1] - u[1] * Bv[0]};
+    const double Eu = (E[0] * u[0] + E[1] * u[1] + E[2] * u[2]) / c2;
+    double J[3], Epr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        J[a] = K.sigma * gam * (E[a] + uxB[a] - Eu * u[a]);
+        Epr[a] = E[a] + K.q * J[a];
+    }
+    FeqCell fe;
+    fe.setup(eps, p, gam, beta, E, Bv, c, K.eps0);
+    const double cj = 1.0 / (16.0 * 1.4142135623730951 * c), ce = 1.0 / (8.0 * 1.4142135623730951 * c);
+    for (int layer = 1; layer <= 2; ++layer) {
+        const int64_t g = i - layer * plane;  // offset of the ghost cell from cell 0
+        static_for<0>([&](auto ic) {
+            constexpr int q = decltype(ic)::value;
+            const double eb = EX[q] * beta[0] + EY[q] * beta[1] + EZ[q] * beta[2];
+            dd[(int64_t)(OFF_F + q) * K.stride + g] = static_cast<TS>(fe.template eq<q>() - fshift(K, q));
+            const double wpi = q == 0 ? K.wp[0] : (q <= 6 ? K.wp[1] : K.wp[2]);
+            dd[(int64_t)(OFF_G + q) * K.stride + g] =
+                static_cast<TS>(wpi * n * gam * (1.0 + K.gc1 * eb + K.gc2 * eb * eb - K.gc3 * b2) - gshift(K, q));
+        });
+#pragma unroll
+        for (int k = 0; k < QH; ++k) {
+            const double heq = cj * (SX[k] * J[0] + SY[k] * J[1] + SZ[k] * J[2]) +
+                               ce * (EHX[k] * Epr[0] + EHY[k] * Epr[1] + EHZ[k] * Epr[2]) +
+                               0.125 * (BHX[k] * Bv[0] + BHY[k] * Bv[1] + BHZ[k] * Bv[2]);
+            dd[(int64_t)(OFF_H + k) * K.stride + g] = static_cast<TS>(heq);
+        }
+        dd[(int64_t)(OFF_H + QH) * K.stride + g] = static_cast<TS>(0.0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) de[(int64_t)a * K.stride + g] = static_cast<TE>(E[a]);
+    }
+}
+
 // Initial state, pass 1: J0 from Eq. Ohm with the Gauss charge of E0, and
 // E'0 = E0 + (dt/2) mu0 c^2 J0 (Reading of the initial h), into scratch.
 __global__ __launch_bounds__(TPB) void k_init_current(InPtrs in, Consts K, int tiles_x, int tiles_y, int ntiles,
@@ -664,7 +931,7 @@ __global__ __launch_bounds__(TPB) void k_init_current(InPtrs in, Consts K, int t
     const int x = tx * TX + (threadIdx.x % TX), y = ty * TY + (threadIdx.x / TX);
     if (x >= K.nx || y >= K.ny) return;
     const int cell = x + K.nx * (y + K.ny * z);
-    const Nbr nb = make_nbr(K, x, y, z);
+    const Nbr nb = make_nbr<false>(K, x, y, z);
     const double c = K.c, c2 = c * c;
     double u[3], E[3], B[3];
 #pragma unroll
@@ -701,7 +968,7 @@ __global__ __launch_bounds__(TPB) void k_init_state(InPtrs in, Consts K, int til
     const int x = tx * TX + (threadIdx.x % TX), y = ty * TY + (threadIdx.x / TX);
     if (x >= K.nx || y >= K.ny) return;
     const int cell = x + K.nx * (y + K.ny * z);
-    const Nbr nb = make_nbr(K, x, y, z);
+    const Nbr nb = make_nbr<false>(K, x, y, z);
     const double c = K.c, c2 = c * c;
     double u[3], Ep[3], Bv[3], beta[3];
 #pragma unroll
@@ -800,10 +1067,20 @@ int num_tiles(const Consts& K) {
 }
 
 template <typename TS>
+hipError_t launch_face_b(const StateBuf& src, const Consts& K, double* faceB, hipStream_t s) {
+    if (!K.divb) return hipSuccess;
+    const int64_t blocks = (K.fo[6] + 255) / 256;
+    hipLaunchKernelGGL((k_face_b<TS>), dim3((unsigned)blocks), dim3(256), 0, s, (const TS*)src.dist, K, faceB);
+    return hipGetLastError();
+}
+
+template <typename TS>
 hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K, const StepTuning& tune,
-                       hipStream_t s) {
+                       double* faceB, hipStream_t s) {
     using TE = typename StoreTypes<TS>::E;
     using V = typename StoreTypes<TS>::V;
+    hipError_t e = launch_face_b<TS>(src, K, faceB, s);
+    if (e != hipSuccess) return e;
     const int zb = tune.zb > 0 ? (tune.zb < K.nz ? tune.zb : K.nz) : 1;
     const int ptx = (K.nx + PX - 1) / PX, pcol = ptx * ((K.ny + PY - 1) / PY);
     const int pblk = pcol * ((K.nz + zb - 1) / zb), pgrid = ((pblk + 7) / 8) * 8;
@@ -812,25 +1089,54 @@ hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K
     TS* dd = (TS*)dst.dist;
     TE* de = (TE*)dst.efield;
     if (tune.nt_store)
-        hipLaunchKernelGGL((k_fused_step<true, TS, TE, V>), dim3(pgrid), dim3(PTPB), 0, s, sd, se, dd, de, K, ptx,
-                           pcol, zb, pblk);
+        hipLaunchKernelGGL((k_fused_step<true, TS, TE, V>), dim3(pgrid), dim3(PTPB), 0, s, sd, se, dd, de,
+                           (const double*)faceB, K, ptx, pcol, zb, pblk);
     else
-        hipLaunchKernelGGL((k_fused_step<false, TS, TE, V>), dim3(pgrid), dim3(PTPB), 0, s, sd, se, dd, de, K, ptx,
-                           pcol, zb, pblk);
+        hipLaunchKernelGGL((k_fused_step<false, TS, TE, V>), dim3(pgrid), dim3(PTPB), 0, s, sd, se, dd, de,
+                           (const double*)faceB, K, ptx, pcol, zb, pblk);
     return hipGetLastError();
 }
 
 template <typename TS>
-hipError_t launch_moments(const StateBuf& src, const Consts& K, const OutPtrs& out, double* Bscr, double* part,
-                          double* part2, double* result, hipStream_t s) {
+hipError_t launch_moments(const StateBuf& src, const Consts& K, const OutPtrs& out, const DiagBufs& D,
+                          hipStream_t s) {
     using TE = typename StoreTypes<TS>::E;
     int tx, ty, nt, nb;
     grid_of(K, tx, ty, nt, nb);
+    hipError_t e = launch_face_b<TS>(src, K, D.faceB, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_moments<TS, TE>), dim3(nb), dim3(TPB), 0, s, (const TS*)src.dist,
-                       (const TE*)src.efield, K, tx, ty, nt, out, Bscr, part);
-    hipLaunchKernelGGL(k_divb, dim3(nb), dim3(TPB), 0, s, (const double*)Bscr, K, tx, ty, nt, part2);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, s, (const double*)part, nt, NPART, 0, result);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, s, (const double*)part2, nt, 1, 1, result + NPART);
+                       (const TE*)src.efield, (const double*)D.faceB, K, tx, ty, nt, out, D.scratch, D.part,
+                       D.nullp);
+    hipLaunchKernelGGL(k_divb, dim3(nb), dim3(TPB), 0, s, (const double*)D.scratch, K, tx, ty, nt, D.part2);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, s, (const double*)D.part, nt, NPART, 0, D.result);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, s, (const double*)D.part2, nt, 1, 1, D.result + NPART);
+    hipLaunchKernelGGL(k_null_reduce, dim3(1), dim3(TPB), 0, s, (const double*)D.nullp, nt,
+                       (const double*)(D.scratch + 3 * K.N), (const double*)D.ez0, (const double*)D.b0,
+                       D.result + NPART + 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_bmax(const InPtrs& in, const Consts& K, double* part, double* b0, hipStream_t s) {
+    const int nblk = (int)((K.N + TPB - 1) / TPB);
+    hipLaunchKernelGGL(k_init_bmax, dim3(nblk), dim3(TPB), 0, s, in, K, part);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, s, (const double*)part, nblk, 1, 1, b0);
+    hipLaunchKernelGGL(k_sqrt1, dim3(1), dim3(64), 0, s, b0);
+    return hipGetLastError();
+}
+
+hipError_t launch_face_check(const FacePtrs& in, const Consts& K, double* part, double* result, hipStream_t s) {
+    const int nblk = (int)(((int64_t)K.nx * K.ny + TPB - 1) / TPB);
+    hipLaunchKernelGGL(k_face_check, dim3(nblk), dim3(TPB), 0, s, in, K, part);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, s, (const double*)part, nblk, 1, 0, result);
+    return hipGetLastError();
+}
+
+template <typename TS>
+hipError_t launch_ghost(const FacePtrs& in, const Consts& K, const StateBuf& dst, hipStream_t s) {
+    using TE = typename StoreTypes<TS>::E;
+    const int nblk = (int)(((int64_t)K.nx * K.ny + TPB - 1) / TPB);
+    hipLaunchKernelGGL((k_init_ghost<TS, TE>), dim3(nblk), dim3(TPB), 0, s, in, K, (TS*)dst.dist, (TE*)dst.efield);
     return hipGetLastError();
 }
 
@@ -873,11 +1179,12 @@ hipError_t launch_import(const double* src, const StateBuf& dst, const Consts& K
 }
 
 #define RMHD_INSTANTIATE(TS)                                                                                          \
-    template hipError_t launch_step<TS>(const StateBuf&, const StateBuf&, const Consts&, const StepTuning&,           \
+    template hipError_t launch_step<TS>(const StateBuf&, const StateBuf&, const Consts&, const StepTuning&, double*,  \
                                         hipStream_t);                                                                 \
-    template hipError_t launch_moments<TS>(const StateBuf&, const Consts&, const OutPtrs&, double*, double*, double*, \
-                                           double*, hipStream_t);                                                     \
+    template hipError_t launch_moments<TS>(const StateBuf&, const Consts&, const OutPtrs&, const DiagBufs&,           \
+                                           hipStream_t);                                                              \
     template hipError_t launch_init<TS>(const InPtrs&, const Consts&, double*, const StateBuf&, hipStream_t);         \
+    template hipError_t launch_ghost<TS>(const FacePtrs&, const Consts&, const StateBuf&, hipStream_t);               \
     template hipError_t launch_export<TS>(const StateBuf&, double*, const Consts&, hipStream_t);                      \
     template hipError_t launch_import<TS>(const double*, const StateBuf&, const Consts&, hipStream_t);
 

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librmhdlb.so")
 
 RMHDLB_OK, RMHDLB_EINVAL, RMHDLB_ENOMEM, RMHDLB_EDEVICE, RMHDLB_ERECOVERY, RMHDLB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-BC = {"periodic": 0, "open": 1}
+BC = {"periodic": 0, "open": 1, "driven": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 OUT_FIELDS = ("n", "p", "eps", "ux", "uy", "uz", "Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho_c")
 
@@ -27,7 +27,8 @@ class rmhdlb_params(ctypes.Structure):
         ("dx", ctypes.c_double), ("c", ctypes.c_double), ("mu0", ctypes.c_double),
         ("tau", ctypes.c_double), ("tau_h", ctypes.c_double), ("alpha", ctypes.c_double),
         ("Gamma", ctypes.c_double), ("sigma", ctypes.c_double), ("nu", ctypes.c_double),
-        ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
+        ("storage", ctypes.c_int32), ("divb_fix", ctypes.c_int32), ("null_band", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -43,11 +44,18 @@ class rmhdlb_fields_out(ctypes.Structure):
 class rmhdlb_diag(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_double), ("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3),
                 ("em_energy", ctypes.c_double), ("max_divB", ctypes.c_double), ("charge", ctypes.c_double),
-                ("mean_iters", ctypes.c_double), ("n_failed", ctypes.c_int64), ("step", ctypes.c_int64)]
+                ("mean_iters", ctypes.c_double), ("recon_rate", ctypes.c_double), ("B0", ctypes.c_double),
+                ("null_index", ctypes.c_int64), ("newton_hist", ctypes.c_int64 * 16),
+                ("n_failed", ctypes.c_int64), ("step", ctypes.c_int64)]
+
+
+class rmhdlb_face_in(ctypes.Structure):
+    _fields_ = [("n", _dp), ("p", _dp), ("u", _dp * 3), ("B", _dp * 3)]
 
 
 SYMBOLS = ("rmhdlb_create", "rmhdlb_init_fields", "rmhdlb_step", "rmhdlb_moments", "rmhdlb_destroy",
-           "rmhdlb_strerror", "rmhdlb_state_len", "rmhdlb_get_state", "rmhdlb_set_state", "rmhdlb_lattice_tables")
+           "rmhdlb_strerror", "rmhdlb_state_len", "rmhdlb_get_state", "rmhdlb_set_state", "rmhdlb_lattice_tables",
+           "rmhdlb_set_driven_face")
 
 _LIB = None
 
@@ -75,6 +83,7 @@ def load():
     L.rmhdlb_set_state.argtypes = [vp, _dp]
     ip = ctypes.POINTER(ctypes.c_int32)
     L.rmhdlb_lattice_tables.argtypes = [ip, _dp, ip, ip, ip]
+    L.rmhdlb_set_driven_face.argtypes = [vp, ctypes.POINTER(rmhdlb_face_in)]
     _LIB = L
     return L
 
@@ -108,6 +117,8 @@ def make_params(shape, bc=None, storage="f64", **kw):
     for k in ("dx", "c", "mu0", "tau", "tau_h", "alpha", "Gamma", "sigma", "nu"):
         setattr(P, k, float(d[k]))
     P.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    P.divb_fix = int(d.get("divb_fix", 1))
+    P.null_band = int(d.get("null_band", 64))
     return P
 
 
@@ -182,6 +193,26 @@ class Solver:
         self.stream.synchronize()   # inputs are borrowed only for the call
         return self
 
+    def set_driven_face(self, face):
+        """Prescribed fields of the driven low-z face: n, p, u (3), B (3), each (ny, nx)."""
+        nx, ny, _ = self.shape
+        torch = self.torch
+
+        def dev(a):
+            if isinstance(a, torch.Tensor):
+                return a.to(device="cuda", dtype=torch.float64).reshape(ny, nx).contiguous()
+            return torch.from_numpy(np.array(np.broadcast_to(np.asarray(a, dtype=np.float64), (ny, nx)))).to("cuda")
+        keep = [dev(face["n"]), dev(face["p"])]
+        u = [dev(x) for x in face["u"]]
+        B = [dev(x) for x in face["B"]]
+        fin = rmhdlb_face_in()
+        fin.n, fin.p = _dptr(keep[0]), _dptr(keep[1])
+        fin.u = (_dp * 3)(*[_dptr(t) for t in u])
+        fin.B = (_dp * 3)(*[_dptr(t) for t in B])
+        _check(load().rmhdlb_set_driven_face(self._h, ctypes.byref(fin)), "rmhdlb_set_driven_face")
+        self.stream.synchronize()   # inputs are borrowed only for the call
+        return self
+
     def step(self, nsteps=1):
         _check(load().rmhdlb_step(self._h, int(nsteps)), "rmhdlb_step")
 
@@ -201,7 +232,9 @@ class Solver:
         if diag:
             res["diag"] = dict(energy=d.energy, mass=d.mass, momentum=np.array(list(d.momentum)),
                                em_energy=d.em_energy, max_divB=d.max_divB, charge=d.charge,
-                               mean_iters=d.mean_iters, n_failed=int(d.n_failed), step=int(d.step))
+                               mean_iters=d.mean_iters, n_failed=int(d.n_failed), step=int(d.step),
+                               recon_rate=d.recon_rate, null_index=int(d.null_index), B0=d.B0,
+                               newton_hist=np.array(list(d.newton_hist), dtype=np.int64))
         res["rc"] = rc
         return res
 

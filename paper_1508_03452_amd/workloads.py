@@ -18,7 +18,8 @@ Workloads (Sec. IV of the paper; sizes and seeds are this project's):
               transverse velocity noise.
   flare    -- 3-D flare-like box 256x256x512: quadrupole arcade plus a
               flux rope (Sec. IV, stellar flare), stratified density,
-              seeded rope height, open faces.
+              seeded rope height, a driven shearing bottom face and open
+              faces elsewhere.
   random   -- smooth random periodic state for parity tests.
 """
 from dataclasses import dataclass, field
@@ -27,18 +28,19 @@ from math import erf, sqrt
 import numpy as np
 
 DEFAULT_PARAMS = dict(dx=1.0, c=1.0, mu0=1.0, tau=1.0, tau_h=0.5, alpha=0.1, Gamma=4.0 / 3.0, sigma=1.0,
-                      nu=27.0 ** 0.5)
+                      nu=27.0 ** 0.5, divb_fix=1, null_band=64)
 
 
 @dataclass
 class Workload:
     name: str
     shape: tuple           # (nx, ny, nz)
-    bc: tuple              # ((lo, hi),) * 3 with "periodic" / "open"
+    bc: tuple              # ((lo, hi),) * 3 with "periodic" / "open" / "driven" (low z only)
     params: dict
     fields: dict           # n, p, u (3), E (3), B (3), rho_c (array or None)
     steps: int = 0
     meta: dict = field(default_factory=dict)
+    driven: dict = None    # prescribed fields of a driven low-z face: n, p, u (3), B (3), each (ny, nx)
 
     @property
     def ncells(self):
@@ -124,14 +126,17 @@ def kh(nx=1024, ny=2048, nz=1, v0=0.2, ratio=10.0, sigma=1e3, B0=0.1, noise=1e-3
     return Workload("kh", shape, bc, _params(sigma=sigma), fields, steps, meta=dict(v0=v0, ratio=ratio, B0=B0))
 
 
-def flare(nx=256, ny=256, nz=512, sigma=1e3, B0=0.06, seed=512, steps=10000, Lx=6.0, Lz=12.0):
+def flare(nx=256, ny=256, nz=512, sigma=1e3, B0=0.06, seed=512, steps=10000, Lx=6.0, Lz=12.0, v_drive=0.1):
     """Flare-like 3-D box: quadrupole arcade + image current + flux rope.
 
     Flux function psi = psi_b + psi_i + psi_l (Sec. IV, stellar flare) in the
     x-z plane, B = curl(psi e_y), scaled so that max |B| = B0, with a
     uniform-twist axial B_y inside the rope.  The rope height is drawn from
     U[1.8, 2.2] with the seed.  Density n = max(0.05, exp(-z/2)), p = 1,
-    u = 0, E = 0.  Physical box [-Lx/2, Lx/2]^2 x [0, Lz].
+    u = 0, E = 0.  Physical box [-Lx/2, Lx/2]^2 x [0, Lz].  The bottom face is
+    driven (ghost planes at the fields of the first plane with the shear
+    u_x = v_drive tanh(y / 0.5) (1 + 1e-3 U[-1, 1]), same seed); the other
+    faces are open.
     """
     shape = (nx, ny, nz)
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -165,13 +170,24 @@ def flare(nx=256, ny=256, nz=512, sigma=1e3, B0=0.06, seed=512, steps=10000, Lx=
     zero = _full(shape, 0.0)
     fields = dict(n=n, p=_full(shape, 1.0), u=(zero, zero.copy(), zero.copy()),
                   E=(zero.copy(), zero.copy(), zero.copy()), B=(Bx, By, Bz), rho_c=zero.copy())
-    bc = (("open", "open"),) * 3
-    return Workload("flare", shape, bc, _params(sigma=sigma), fields, steps, meta=dict(h=h, B0=B0))
+    # driven photosphere: shear u_x = v_drive tanh(y / 0.5) (1 + 1e-3 U[-1, 1]) below the first plane,
+    # with the density, pressure and field of that plane
+    ys = (np.arange(ny) + 0.5) * (Lx / ny) - Lx / 2.0
+    jitter = 1.0 + 1e-3 * rng.uniform(-1.0, 1.0, size=(ny, nx))
+    ux = v_drive * np.tanh(ys / 0.5)[:, None] * jitter
+    fz = np.zeros((ny, nx))
+    driven = dict(n=n[0].copy(), p=np.ones((ny, nx)), u=(ux, fz, fz.copy()),
+                  B=(Bx[0].copy(), By[0].copy(), Bz[0].copy()))
+    bc = (("open", "open"), ("open", "open"), ("driven", "open"))
+    return Workload("flare", shape, bc, _params(sigma=sigma), fields, steps, meta=dict(h=h, B0=B0, v_drive=v_drive),
+                    driven=driven)
 
 
 def random_state(shape=(8, 8, 8), seed=0, vmax=0.3, amp=0.05, Bmag=0.3, Emag=0.05, sigma=10.0, modes=3,
-                 bc=PERIODIC3, **params):
-    """Smooth random state: a few random Fourier modes per field."""
+                 bc=PERIODIC3, solenoidal=False, **params):
+    """Smooth random state: a few random Fourier modes per field.  With
+    solenoidal=True, B = Bmag x + curl of random vector-potential modes
+    (divergence free) and E = -u x B (ideal Ohm)."""
     nx, ny, nz = shape
     rng = np.random.Generator(np.random.PCG64(seed))
     x, y, z = _grid(shape)
@@ -192,7 +208,21 @@ def random_state(shape=(8, 8, 8), seed=0, vmax=0.3, amp=0.05, Bmag=0.3, Emag=0.0
     u = [smooth(vmax) for _ in range(3)]
     B = [smooth(Bmag) + (Bmag if a == 0 else 0.0) for a in range(3)]
     E = [smooth(Emag) for _ in range(3)]
-    fields = dict(n=n, p=p, u=tuple(u), E=tuple(E), B=tuple(B), rho_c=smooth(0.01))
+    rho_c = smooth(0.01)
+    if solenoidal:
+        B = [np.full((nz, ny, nx), float(Bmag)), np.zeros((nz, ny, nx)), np.zeros((nz, ny, nx))]
+        for _ in range(modes):
+            k = 2 * np.pi * rng.integers(1, 3, size=3) / np.array([nx, ny, nz], dtype=np.float64)
+            a = rng.normal(size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            s = -np.sin(k[0] * (x + nx / 2.0) + k[1] * (y + ny / 2.0) + k[2] * (z + nz / 2.0) + ph)
+            kxa = np.cross(k, a)
+            for c in range(3):
+                B[c] = B[c] + (Bmag / modes) * s * kxa[c]
+        uv = np.stack(u, -1)
+        E = list(np.moveaxis(-np.cross(uv, np.stack(B, -1)), -1, 0))
+        rho_c = None
+    fields = dict(n=n, p=p, u=tuple(u), E=tuple(np.ascontiguousarray(e) for e in E), B=tuple(B), rho_c=rho_c)
     return Workload("random", tuple(shape), bc, _params(sigma=sigma, **params), fields, 0)
 
 

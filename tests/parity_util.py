@@ -38,6 +38,8 @@ def state_errors(ref, got):
 def run_oracle(w, steps):
     o = oracle.Oracle(w.shape, w.bc, **w.params)
     o.init(w.fields)
+    if w.driven is not None:
+        o.set_driven(w.driven)
     if steps:
         o.step(steps)
     return o
@@ -47,6 +49,8 @@ def run_gpu(w, steps, storage="f64"):
     from paper_1508_03452_amd.rmhdlb import Solver
     s = Solver(w.shape, w.bc, storage=storage, **w.params)
     s.init_fields(w.fields)
+    if w.driven is not None:
+        s.set_driven_face(w.driven)
     if steps:
         s.step(steps)
     return s

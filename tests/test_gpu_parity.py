@@ -36,6 +36,8 @@ def oracle_sensitivity(w, steps, o_ref, symmetric):
     oracle started from a one-ulp perturbed state."""
     b = oracle.Oracle(w.shape, w.bc, **w.params)
     b.init(w.fields)
+    if w.driven is not None:
+        b.set_driven(w.driven)
     st = b.get_state()
     rng = np.random.default_rng(1234)
     shp = (st.shape[0], 1, 1, st.shape[3]) if symmetric else st.shape
@@ -78,7 +80,36 @@ def check_case(w, steps, conditioned=False, symmetric=False):
     assert np.abs(dg["momentum"] - do["momentum"]).max() <= dtol * abs(do["energy"])
     assert abs(dg["charge"] - do["charge"]) <= 1e-12 * max(1.0, w.ncells * 1e-3)
     assert abs(dg["max_divB"] - do["max_divB"]) <= 1e-12 * max(do["max_divB"], field_scale(w))
+    check_null_point(w, mo, mg, do, dg, ftol)
+    check_newton_histogram(w, dg)
     return errs
+
+
+def check_null_point(w, mo, mg, do, dg, ftol):
+    """Reconnection rate: same null cell as the oracle, or (near-tie) a cell whose key is the band minimum
+    to rounding; R within the E_z bound divided by B0."""
+    assert abs(dg["B0"] - do["B0"]) <= 1e-15 * max(do["B0"], 1e-300)
+    assert dg["null_index"] >= 0 and do["null_index"] >= 0
+    key = mo["Bx"] ** 2 + mo["By"] ** 2
+    flat = key.reshape(-1)
+    if dg["null_index"] != do["null_index"]:
+        assert flat[dg["null_index"]] <= flat[do["null_index"]] * (1 + 1e-11) + 1e-300, (dg["null_index"],
+                                                                                             do["null_index"])
+        ez = mo["Ez"].reshape(-1)[dg["null_index"]]
+        ref = (ez - w.fields["E"][2].reshape(-1)[dg["null_index"]]) / do["B0"]
+    else:
+        ref = do["recon_rate"]
+    tol = max(ftol["Ez"], TOL) * max(np.abs(mo["Ez"]).max(), field_scale(w)) / do["B0"]
+    print(f"[parity] null {dg['null_index']} / {do['null_index']}: R {dg['recon_rate']:.6e} vs {ref:.6e}", flush=True)
+    assert abs(dg["recon_rate"] - ref) <= tol, (dg["recon_rate"], ref, tol)
+
+
+def check_newton_histogram(w, dg):
+    """Every cell is counted once, and the histogram carries the mean iteration count."""
+    h = dg["newton_hist"]
+    assert h.sum() == w.ncells and (h >= 0).all()
+    if h[15] == 0:
+        assert abs((h * np.arange(16)).sum() / w.ncells - dg["mean_iters"]) <= 1e-12 * max(dg["mean_iters"], 1.0)
 
 
 def test_init_round_trip():
@@ -93,9 +124,53 @@ def test_random_3d_periodic_ragged_tiles():
 
 
 def test_random_3d_open_faces():
+    """Open faces on every axis with the normal-B adjustment (div B = 0 on the faces)."""
     w = W.random_state(shape=(20, 9, 7), seed=3, vmax=0.05, Bmag=0.2, Emag=0.02, sigma=30.0,
                        bc=(("open", "open"),) * 3)
     check_case(w, 10)
+
+
+def test_solenoidal_box_open_on_every_face_40_steps():
+    w = W.random_state(shape=(20, 9, 7), seed=3, vmax=0.05, Bmag=0.1, sigma=30.0, bc=(("open", "open"),) * 3,
+                       solenoidal=True)
+    check_case(w, 40)
+
+
+def test_random_3d_open_faces_without_divb_fix():
+    w = W.random_state(shape=(20, 9, 7), seed=3, vmax=0.05, Bmag=0.2, Emag=0.02, sigma=30.0,
+                       bc=(("open", "open"),) * 3, divb_fix=0)
+    check_case(w, 10)
+
+
+def _driven_case(shape=(20, 9, 12), seed=5, v_drive=0.15, storage="f64"):
+    bc = (("periodic", "periodic"), ("open", "open"), ("driven", "open"))
+    w = W.random_state(shape=shape, seed=seed, vmax=0.05, Bmag=0.2, Emag=0.02, sigma=30.0, bc=bc)
+    nx, ny, _ = shape
+    rng = np.random.default_rng(seed)
+    yy = (np.arange(ny) + 0.5 - ny / 2)[:, None] * np.ones((1, nx))
+    w.driven = dict(n=w.fields["n"][0].copy(), p=w.fields["p"][0].copy(),
+                    u=(v_drive * np.tanh(yy / 2.0) * (1 + 1e-3 * rng.uniform(-1, 1, (ny, nx))),
+                       np.zeros((ny, nx)), np.zeros((ny, nx))),
+                    B=tuple(b[0].copy() for b in w.fields["B"]))
+    return w
+
+
+def test_driven_bottom_face():
+    """Driven low-z face (fixed equilibrium ghost planes of a prescribed shear) under open y faces."""
+    check_case(_driven_case(), 15)
+
+
+def test_driven_face_rejects_invalid_fields():
+    from paper_1508_03452_amd.rmhdlb import RmhdlbError
+    _torch_cuda()
+    w = _driven_case(shape=(8, 6, 5))
+    s = run_gpu(w, 0)
+    bad = dict(w.driven)
+    bad["u"] = (np.full((6, 8), 1.0), np.zeros((6, 8)), np.zeros((6, 8)))
+    with pytest.raises(RmhdlbError):
+        s.set_driven_face(bad)
+    s.step(2)  # the ghost planes kept the valid fields
+    assert s.moments(fields=())["diag"]["n_failed"] == 0
 
 
 def test_alfven_wave_500_steps():
@@ -210,6 +285,54 @@ def test_full_size_sampled_cells_one_step(name):
     assert worst <= TOL
 
 
+def test_full_size_sampled_face_cells_one_step():
+    """The flare box at full size: cells on the open x-low, y-high and z-high faces (normal-B
+    adjustment) and on the driven bottom face, each advanced one step by the oracle on a 5x5x5
+    window that keeps the face (and, for the bottom, the prescribed face fields)."""
+    torch = _torch_cuda()
+    w = W.flare()
+    s = run_gpu(w, 3)
+    st = s.get_state()
+    s.step(1)
+    st1 = s.get_state()
+    rng = np.random.default_rng(12)
+    nx, ny, nz = w.shape
+    worst = 0.0
+    for face in ("x_lo", "y_hi", "z_hi", "z_lo"):
+        for _ in range(6):
+            c = [int(rng.integers(3, nx - 3)), int(rng.integers(3, ny - 3)), int(rng.integers(3, nz - 3))]
+            ax, hi = {"x_lo": (0, 0), "y_hi": (1, 1), "z_hi": (2, 1), "z_lo": (2, 0)}[face]
+            n_ax = w.shape[ax]
+            c[ax] = n_ax - 1 if hi else 0
+            win = []
+            for a in range(3):
+                if a == ax:
+                    win.append(np.arange(n_ax - 5, n_ax) if hi else np.arange(0, 5))
+                else:
+                    win.append(np.arange(c[a] - 2, c[a] + 3))
+            ix, iy, iz = win
+            sub = st[:, torch.as_tensor(iz, device="cuda")][:, :, torch.as_tensor(iy, device="cuda")][
+                :, :, :, torch.as_tensor(ix, device="cuda")].cpu().numpy()
+            bc = [["periodic", "periodic"] for _ in range(3)]
+            bc[ax] = ["driven", "open"] if face == "z_lo" else ["open", "open"]
+            o = oracle.Oracle((5, 5, 5), tuple(tuple(b) for b in bc), **w.params)
+            o.set_state(np.ascontiguousarray(sub))
+            if face == "z_lo":
+                d = w.driven
+                cut = lambda a: np.ascontiguousarray(a[np.ix_(iy, ix)])
+                o.set_driven(dict(n=cut(d["n"]), p=cut(d["p"]), u=tuple(cut(v) for v in d["u"]),
+                                  B=tuple(cut(v) for v in d["B"])))
+            o.step(1)
+            li = [int(np.where(win[a] == c[a])[0][0]) for a in range(3)]
+            got = st1[:, c[2], c[1], c[0]].cpu().numpy()
+            ref = o.get_state()[:, li[2], li[1], li[0]]
+            for sl in (slice(0, 19), slice(19, 38), slice(38, 63), slice(63, 66)):
+                scale = max(np.abs(ref[sl]).max(), 1e-3 * field_scale(w))
+                worst = max(worst, np.abs(got[sl] - ref[sl]).max() / scale)
+    print(f"[parity] flare full-size sampled face cells worst {worst:.2e}", flush=True)
+    assert worst <= TOL
+
+
 # ------------------------------------------------ mixed storage forms (a10) ---
 
 # Stated per-field bounds against the FP64 oracle (max error over the field's
@@ -260,6 +383,12 @@ def test_mixed_current_sheet(storage):
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_mixed_kh_prefix(storage):
     _mixed_case(W.kh(nx=96, ny=160, v0=0.4, ratio=10.0, sigma=1e3), 20, storage)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_mixed_driven_face(storage):
+    """Ghost planes of the driven face are stored as shifted deviations like the interior."""
+    _mixed_case(_driven_case(), 15, storage)
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
