@@ -64,6 +64,7 @@ def lib():
         L.rmhdlb_oracle_recover.argtypes = [ctypes.POINTER(_Params), dp, ctypes.c_double, dp, dp, dp]
         L.rmhdlb_oracle_ohm.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, ctypes.c_double, dp, dp]
         L.rmhdlb_oracle_set_driven.argtypes = [ctypes.c_void_p, dp, dp, dp * 3, dp * 3]
+        L.rmhdlb_oracle_fluid_tensor.argtypes = [ctypes.c_void_p, dp, dp]
         _LIB = L
     return _LIB
 
@@ -159,6 +160,19 @@ class Oracle:
         lib().rmhdlb_oracle_diagnostics(self._h, _ptr(d))
         return dict(energy=d[0], mass=d[1], momentum=d[2:5].copy(), em_energy=d[5], max_divB=d[6], charge=d[7],
                     n_failed=int(d[8]), mean_iters=d[9], recon_rate=d[10], null_index=int(d[11]), B0=d[12])
+
+    def fluid_tensor(self):
+        """Per cell (flattened x fastest): E_f (n,), S (n, 3), Pi (n, 3, 3), N0 (n,) of the recovery of
+        the current state, and the recovered eps (n,), beta (n, 3)."""
+        n = int(np.prod(self.grid))
+        out = np.empty((n, 11))
+        rec = np.empty((n, 4))
+        lib().rmhdlb_oracle_fluid_tensor(self._h, _ptr(out), _ptr(rec))
+        Pi = np.empty((n, 3, 3))
+        for (a, b), j in (((0, 0), 4), ((1, 1), 5), ((2, 2), 6), ((0, 1), 7), ((0, 2), 8), ((1, 2), 9)):
+            Pi[:, a, b] = Pi[:, b, a] = out[:, j]
+        return dict(Ef=out[:, 0].copy(), S=out[:, 1:4].copy(), Pi=Pi, N0=out[:, 10].copy(), eps=rec[:, 0].copy(),
+                    beta=rec[:, 1:4].copy())
 
     def set_driven(self, face):
         """Prescribed fields of the driven low-z face: n, p, u (3-tuple), B (3-tuple), each (ny, nx)."""

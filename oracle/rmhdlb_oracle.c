@@ -133,6 +133,7 @@ static void lattice_build(orc_lattice *L, double nu, double c, double dx, double
 typedef struct {
     double eps, p, n, gam, beta[3], E[3], B[3], J[3], rhoc;
     double T[4][4], N0;
+    double Tfl[4][4]; /* fluid tensor T - T_EM of the recovery */
     int fail, iters;
 } orc_macro;
 
@@ -593,7 +594,7 @@ static void macroscopic_cell(orc_ctx *C, int x, int y, int z, orc_macro *m, cons
     for (int a = 0; a < 3; a++) Eprev[a] = Ep[(long)a * N + id];
     t_em(C->eps0, c, Eprev, B, Tem);
     for (int mu = 0; mu < 4; mu++)
-        for (int nv = 0; nv < 4; nv++) Tfl[mu][nv] = m->T[mu][nv] - Tem[mu][nv];
+        for (int nv = 0; nv < 4; nv++) m->Tfl[mu][nv] = Tfl[mu][nv] = m->T[mu][nv] - Tem[mu][nv];
 
     double beta[3], lam = NAN;
     int it = 0;
@@ -1018,6 +1019,37 @@ ORC_API int rmhdlb_oracle_moments(void *ctx, double *const out[16], long *n_fail
             if (out[q]) out[q][id] = vals[q];
     }
     if (n_failed) *n_failed = C->n_failed;
+    return C->n_failed ? ORC_ERECOVERY : ORC_OK;
+}
+
+/* Fluid tensor of the recovery of every cell of the current state and its
+ * N^0: out[11 * cell + j] = T_fl^00, T_fl^0x, T_fl^0y, T_fl^0z, T_fl^xx,
+ * T_fl^yy, T_fl^zz, T_fl^xy, T_fl^xz, T_fl^yz, N^0 (the inputs of the
+ * learned recovery guess), and the recovered eps, beta in rec[4 * cell + j]. */
+ORC_API int rmhdlb_oracle_fluid_tensor(void *ctx, double *out, double *rec)
+{
+    orc_ctx *C = (orc_ctx *)ctx;
+    if (!C || !out) return ORC_EINVAL;
+    macroscopic_pass(C);
+    for (long id = 0; id < C->N; id++) {
+        const orc_macro *m = &C->mac[id];
+        double *o = out + 11 * id;
+        o[0] = m->Tfl[0][0];
+        o[1] = m->Tfl[0][1];
+        o[2] = m->Tfl[0][2];
+        o[3] = m->Tfl[0][3];
+        o[4] = m->Tfl[1][1];
+        o[5] = m->Tfl[2][2];
+        o[6] = m->Tfl[3][3];
+        o[7] = m->Tfl[1][2];
+        o[8] = m->Tfl[1][3];
+        o[9] = m->Tfl[2][3];
+        o[10] = m->N0;
+        if (rec) {
+            rec[4 * id] = m->eps;
+            for (int a = 0; a < 3; a++) rec[4 * id + 1 + a] = m->beta[a];
+        }
+    }
     return C->n_failed ? ORC_ERECOVERY : ORC_OK;
 }
 

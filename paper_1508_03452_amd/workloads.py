@@ -226,6 +226,19 @@ def random_state(shape=(8, 8, 8), seed=0, vmax=0.3, amp=0.05, Bmag=0.3, Emag=0.0
     return Workload("random", tuple(shape), bc, _params(sigma=sigma, **params), fields, 0)
 
 
+def mlp_init(seed=2024, n_in=6, n_h=32, n_out=2):
+    """Initial weights of the learned recovery guess (uniform Glorot scale, zero biases), drawn here so
+    that the library and the tests start from the same numbers.  Order: W1 (n_h x n_in), b1,
+    W2 (n_h x n_h), b2, W3 (n_out x n_h), b3, flattened row-major."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for fan_in, fan_out in ((n_in, n_h), (n_h, n_h), (n_h, n_out)):
+        lim = np.sqrt(6.0 / (fan_in + fan_out))
+        out.append(rng.uniform(-lim, lim, size=fan_out * fan_in))
+        out.append(np.zeros(fan_out))
+    return np.concatenate(out)
+
+
 CONFIGS = {
     "alfven": alfven,
     "sheet": sheet,
