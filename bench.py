@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="flare", choices=["flare", "kh"])
     ap.add_argument("--storage", default="f64", choices=["f64", "f32", "f16"])
+    ap.add_argument("--guess", action="store_true",
+                    help="learned recovery guess: trained on the state after the warm-up (untimed), then used")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
@@ -97,6 +99,14 @@ def main():
         s.set_driven_face(w.driven)
     del w.fields
     s.step(args.warmup)
+    train_info = None
+    if args.guess:
+        t_tr = time.perf_counter()
+        weights, losses = s.train_guess(W.mlp_init(11), n_samples=65536, iters=400, batch=512, lr=3e-3)
+        s.set_guess(True)
+        s.step(2)
+        train_info = {"samples": 65536, "iters": 400, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+                      "train_s": round(time.perf_counter() - t_tr, 3)}
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -133,7 +143,9 @@ def main():
                                 f"driven shearing bottom face, open faces elsewhere"
                                 if args.workload == "flare" else
                                 f"KH shear layer {w.shape[0]}x{w.shape[1]}x{w.shape[2]}, v0=0.2, ratio 10, sigma=1e3"),
-                   "storage": args.storage, "cells": ncell, "recovery": "plain Newton",
+                   "storage": args.storage, "cells": ncell,
+                   "recovery": "Newton from the learned guess" if args.guess else "plain Newton",
+                   "guess_training": train_info, "guess_fallbacks": d["n_fallback"],
                    "arithmetic": "f64" if args.storage == "f64" else "f32 (recovery and Ohm solve in f64)",
                    "wall_s_timed": round(wall, 3), "failed_cells": d["n_failed"],
                    "mean_newton_iters": round(d["mean_iters"], 3)},

@@ -117,6 +117,7 @@ typedef struct {
     int64_t null_index;  /* linear cell index of the null point (-1: none) */
     int64_t newton_hist[16]; /* cells by Newton iterations of the recovery (last bin: 15 or more) */
     int64_t n_failed;    /* cells whose recovery failed */
+    int64_t n_fallback;  /* cells whose learned guess was rejected (Newton started from T_fl^00) */
     int64_t step;        /* steps taken since rmhdlb_init_fields */
 } rmhdlb_diag;
 
@@ -169,6 +170,71 @@ int rmhdlb_moments(rmhdlb_ctx *ctx, rmhdlb_fields_out *out, rmhdlb_diag *diag);
  * pointers, or any face cell with |u| >= c, n <= 0 or p < 0 (checked on the
  * device; this call synchronises the stream). */
 int rmhdlb_set_driven_face(rmhdlb_ctx *ctx, const rmhdlb_face_in *face);
+
+/* ---- learned recovery guess (not in the paper) ----------------------------
+ * The recovery (Sec. III, coupling subsection) finds the timelike eigenpair
+ * of the fluid tensor; this library solves it by Newton on the secular
+ * equation from lambda = T_fl^00.  A 6 -> 32 -> 32 -> 2 perceptron (tanh
+ * hidden layers) can seed that Newton iteration instead: from six rotation
+ * and scale invariants of the cell's fluid tensor (|S|/E_f, S^.Pi S^/E_f,
+ * tr Pi/E_f, |Pi S^ - (S^.Pi S^) S^|/E_f, |Pi|_F/E_f, N^0/E_f with E_f =
+ * T_fl^00, S = T_fl^0a, Pi = T_fl^ab, S^ = S/|S|), normalised, it predicts
+ * (lambda/E_f, |beta|) normalised.  The guess is used when it lies below E_f
+ * with Pi + lambda I positive definite and phi' > 0 there (and predicted
+ * |beta| < 0.999); otherwise Newton starts from E_f (a fallback).  Newton
+ * then converges to the same root, so the guess changes iteration counts,
+ * not results.  Inference runs inside the step on MFMA (FP16 weights and
+ * inputs, FP32 accumulation), 32 cells per wavefront. */
+enum { RMHDLB_GUESS_PLAIN = 0, RMHDLB_GUESS_MLP = 1 };
+#define RMHDLB_GUESS_PARAMS 1346 /* W1 (32 x 6), b1, W2 (32 x 32), b2, W3 (2 x 32), b3, row-major */
+
+typedef struct {
+    float w[RMHDLB_GUESS_PARAMS];
+    float mu_x[6], sd_x[6]; /* input normalisation x = (f - mu_x) / sd_x */
+    float mu_t[2], sd_t[2]; /* outputs: t = mu_t + sd_t y */
+} rmhdlb_guess_weights;
+
+typedef struct {
+    int32_t n_samples; /* cells sampled from the current state: cell floor(i N / n_samples), 128 <= n_samples <= N */
+    int32_t iters;     /* Adam iterations (>= 0) */
+    int32_t batch;     /* minibatch size: a multiple of 128, <= n_samples */
+    int32_t stride;    /* minibatch b takes samples (b batch + i) stride mod n_samples (>= 1) */
+    float lr;          /* Adam learning rate (> 0; beta1 0.9, beta2 0.999, eps 1e-8) */
+    int32_t reserved[3]; /* must be zero */
+} rmhdlb_train_opts;
+
+/* Train the guess on the GPU from cells of the current state: their features
+ * and, as targets, (lambda / E_f, |beta|) of the plain recovery; normalise
+ * with the sample mean and standard deviation (floor 1e-6); minibatch Adam
+ * from init_w (host, RMHDLB_GUESS_PARAMS values: the library draws no random
+ * numbers) on the mean squared error / 2 of the normalised outputs.  Installs
+ * the result (see rmhdlb_set_guess) and returns it in *out and the loss of
+ * every iteration in losses (host, iters values); both may be NULL.  Returns
+ * RMHDLB_ERECOVERY if a sampled cell fails its recovery.  Synchronises. */
+int rmhdlb_train_guess(rmhdlb_ctx *ctx, const rmhdlb_train_opts *opts, const float *init_w,
+                       rmhdlb_guess_weights *out, float *losses);
+
+/* Install guess weights (host struct) for the context's steps and moments. */
+int rmhdlb_set_guess_weights(rmhdlb_ctx *ctx, const rmhdlb_guess_weights *w);
+
+/* RMHDLB_GUESS_PLAIN (default) or RMHDLB_GUESS_MLP (needs installed
+ * weights, else RMHDLB_EINVAL).  Applies to later steps and moments. */
+int rmhdlb_set_guess(rmhdlb_ctx *ctx, int32_t mode);
+
+/* The training samples of rmhdlb_train_guess without training: features
+ * F (DEVICE, n_samples x 6) and targets T (DEVICE, n_samples x 2) of cells
+ * floor(i N / n_samples) of the current state.  Synchronises. */
+int rmhdlb_guess_samples(rmhdlb_ctx *ctx, int32_t n_samples, double *F, double *T);
+
+/* One forward and backward pass of the network on a batch: w (host,
+ * RMHDLB_GUESS_PARAMS), normalised inputs X (DEVICE, n x 6) and targets Yt
+ * (DEVICE, n x 2), n a multiple of 128 (<= 65536).  Writes the outputs Y
+ * (DEVICE, n x 2, may be NULL), the gradient of sum (Y - Yt)^2 / (2 n) with
+ * respect to w (DEVICE, RMHDLB_GUESS_PARAMS) and that loss (DEVICE, 1 value),
+ * using the training kernel's MFMA arithmetic.  Queued on hip_stream and
+ * synchronised. */
+int rmhdlb_mlp_eval(const float *w, const float *X, const float *Yt, int32_t n, float *Y, float *grad, float *loss,
+                    void *hip_stream);
 
 /* Release the context and its device memory.  NULL is accepted. */
 int rmhdlb_destroy(rmhdlb_ctx *ctx);

@@ -12,6 +12,7 @@
 
 #include "rmhdlb.h"
 #include "rmhdlb_internal.h"
+#include "rmhdlb_mlp.h"
 
 using rmhd::Consts;
 
@@ -34,6 +35,8 @@ struct rmhdlb_ctx {
     double* ez0;       // initial E^z (reconnection rate)
     double* aux;       // aux[0] = max |B| of the initial fields
     double* result;    // NPART sums, max |div B|, R, null cell, B0
+    rmhd::GuessTables* gt;  // inference tables of the learned guess (device), null until installed
+    int guess_mode;    // RMHDLB_GUESS_*
     int64_t step;
     rmhd::StepTuning tune;
 };
@@ -145,6 +148,75 @@ void set_shifts(Consts& K, int storage, double eref, double nref) {
     K.gs0 = K.gsh[0] + 6.0 * K.gsh[1] + 12.0 * K.gsh[2];
 }
 
+// Per-lane operand tables of the MFMA inference from the flat weights (the
+// layouts are those of rmhd::mlp_wave).
+void pack_tables(const rmhdlb_guess_weights& W, rmhd::GuessTables& T) {
+    using namespace rmhd;
+    const float* w = W.w;
+    for (int l = 0; l < 64; ++l) {
+        const int row = l & 31, h = l >> 5;
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * h + j;
+            T.a1[l][j] = (_Float16)(k < MLP_IN ? w[OW1 + row * MLP_IN + k] : 0.0f);
+        }
+        for (int s = 0; s < 4; ++s)
+            for (int j = 0; j < 4; ++j) {
+                const int k = 8 * s + 4 * h + j;
+                T.a2[l][s][j] = (_Float16)w[OW2 + row * 32 + k];
+                T.a3[l][s][j] = (_Float16)(row < MLP_OUT ? w[OW3 + row * 32 + k] : 0.0f);
+            }
+        for (int r = 0; r < 16; ++r) {
+            T.b1[l][r] = w[OB1 + mfma_row(r, l)];
+            T.b2[l][r] = w[OB2 + mfma_row(r, l)];
+        }
+    }
+    for (int k = 0; k < MLP_OUT; ++k) {
+        T.b3[k] = w[OB3 + k];
+        T.mu_t[k] = W.mu_t[k];
+        T.sd_t[k] = W.sd_t[k];
+    }
+    for (int j = 0; j < MLP_IN; ++j) {
+        T.mu_x[j] = W.mu_x[j];
+        T.inv_sd_x[j] = 1.0f / W.sd_x[j];
+    }
+}
+
+int install_guess(rmhdlb_ctx* C, const rmhdlb_guess_weights& W) {
+    rmhd::GuessTables* T = new (std::nothrow) rmhd::GuessTables();
+    if (!T) return RMHDLB_ENOMEM;
+    pack_tables(W, *T);
+    int rc = RMHDLB_OK;
+    if (!C->gt && hipMalloc((void**)&C->gt, sizeof(rmhd::GuessTables)) != hipSuccess) {
+        C->gt = nullptr;
+        rc = RMHDLB_ENOMEM;
+    } else if (hipMemcpyAsync(C->gt, T, sizeof(rmhd::GuessTables), hipMemcpyHostToDevice, C->stream) != hipSuccess ||
+               hipStreamSynchronize(C->stream) != hipSuccess) {
+        rc = RMHDLB_EDEVICE;
+    }
+    delete T;
+    return rc;
+}
+
+// Device buffers of one training run, freed together.
+struct TrainBufs {
+    double *F = nullptr, *T = nullptr, *part = nullptr;
+    float *X = nullptr, *Y = nullptr, *w = nullptr, *m = nullptr, *v = nullptr, *losses = nullptr;
+    ~TrainBufs() {
+        for (void* p : {(void*)F, (void*)T, (void*)part, (void*)X, (void*)Y, (void*)w, (void*)m, (void*)v,
+                        (void*)losses})
+            if (p) (void)hipFree(p);
+    }
+};
+
+template <typename Tp>
+bool dalloc(Tp** p, size_t n) {
+    if (hipMalloc((void**)p, sizeof(Tp) * (n > 0 ? n : 1)) != hipSuccess) {
+        *p = nullptr;
+        return false;
+    }
+    return true;
+}
+
 void release(rmhdlb_ctx* C) {
     if (!C) return;
     for (int b = 0; b < 2; ++b)
@@ -156,6 +228,7 @@ void release(rmhdlb_ctx* C) {
     if (C->faceB) (void)hipFree(C->faceB);
     if (C->ez0) (void)hipFree(C->ez0);
     if (C->aux) (void)hipFree(C->aux);
+    if (C->gt) (void)hipFree(C->gt);
     if (C->result) (void)hipFree(C->result);
     delete C;
 }
@@ -216,12 +289,10 @@ int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** ou
     }
     C->cur = 0;
     C->step = 0;
-    // Launch shape: z-planes per block and non-temporal stores; overridable
-    // through RMHDLB_ZB / RMHDLB_NT for tuning sweeps.
+    // Launch shape: z-planes per block (overridable through RMHDLB_ZB for
+    // tuning sweeps).
     C->tune.zb = 4;
-    C->tune.nt_store = 1;
     if (const char* v = getenv("RMHDLB_ZB")) C->tune.zb = atoi(v) > 0 ? atoi(v) : 1;
-    if (const char* v = getenv("RMHDLB_NT")) C->tune.nt_store = atoi(v) != 0;
     *out = C;
     return RMHDLB_OK;
 }
@@ -304,8 +375,8 @@ int rmhdlb_set_driven_face(rmhdlb_ctx* C, const rmhdlb_face_in* face) {
 int rmhdlb_step(rmhdlb_ctx* C, int64_t nsteps) {
     if (!C || nsteps < 0) return RMHDLB_EINVAL;
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e =
-            RMHD_DISPATCH(C, launch_step)(C->sb[C->cur], C->sb[1 - C->cur], C->K, C->tune, C->faceB, C->stream);
+        hipError_t e = RMHD_DISPATCH(C, launch_step)(C->sb[C->cur], C->sb[1 - C->cur], C->K, C->tune, C->faceB,
+                                                     C->guess_mode ? C->gt : nullptr, C->stream);
         if (e != hipSuccess) return RMHDLB_EDEVICE;
         C->cur = 1 - C->cur;
         C->step++;
@@ -338,7 +409,8 @@ int rmhdlb_moments(rmhdlb_ctx* C, rmhdlb_fields_out* out, rmhdlb_diag* diag) {
     D.ez0 = C->ez0;
     D.b0 = C->aux;
     D.result = C->result;
-    hipError_t e = RMHD_DISPATCH(C, launch_moments)(C->sb[C->cur], C->K, op, D, C->stream);
+    hipError_t e = RMHD_DISPATCH(C, launch_moments)(C->sb[C->cur], C->K, op, D, C->guess_mode ? C->gt : nullptr,
+                                                    C->stream);
     if (e != hipSuccess) return RMHDLB_EDEVICE;
     double r[RESULT_LEN];
     if (hipMemcpyAsync(r, C->result, sizeof(r), hipMemcpyDeviceToHost, C->stream) != hipSuccess)
@@ -356,6 +428,7 @@ int rmhdlb_moments(rmhdlb_ctx* C, rmhdlb_fields_out* out, rmhdlb_diag* diag) {
         diag->mean_iters = r[7] / (double)C->K.N;
         for (int k = 0; k < 16; ++k) diag->newton_hist[k] = (int64_t)llround(r[9 + k]);
         diag->n_failed = failed;
+        diag->n_fallback = (int64_t)llround(r[25]);
         diag->max_divB = r[rmhd::NPART];
         diag->recon_rate = r[rmhd::NPART + 1];
         diag->null_index = (int64_t)llround(r[rmhd::NPART + 2]);
@@ -363,6 +436,134 @@ int rmhdlb_moments(rmhdlb_ctx* C, rmhdlb_fields_out* out, rmhdlb_diag* diag) {
         diag->step = C->step;
     }
     return failed ? RMHDLB_ERECOVERY : RMHDLB_OK;
+}
+
+int rmhdlb_set_guess_weights(rmhdlb_ctx* C, const rmhdlb_guess_weights* w) {
+    if (!C || !w) return RMHDLB_EINVAL;
+    for (int j = 0; j < 6; ++j)
+        if (!(w->sd_x[j] > 0.0f)) return RMHDLB_EINVAL;
+    return install_guess(C, *w);
+}
+
+int rmhdlb_set_guess(rmhdlb_ctx* C, int32_t mode) {
+    if (!C || (mode != RMHDLB_GUESS_PLAIN && mode != RMHDLB_GUESS_MLP)) return RMHDLB_EINVAL;
+    if (mode == RMHDLB_GUESS_MLP && !C->gt) return RMHDLB_EINVAL;
+    C->guess_mode = mode;
+    return RMHDLB_OK;
+}
+
+static int sample_cells(rmhdlb_ctx* C, int ns, double* F, double* T, double* part, double sums[rmhd::SAMPLE_SUMS]) {
+    hipError_t e = RMHD_DISPATCH(C, launch_guess_samples)(C->sb[C->cur], C->K, C->faceB, ns, F, T, part, C->result,
+                                                          C->stream);
+    if (e != hipSuccess ||
+        hipMemcpyAsync(sums, C->result, sizeof(double) * rmhd::SAMPLE_SUMS, hipMemcpyDeviceToHost, C->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(C->stream) != hipSuccess)
+        return RMHDLB_EDEVICE;
+    return sums[16] != 0.0 ? RMHDLB_ERECOVERY : RMHDLB_OK;
+}
+
+int rmhdlb_guess_samples(rmhdlb_ctx* C, int32_t ns, double* F, double* T) {
+    if (!C || !F || !T || ns < 1 || ns > C->K.N) return RMHDLB_EINVAL;
+    double* part = nullptr;
+    if (!dalloc(&part, (size_t)rmhd::SAMPLE_SUMS * ((ns + 255) / 256))) return RMHDLB_ENOMEM;
+    double sums[rmhd::SAMPLE_SUMS];
+    const int rc = sample_cells(C, ns, F, T, part, sums);
+    (void)hipFree(part);
+    return rc;
+}
+
+int rmhdlb_train_guess(rmhdlb_ctx* C, const rmhdlb_train_opts* o, const float* init_w, rmhdlb_guess_weights* out,
+                       float* losses) {
+    if (!C || !o || !init_w) return RMHDLB_EINVAL;
+    const int ns = o->n_samples;
+    if (ns < 128 || ns > C->K.N || o->batch < 128 || o->batch % 128 != 0 || o->batch > ns || o->iters < 0 ||
+        o->stride < 1 || !(o->lr > 0.0f) || !isfinite(o->lr) || o->reserved[0] || o->reserved[1] || o->reserved[2])
+        return RMHDLB_EINVAL;
+    TrainBufs B;
+    const int np = rmhd::MLP_NP;
+    if (!dalloc(&B.F, (size_t)ns * 6) || !dalloc(&B.T, (size_t)ns * 2) ||
+        !dalloc(&B.part, (size_t)rmhd::SAMPLE_SUMS * ((ns + 255) / 256)) || !dalloc(&B.X, (size_t)ns * 6) ||
+        !dalloc(&B.Y, (size_t)ns * 2) || !dalloc(&B.w, np) || !dalloc(&B.m, np) || !dalloc(&B.v, np) ||
+        !dalloc(&B.losses, (size_t)o->iters))
+        return RMHDLB_ENOMEM;
+    double sums[rmhd::SAMPLE_SUMS];
+    int rc = sample_cells(C, ns, B.F, B.T, B.part, sums);
+    if (rc != RMHDLB_OK) return rc;
+    // normalisation: sample mean and (population) standard deviation, floor 1e-6
+    rmhd::Norm4 nm;
+    rmhdlb_guess_weights W;
+    for (int j = 0; j < 8; ++j) {
+        const double mu = (j < 6 ? sums[j] : sums[12 + (j - 6)]) / ns;
+        const double sq = (j < 6 ? sums[6 + j] : sums[14 + (j - 6)]) / ns;
+        const double sd = fmax(sqrt(fmax(sq - mu * mu, 0.0)), 1e-6);
+        if (j < 6) {
+            nm.mu_x[j] = mu;
+            nm.sd_x[j] = sd;
+            W.mu_x[j] = (float)mu;
+            W.sd_x[j] = (float)sd;
+        } else {
+            nm.mu_t[j - 6] = mu;
+            nm.sd_t[j - 6] = sd;
+            W.mu_t[j - 6] = (float)mu;
+            W.sd_t[j - 6] = (float)sd;
+        }
+    }
+    if (rmhd::launch_guess_normalise(B.F, B.T, ns, nm, B.X, B.Y, C->stream) != hipSuccess ||
+        hipMemcpyAsync(B.w, init_w, sizeof(float) * np, hipMemcpyHostToDevice, C->stream) != hipSuccess ||
+        hipMemsetAsync(B.m, 0, sizeof(float) * np, C->stream) != hipSuccess ||
+        hipMemsetAsync(B.v, 0, sizeof(float) * np, C->stream) != hipSuccess)
+        return RMHDLB_EDEVICE;
+    rmhd::TrainArgs A;
+    memset(&A, 0, sizeof(A));
+    A.X = B.X;
+    A.Yt = B.Y;
+    A.n = ns;
+    A.batch = o->batch;
+    A.iters = o->iters;
+    A.stride = o->stride;
+    A.lr = o->lr;
+    A.w = B.w;
+    A.m = B.m;
+    A.v = B.v;
+    A.losses = B.losses;
+    if (rmhd::launch_train(A, C->stream) != hipSuccess ||
+        hipMemcpyAsync(W.w, B.w, sizeof(float) * np, hipMemcpyDeviceToHost, C->stream) != hipSuccess ||
+        (losses && o->iters > 0 &&
+         hipMemcpyAsync(losses, B.losses, sizeof(float) * o->iters, hipMemcpyDeviceToHost, C->stream) != hipSuccess) ||
+        hipStreamSynchronize(C->stream) != hipSuccess)
+        return RMHDLB_EDEVICE;
+    rc = install_guess(C, W);
+    if (rc == RMHDLB_OK && out) *out = W;
+    return rc;
+}
+
+int rmhdlb_mlp_eval(const float* w, const float* X, const float* Yt, int32_t n, float* Y, float* grad, float* loss,
+                    void* hip_stream) {
+    if (!w || !X || !Yt || !grad || !loss || n < 128 || n % 128 != 0 || n > 65536) return RMHDLB_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    float* wd = nullptr;
+    if (!dalloc(&wd, rmhd::MLP_NP)) return RMHDLB_ENOMEM;
+    rmhd::TrainArgs A;
+    memset(&A, 0, sizeof(A));
+    A.X = X;
+    A.Yt = Yt;
+    A.n = n;
+    A.batch = n;
+    A.iters = 1;
+    A.stride = 1;
+    A.lr = 0.0f;
+    A.w = wd;
+    A.losses = loss;
+    A.grad = grad;
+    A.y = Y;
+    A.grad_only = 1;
+    int rc = RMHDLB_OK;
+    if (hipMemcpyAsync(wd, w, sizeof(float) * rmhd::MLP_NP, hipMemcpyHostToDevice, st) != hipSuccess ||
+        rmhd::launch_train(A, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+        rc = RMHDLB_EDEVICE;
+    (void)hipFree(wd);
+    return rc;
 }
 
 int64_t rmhdlb_state_len(const rmhdlb_ctx* C) { return C ? (int64_t)rmhd::NSTATE * C->K.N : -1; }

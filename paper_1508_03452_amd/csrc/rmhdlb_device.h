@@ -104,18 +104,34 @@ __device__ __forceinline__ void solve_shifted(const double Pi[6], double lam, co
     y[2] = (c02 * S[0] + c12 * S[1] + c22 * S[2]) * inv;
 }
 
+// (Pi + lam I) y = S with a positive-definiteness test of Pi + lam I (its
+// leading principal minors).
+__device__ __forceinline__ bool solve_shifted_pd(const double Pi[6], double lam, const double S[3], double y[3]) {
+    const double a = Pi[0] + lam, b = Pi[1] + lam, c = Pi[2] + lam;
+    const double d = Pi[3], e = Pi[4], f = Pi[5];
+    const double c00 = b * c - f * f, c01 = e * f - d * c, c02 = d * f - e * b;
+    const double c11 = a * c - e * e, c12 = d * e - a * f, c22 = a * b - d * d;
+    const double det = a * c00 + d * c01 + e * c02;
+    const double inv = 1.0 / det;
+    y[0] = (c00 * S[0] + c01 * S[1] + c02 * S[2]) * inv;
+    y[1] = (c01 * S[0] + c11 * S[1] + c12 * S[2]) * inv;
+    y[2] = (c02 * S[0] + c12 * S[1] + c22 * S[2]) * inv;
+    return a > 0.0 && c22 > 0.0 && det > 0.0;
+}
+
 // Landau-frame recovery.  The fluid tensor T_fl = T - T_EM has the timelike
 // eigenvector (1, beta) with eigenvalue eps: (Pi + eps I) beta = S and
 // eps = E_f - S.beta.  Eliminating beta gives the secular equation
-// phi(lam) = lam - E_f + S^T (Pi + lam I)^-1 S = 0, increasing and convex for
-// lam above its root (phi' = 1 - |beta|^2 = 1/gamma^2 there), so Newton from
-// lam = E_f (where phi = S^T A^-1 S >= 0) decreases monotonically to it.
-// Every Newton step is applied (so lam carries no one-sided bias from the
-// monotone approach) until the step is at the rounding floor; beta is then
+// phi(lam) = lam - E_f + S^T (Pi + lam I)^-1 S = 0, convex where Pi + lam I
+// is positive definite and increasing above its minimum (phi' = 1 - |beta|^2
+// = 1/gamma^2 at the root).  Newton from a start on the increasing branch
+// passes the root at most once (from below) and then decreases
+// monotonically to it.  Every Newton step is applied (so lam carries no
+// one-sided bias) until the step is at the rounding floor; beta is then
 // solved at the final lam.  Returns the number of Newton steps.
-__device__ __forceinline__ int recover(double Ef, const double S[3], const double Pi[6], double& lam,
-                                       double beta[3]) {
-    lam = Ef;
+__device__ __forceinline__ int newton_from(double Ef, const double S[3], const double Pi[6], double lam0,
+                                           double& lam, double beta[3]) {
+    lam = lam0;
     int it = 0;
     while (it < 60) {
         solve_shifted(Pi, lam, S, beta);
@@ -129,6 +145,29 @@ __device__ __forceinline__ int recover(double Ef, const double S[3], const doubl
     }
     solve_shifted(Pi, lam, S, beta);
     return it;
+}
+
+// Plain start: lam = E_f, where phi = S^T (Pi + E_f I)^-1 S >= 0.
+__device__ __forceinline__ int recover(double Ef, const double S[3], const double Pi[6], double& lam,
+                                       double beta[3]) {
+    return newton_from(Ef, S, Pi, Ef, lam, beta);
+}
+
+// Start from a guess lam0 when it lies below E_f on the increasing branch of
+// phi (Pi + lam0 I positive definite, phi'(lam0) > 0); otherwise from E_f,
+// with fallback = 1.
+__device__ __forceinline__ int recover_from_guess(double Ef, const double S[3], const double Pi[6], double lam0,
+                                                  double& lam, double beta[3], int& fallback) {
+    fallback = 1;
+    if (lam0 < Ef) {  // false for NaN
+        double y[3];
+        const bool pd = solve_shifted_pd(Pi, lam0, S, y);
+        if (pd && 1.0 - (y[0] * y[0] + y[1] * y[1] + y[2] * y[2]) > 0.0) {
+            fallback = 0;
+            return newton_from(Ef, S, Pi, lam0, lam, beta);
+        }
+    }
+    return recover(Ef, S, Pi, lam, beta);
 }
 
 }  // namespace rmhd

@@ -9,7 +9,7 @@
 
 namespace rmhd {
 
-constexpr int NPART = 25;  // partial diagnostic sums per block: 9 (see k_moments) + 16 Newton bins
+constexpr int NPART = 26;  // partial diagnostic sums per block: 9 (see k_moments), 16 Newton bins, fallbacks
 constexpr int RED_WAVES = 4;
 
 struct InPtrs {
@@ -94,12 +94,36 @@ __device__ __forceinline__ double block_max_value(double v) {
 
 int num_tiles(const Consts& K);
 
-// Launch shape of the fused step: z-planes walked per block and non-temporal
-// stores of the next state.
+// Launch shape of the fused step: z-planes walked per block.
 struct StepTuning {
     int zb;
-    int nt_store;
 };
+
+struct GuessTables;
+
+// Normalisation of the learned guess's inputs and targets (training-set
+// mean and standard deviation).
+struct Norm4 {
+    double mu_x[6], sd_x[6], mu_t[2], sd_t[2];
+};
+
+constexpr int SAMPLE_SUMS = 17;  // per-block sums of the sampling pass: F, F^2 (6 each), T, T^2 (2 each), failed
+
+struct TrainArgs {
+    const float* X;   // n x 6 normalised inputs
+    const float* Yt;  // n x 2 normalised targets
+    int n, batch, iters, stride;
+    float lr;
+    float* w;         // MLP_NP master weights: initial on entry, trained on exit
+    float* m;         // Adam moments (zero on entry)
+    float* v;
+    float* losses;    // loss of every iteration (may be null)
+    float* grad;      // gradient-only mode: the gradient of the batch
+    float* y;         // gradient-only mode: the outputs, n x 2 (may be null)
+    int grad_only;
+};
+
+
 
 // Device pointers of one state buffer: the 63 distribution arrays and the 3
 // E_prev arrays (each `stride` values long).
@@ -139,17 +163,27 @@ struct DiagBufs {
     double* result;   // NPART sums, max |div B|, R, null cell, B0
 };
 
+// gt: inference tables of the learned recovery guess, or nullptr for the
+// plain recovery (Newton from E_f).
 template <typename TS>
 hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K, const StepTuning& tune,
-                       double* faceB, hipStream_t s);
+                       double* faceB, const GuessTables* gt, hipStream_t s);
 template <typename TS>
 hipError_t launch_moments(const StateBuf& src, const Consts& K, const OutPtrs& out, const DiagBufs& D,
-                          hipStream_t s);
+                          const GuessTables* gt, hipStream_t s);
 hipError_t launch_init_bmax(const InPtrs& in, const Consts& K, double* part, double* b0, hipStream_t s);
 hipError_t launch_face_check(const FacePtrs& in, const Consts& K, double* part, double* result, hipStream_t s);
 template <typename TS>
 hipError_t launch_ghost(const FacePtrs& in, const Consts& K, const StateBuf& dst, hipStream_t s);
 hipError_t launch_init_ref(const InPtrs& in, const Consts& K, double* part, double* result, hipStream_t s);
+template <typename TS>
+hipError_t launch_face_b(const StateBuf& src, const Consts& K, double* faceB, hipStream_t s);
+template <typename TS>
+hipError_t launch_guess_samples(const StateBuf& src, const Consts& K, double* faceB, int ns, double* F, double* T,
+                                double* part, double* result, hipStream_t s);
+hipError_t launch_guess_normalise(const double* F, const double* T, int ns, const Norm4& nm, float* X, float* Y,
+                                  hipStream_t s);
+hipError_t launch_train(const TrainArgs& A, hipStream_t s);
 template <typename TS>
 hipError_t launch_init(const InPtrs& in, const Consts& K, double* scr, const StateBuf& dst, hipStream_t s);
 template <typename TS>

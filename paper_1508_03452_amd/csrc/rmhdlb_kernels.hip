@@ -11,6 +11,7 @@
 // arithmetic, with the recovery and the Ohm solve in FP64.
 #include "rmhdlb_device.h"
 #include "rmhdlb_internal.h"
+#include "rmhdlb_mlp.h"
 
 namespace rmhd {
 
@@ -131,6 +132,7 @@ struct CellSol {
     double Epr[3];                   // E' of Eq. Cal_E
     double eps, p, n, gam, beta[3], E[3], J[3];
     int iters;
+    int fallback;  // the learned guess was rejected (Newton started from E_f)
     bool ok;
 };
 
@@ -139,10 +141,10 @@ struct Macro : CellSol {
     double F[Q], G[Q], H[QH + 1];
 };
 
-// Recovery and the Ohm-coupled E, J of one cell from its moments (M.T00,
-// M.T0, M.Tab, M.N0, M.Epr, M.B, M.Ep, M.rho_g): fills eps, p, n, gam, beta,
-// E, J, iters, ok.
-__device__ __forceinline__ void solve_cell(const Consts& K, CellSol& M) {
+// Fluid tensor T_fl = T - T_EM of the recovery: E_f = T_fl^00, S = T_fl^0a,
+// Pi = T_fl^ab (xx, yy, zz, xy, xz, yz), with E_prev and this step's B.
+__device__ __forceinline__ void fluid_tensor(const Consts& K, const CellSol& M, double& Ef, double S[3],
+                                             double Pi[6]) {
     // fluid tensor with E_prev and this step's B
     const double c = K.c, c2 = c * c;
     const double* E = M.Ep;
@@ -150,8 +152,7 @@ __device__ __forceinline__ void solve_cell(const Consts& K, CellSol& M) {
     const double E2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2];
     const double B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
     const double U = 0.5 * (E2 + c2 * B2);
-    const double Ef = M.T00 - K.eps0 * U;
-    double S[3], Pi[6];
+    Ef = M.T00 - K.eps0 * U;
     S[0] = M.T0[0] - K.eps0 * c * (E[1] * B[2] - E[2] * B[1]);
     S[1] = M.T0[1] - K.eps0 * c * (E[2] * B[0] - E[0] * B[2]);
     S[2] = M.T0[2] - K.eps0 * c * (E[0] * B[1] - E[1] * B[0]);
@@ -161,9 +162,58 @@ __device__ __forceinline__ void solve_cell(const Consts& K, CellSol& M) {
     Pi[3] = M.Tab[3] + K.eps0 * (E[0] * E[1] + c2 * B[0] * B[1]);
     Pi[4] = M.Tab[4] + K.eps0 * (E[0] * E[2] + c2 * B[0] * B[2]);
     Pi[5] = M.Tab[5] + K.eps0 * (E[1] * E[2] + c2 * B[1] * B[2]);
+}
 
+// Where the learned guess comes from: none (Newton from E_f), or the
+// network evaluated on the wavefront with two lanes per cell (PAIR) or one
+// lane per cell (SINGLE, two passes of 32 cells).
+enum GuessMode { GUESS_NONE = 0, GUESS_PAIR = 1, GUESS_SINGLE = 2 };
+
+// Network guess of the eigenvalue for this lane's cell (all lanes of the
+// wavefront call it together).  NaN when the predicted |beta| >= 0.999
+// (those cells start from E_f).
+template <int GM>
+__device__ __forceinline__ double guess_lambda(const GuessTables* __restrict__ gt, double Ef, const double S[3],
+                                               const double Pi[6], double N0) {
+    double f[6];
+    mlp_features(Ef, S, Pi, N0, f);
+    float x[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) x[j] = (float)((f[j] - (double)gt->mu_x[j]) * (double)gt->inv_sd_x[j]);
+    const int lane = threadIdx.x & 63;
+    float y0, y1;
+    if constexpr (GM == GUESS_PAIR) {
+        mlp_wave(gt, x, 2 * (lane & 31), lane >> 1, y0, y1);
+    } else {
+        float a0, a1, c0, c1;
+        mlp_wave(gt, x, lane & 31, lane & 31, a0, a1);
+        mlp_wave(gt, x, 32 + (lane & 31), lane & 31, c0, c1);
+        y0 = lane < 32 ? a0 : c0;
+        y1 = lane < 32 ? a1 : c1;
+    }
+    const double t0 = (double)gt->mu_t[0] + (double)gt->sd_t[0] * (double)y0;
+    const double bn = (double)gt->mu_t[1] + (double)gt->sd_t[1] * (double)y1;
+    return bn < 0.999 ? Ef * t0 : __builtin_nan("");
+}
+
+// Recovery and the Ohm-coupled E, J of one cell from its moments (M.T00,
+// M.T0, M.Tab, M.N0, M.Epr, M.B, M.Ep, M.rho_g): fills eps, p, n, gam, beta,
+// E, J, iters, fallback, ok.  With a guess mode every lane of the wavefront
+// must call it together.
+template <int GM = GUESS_NONE>
+__device__ __forceinline__ void solve_cell(const Consts& K, CellSol& M, const GuessTables* __restrict__ gt = nullptr) {
+    const double c = K.c, c2 = c * c;
+    const double* B = M.B;
+    double Ef, S[3], Pi[6];
+    fluid_tensor(K, M, Ef, S, Pi);
     double lam;
-    M.iters = recover(Ef, S, Pi, lam, M.beta);
+    if constexpr (GM == GUESS_NONE) {
+        M.iters = recover(Ef, S, Pi, lam, M.beta);
+        M.fallback = 0;
+    } else {
+        const double lam0 = guess_lambda<GM>(gt, Ef, S, Pi, M.N0);
+        M.iters = recover_from_guess(Ef, S, Pi, lam0, lam, M.beta, M.fallback);
+    }
     const double b2 = M.beta[0] * M.beta[0] + M.beta[1] * M.beta[1] + M.beta[2] * M.beta[2];
     M.gam = 1.0 / sqrt(1.0 - b2);
     M.n = M.N0 / M.gam;
@@ -207,10 +257,10 @@ __device__ __forceinline__ void solve_cell(const Consts& K, CellSol& M) {
 // One thread per cell, FP64 arithmetic (moments and diagnostics pass).  The
 // shift of a stored array is constant in space, so it transports to itself
 // and is added back after the transport.
-template <typename TS, typename TE>
+template <int GM, typename TS, typename TE>
 __device__ __forceinline__ void macroscopic(const TS* __restrict__ src, const TE* __restrict__ esrc,
-                                            const double* __restrict__ faceB, const Consts& K, int cell,
-                                            const Nbr& nb, int x, int y, int z, Macro& M) {
+                                            const double* __restrict__ faceB, const GuessTables* __restrict__ gt,
+                                            const Consts& K, int cell, const Nbr& nb, int x, int y, int z, Macro& M) {
     M.T00 = 0.0;
     M.N0 = 0.0;
     double t0x = 0, t0y = 0, t0z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
@@ -302,7 +352,7 @@ __device__ __forceinline__ void macroscopic(const TS* __restrict__ src, const TE
                (ld(e2, nb.at(0, 0, 1)) - ld(e2, nb.at(0, 0, -1))));
 
     if (K.divb) apply_face_b(K, faceB, x, y, z, M.B);
-    solve_cell(K, M);
+    solve_cell<GM>(K, M, gt);
 }
 
 // f_eq of Eq. Dis_fun_EM in normalised variables (F = (c_t/c_0)^2 f), with
@@ -422,10 +472,16 @@ __device__ __forceinline__ V pair_sum(V v) {
     return v + __shfl_xor(v, 1, 64);
 }
 
-template <bool NT, typename TS, typename TE, typename V>
+template <bool NT, typename TS, typename TE, typename V, int GM>
 __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* __restrict__ se, TS* __restrict__ dd,
-                                          TE* __restrict__ de, const double* __restrict__ faceB, const Consts& K,
-                                          int cell, const Nbr& nb, int h, int x, int y, int z) {
+                                          TE* __restrict__ de, const double* __restrict__ faceB,
+                                          const GuessTables* __restrict__ gt, const Consts& K, int cell,
+                                          const Nbr& nb, int h, int x, int y, int z, bool active) {
+    // stores of this cell's new state (lanes that only take part in the
+    // wavefront's network evaluation store nothing)
+    auto put = [&](auto* p, auto v) {
+        if (active) st<NT>(p, v);
+    };
     const V sgn = h ? V(-1) : V(1);
     const int64_t S = K.stride;
     // Array bases stay uniform (scalar registers); the lane's choice between
@@ -548,7 +604,7 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
     M.rho = (double)pair_sum(Hv[12] + hs);
     M.rho_g = K.eps0 * K.inv_2dx * pair_sum(gpart);
     if (K.divb) apply_face_b(K, faceB, x, y, z, M.B);
-    solve_cell(K, M);
+    solve_cell<GM>(K, M, gt);
 
     // collisions and stores (new deviations)
     FeqCellT<V> fe;
@@ -561,11 +617,11 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
     const V bx_ = (V)M.beta[0], by_ = (V)M.beta[1], bz_ = (V)M.beta[2];
     if (h == 0) {
         const V q0 = (V)K.fsh[0] - fe.template eq<0>();
-        st<NT>(dd + (int64_t)OFF_F * S + cell, Fv[0] - rate * (Fv[0] + q0));
+        put(dd + (int64_t)OFF_F * S + cell, Fv[0] - rate * (Fv[0] + q0));
         const V geq0 = (V)K.wp[0] * ng * (V(1) - gc3b2);
-        st<NT>(dd + (int64_t)OFF_G * S + cell, (Gv[0] + wg * (geq0 - (V)K.gsh[0])) * inv1wg);
+        put(dd + (int64_t)OFF_G * S + cell, (Gv[0] + wg * (geq0 - (V)K.gsh[0])) * inv1wg);
     } else {
-        st<NT>(dd + (int64_t)(OFF_H + QH) * S + cell, (V)(2.0 * M.rho) - Hv[12]);
+        put(dd + (int64_t)(OFF_H + QH) * S + cell, (V)(2.0 * M.rho) - Hv[12]);
     }
     static_for<1>([&](auto ic) {
         constexpr int s = decltype(ic)::value;
@@ -575,9 +631,9 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
             const V eb = sgn * (EX[i0] * bx_ + EY[i0] * by_ + EZ[i0] * bz_);
             const V om = rate * (V(1) - V(KAPPA) * eb);
             const V q = (V)K.fsh[cls] - feq_signed<i0>(fe, sgn);
-            st<NT>(dd + (int64_t)(OFF_F + i0) * S + hc, Fv[s] - om * (Fv[s] + q));
+            put(dd + (int64_t)(OFF_F + i0) * S + hc, Fv[s] - om * (Fv[s] + q));
             const V geq = (V)K.wp[cls] * ng * (V(1) + gc1 * eb + gc2 * eb * eb - gc3b2);
-            st<NT>(dd + (int64_t)(OFF_G + i0) * S + hc, (Gv[s] + wg * (geq - (V)K.gsh[cls])) * inv1wg);
+            put(dd + (int64_t)(OFF_G + i0) * S + hc, (Gv[s] + wg * (geq - (V)K.gsh[cls])) * inv1wg);
         }
     });
     const V cj = (V)(1.0 / (16.0 * 1.4142135623730951 * K.c)), ce = (V)(1.0 / (8.0 * 1.4142135623730951 * K.c));
@@ -587,11 +643,11 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
     for (int m = 0; m < 12; ++m) {
         const int k0 = 2 * m;
         const V heq = cj * (SX[k0] * J0 + SY[k0] * J1 + SZ[k0] * J2) + sgn * ce * (EHX[k0] * E0 + EHY[k0] * E1 + EHZ[k0] * E2);
-        st<NT>(dd + (int64_t)(OFF_H + k0) * S + hc, V(2) * heq - Hv[m]);
+        put(dd + (int64_t)(OFF_H + k0) * S + hc, V(2) * heq - Hv[m]);
     }
     if (h == 0) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) st<NT>(de + (int64_t)a * S + cell, M.E[a]);
+        for (int a = 0; a < 3; ++a) put(de + (int64_t)a * S + cell, M.E[a]);
     }
 }
 
@@ -603,23 +659,33 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
 // one XCD runs at the same time are neighbours marching through the same
 // planes, so the y-halo and the z-neighbour planes of the stencil meet in
 // that XCD's L2.
-template <bool NT, typename TS, typename TE, typename V>
+// With the learned guess the network runs on whole wavefronts, so lanes past
+// a ragged edge stay and compute a copy of the edge cell without storing it.
+template <bool NT, typename TS, typename TE, typename V, int GM>
 __global__ __launch_bounds__(PTPB, RMHDLB_WAVES) void k_fused_step(const TS* __restrict__ sd, const TE* __restrict__ se,
                                                         TS* __restrict__ dd, TE* __restrict__ de,
-                                                        const double* __restrict__ faceB, Consts K,
+                                                        const double* __restrict__ faceB,
+                                                        const GuessTables* __restrict__ gt, Consts K,
                                                         int tiles_x, int ncol, int zb, int nblk) {
     const int b = tile_of_block(nblk);
-    if (b >= nblk) return;
+    if (b >= nblk) return;  // uniform over the block
     const int col = b % ncol, zc = b / ncol;
     const int tx = col % tiles_x, ty = col / tiles_x;
     const int c = threadIdx.x >> 1, h = threadIdx.x & 1;
-    const int x = tx * PX + (c % PX), y = ty * PY + c / PX;
-    if (x >= K.nx || y >= K.ny) return;  // both lanes of a pair leave together
+    int x = tx * PX + (c % PX), y = ty * PY + c / PX;
+    const bool active = x < K.nx && y < K.ny;
+    if constexpr (GM == GUESS_NONE) {
+        if (!active) return;  // both lanes of a pair leave together
+    } else {
+        x = min(x, K.nx - 1);
+        y = min(y, K.ny - 1);
+    }
     const int z0 = zc * zb, z1 = min(K.nz, z0 + zb);
     for (int z = z0; z < z1; ++z) {
         const int cell = x + K.nx * (y + K.ny * z);
         const Nbr nb = make_nbr<true>(K, x, y, z);
-        pair_cell<NT, TS, TE, V>(sd, se, dd, de, faceB, K, cell, nb, h, x, y, z);
+        pair_cell<NT, TS, TE, V, GM>(sd, se, dd, de, faceB, gt, K, cell, nb, h, x, y, z,
+                                     GM == GUESS_NONE ? true : active);
     }
 }
 
@@ -709,26 +775,31 @@ constexpr double NO_INDEX = 9.0e15;  // larger than any cell index, exact in FP6
 
 // Primitives of the current state and per-block partial diagnostics:
 // part[blk * NPART + j], j = T00, N0, T0x, T0y, T0z, em energy, rho, iters,
-// failed, then 16 Newton-iteration bins; null-search partials (least
-// B_x^2 + B_y^2 in the band and its cell) in nullp[2 blk ..]; B and E^z of
-// every cell into scratch (4 arrays of N).
-template <typename TS, typename TE>
+// failed, then 16 Newton-iteration bins, then learned-guess fallbacks;
+// null-search partials (least B_x^2 + B_y^2 in the band and its cell) in
+// nullp[2 blk ..]; B and E^z of every cell into scratch (4 arrays of N).
+// Every thread runs the cell pass (on the edge cell when past a ragged edge,
+// so that the network sees whole wavefronts); only real cells write.
+template <typename TS, typename TE, int GM>
 __global__ __launch_bounds__(TPB) void k_moments(const TS* __restrict__ src, const TE* __restrict__ esrc,
-                                                 const double* __restrict__ faceB, Consts K, int tiles_x,
+                                                 const double* __restrict__ faceB,
+                                                 const GuessTables* __restrict__ gt, Consts K, int tiles_x,
                                                  int tiles_y, int ntiles, OutPtrs out, double* __restrict__ scratch,
                                                  double* __restrict__ part, double* __restrict__ nullp) {
     const int tile = tile_of_block(ntiles);
-    if (tile >= ntiles) return;
+    if (tile >= ntiles) return;  // uniform over the block
     const int tx = tile % tiles_x, rest = tile / tiles_x;
     const int ty = rest % tiles_y, z = rest / tiles_y;
-    const int x = tx * TX + (threadIdx.x % TX), y = ty * TY + (threadIdx.x / TX);
+    const int x0 = tx * TX + (threadIdx.x % TX), y0 = ty * TY + (threadIdx.x / TX);
+    const bool active = x0 < K.nx && y0 < K.ny;
+    const int x = min(x0, K.nx - 1), y = min(y0, K.ny - 1);
     double v[NPART] = {0};
     double key = __builtin_inf(), idx = NO_INDEX;
-    if (x < K.nx && y < K.ny) {
-        const int cell = x + K.nx * (y + K.ny * z);
-        const Nbr nb = make_nbr<true>(K, x, y, z);
-        Macro M;
-        macroscopic(src, esrc, faceB, K, cell, nb, x, y, z, M);
+    const int cell = x + K.nx * (y + K.ny * z);
+    const Nbr nb = make_nbr<true>(K, x, y, z);
+    Macro M;
+    macroscopic<GM>(src, esrc, faceB, gt, K, cell, nb, x, y, z, M);
+    if (active) {
         const double c = K.c;
         if (out.n) out.n[cell] = M.n;
         if (out.p) out.p[cell] = M.p;
@@ -757,6 +828,7 @@ __global__ __launch_bounds__(TPB) void k_moments(const TS* __restrict__ src, con
         const int bin = M.iters < 15 ? (M.iters > 0 ? M.iters : 0) : 15;
 #pragma unroll
         for (int k = 0; k < 16; ++k) v[9 + k] = bin == k ? 1.0 : 0.0;
+        v[25] = M.fallback;
         // |y_j| <= band with cell centres y_j = j + 1/2 - ny/2
         const int dy = 2 * y + 1 - K.ny;
         if ((dy < 0 ? -dy : dy) <= 2 * K.band) {
@@ -1051,6 +1123,49 @@ __global__ void k_import(const double* __restrict__ s, TS* __restrict__ d, TE* _
     }
 }
 
+// (features, targets) of sampled cells of the current state with the plain
+// recovery: cell floor(i N / ns) for sample i.  F: ns x 6, T: ns x 2 (FP64).
+// Per-block partial sums of F, F^2, T, T^2 and failed cells into part (17 per block).
+
+template <typename TS, typename TE>
+__global__ __launch_bounds__(256) void k_guess_samples(const TS* __restrict__ src, const TE* __restrict__ esrc,
+                                                       const double* __restrict__ faceB, Consts K, int ns,
+                                                       double* __restrict__ F, double* __restrict__ T,
+                                                       double* __restrict__ part) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double acc[SAMPLE_SUMS] = {0};
+    if (i < ns) {
+        const int64_t cell = (int64_t)i * K.N / ns;
+        const int x = (int)(cell % K.nx), y = (int)((cell / K.nx) % K.ny), z = (int)(cell / ((int64_t)K.nx * K.ny));
+        const Nbr nb = make_nbr<true>(K, x, y, z);
+        Macro M;
+        macroscopic<GUESS_NONE>(src, esrc, faceB, nullptr, K, (int)cell, nb, x, y, z, M);
+        double Ef, S[3], Pi[6];
+        fluid_tensor(K, M, Ef, S, Pi);
+        double f[6];
+        mlp_features(Ef, S, Pi, M.N0, f);
+        const double t0 = M.eps / Ef;
+        const double t1 = sqrt(M.beta[0] * M.beta[0] + M.beta[1] * M.beta[1] + M.beta[2] * M.beta[2]);
+        if (M.ok) {
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                F[(int64_t)i * 6 + j] = f[j];
+                acc[j] = f[j];
+                acc[6 + j] = f[j] * f[j];
+            }
+            T[(int64_t)i * 2] = t0;
+            T[(int64_t)i * 2 + 1] = t1;
+            acc[12] = t0;
+            acc[13] = t1;
+            acc[14] = t0 * t0;
+            acc[15] = t1 * t1;
+        } else {
+            acc[16] = 1.0;
+        }
+    }
+    block_sum<SAMPLE_SUMS>(acc, part + (int64_t)blockIdx.x * SAMPLE_SUMS);
+}
+
 // ------------------------------------------------------------ host launchers
 
 static inline void grid_of(const Consts& K, int& tiles_x, int& tiles_y, int& ntiles, int& nblocks) {
@@ -1076,7 +1191,7 @@ hipError_t launch_face_b(const StateBuf& src, const Consts& K, double* faceB, hi
 
 template <typename TS>
 hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K, const StepTuning& tune,
-                       double* faceB, hipStream_t s) {
+                       double* faceB, const GuessTables* gt, hipStream_t s) {
     using TE = typename StoreTypes<TS>::E;
     using V = typename StoreTypes<TS>::V;
     hipError_t e = launch_face_b<TS>(src, K, faceB, s);
@@ -1088,26 +1203,31 @@ hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K
     const TE* se = (const TE*)src.efield;
     TS* dd = (TS*)dst.dist;
     TE* de = (TE*)dst.efield;
-    if (tune.nt_store)
-        hipLaunchKernelGGL((k_fused_step<true, TS, TE, V>), dim3(pgrid), dim3(PTPB), 0, s, sd, se, dd, de,
-                           (const double*)faceB, K, ptx, pcol, zb, pblk);
+    if (gt)
+        hipLaunchKernelGGL((k_fused_step<true, TS, TE, V, GUESS_PAIR>), dim3(pgrid), dim3(PTPB), 0, s, sd, se, dd,
+                           de, (const double*)faceB, gt, K, ptx, pcol, zb, pblk);
     else
-        hipLaunchKernelGGL((k_fused_step<false, TS, TE, V>), dim3(pgrid), dim3(PTPB), 0, s, sd, se, dd, de,
-                           (const double*)faceB, K, ptx, pcol, zb, pblk);
+        hipLaunchKernelGGL((k_fused_step<true, TS, TE, V, GUESS_NONE>), dim3(pgrid), dim3(PTPB), 0, s, sd, se, dd,
+                           de, (const double*)faceB, gt, K, ptx, pcol, zb, pblk);
     return hipGetLastError();
 }
 
 template <typename TS>
 hipError_t launch_moments(const StateBuf& src, const Consts& K, const OutPtrs& out, const DiagBufs& D,
-                          hipStream_t s) {
+                          const GuessTables* gt, hipStream_t s) {
     using TE = typename StoreTypes<TS>::E;
     int tx, ty, nt, nb;
     grid_of(K, tx, ty, nt, nb);
     hipError_t e = launch_face_b<TS>(src, K, D.faceB, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_moments<TS, TE>), dim3(nb), dim3(TPB), 0, s, (const TS*)src.dist,
-                       (const TE*)src.efield, (const double*)D.faceB, K, tx, ty, nt, out, D.scratch, D.part,
-                       D.nullp);
+    if (gt)
+        hipLaunchKernelGGL((k_moments<TS, TE, GUESS_SINGLE>), dim3(nb), dim3(TPB), 0, s, (const TS*)src.dist,
+                           (const TE*)src.efield, (const double*)D.faceB, gt, K, tx, ty, nt, out, D.scratch, D.part,
+                           D.nullp);
+    else
+        hipLaunchKernelGGL((k_moments<TS, TE, GUESS_NONE>), dim3(nb), dim3(TPB), 0, s, (const TS*)src.dist,
+                           (const TE*)src.efield, (const double*)D.faceB, gt, K, tx, ty, nt, out, D.scratch, D.part,
+                           D.nullp);
     hipLaunchKernelGGL(k_divb, dim3(nb), dim3(TPB), 0, s, (const double*)D.scratch, K, tx, ty, nt, D.part2);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, s, (const double*)D.part, nt, NPART, 0, D.result);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, s, (const double*)D.part2, nt, 1, 1, D.result + NPART);
@@ -1178,13 +1298,28 @@ hipError_t launch_import(const double* src, const StateBuf& dst, const Consts& K
     return hipGetLastError();
 }
 
+template <typename TS>
+hipError_t launch_guess_samples(const StateBuf& src, const Consts& K, double* faceB, int ns, double* F, double* T,
+                                double* part, double* result, hipStream_t s) {
+    using TE = typename StoreTypes<TS>::E;
+    hipError_t e = launch_face_b<TS>(src, K, faceB, s);
+    if (e != hipSuccess) return e;
+    const int nblk = (ns + 255) / 256;
+    hipLaunchKernelGGL((k_guess_samples<TS, TE>), dim3(nblk), dim3(256), 0, s, (const TS*)src.dist,
+                       (const TE*)src.efield, (const double*)faceB, K, ns, F, T, part);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, (const double*)part, nblk, SAMPLE_SUMS, 0, result);
+    return hipGetLastError();
+}
+
 #define RMHD_INSTANTIATE(TS)                                                                                          \
     template hipError_t launch_step<TS>(const StateBuf&, const StateBuf&, const Consts&, const StepTuning&, double*,  \
-                                        hipStream_t);                                                                 \
+                                        const GuessTables*, hipStream_t);                                             \
     template hipError_t launch_moments<TS>(const StateBuf&, const Consts&, const OutPtrs&, const DiagBufs&,           \
-                                           hipStream_t);                                                              \
+                                           const GuessTables*, hipStream_t);                                          \
     template hipError_t launch_init<TS>(const InPtrs&, const Consts&, double*, const StateBuf&, hipStream_t);         \
     template hipError_t launch_ghost<TS>(const FacePtrs&, const Consts&, const StateBuf&, hipStream_t);               \
+    template hipError_t launch_guess_samples<TS>(const StateBuf&, const Consts&, double*, int, double*, double*,      \
+                                                 double*, double*, hipStream_t);                                      \
     template hipError_t launch_export<TS>(const StateBuf&, double*, const Consts&, hipStream_t);                      \
     template hipError_t launch_import<TS>(const double*, const StateBuf&, const Consts&, hipStream_t);
 

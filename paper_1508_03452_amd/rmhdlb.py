@@ -46,7 +46,20 @@ class rmhdlb_diag(ctypes.Structure):
                 ("em_energy", ctypes.c_double), ("max_divB", ctypes.c_double), ("charge", ctypes.c_double),
                 ("mean_iters", ctypes.c_double), ("recon_rate", ctypes.c_double), ("B0", ctypes.c_double),
                 ("null_index", ctypes.c_int64), ("newton_hist", ctypes.c_int64 * 16),
-                ("n_failed", ctypes.c_int64), ("step", ctypes.c_int64)]
+                ("n_failed", ctypes.c_int64), ("n_fallback", ctypes.c_int64), ("step", ctypes.c_int64)]
+
+
+GUESS_PARAMS = 1346
+
+
+class rmhdlb_guess_weights(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_float * GUESS_PARAMS), ("mu_x", ctypes.c_float * 6), ("sd_x", ctypes.c_float * 6),
+                ("mu_t", ctypes.c_float * 2), ("sd_t", ctypes.c_float * 2)]
+
+
+class rmhdlb_train_opts(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int32), ("iters", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("stride", ctypes.c_int32), ("lr", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
 
 
 class rmhdlb_face_in(ctypes.Structure):
@@ -55,7 +68,8 @@ class rmhdlb_face_in(ctypes.Structure):
 
 SYMBOLS = ("rmhdlb_create", "rmhdlb_init_fields", "rmhdlb_step", "rmhdlb_moments", "rmhdlb_destroy",
            "rmhdlb_strerror", "rmhdlb_state_len", "rmhdlb_get_state", "rmhdlb_set_state", "rmhdlb_lattice_tables",
-           "rmhdlb_set_driven_face")
+           "rmhdlb_set_driven_face", "rmhdlb_train_guess", "rmhdlb_set_guess_weights", "rmhdlb_set_guess",
+           "rmhdlb_guess_samples", "rmhdlb_mlp_eval")
 
 _LIB = None
 
@@ -84,6 +98,13 @@ def load():
     ip = ctypes.POINTER(ctypes.c_int32)
     L.rmhdlb_lattice_tables.argtypes = [ip, _dp, ip, ip, ip]
     L.rmhdlb_set_driven_face.argtypes = [vp, ctypes.POINTER(rmhdlb_face_in)]
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.rmhdlb_train_guess.argtypes = [vp, ctypes.POINTER(rmhdlb_train_opts), fp, ctypes.POINTER(rmhdlb_guess_weights),
+                                     fp]
+    L.rmhdlb_set_guess_weights.argtypes = [vp, ctypes.POINTER(rmhdlb_guess_weights)]
+    L.rmhdlb_set_guess.argtypes = [vp, ctypes.c_int32]
+    L.rmhdlb_guess_samples.argtypes = [vp, ctypes.c_int32, _dp, _dp]
+    L.rmhdlb_mlp_eval.argtypes = [fp, fp, fp, ctypes.c_int32, fp, fp, fp, vp]
     _LIB = L
     return L
 
@@ -138,6 +159,44 @@ def _dptr(t):
     import torch
     assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
     return ctypes.cast(ctypes.c_void_p(t.data_ptr()), _dp)
+
+
+def _fptr(t):
+    """Device pointer of a contiguous float32 torch tensor (None -> NULL)."""
+    import torch
+    if t is None:
+        return ctypes.POINTER(ctypes.c_float)()
+    assert t.dtype == torch.float32 and t.is_cuda and t.is_contiguous()
+    return ctypes.cast(ctypes.c_void_p(t.data_ptr()), ctypes.POINTER(ctypes.c_float))
+
+
+def weights_to_dict(W):
+    return dict(w=np.array(list(W.w), dtype=np.float32), mu_x=np.array(list(W.mu_x)), sd_x=np.array(list(W.sd_x)),
+                mu_t=np.array(list(W.mu_t)), sd_t=np.array(list(W.sd_t)))
+
+
+def weights_from_dict(d):
+    W = rmhdlb_guess_weights()
+    W.w[:] = [float(v) for v in np.asarray(d["w"]).reshape(-1)]
+    for k in ("mu_x", "sd_x", "mu_t", "sd_t"):
+        getattr(W, k)[:] = [float(v) for v in np.asarray(d[k]).reshape(-1)]
+    return W
+
+
+def mlp_eval(w, X, Yt, stream=None):
+    """Forward and backward of the network on a batch (device tensors X: n x 6, Yt: n x 2, float32).
+    Returns (Y, grad, loss) as tensors."""
+    import torch
+    n = X.shape[0]
+    Y = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+    g = torch.empty(GUESS_PARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    wh = np.ascontiguousarray(np.asarray(w, dtype=np.float32))
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(load().rmhdlb_mlp_eval(wh.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _fptr(X.contiguous()),
+                                  _fptr(Yt.contiguous()), int(n), _fptr(Y), _fptr(g), _fptr(loss),
+                                  ctypes.c_void_p(st.cuda_stream)), "rmhdlb_mlp_eval")
+    return Y, g, loss
 
 
 class Solver:
@@ -213,6 +272,33 @@ class Solver:
         self.stream.synchronize()   # inputs are borrowed only for the call
         return self
 
+    def train_guess(self, init_w, n_samples, iters, batch=512, lr=3e-3, stride=7919):
+        """Train the learned recovery guess on cells of the current state; installs it and returns
+        (weights dict, losses)."""
+        o = rmhdlb_train_opts()
+        o.n_samples, o.iters, o.batch, o.stride, o.lr = int(n_samples), int(iters), int(batch), int(stride), float(lr)
+        w0 = np.ascontiguousarray(np.asarray(init_w, dtype=np.float32))
+        W = rmhdlb_guess_weights()
+        losses = np.zeros(max(int(iters), 1), dtype=np.float32)
+        fp = ctypes.POINTER(ctypes.c_float)
+        _check(load().rmhdlb_train_guess(self._h, ctypes.byref(o), w0.ctypes.data_as(fp), ctypes.byref(W),
+                                         losses.ctypes.data_as(fp)), "rmhdlb_train_guess")
+        return weights_to_dict(W), losses[:int(iters)]
+
+    def set_guess_weights(self, d):
+        _check(load().rmhdlb_set_guess_weights(self._h, ctypes.byref(weights_from_dict(d))), "rmhdlb_set_guess_weights")
+
+    def set_guess(self, on):
+        _check(load().rmhdlb_set_guess(self._h, 1 if on else 0), "rmhdlb_set_guess")
+
+    def guess_samples(self, n_samples):
+        torch = self.torch
+        F = torch.empty((n_samples, 6), dtype=torch.float64, device="cuda")
+        T = torch.empty((n_samples, 2), dtype=torch.float64, device="cuda")
+        rc = _check(load().rmhdlb_guess_samples(self._h, int(n_samples), _dptr(F), _dptr(T)), "rmhdlb_guess_samples",
+                    allow=(RMHDLB_ERECOVERY,))
+        return F, T, rc
+
     def step(self, nsteps=1):
         _check(load().rmhdlb_step(self._h, int(nsteps)), "rmhdlb_step")
 
@@ -234,6 +320,7 @@ class Solver:
                                em_energy=d.em_energy, max_divB=d.max_divB, charge=d.charge,
                                mean_iters=d.mean_iters, n_failed=int(d.n_failed), step=int(d.step),
                                recon_rate=d.recon_rate, null_index=int(d.null_index), B0=d.B0,
+                               n_fallback=int(d.n_fallback),
                                newton_hist=np.array(list(d.newton_hist), dtype=np.int64))
         res["rc"] = rc
         return res

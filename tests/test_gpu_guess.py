@@ -1,0 +1,122 @@
+"""The learned recovery guess on the GPU, through the C ABI: MFMA forward and backward against the
+FP64 oracle network (oracle/mlp.py) on the same FP16-rounded weights and inputs, sampled features
+against the oracle's own cells, training, and the step with the guess against the plain oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_1508_03452_amd import workloads as W
+
+from .parity_util import field_errors, field_scale, gpu_moments_np, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _f16(a):
+    return np.asarray(a, dtype=np.float16).astype(np.float64)
+
+
+def test_mfma_forward_and_gradient_match_the_oracle_network():
+    """FP16 weights and inputs (biases FP32), FP32 accumulation: outputs, loss and every gradient
+    tensor within 1e-2 of the FP64 oracle evaluated on the same rounded numbers (max-norm relative)."""
+    torch = _torch_cuda()
+    from paper_1508_03452_amd.rmhdlb import mlp_eval
+    rng = np.random.default_rng(21)
+    w = W.mlp_init(5).astype(np.float32)
+    w[mlp.N_PARAMS - 2:] = [0.1, -0.2]
+    n = 384
+    X = rng.normal(size=(n, 6)).astype(np.float32)
+    Yt = rng.normal(size=(n, 2)).astype(np.float32)
+    Y, g, loss = mlp_eval(w, torch.from_numpy(X).cuda(), torch.from_numpy(Yt).cuda())
+    Y, g, loss = Y.cpu().numpy(), g.cpu().numpy(), float(loss.cpu().numpy()[0])
+    P = mlp.unflatten(w.astype(np.float64))
+    for k in ("W1", "W2", "W3"):
+        P[k] = _f16(P[k])
+    Yo, _ = mlp.forward(P, _f16(X))
+    Lo, Go = mlp.loss_and_grad(P, _f16(X), Yt.astype(np.float64))
+    print(f"[guess] forward max rel {np.abs(Y - Yo).max() / np.abs(Yo).max():.2e}", flush=True)
+    assert np.abs(Y - Yo).max() <= 1e-2 * np.abs(Yo).max()
+    assert abs(loss - Lo) <= 1e-2 * Lo
+    G = mlp.unflatten(g.astype(np.float64))
+    for k, _ in mlp.SHAPES:
+        err = np.abs(G[k] - Go[k]).max() / np.abs(Go[k]).max()
+        print(f"[guess] grad {k} rel {err:.2e}", flush=True)
+        assert err <= 1e-2, k
+
+
+def test_sampled_features_and_targets_match_the_oracle_cells():
+    _torch_cuda()
+    w = W.kh(nx=96, ny=160, v0=0.4, ratio=10.0, sigma=1e3)
+    o = run_oracle(w, 5)
+    s = run_gpu(w, 5)
+    ns = 1000
+    F, T, rc = s.guess_samples(ns)
+    assert rc == 0
+    ft = o.fluid_tensor()
+    cells = (np.arange(ns, dtype=np.int64) * w.ncells) // ns
+    Fo = mlp.features(ft["Ef"][cells], ft["S"][cells], ft["Pi"][cells], ft["N0"][cells])
+    To = mlp.targets(ft["eps"][cells], ft["beta"][cells], ft["Ef"][cells])
+    ef = np.abs(F.cpu().numpy() - Fo).max() / np.abs(Fo).max()
+    et = np.abs(T.cpu().numpy() - To).max()
+    print(f"[guess] features {ef:.2e} targets {et:.2e}", flush=True)
+    assert ef < 1e-12 and et < 1e-12
+
+
+def _trained_solver(w, steps, storage="f64", iters=400):
+    s = run_gpu(w, steps, storage=storage)
+    weights, losses = s.train_guess(W.mlp_init(11), n_samples=min(w.ncells, 16384), iters=iters, batch=512,
+                                    lr=3e-3)
+    return s, weights, losses
+
+
+def test_training_reduces_the_loss():
+    _torch_cuda()
+    s, weights, losses = _trained_solver(W.kh(nx=96, ny=160, v0=0.4, ratio=10.0, sigma=1e3), 10)
+    print(f"[guess] loss {losses[:3]} -> {losses[-3:]}", flush=True)
+    assert np.isfinite(losses).all()
+    assert losses[-20:].mean() < 0.2 * losses[:5].mean()
+    assert np.isfinite(weights["w"]).all() and (weights["sd_x"] > 0).all()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f16"])
+def test_step_with_learned_guess_matches_the_plain_oracle(storage):
+    """Newton from the network's guess reaches the same root: the FP64 state agrees with the plain
+    oracle to the plain bound; the FP16-shifted form stays within its stated bound.  The iteration
+    counts with and without the guess are reported (the gain test)."""
+    _torch_cuda()
+    w = W.kh(nx=96, ny=160, v0=0.4, ratio=10.0, sigma=1e3)
+    s, weights, _ = _trained_solver(w, 10, storage)
+    plain = run_gpu(w, 10, storage=storage)
+    s.set_guess(True)
+    s.step(10)
+    plain.step(10)
+    o = run_oracle(w, 20)
+    mo = o.moments()
+    mg = gpu_moments_np(s)
+    mp = gpu_moments_np(plain)
+    dg, dp = mg["diag"], mp["diag"]
+    assert dg["n_failed"] == 0
+    print(f"[guess] {storage} mean Newton iterations: guess {dg['mean_iters']:.3f} "
+          f"(fallbacks {dg['n_fallback']}) vs plain {dp['mean_iters']:.3f}; "
+          f"hist guess {dg['newton_hist'][:8].tolist()} plain {dp['newton_hist'][:8].tolist()}", flush=True)
+    errs = field_errors(mo, mg, field_scale(w))
+    worst = max(errs, key=errs.get)
+    print(f"[guess] {storage} vs oracle worst {worst}={errs[worst]:.2e}", flush=True)
+    if storage == "f64":
+        assert errs[worst] <= TOL, (worst, errs[worst])
+    else:
+        e_plain = field_errors(mo, mp, field_scale(w))
+        # same stated bound as the plain FP16 form (the root is the same; only rounding differs)
+        for k in errs:
+            assert errs[k] <= max(5e-2 if k in ("Jx", "Jy", "Jz", "rho_c") else 5e-3, 2 * e_plain[k]), k
+    assert dg["n_fallback"] < 0.05 * w.ncells
