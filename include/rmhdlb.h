@@ -179,8 +179,10 @@ int rmhdlb_set_driven_face(rmhdlb_ctx *ctx, const rmhdlb_face_in *face);
  * and scale invariants of the cell's fluid tensor (|S|/E_f, S^.Pi S^/E_f,
  * tr Pi/E_f, |Pi S^ - (S^.Pi S^) S^|/E_f, |Pi|_F/E_f, N^0/E_f with E_f =
  * T_fl^00, S = T_fl^0a, Pi = T_fl^ab, S^ = S/|S|), normalised, it predicts
- * (lambda/E_f, |beta|) normalised.  The guess is used when it lies below E_f
- * with Pi + lambda I positive definite and phi' > 0 there (and predicted
+ * (lambda/E_f, |beta|) normalised.  Cells with |S|/E_f <= 0.02 take no
+ * guess (Newton from E_f needs one or two steps there), and a wavefront of
+ * only such cells skips the network.  The guess is used when it lies below
+ * E_f with Pi + lambda I positive definite and phi' > 0 there (and predicted
  * |beta| < 0.999); otherwise Newton starts from E_f (a fallback).  Newton
  * then converges to the same root, so the guess changes iteration counts,
  * not results.  Inference runs inside the step on MFMA (FP16 weights and

@@ -155,10 +155,10 @@ __device__ __forceinline__ int recover(double Ef, const double S[3], const doubl
 
 // Start from a guess lam0 when it lies below E_f on the increasing branch of
 // phi (Pi + lam0 I positive definite, phi'(lam0) > 0); otherwise from E_f,
-// with fallback = 1.
+// with fallback = 1 (lam0 = E_f means no guess was offered: fallback = 0).
 __device__ __forceinline__ int recover_from_guess(double Ef, const double S[3], const double Pi[6], double lam0,
                                                   double& lam, double beta[3], int& fallback) {
-    fallback = 1;
+    fallback = lam0 == Ef ? 0 : 1;
     if (lam0 < Ef) {  // false for NaN
         double y[3];
         const bool pd = solve_shifted_pd(Pi, lam0, S, y);

@@ -169,14 +169,21 @@ __device__ __forceinline__ void fluid_tensor(const Consts& K, const CellSol& M, 
 // lane per cell (SINGLE, two passes of 32 cells).
 enum GuessMode { GUESS_NONE = 0, GUESS_PAIR = 1, GUESS_SINGLE = 2 };
 
+// Below this momentum ratio |S| / E_f Newton from E_f converges in one or
+// two steps; such cells take no guess, and a wavefront of only such cells
+// skips the network.
+constexpr double GUESS_MIN_FLOW = 0.02;
+
 // Network guess of the eigenvalue for this lane's cell (all lanes of the
-// wavefront call it together).  NaN when the predicted |beta| >= 0.999
-// (those cells start from E_f).
+// wavefront call it together).  E_f (no guess) for nearly resting cells; NaN
+// when the predicted |beta| >= 0.999 (those cells fall back to E_f).
 template <int GM>
 __device__ __forceinline__ double guess_lambda(const GuessTables* __restrict__ gt, double Ef, const double S[3],
                                                const double Pi[6], double N0) {
     double f[6];
     mlp_features(Ef, S, Pi, N0, f);
+    const bool moving = f[0] > GUESS_MIN_FLOW;
+    if (!__any(moving)) return Ef;  // uniform over the wavefront
     float x[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) x[j] = (float)((f[j] - (double)gt->mu_x[j]) * (double)gt->inv_sd_x[j]);
@@ -193,6 +200,7 @@ __device__ __forceinline__ double guess_lambda(const GuessTables* __restrict__ g
     }
     const double t0 = (double)gt->mu_t[0] + (double)gt->sd_t[0] * (double)y0;
     const double bn = (double)gt->mu_t[1] + (double)gt->sd_t[1] * (double)y1;
+    if (!moving) return Ef;
     return bn < 0.999 ? Ef * t0 : __builtin_nan("");
 }
 
