@@ -52,7 +52,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="flare", choices=["flare", "kh"])
+    ap.add_argument("--workload", default="flare", choices=["flare", "kh", "sweep"],
+                    help="flare: the 256x256x512 box (headline); kh: the 1024x2048 slab; sweep: 64 KH slabs "
+                         "of uneven sizes stepped as one batch")
     ap.add_argument("--storage", default="f64", choices=["f64", "f32", "f16"])
     ap.add_argument("--guess", action="store_true",
                     help="learned recovery guess: trained on the state after the warm-up (untimed), then used")
@@ -81,8 +83,57 @@ def cpu_baseline(budget_s):
                       f"single-threaded FP64 C oracle on {os.cpu_count()} visible host cores"}
 
 
+def sweep_main(args):
+    """The batched sweep: 64 KH slabs (uneven sizes, sigma, shear, density ratio), FP32 storage, stepped
+    as one batch (one launch per step over all instances, hipGraph replays), tile width autotuned."""
+    import torch
+    from paper_1508_03452_amd import workloads as W
+    from paper_1508_03452_amd.rmhdlb import Batch
+    torch.cuda.set_device(0)
+    specs = W.sweep_specs()
+    st = torch.cuda.Stream()
+    storage = "f32" if args.storage == "f64" else args.storage
+    b = Batch([W.sweep_layout(sp) for sp in specs], storage=storage, stream=st)
+    for sp, inst in zip(specs, b.instances):
+        w = W.sweep_instance(sp)
+        inst.init_fields(w.fields)
+        del w
+    ncell = sum(sp["nx"] * sp["ny"] for sp in specs)
+    b.step(args.warmup)
+    px = b.autotune()
+    b.step(2)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(st)
+    b.step(args.steps)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    failed = sum(inst.moments(fields=())["diag"]["n_failed"] for inst in b.instances)
+    dist_b, e_b = {"f32": (4, 4), "f16": (2, 4)}[storage]
+    alg_bytes = 2 * (63 * dist_b + 3 * e_b) * ncell
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    out = {"metric": METRIC, "value": round(ncell / (ms * 1e-3) / 1e6, 2), "unit": "MLUPS", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": f"{storage} storage, f32 arithmetic", "data": "synthetic",
+           "config": {"workload": f"batched sweep: {len(specs)} KH slabs, nx, ny in 256..1024, {ncell} cells, "
+                                  f"sigma 1e2..1e5, one launch per step, hipGraph replays",
+                      "storage": storage, "cells": ncell, "tile_px": px, "failed_cells": failed,
+                      "wall_s_timed": round(wall, 3)},
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_fused_batch",
+                        "alg_bytes_per_launch": alg_bytes}}
+    print(json.dumps(out), flush=True)
+    b.close()
+
+
 def main():
     args = parse()
+    if args.workload == "sweep" and args.gpus == 1:
+        return sweep_main(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
                                    "described in DESIGN.md, not implemented)"}))

@@ -238,6 +238,51 @@ int rmhdlb_guess_samples(rmhdlb_ctx *ctx, int32_t n_samples, double *F, double *
 int rmhdlb_mlp_eval(const float *w, const float *X, const float *Yt, int32_t n, float *Y, float *grad, float *loss,
                     void *hip_stream);
 
+/* ---- launch tuning and batched sweeps --------------------------------------
+ * The fused step runs blocks of 128 cells (two lanes per cell) shaped
+ * px x (128 / px), px in {64, 32, 16}, each walking zb z-planes. */
+
+/* Time every (px, zb) shape (zb in {1, 2, 4, 8} up to nz) on the context's
+ * current state with HIP events and keep the fastest for its later steps.
+ * The state is not advanced (each timed step reads the current buffer and
+ * writes the other).  Results are cached per process by grid size, storage
+ * and boundary kinds; a cached shape is reused without timing.  The chosen
+ * shape is returned in *px, *zb (either may be NULL).  Synchronises. */
+int rmhdlb_autotune(rmhdlb_ctx *ctx, int32_t *px, int32_t *zb);
+
+/* Set the shape directly: px in {64, 32, 16}, zb >= 1 (RMHDLB_EINVAL otherwise). */
+int rmhdlb_set_tuning(rmhdlb_ctx *ctx, int32_t px, int32_t zb);
+
+/* A batch of independent instances (for example a parameter sweep) stepped
+ * together: every step is one launch over the blocks of all instances (plus
+ * one face-pass launch when some instance has open faces with the div B
+ * adjustment), instead of one launch per instance.  On a non-NULL stream
+ * two consecutive steps are captured once into a hipGraph and replayed.
+ * Every instance is a full context (rmhdlb_batch_instance) for
+ * init_fields, set_driven_face, moments, get/set_state; all share the
+ * storage type and the stream; the learned guess is not used in batched
+ * steps (RMHDLB_EUNSUPPORTED if an instance has it on).  Results are
+ * bitwise those of stepping each instance alone with the same tile shape. */
+typedef struct rmhdlb_batch rmhdlb_batch;
+
+/* params: n parameter sets (n >= 1); on failure *out is NULL. */
+int rmhdlb_batch_create(const rmhdlb_params *params, int32_t n, void *hip_stream, rmhdlb_batch **out);
+
+/* Instance i (0 <= i < n) as a context owned by the batch (NULL if out of range). */
+rmhdlb_ctx *rmhdlb_batch_instance(rmhdlb_batch *batch, int32_t i);
+
+/* Queue nsteps batched steps.  Every instance must be at the same buffer
+ * parity (stepped only through the batch since init_fields), else
+ * RMHDLB_EINVAL. */
+int rmhdlb_batch_step(rmhdlb_batch *batch, int64_t nsteps);
+
+/* Time the tile widths px in {64, 32, 16} of the batched step (state not
+ * advanced) and keep the fastest; *px receives it (may be NULL).  Synchronises. */
+int rmhdlb_batch_autotune(rmhdlb_batch *batch, int32_t *px);
+
+/* Release the batch and its instances.  NULL is accepted. */
+int rmhdlb_batch_destroy(rmhdlb_batch *batch);
+
 /* Release the context and its device memory.  NULL is accepted. */
 int rmhdlb_destroy(rmhdlb_ctx *ctx);
 

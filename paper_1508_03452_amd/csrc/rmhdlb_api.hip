@@ -8,7 +8,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
+#include <vector>
 
 #include "rmhdlb.h"
 #include "rmhdlb_internal.h"
@@ -292,6 +296,7 @@ int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** ou
     // Launch shape: z-planes per block (overridable through RMHDLB_ZB for
     // tuning sweeps).
     C->tune.zb = 4;
+    C->tune.px = 64;
     if (const char* v = getenv("RMHDLB_ZB")) C->tune.zb = atoi(v) > 0 ? atoi(v) : 1;
     *out = C;
     return RMHDLB_OK;
@@ -564,6 +569,297 @@ int rmhdlb_mlp_eval(const float* w, const float* X, const float* Yt, int32_t n, 
         rc = RMHDLB_EDEVICE;
     (void)hipFree(wd);
     return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- tuning
+
+namespace {
+
+typedef std::tuple<int, int, int, int, int, int> TuneKey;  // nx, ny, nz, storage, divb, driven
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+std::mutex g_tune_mutex;
+
+// Average duration (ms) of `reps` calls of fn on the stream after one warm-up.
+template <typename Fn>
+int time_ms(hipStream_t st, int reps, Fn fn, float* ms) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return RMHDLB_EDEVICE;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return RMHDLB_EDEVICE;
+    }
+    int rc = fn() == hipSuccess ? RMHDLB_OK : RMHDLB_EDEVICE;
+    if (rc == RMHDLB_OK && hipEventRecord(a, st) != hipSuccess) rc = RMHDLB_EDEVICE;
+    for (int r = 0; r < reps && rc == RMHDLB_OK; ++r)
+        if (fn() != hipSuccess) rc = RMHDLB_EDEVICE;
+    if (rc == RMHDLB_OK && (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                            hipEventElapsedTime(ms, a, b) != hipSuccess))
+        rc = RMHDLB_EDEVICE;
+    *ms /= reps;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out) {
+    if (!C) return RMHDLB_EINVAL;
+    const TuneKey key(C->K.nx, C->K.ny, C->K.nz, C->storage, C->K.divb, C->K.drv);
+    std::pair<int, int> best(64, 4);
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mutex);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            best = it->second;
+            cached = true;
+        }
+    }
+    if (!cached) {
+        float best_ms = 1e30f;
+        const int pxs[3] = {64, 32, 16}, zbs[4] = {1, 2, 4, 8};
+        for (int pi = 0; pi < 3; ++pi)
+            for (int zi = 0; zi < 4; ++zi) {
+                if (zbs[zi] > C->K.nz && zbs[zi] != 1) continue;
+                if (C->guess_mode && pxs[pi] != 64) continue;  // the guess path has 64-wide tiles only
+                rmhd::StepTuning t;
+                t.px = pxs[pi];
+                t.zb = zbs[zi];
+                float ms = 0.0f;
+                const int rc = time_ms(C->stream, 3, [&]() {
+                    return RMHD_DISPATCH(C, launch_step)(C->sb[C->cur], C->sb[1 - C->cur], C->K, t, C->faceB,
+                                                         C->guess_mode ? C->gt : nullptr, C->stream);
+                }, &ms);
+                if (rc != RMHDLB_OK) return rc;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = std::make_pair(t.px, t.zb);
+                }
+            }
+        std::lock_guard<std::mutex> g(g_tune_mutex);
+        g_tune_cache[key] = best;
+    }
+    C->tune.px = best.first;
+    C->tune.zb = best.second;
+    if (px_out) *px_out = best.first;
+    if (zb_out) *zb_out = best.second;
+    return RMHDLB_OK;
+}
+
+int rmhdlb_set_tuning(rmhdlb_ctx* C, int32_t px, int32_t zb) {
+    if (!C || (px != 64 && px != 32 && px != 16) || zb < 1) return RMHDLB_EINVAL;
+    if (C->guess_mode && px != 64) return RMHDLB_EINVAL;
+    C->tune.px = px;
+    C->tune.zb = zb;
+    return RMHDLB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+
+struct rmhdlb_batch {
+    int n;
+    std::vector<rmhdlb_ctx*> ctx;
+    hipStream_t stream;
+    int storage;
+    int px;
+    std::vector<rmhd::BatchInst> host;
+    rmhd::BatchInst* dev;
+    int total_blocks;
+    int64_t total_face;
+    hipGraphExec_t exec;  // two captured steps (parity 0 then 1), or null
+    int graph_px;         // tile width the graph was captured with
+};
+
+namespace {
+
+// Per-instance table of the batched launches from the instances' current
+// constants and buffers.
+int batch_table(rmhdlb_batch* B) {
+    int64_t blk = 0, face = 0;
+    for (int i = 0; i < B->n; ++i) {
+        rmhdlb_ctx* C = B->ctx[i];
+        rmhd::BatchInst& I = B->host[i];
+        I.K = C->K;
+        for (int b = 0; b < 2; ++b) {
+            I.dist[b] = C->sb[b].dist;
+            I.efield[b] = C->sb[b].efield;
+        }
+        I.faceB = C->faceB;
+        I.zb = std::max(1, std::min(C->tune.zb, C->K.nz));
+        rmhd::step_geometry(C->K, B->px, I.zb, I.tiles_x, I.ncol, I.nblk);
+        I.blk0 = blk;
+        I.face0 = face;
+        blk += I.nblk;
+        face += C->K.divb ? C->K.fo[6] : 0;
+    }
+    if (blk > 2147483647LL - 8) return RMHDLB_EINVAL;
+    B->total_blocks = (int)blk;
+    B->total_face = face;
+    return hipMemcpyAsync(B->dev, B->host.data(), sizeof(rmhd::BatchInst) * B->n, hipMemcpyHostToDevice, B->stream) ==
+                   hipSuccess
+               ? RMHDLB_OK
+               : RMHDLB_EDEVICE;
+}
+
+hipError_t batch_launch(rmhdlb_batch* B, int parity) {
+    switch (B->storage) {
+        case RMHDLB_STORE_F64:
+            return rmhd::launch_batch<double>(B->dev, B->n, B->total_blocks, B->total_face, B->px, parity, B->stream);
+        case RMHDLB_STORE_F32:
+            return rmhd::launch_batch<float>(B->dev, B->n, B->total_blocks, B->total_face, B->px, parity, B->stream);
+        default:
+            return rmhd::launch_batch<_Float16>(B->dev, B->n, B->total_blocks, B->total_face, B->px, parity,
+                                                B->stream);
+    }
+}
+
+void drop_graph(rmhdlb_batch* B) {
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    B->exec = nullptr;
+}
+
+// Capture two steps (parity 0, then 1) into an executable graph; on any
+// failure the batch steps eagerly.
+void capture_graph(rmhdlb_batch* B) {
+    drop_graph(B);
+    if (!B->stream) return;  // the legacy default stream cannot be captured
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    const bool ok = batch_launch(B, 0) == hipSuccess && batch_launch(B, 1) == hipSuccess;
+    if (hipStreamEndCapture(B->stream, &g) != hipSuccess || !ok || !g) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        return;
+    }
+    hipGraphExec_t e = nullptr;
+    if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) == hipSuccess) {
+        B->exec = e;
+        B->graph_px = B->px;
+    } else {
+        (void)hipGetLastError();
+    }
+    (void)hipGraphDestroy(g);
+}
+
+}  // namespace
+
+extern "C" {
+
+int rmhdlb_batch_create(const rmhdlb_params* params, int32_t n, void* hip_stream, rmhdlb_batch** out) {
+    if (!out) return RMHDLB_EINVAL;
+    *out = nullptr;
+    if (!params || n < 1) return RMHDLB_EINVAL;
+    for (int i = 1; i < n; ++i)
+        if (params[i].storage != params[0].storage) return RMHDLB_EINVAL;
+    rmhdlb_batch* B = new (std::nothrow) rmhdlb_batch();
+    if (!B) return RMHDLB_ENOMEM;
+    B->n = n;
+    B->stream = (hipStream_t)hip_stream;
+    B->storage = params[0].storage;
+    B->px = 64;
+    B->dev = nullptr;
+    B->exec = nullptr;
+    B->graph_px = 0;
+    B->ctx.assign(n, nullptr);
+    B->host.resize(n);
+    int rc = RMHDLB_OK;
+    for (int i = 0; i < n && rc == RMHDLB_OK; ++i) rc = rmhdlb_create(&params[i], hip_stream, &B->ctx[i]);
+    if (rc == RMHDLB_OK && hipMalloc((void**)&B->dev, sizeof(rmhd::BatchInst) * n) != hipSuccess) {
+        B->dev = nullptr;
+        rc = RMHDLB_ENOMEM;
+    }
+    if (rc != RMHDLB_OK) {
+        rmhdlb_batch_destroy(B);
+        return rc;
+    }
+    *out = B;
+    return RMHDLB_OK;
+}
+
+rmhdlb_ctx* rmhdlb_batch_instance(rmhdlb_batch* B, int32_t i) {
+    return (B && i >= 0 && i < B->n) ? B->ctx[i] : nullptr;
+}
+
+int rmhdlb_batch_destroy(rmhdlb_batch* B) {
+    if (!B) return RMHDLB_OK;
+    if (B->stream) (void)hipStreamSynchronize(B->stream);
+    drop_graph(B);
+    for (rmhdlb_ctx* C : B->ctx) rmhdlb_destroy(C);
+    if (B->dev) (void)hipFree(B->dev);
+    delete B;
+    return RMHDLB_OK;
+}
+
+int rmhdlb_batch_step(rmhdlb_batch* B, int64_t nsteps) {
+    if (!B || nsteps < 0) return RMHDLB_EINVAL;
+    const int parity0 = B->ctx[0]->cur;
+    for (rmhdlb_ctx* C : B->ctx) {
+        if (C->cur != parity0) return RMHDLB_EINVAL;
+        if (C->guess_mode) return RMHDLB_EUNSUPPORTED;
+    }
+    if (nsteps == 0) return RMHDLB_OK;
+    int rc = batch_table(B);
+    if (rc != RMHDLB_OK) return rc;
+    int parity = parity0;
+    int64_t left = nsteps;
+    if (parity == 1) {
+        if (batch_launch(B, 1) != hipSuccess) return RMHDLB_EDEVICE;
+        parity = 0;
+        --left;
+    }
+    if (left >= 2 && (!B->exec || B->graph_px != B->px)) capture_graph(B);
+    while (left >= 2) {
+        if (B->exec) {
+            if (hipGraphLaunch(B->exec, B->stream) != hipSuccess) return RMHDLB_EDEVICE;
+        } else if (batch_launch(B, 0) != hipSuccess || batch_launch(B, 1) != hipSuccess) {
+            return RMHDLB_EDEVICE;
+        }
+        left -= 2;
+    }
+    if (left == 1) {
+        if (batch_launch(B, 0) != hipSuccess) return RMHDLB_EDEVICE;
+        parity = 1;
+    }
+    for (rmhdlb_ctx* C : B->ctx) {
+        C->cur = parity;
+        C->step += nsteps;
+    }
+    return RMHDLB_OK;
+}
+
+int rmhdlb_batch_autotune(rmhdlb_batch* B, int32_t* px_out) {
+    if (!B) return RMHDLB_EINVAL;
+    const int parity = B->ctx[0]->cur;
+    for (rmhdlb_ctx* C : B->ctx)
+        if (C->cur != parity) return RMHDLB_EINVAL;
+    const int pxs[3] = {64, 32, 16};
+    float best_ms = 1e30f;
+    int best = 64;
+    for (int pi = 0; pi < 3; ++pi) {
+        B->px = pxs[pi];
+        int rc = batch_table(B);
+        if (rc != RMHDLB_OK) return rc;
+        float ms = 0.0f;
+        rc = time_ms(B->stream, 3, [&]() { return batch_launch(B, parity); }, &ms);
+        if (rc != RMHDLB_OK) return rc;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = pxs[pi];
+        }
+    }
+    B->px = best;
+    if (px_out) *px_out = best;
+    return RMHDLB_OK;
 }
 
 int64_t rmhdlb_state_len(const rmhdlb_ctx* C) { return C ? (int64_t)rmhd::NSTATE * C->K.N : -1; }

@@ -94,9 +94,24 @@ __device__ __forceinline__ double block_max_value(double v) {
 
 int num_tiles(const Consts& K);
 
-// Launch shape of the fused step: z-planes walked per block.
+// Launch shape of the fused step: z-planes walked per block and the tile
+// width along x (64, 32 or 16 cells; the tile has 128 cells).
 struct StepTuning {
     int zb;
+    int px;
+};
+
+// One instance of a batched step: its constants, both state buffers (cell
+// 0 of the distributions and of E_prev), its face-pass output, its launch
+// geometry and its first block and face-pass thread in the batched launches.
+struct BatchInst {
+    Consts K;
+    void* dist[2];
+    void* efield[2];
+    double* faceB;
+    int tiles_x, ncol, zb, nblk;
+    int64_t blk0;
+    int64_t face0;
 };
 
 struct GuessTables;
@@ -178,6 +193,14 @@ hipError_t launch_ghost(const FacePtrs& in, const Consts& K, const StateBuf& dst
 hipError_t launch_init_ref(const InPtrs& in, const Consts& K, double* part, double* result, hipStream_t s);
 template <typename TS>
 hipError_t launch_face_b(const StateBuf& src, const Consts& K, double* faceB, hipStream_t s);
+// Launch geometry of the fused step for a tile width px and zb planes:
+// tiles along x, columns, blocks.
+void step_geometry(const Consts& K, int px, int zb, int& tiles_x, int& ncol, int& nblk);
+// One batched step (face pass of the instances that need it, then the fused
+// step of all) reading buffer `parity` of every instance.
+template <typename TS>
+hipError_t launch_batch(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face, int px, int parity,
+                        hipStream_t s);
 template <typename TS>
 hipError_t launch_guess_samples(const StateBuf& src, const Consts& K, double* faceB, int ns, double* F, double* T,
                                 double* part, double* result, hipStream_t s);

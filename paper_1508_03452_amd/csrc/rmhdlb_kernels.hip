@@ -459,7 +459,7 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 // path): the transport is linear and the shift is uniform, so the transported
 // value is shift + transport(d); the moments add the exact sums of the shifts;
 // the collisions write the new deviations directly.
-constexpr int PX = 64, PY = 2, PTPB = 2 * PX * PY;
+constexpr int PTPB = 256;  // threads of a fused-step block: 128 cells, two lanes each
 #ifndef RMHDLB_WAVES
 #define RMHDLB_WAVES 2  // waves per SIMD the fused kernel is compiled for
 #endif
@@ -661,26 +661,24 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
 
 // ------------------------------------------------------------------ kernels
 
-// One block owns a 64 x 2 column of cells (two lanes per cell) and walks zb
-// consecutive z-planes.  Blocks are numbered column-fastest within a z-chunk
-// and XCD k receives the contiguous block range [k P, (k + 1) P): the columns
-// one XCD runs at the same time are neighbours marching through the same
-// planes, so the y-halo and the z-neighbour planes of the stencil meet in
-// that XCD's L2.
+// One block owns a PXT x (128 / PXT) column of cells (two lanes per cell)
+// and walks zb consecutive z-planes.  Blocks are numbered column-fastest
+// within a z-chunk and XCD k receives the contiguous block range
+// [k P, (k + 1) P): the columns one XCD runs at the same time are neighbours
+// marching through the same planes, so the y-halo and the z-neighbour planes
+// of the stencil meet in that XCD's L2.
 // With the learned guess the network runs on whole wavefronts, so lanes past
 // a ragged edge stay and compute a copy of the edge cell without storing it.
-template <bool NT, typename TS, typename TE, typename V, int GM>
-__global__ __launch_bounds__(PTPB, RMHDLB_WAVES) void k_fused_step(const TS* __restrict__ sd, const TE* __restrict__ se,
-                                                        TS* __restrict__ dd, TE* __restrict__ de,
-                                                        const double* __restrict__ faceB,
-                                                        const GuessTables* __restrict__ gt, Consts K,
-                                                        int tiles_x, int ncol, int zb, int nblk) {
-    const int b = tile_of_block(nblk);
-    if (b >= nblk) return;  // uniform over the block
+template <bool NT, typename TS, typename TE, typename V, int GM, int PXT>
+__device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE* __restrict__ se,
+                                            TS* __restrict__ dd, TE* __restrict__ de,
+                                            const double* __restrict__ faceB, const GuessTables* __restrict__ gt,
+                                            const Consts& K, int tiles_x, int ncol, int zb, int b) {
+    constexpr int PYT = 128 / PXT;
     const int col = b % ncol, zc = b / ncol;
     const int tx = col % tiles_x, ty = col / tiles_x;
     const int c = threadIdx.x >> 1, h = threadIdx.x & 1;
-    int x = tx * PX + (c % PX), y = ty * PY + c / PX;
+    int x = tx * PXT + (c % PXT), y = ty * PYT + c / PXT;
     const bool active = x < K.nx && y < K.ny;
     if constexpr (GM == GUESS_NONE) {
         if (!active) return;  // both lanes of a pair leave together
@@ -695,6 +693,48 @@ __global__ __launch_bounds__(PTPB, RMHDLB_WAVES) void k_fused_step(const TS* __r
         pair_cell<NT, TS, TE, V, GM>(sd, se, dd, de, faceB, gt, K, cell, nb, h, x, y, z,
                                      GM == GUESS_NONE ? true : active);
     }
+}
+
+template <bool NT, typename TS, typename TE, typename V, int GM, int PXT>
+__global__ __launch_bounds__(PTPB, RMHDLB_WAVES) void k_fused_step(const TS* __restrict__ sd, const TE* __restrict__ se,
+                                                        TS* __restrict__ dd, TE* __restrict__ de,
+                                                        const double* __restrict__ faceB,
+                                                        const GuessTables* __restrict__ gt, Consts K,
+                                                        int tiles_x, int ncol, int zb, int nblk) {
+    const int b = tile_of_block(nblk);
+    if (b >= nblk) return;  // uniform over the block
+    fused_block<NT, TS, TE, V, GM, PXT>(sd, se, dd, de, faceB, gt, K, tiles_x, ncol, zb, b);
+}
+
+// Index of the instance whose range [first[i], first[i + 1]) holds v (first
+// is ascending with first[0] = 0); uniform over the block.
+template <typename Get>
+__device__ __forceinline__ int find_instance(int ninst, int64_t v, Get first) {
+    int lo = 0, hi = ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first(mid) <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Batched step: the blocks of every instance in one launch.  Block b is
+// mapped XCD-aware over the whole batch, then to its instance by the prefix
+// table of block counts, so neighbouring tiles of one instance still share
+// an XCD.  parity selects which of each instance's buffers is read.
+template <bool NT, typename TS, typename TE, typename V, int PXT>
+__global__ __launch_bounds__(PTPB, RMHDLB_WAVES) void k_fused_batch(const BatchInst* __restrict__ I, int ninst,
+                                                         int total, int parity) {
+    const int b = tile_of_block(total);
+    if (b >= total) return;
+    const int i = find_instance(ninst, b, [&](int j) { return I[j].blk0; });
+    const BatchInst& B = I[i];
+    fused_block<NT, TS, TE, V, GUESS_NONE, PXT>(
+        (const TS*)B.dist[parity], (const TE*)B.efield[parity], (TS*)B.dist[1 - parity], (TE*)B.efield[1 - parity],
+        B.faceB, nullptr, B.K, B.tiles_x, B.ncol, B.zb, (int)(b - B.blk0));
 }
 
 // B of Eq. Cal_B at a cell from the streamed h (population order, FP64).
@@ -720,8 +760,8 @@ __device__ __forceinline__ double streamed_B(const TS* __restrict__ src, const C
 //                  high face B_a = B_a(x - e_a) - dx sum_{b != a} d_b B_b.
 // One thread per face cell over the six faces; inactive faces return.
 template <typename TS>
-__global__ __launch_bounds__(256) void k_face_b(const TS* __restrict__ src, Consts K, double* __restrict__ faceB) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void face_b_cell(const TS* __restrict__ src, const Consts& K, double* __restrict__ faceB,
+                                            int64_t i) {
     if (i >= K.fo[6]) return;
     int f = 0;
     while (f < 5 && i >= K.fo[f + 1]) ++f;
@@ -751,6 +791,23 @@ __global__ __launch_bounds__(256) void k_face_b(const TS* __restrict__ src, Cons
     const int s = high ? -1 : 1;
     const double inner = streamed_B(src, K, a, x + s * (a == 0), y + s * (a == 1), z + s * (a == 2));
     faceB[i] = high ? inner - K.dx * dsum : inner + K.dx * dsum;
+}
+
+template <typename TS>
+__global__ __launch_bounds__(256) void k_face_b(const TS* __restrict__ src, Consts K, double* __restrict__ faceB) {
+    face_b_cell(src, K, faceB, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+// The face pass of every instance of a batch in one launch.
+template <typename TS>
+__global__ __launch_bounds__(256) void k_face_b_batch(const BatchInst* __restrict__ I, int ninst, int64_t total,
+                                                      int parity) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_instance(ninst, g, [&](int j) { return I[j].face0; });
+    const BatchInst& B = I[i];
+    if (!B.K.divb) return;
+    face_b_cell((const TS*)B.dist[parity], B.K, B.faceB, g - B.face0);
 }
 
 // Deterministic (key, index) minimum, ties to the lower index; NaN keys never win.
@@ -1197,26 +1254,62 @@ hipError_t launch_face_b(const StateBuf& src, const Consts& K, double* faceB, hi
     return hipGetLastError();
 }
 
+void step_geometry(const Consts& K, int px, int zb, int& tiles_x, int& ncol, int& nblk) {
+    const int py = 128 / px;
+    tiles_x = (K.nx + px - 1) / px;
+    ncol = tiles_x * ((K.ny + py - 1) / py);
+    nblk = ncol * ((K.nz + zb - 1) / zb);
+}
+
+template <typename TS, int GM, int PXT>
+static void launch_fused(const TS* sd, const void* se, TS* dd, void* de, double* faceB, const GuessTables* gt,
+                         const Consts& K, int zb, hipStream_t s) {
+    using TE = typename StoreTypes<TS>::E;
+    using V = typename StoreTypes<TS>::V;
+    int tx, ncol, nblk;
+    step_geometry(K, PXT, zb, tx, ncol, nblk);
+    const int grid = ((nblk + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_fused_step<true, TS, TE, V, GM, PXT>), dim3(grid), dim3(PTPB), 0, s, sd, (const TE*)se, dd,
+                       (TE*)de, (const double*)faceB, gt, K, tx, ncol, zb, nblk);
+}
+
 template <typename TS>
 hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K, const StepTuning& tune,
                        double* faceB, const GuessTables* gt, hipStream_t s) {
-    using TE = typename StoreTypes<TS>::E;
-    using V = typename StoreTypes<TS>::V;
     hipError_t e = launch_face_b<TS>(src, K, faceB, s);
     if (e != hipSuccess) return e;
     const int zb = tune.zb > 0 ? (tune.zb < K.nz ? tune.zb : K.nz) : 1;
-    const int ptx = (K.nx + PX - 1) / PX, pcol = ptx * ((K.ny + PY - 1) / PY);
-    const int pblk = pcol * ((K.nz + zb - 1) / zb), pgrid = ((pblk + 7) / 8) * 8;
     const TS* sd = (const TS*)src.dist;
-    const TE* se = (const TE*)src.efield;
     TS* dd = (TS*)dst.dist;
-    TE* de = (TE*)dst.efield;
-    if (gt)
-        hipLaunchKernelGGL((k_fused_step<true, TS, TE, V, GUESS_PAIR>), dim3(pgrid), dim3(PTPB), 0, s, sd, se, dd,
-                           de, (const double*)faceB, gt, K, ptx, pcol, zb, pblk);
+    if (gt)  // the guess path is built for 64-wide tiles only
+        launch_fused<TS, GUESS_PAIR, 64>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+    else if (tune.px == 32)
+        launch_fused<TS, GUESS_NONE, 32>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+    else if (tune.px == 16)
+        launch_fused<TS, GUESS_NONE, 16>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
     else
-        hipLaunchKernelGGL((k_fused_step<true, TS, TE, V, GUESS_NONE>), dim3(pgrid), dim3(PTPB), 0, s, sd, se, dd,
-                           de, (const double*)faceB, gt, K, ptx, pcol, zb, pblk);
+        launch_fused<TS, GUESS_NONE, 64>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+    return hipGetLastError();
+}
+
+template <typename TS>
+hipError_t launch_batch(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face, int px, int parity,
+                        hipStream_t s) {
+    using TE = typename StoreTypes<TS>::E;
+    using V = typename StoreTypes<TS>::V;
+    if (total_face > 0)
+        hipLaunchKernelGGL((k_face_b_batch<TS>), dim3((unsigned)((total_face + 255) / 256)), dim3(256), 0, s, dev,
+                           ninst, total_face, parity);
+    const int grid = ((total_blocks + 7) / 8) * 8;
+    if (px == 32)
+        hipLaunchKernelGGL((k_fused_batch<true, TS, TE, V, 32>), dim3(grid), dim3(PTPB), 0, s, dev, ninst,
+                           total_blocks, parity);
+    else if (px == 16)
+        hipLaunchKernelGGL((k_fused_batch<true, TS, TE, V, 16>), dim3(grid), dim3(PTPB), 0, s, dev, ninst,
+                           total_blocks, parity);
+    else
+        hipLaunchKernelGGL((k_fused_batch<true, TS, TE, V, 64>), dim3(grid), dim3(PTPB), 0, s, dev, ninst,
+                           total_blocks, parity);
     return hipGetLastError();
 }
 
@@ -1326,6 +1419,7 @@ hipError_t launch_guess_samples(const StateBuf& src, const Consts& K, double* fa
                                            const GuessTables*, hipStream_t);                                          \
     template hipError_t launch_init<TS>(const InPtrs&, const Consts&, double*, const StateBuf&, hipStream_t);         \
     template hipError_t launch_ghost<TS>(const FacePtrs&, const Consts&, const StateBuf&, hipStream_t);               \
+    template hipError_t launch_batch<TS>(const BatchInst*, int, int, int64_t, int, int, hipStream_t);                 \
     template hipError_t launch_guess_samples<TS>(const StateBuf&, const Consts&, double*, int, double*, double*,      \
                                                  double*, double*, hipStream_t);                                      \
     template hipError_t launch_export<TS>(const StateBuf&, double*, const Consts&, hipStream_t);                      \

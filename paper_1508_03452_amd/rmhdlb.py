@@ -69,7 +69,8 @@ class rmhdlb_face_in(ctypes.Structure):
 SYMBOLS = ("rmhdlb_create", "rmhdlb_init_fields", "rmhdlb_step", "rmhdlb_moments", "rmhdlb_destroy",
            "rmhdlb_strerror", "rmhdlb_state_len", "rmhdlb_get_state", "rmhdlb_set_state", "rmhdlb_lattice_tables",
            "rmhdlb_set_driven_face", "rmhdlb_train_guess", "rmhdlb_set_guess_weights", "rmhdlb_set_guess",
-           "rmhdlb_guess_samples", "rmhdlb_mlp_eval")
+           "rmhdlb_guess_samples", "rmhdlb_mlp_eval", "rmhdlb_autotune", "rmhdlb_set_tuning", "rmhdlb_batch_create",
+           "rmhdlb_batch_instance", "rmhdlb_batch_step", "rmhdlb_batch_autotune", "rmhdlb_batch_destroy")
 
 _LIB = None
 
@@ -105,6 +106,15 @@ def load():
     L.rmhdlb_set_guess.argtypes = [vp, ctypes.c_int32]
     L.rmhdlb_guess_samples.argtypes = [vp, ctypes.c_int32, _dp, _dp]
     L.rmhdlb_mlp_eval.argtypes = [fp, fp, fp, ctypes.c_int32, fp, fp, fp, vp]
+    ip32 = ctypes.POINTER(ctypes.c_int32)
+    L.rmhdlb_autotune.argtypes = [vp, ip32, ip32]
+    L.rmhdlb_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.rmhdlb_batch_create.argtypes = [ctypes.POINTER(rmhdlb_params), ctypes.c_int32, vp, ctypes.POINTER(vp)]
+    L.rmhdlb_batch_instance.argtypes = [vp, ctypes.c_int32]
+    L.rmhdlb_batch_instance.restype = vp
+    L.rmhdlb_batch_step.argtypes = [vp, ctypes.c_int64]
+    L.rmhdlb_batch_autotune.argtypes = [vp, ip32]
+    L.rmhdlb_batch_destroy.argtypes = [vp]
     _LIB = L
     return L
 
@@ -202,7 +212,7 @@ def mlp_eval(w, X, Yt, stream=None):
 class Solver:
     """One rmhdlb context on the current torch device and stream.  shape = (nx, ny, nz)."""
 
-    def __init__(self, shape, bc=None, storage="f64", stream=None, **params):
+    def __init__(self, shape, bc=None, storage="f64", stream=None, _handle=None, **params):
         import torch
         self.torch = torch
         self.shape = tuple(int(v) for v in shape)
@@ -210,14 +220,26 @@ class Solver:
         self.grid = (nz, ny, nx)
         self.P = make_params(self.shape, bc, storage, **params)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._owned = _handle is None
+        if _handle is not None:   # an instance owned by a Batch
+            self._h = ctypes.c_void_p(_handle)
+            return
         self._h = ctypes.c_void_p()
         _check(load().rmhdlb_create(ctypes.byref(self.P), ctypes.c_void_p(self.stream.cuda_stream),
                                     ctypes.byref(self._h)), "rmhdlb_create")
 
     def close(self):
-        if getattr(self, "_h", None) and self._h.value:
+        if getattr(self, "_h", None) and self._h.value and getattr(self, "_owned", True):
             load().rmhdlb_destroy(self._h)
-            self._h = ctypes.c_void_p()
+        self._h = ctypes.c_void_p()
+
+    def autotune(self):
+        px, zb = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().rmhdlb_autotune(self._h, ctypes.byref(px), ctypes.byref(zb)), "rmhdlb_autotune")
+        return int(px.value), int(zb.value)
+
+    def set_tuning(self, px, zb):
+        _check(load().rmhdlb_set_tuning(self._h, int(px), int(zb)), "rmhdlb_set_tuning")
 
     def __del__(self):
         try:
@@ -342,3 +364,43 @@ class Solver:
         if isinstance(a, torch.Tensor):
             return a.to(device="cuda", dtype=torch.float64).reshape(-1).contiguous()
         return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).to("cuda")
+
+
+class Batch:
+    """Independent instances stepped together (one launch per step over all of them, captured into a
+    hipGraph on a non-default stream).  specs: list of (shape, bc, params dict)."""
+
+    def __init__(self, specs, storage="f32", stream=None):
+        import torch
+        self.torch = torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        n = len(specs)
+        arr = (rmhdlb_params * n)()
+        for i, (shape, bc, params) in enumerate(specs):
+            arr[i] = make_params(shape, bc, storage, **params)
+        self._h = ctypes.c_void_p()
+        _check(load().rmhdlb_batch_create(arr, n, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._h)),
+               "rmhdlb_batch_create")
+        self.instances = [Solver(shape, bc, storage, self.stream, _handle=load().rmhdlb_batch_instance(self._h, i),
+                                 **params) for i, (shape, bc, params) in enumerate(specs)]
+
+    def step(self, nsteps=1):
+        _check(load().rmhdlb_batch_step(self._h, int(nsteps)), "rmhdlb_batch_step")
+
+    def autotune(self):
+        px = ctypes.c_int32()
+        _check(load().rmhdlb_batch_autotune(self._h, ctypes.byref(px)), "rmhdlb_batch_autotune")
+        return int(px.value)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            for s in self.instances:
+                s._h = ctypes.c_void_p()
+            load().rmhdlb_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -72,6 +72,7 @@ def _params(**kw):
 
 
 PERIODIC3 = (("periodic", "periodic"),) * 3
+KH_BC = (("periodic", "periodic"), ("open", "open"), ("periodic", "periodic"))
 
 
 def alfven(nx=256, ny=4, nz=4, amp=0.01, sigma=1e6, steps=500):
@@ -122,8 +123,7 @@ def kh(nx=1024, ny=2048, nz=1, v0=0.2, ratio=10.0, sigma=1e3, B0=0.1, noise=1e-3
     Bx = B0 * th
     fields = dict(n=n, p=_full(shape, 1.0), u=(ux, uy, zero.copy()), E=(zero.copy(), zero.copy(), uy * Bx),
                   B=(Bx, zero.copy(), zero.copy()), rho_c=zero.copy())
-    bc = (("periodic", "periodic"), ("open", "open"), ("periodic", "periodic"))
-    return Workload("kh", shape, bc, _params(sigma=sigma), fields, steps, meta=dict(v0=v0, ratio=ratio, B0=B0))
+    return Workload("kh", shape, KH_BC, _params(sigma=sigma), fields, steps, meta=dict(v0=v0, ratio=ratio, B0=B0))
 
 
 def flare(nx=256, ny=256, nz=512, sigma=1e3, B0=0.06, seed=512, steps=10000, Lx=6.0, Lz=12.0, v_drive=0.1):
@@ -224,6 +224,29 @@ def random_state(shape=(8, 8, 8), seed=0, vmax=0.3, amp=0.05, Bmag=0.3, Emag=0.0
         rho_c = None
     fields = dict(n=n, p=p, u=tuple(u), E=tuple(np.ascontiguousarray(e) for e in E), B=tuple(B), rho_c=rho_c)
     return Workload("random", tuple(shape), bc, _params(sigma=sigma, **params), fields, 0)
+
+
+def sweep_specs(n=64, seed=64, sizes=tuple(range(256, 1025, 64))):
+    """Parameters of a batched KH sweep: per instance nx, ny uniform on `sizes`, sigma = 10^U[2, 5],
+    v0 ~ U[0.05, 0.4], density ratio ~ U[1, 10], noise seed from the sweep seed.  Returns a list of
+    dicts (nx, ny, sigma, v0, ratio, seed); fields come from kh() with these."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n):
+        out.append(dict(nx=int(rng.choice(sizes)), ny=int(rng.choice(sizes)), sigma=float(10.0 ** rng.uniform(2, 5)),
+                        v0=float(rng.uniform(0.05, 0.4)), ratio=float(rng.uniform(1.0, 10.0)),
+                        seed=int(rng.integers(0, 2 ** 31 - 1))))
+    return out
+
+
+def sweep_layout(spec):
+    """(shape, bc, params) of a sweep instance, as kh() builds them, without its fields."""
+    return (spec["nx"], spec["ny"], 1), KH_BC, _params(sigma=spec["sigma"])
+
+
+def sweep_instance(spec):
+    """The KH slab of one sweep instance."""
+    return kh(nx=spec["nx"], ny=spec["ny"], v0=spec["v0"], ratio=spec["ratio"], sigma=spec["sigma"], seed=spec["seed"])
 
 
 def mlp_init(seed=2024, n_in=6, n_h=32, n_out=2):

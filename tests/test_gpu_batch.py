@@ -1,0 +1,128 @@
+"""Launch shapes, the autotuner and batched sweeps on the GPU, through the C ABI.
+
+Every cell's arithmetic is independent of the block shape and of the other instances of a batch,
+so a different tile shape, a batched launch or a replayed hipGraph must give the same state bit
+for bit; the plain path itself is pinned to the oracle in test_gpu_parity.py."""
+import numpy as np
+import pytest
+
+from paper_1508_03452_amd import workloads as W
+
+from .parity_util import run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _state(s):
+    return s.get_state().cpu().numpy()
+
+
+@pytest.mark.parametrize("px,zb", [(32, 1), (16, 2), (64, 8)])
+def test_tile_shapes_give_identical_states(px, zb):
+    _torch_cuda()
+    w = W.random_state(shape=(70, 13, 9), seed=6, vmax=0.1, Bmag=0.2, Emag=0.02, sigma=3.0,
+                       bc=(("open", "open"), ("periodic", "periodic"), ("open", "open")))
+    a = run_gpu(w, 0)
+    b = run_gpu(w, 0)
+    b.set_tuning(px, zb)
+    a.step(6)
+    b.step(6)
+    assert np.array_equal(_state(a), _state(b))
+
+
+def test_autotune_picks_a_valid_shape_and_keeps_the_state():
+    _torch_cuda()
+    w = W.kh(nx=192, ny=256, v0=0.3, ratio=5.0, sigma=1e3)
+    s = run_gpu(w, 2)
+    before = _state(s)
+    px, zb = s.autotune()
+    print(f"[batch] autotune kh 192x256x1 -> px {px} zb {zb}", flush=True)
+    assert px in (64, 32, 16) and zb >= 1
+    assert np.array_equal(before, _state(s))   # timing does not advance the state
+    assert s.autotune() == (px, zb)            # cached
+    ref = run_gpu(w, 2)
+    s.step(3)
+    ref.step(3)
+    assert np.array_equal(_state(s), _state(ref))
+
+
+def _sweep_workloads(n=5, seed=3):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        nx, ny = int(rng.choice([48, 64, 96, 130])), int(rng.choice([40, 64, 100]))
+        out.append(W.kh(nx=nx, ny=ny, v0=float(rng.uniform(0.05, 0.4)), ratio=float(rng.uniform(1, 10)),
+                        sigma=float(10 ** rng.uniform(2, 4)), seed=i))
+    out.append(W.random_state(shape=(20, 9, 7), seed=9, vmax=0.05, Bmag=0.1, sigma=30.0, solenoidal=True,
+                              bc=(("open", "open"),) * 3))
+    return out
+
+
+def _batch(ws, storage, stream):
+    from paper_1508_03452_amd.rmhdlb import Batch
+    b = Batch([(w.shape, w.bc, w.params) for w in ws], storage=storage, stream=stream)
+    for w, s in zip(ws, b.instances):
+        s.init_fields(w.fields)
+    return b
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_batch_matches_instances_stepped_alone(storage):
+    """Uneven 2-D KH slabs (ragged tiles) plus a 3-D box with open faces: 7 batched steps (graph
+    replays and an eager remainder) equal 7 steps of each instance alone, bit for bit."""
+    torch = _torch_cuda()
+    ws = _sweep_workloads()
+    st = torch.cuda.Stream()
+    b = _batch(ws, storage, st)
+    b.step(7)
+    st.synchronize()
+    for w, s in zip(ws, b.instances):
+        ref = run_gpu(w, 7, storage=storage)
+        assert np.array_equal(_state(s), _state(ref)), w.shape
+        assert s.moments(fields=())["diag"]["step"] == 7
+    b.close()
+
+
+def test_batch_graph_replays_match_eager_steps():
+    """The captured two-step graph replayed three times, with eager work and synchronisation between
+    the replays, against the same batch stepped eagerly on the default stream (no capture)."""
+    torch = _torch_cuda()
+    ws = _sweep_workloads(n=3, seed=4)
+    st = torch.cuda.Stream()
+    g = _batch(ws, "f32", st)
+    e = _batch(ws, "f32", torch.cuda.default_stream())
+    for r in range(3):
+        g.step(2)
+        e.step(2)
+        scratch = torch.ones(1 << 20, device="cuda", dtype=torch.float32).sum()   # unrelated eager work
+        torch.cuda.synchronize()
+        assert float(scratch) == float(1 << 20)
+        for sg, se in zip(g.instances, e.instances):
+            assert np.array_equal(_state(sg), _state(se)), r
+    g.close()
+    e.close()
+
+
+def test_batch_rejects_mixed_parity_and_autotunes():
+    torch = _torch_cuda()
+    from paper_1508_03452_amd.rmhdlb import RmhdlbError
+    ws = _sweep_workloads(n=3, seed=5)
+    st = torch.cuda.Stream()
+    b = _batch(ws, "f32", st)
+    before = [_state(s) for s in b.instances]
+    px = b.autotune()
+    print(f"[batch] batch autotune -> px {px}", flush=True)
+    assert px in (64, 32, 16)
+    for s, x in zip(b.instances, before):
+        assert np.array_equal(_state(s), x)   # timing does not advance the state
+    b.instances[0].step(1)                    # one instance stepped alone: parities differ
+    with pytest.raises(RmhdlbError):
+        b.step(1)
+    b.close()
