@@ -56,6 +56,8 @@ def parse():
                     help="flare: the 256x256x512 box (headline); kh: the 1024x2048 slab; sweep: 64 KH slabs "
                          "of uneven sizes stepped as one batch")
     ap.add_argument("--storage", default="f64", choices=["f64", "f32", "f16"])
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shape (64 x 2 tiles, 4 planes) instead of the autotuned one")
     ap.add_argument("--guess", action="store_true",
                     help="learned recovery guess: trained on the state after the warm-up (untimed), then used")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
@@ -150,6 +152,7 @@ def main():
         s.set_driven_face(w.driven)
     del w.fields
     s.step(args.warmup)
+    shape = (64, 4) if args.no_autotune else s.autotune()   # untimed; the state is not advanced
     train_info = None
     if args.guess:
         t_tr = time.perf_counter()
@@ -194,7 +197,8 @@ def main():
                                 f"driven shearing bottom face, open faces elsewhere"
                                 if args.workload == "flare" else
                                 f"KH shear layer {w.shape[0]}x{w.shape[1]}x{w.shape[2]}, v0=0.2, ratio 10, sigma=1e3"),
-                   "storage": args.storage, "cells": ncell,
+                   "storage": args.storage, "cells": ncell, "tile": f"{shape[0]}x{128 // shape[0]} cells, "
+                                                                    f"{shape[1]} z-planes per block",
                    "recovery": "Newton from the learned guess" if args.guess else "plain Newton",
                    "guess_training": train_info, "guess_fallbacks": d["n_fallback"],
                    "arithmetic": "f64" if args.storage == "f64" else "f32 (recovery and Ohm solve in f64)",

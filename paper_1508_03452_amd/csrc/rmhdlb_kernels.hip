@@ -190,7 +190,7 @@ __device__ __forceinline__ double guess_lambda(const GuessTables* __restrict__ g
     const int lane = threadIdx.x & 63;
     float y0, y1;
     if constexpr (GM == GUESS_PAIR) {
-        mlp_wave(gt, x, 2 * (lane & 31), lane >> 1, y0, y1);
+        mlp_wave(gt, x, lane & 31, lane & 31, y0, y1);  // cell n of the wavefront is lane n (and n + 32)
     } else {
         float a0, a1, c0, c1;
         mlp_wave(gt, x, lane & 31, lane & 31, a0, a1);
@@ -446,13 +446,13 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 
 // ---------------------------------------------------- two lanes per cell
 
-// The fused step with the populations of one cell split over an adjacent
-// lane pair (h = lane & 1).  Slot s = 1..9 of f and g is direction 2s-1+h,
+// The fused step with the populations of one cell split over a lane pair
+// (lanes l and l ^ 32 of a wavefront, h = 0, 1).  Slot s = 1..9 of f and g is direction 2s-1+h,
 // i.e. sgn * e_{2s-1} with sgn = +1 / -1, so both lanes run the same
 // instructions on opposite directions; slot m = 0..11 of h is population
 // 2m+h (same streaming offset, opposite e and b).  Lane 0 also owns the rest
 // populations f_0, g_0; lane 1 owns h_rest.  Partial moments are summed over
-// the pair with one xor-1 shuffle each, and both lanes then run the recovery
+// the pair with one xor-32 shuffle each, and both lanes then run the recovery
 // and the Ohm solve on identical inputs.
 //
 // f and g are handled as stored deviations d (the shift is 0 on the plain
@@ -475,9 +475,14 @@ constexpr int pin_group() {
     return sizeof(V) == 8 ? RMHDLB_GROUP_F64 : RMHDLB_GROUP_F32;
 }
 
+// The two lanes of a cell are l and l ^ 32 of a wavefront: each half of the
+// wavefront then reads 32 consecutive values of one array, which the vector
+// memory path coalesces (with the partner in the adjacent lane every
+// instruction touched two arrays lane by lane and the texture units, not
+// HBM, set the step time).
 template <typename V>
 __device__ __forceinline__ V pair_sum(V v) {
-    return v + __shfl_xor(v, 1, 64);
+    return v + __shfl_xor(v, 32, 64);
 }
 
 template <bool NT, typename TS, typename TE, typename V, int GM>
@@ -677,7 +682,9 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
     constexpr int PYT = 128 / PXT;
     const int col = b % ncol, zc = b / ncol;
     const int tx = col % tiles_x, ty = col / tiles_x;
-    const int c = threadIdx.x >> 1, h = threadIdx.x & 1;
+    // cell c of the tile is lane c % 32 (h = 0) and lane c % 32 + 32 (h = 1) of wavefront c / 32
+    const int lane = threadIdx.x & 63;
+    const int c = (threadIdx.x >> 6) * 32 + (lane & 31), h = lane >> 5;
     int x = tx * PXT + (c % PXT), y = ty * PYT + c / PXT;
     const bool active = x < K.nx && y < K.ny;
     if constexpr (GM == GUESS_NONE) {
