@@ -101,7 +101,8 @@ Consts make_consts(const rmhdlb_params* P) {
     K.fo[0] = 0;
     for (int f = 0; f < 6; ++f) K.fo[f + 1] = K.fo[f] + fsz[f >> 1];
     K.N = (int64_t)P->nx * P->ny * P->nz;
-    K.stride = (ghost_cells(K) + K.N + 63) / 64 * 64;
+    K.g0 = ghost_cells(K);
+    K.stride = (K.g0 + K.N + 63) / 64 * 64;
     const double dt = P->dx / (sqrt(2.0) * P->c);  // dx / dt = sqrt(2) c
     K.c = P->c;
     K.dx = P->dx;

@@ -60,6 +60,7 @@ struct Consts {
     int64_t fo[7];       // offsets of the six face arrays of adjusted normal B (x lo, x hi, y lo, ...), fo[6] = total
     int64_t N;           // cells
     int64_t stride;      // values per state array (ghost planes + N, rounded up)
+    int64_t g0;          // ghost cells in front of cell 0 of every array
     double c, dx, eps0;
     double cour;         // Courant number along a link: kappa c dt / dx
     double kv;           // bulk-viscosity coefficient alpha c dt / dx

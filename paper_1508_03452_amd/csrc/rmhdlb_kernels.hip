@@ -37,6 +37,37 @@ __device__ __forceinline__ void st(T* __restrict__ p, V v) {
         *p = static_cast<T>(v);
 }
 
+// f and g of one direction are stored interleaved: the pair (f_i, g_i) of
+// cell c sits at fg[2 (i S + c)], fg = dist + g0 (the f-g block spans the
+// first 38 S values; ghost cells in front of cell 0 take 2 g0 of them).
+// Both use the same transport stencil, so one vector load serves both.
+template <typename T>
+using vec2 = T __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ int64_t fg_index(const Consts& K, int i, int64_t c) {
+    return 2 * ((int64_t)i * K.stride + c) + K.g0;
+}
+
+template <typename V, typename T>
+__device__ __forceinline__ vec2<V> ldv2(const T* __restrict__ p, int64_t i) {
+    const vec2<T> v = *reinterpret_cast<const vec2<T>*>(p + i);
+    vec2<V> r;
+    r.x = static_cast<V>(v.x);
+    r.y = static_cast<V>(v.y);
+    return r;
+}
+
+template <bool NT, typename T, typename V>
+__device__ __forceinline__ void st2(T* __restrict__ p, V f, V g) {
+    vec2<T> v;
+    v.x = static_cast<T>(f);
+    v.y = static_cast<T>(g);
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, reinterpret_cast<vec2<T>*>(p));
+    else
+        *reinterpret_cast<vec2<T>*>(p) = v;
+}
+
 // Shift of the stored f, g of direction i (0 on the plain FP64 path).
 __device__ __forceinline__ double fshift(const Consts& K, int i) { return K.fsh[i == 0 ? 0 : (i <= 6 ? 1 : 2)]; }
 __device__ __forceinline__ double gshift(const Consts& K, int i) { return K.gsh[i == 0 ? 0 : (i <= 6 ? 1 : 2)]; }
@@ -274,24 +305,27 @@ __device__ __forceinline__ void macroscopic(const TS* __restrict__ src, const TE
     double t0x = 0, t0y = 0, t0z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const TS* __restrict__ fa = src + (int64_t)(OFF_F + i) * K.stride + cell;
-        const TS* __restrict__ ga = src + (int64_t)(OFF_G + i) * K.stride + cell;
-        const double f0 = ld(fa, 0), g0 = ld(ga, 0);
+        const TS* __restrict__ fga = src + fg_index(K, i, cell);
+        auto fg = [&](int o) { return ldv2<double>(fga, 2 * (int64_t)o); };
+        auto fo = [&](int o) { return ld(fga, 2 * (int64_t)o); };
+        const vec2<double> c0 = fg(0);
+        const double f0 = c0.x, g0 = c0.y;
         double fv = f0, gv = g0;
         if (i != 0) {
             const int ex = EX[i], ey = EY[i], ez = EZ[i];
             const int om2 = nb.at(-2 * ex, -2 * ey, -2 * ez), om1 = nb.at(-ex, -ey, -ez), op1 = nb.at(ex, ey, ez);
+            const vec2<double> m2 = fg(om2), m1 = fg(om1), p1 = fg(op1);
             {
-                const double fm2 = ld(fa, om2), fm1 = ld(fa, om1), fp1 = ld(fa, op1);
+                const double fm2 = m2.x, fm1 = m1.x, fp1 = p1.x;
                 const double face_p = f0 + 0.5 * minmod(f0 - fm1, fp1 - f0);
                 const double face_m = fm1 + 0.5 * minmod(fm1 - fm2, f0 - fm1);
-                const double lap = (ld(fa, nb.at(1, 0, 0)) + ld(fa, nb.at(-1, 0, 0))) +
-                                   (ld(fa, nb.at(0, 1, 0)) + ld(fa, nb.at(0, -1, 0))) +
-                                   (ld(fa, nb.at(0, 0, 1)) + ld(fa, nb.at(0, 0, -1))) - 6.0 * f0;
+                const double lap = (fo(nb.at(1, 0, 0)) + fo(nb.at(-1, 0, 0))) +
+                                   (fo(nb.at(0, 1, 0)) + fo(nb.at(0, -1, 0))) +
+                                   (fo(nb.at(0, 0, 1)) + fo(nb.at(0, 0, -1))) - 6.0 * f0;
                 fv = f0 - K.cour * (face_p - face_m) + K.kv * lap;
             }
             {
-                const double gm2 = ld(ga, om2), gm1 = ld(ga, om1), gp1 = ld(ga, op1);
+                const double gm2 = m2.y, gm1 = m1.y, gp1 = p1.y;
                 const double face_p = g0 + 0.5 * minmod(g0 - gm1, gp1 - g0);
                 const double face_m = gm1 + 0.5 * minmod(gm1 - gm2, g0 - gm1);
                 gv = g0 - K.cour * (face_p - face_m);
@@ -505,11 +539,11 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
     V t00 = 0, t0x = 0, t0y = 0, t0z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0, n0 = 0;
     // slot 0: f_0, g_0 (lane 0) and h_rest (lane 1)
     {
-        const V a = ldv<V>(sd, (h ? (int64_t)(OFF_H + QH) : (int64_t)OFF_F) * S + cell);
-        const V g = ldv<V>(sd, (int64_t)OFF_G * S + cell);
-        Fv[0] = h ? V(0) : a;
-        Gv[0] = h ? V(0) : g;
-        Hv[12] = h ? a : V(0);
+        const vec2<V> fg0 = ldv2<V>(sd, fg_index(K, 0, cell));
+        const V hr = ldv<V>(sd, (int64_t)(OFF_H + QH) * S + cell);
+        Fv[0] = h ? V(0) : fg0.x;
+        Gv[0] = h ? V(0) : fg0.y;
+        Hv[12] = h ? hr : V(0);
         t00 = Fv[0];
         n0 = Gv[0];
     }
@@ -523,17 +557,17 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
             const int om2 = h ? nb.at(2 * ex, 2 * ey, 2 * ez) : nb.at(-2 * ex, -2 * ey, -2 * ez);
             const int om1 = h ? nb.at(ex, ey, ez) : nb.at(-ex, -ey, -ez);
             const int op1 = h ? nb.at(-ex, -ey, -ez) : nb.at(ex, ey, ez);
-            const TS* __restrict__ fa = sd + (int64_t)(OFF_F + i0) * S;
-            const TS* __restrict__ ga = sd + (int64_t)(OFF_G + i0) * S;
-            const V f0 = ldv<V>(fa, hc), fm2 = ldv<V>(fa, hc + om2), fm1 = ldv<V>(fa, hc + om1),
-                    fp1 = ldv<V>(fa, hc + op1);
-            const V lap = (ldv<V>(fa, hc + lap_xp) + ldv<V>(fa, hc + lap_xm)) +
-                          (ldv<V>(fa, hc + lap_yp) + ldv<V>(fa, hc + lap_ym)) +
-                          (ldv<V>(fa, hc + lap_zp) + ldv<V>(fa, hc + lap_zm)) - V(6) * f0;
+            const TS* __restrict__ fga = sd + fg_index(K, i0, 0);  // uniform base of direction i0's pairs
+            const vec2<V> c0 = ldv2<V>(fga, 2 * (int64_t)hc), m2 = ldv2<V>(fga, 2 * (int64_t)(hc + om2)),
+                          m1 = ldv2<V>(fga, 2 * (int64_t)(hc + om1)), p1 = ldv2<V>(fga, 2 * (int64_t)(hc + op1));
+            const V f0 = c0.x, fm2 = m2.x, fm1 = m1.x, fp1 = p1.x;
+            const V lap = (ldv<V>(fga, 2 * (int64_t)(hc + lap_xp)) + ldv<V>(fga, 2 * (int64_t)(hc + lap_xm))) +
+                          (ldv<V>(fga, 2 * (int64_t)(hc + lap_yp)) + ldv<V>(fga, 2 * (int64_t)(hc + lap_ym))) +
+                          (ldv<V>(fga, 2 * (int64_t)(hc + lap_zp)) + ldv<V>(fga, 2 * (int64_t)(hc + lap_zm))) -
+                          V(6) * f0;
             const V fv = f0 - cour * ((f0 + V(0.5) * minmod(f0 - fm1, fp1 - f0)) -
                                       (fm1 + V(0.5) * minmod(fm1 - fm2, f0 - fm1))) + kv * lap;
-            const V g0 = ldv<V>(ga, hc), gm2 = ldv<V>(ga, hc + om2), gm1 = ldv<V>(ga, hc + om1),
-                    gp1 = ldv<V>(ga, hc + op1);
+            const V g0 = c0.y, gm2 = m2.y, gm1 = m1.y, gp1 = p1.y;
             const V gv = g0 - cour * ((g0 + V(0.5) * minmod(g0 - gm1, gp1 - g0)) -
                                       (gm1 + V(0.5) * minmod(gm1 - gm2, g0 - gm1)));
             Fv[s] = fv;
@@ -630,9 +664,10 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
     const V bx_ = (V)M.beta[0], by_ = (V)M.beta[1], bz_ = (V)M.beta[2];
     if (h == 0) {
         const V q0 = (V)K.fsh[0] - fe.template eq<0>();
-        put(dd + (int64_t)OFF_F * S + cell, Fv[0] - rate * (Fv[0] + q0));
         const V geq0 = (V)K.wp[0] * ng * (V(1) - gc3b2);
-        put(dd + (int64_t)OFF_G * S + cell, (Gv[0] + wg * (geq0 - (V)K.gsh[0])) * inv1wg);
+        if (active)
+            st2<NT>(dd + fg_index(K, 0, cell), Fv[0] - rate * (Fv[0] + q0),
+                    (Gv[0] + wg * (geq0 - (V)K.gsh[0])) * inv1wg);
     } else {
         put(dd + (int64_t)(OFF_H + QH) * S + cell, (V)(2.0 * M.rho) - Hv[12]);
     }
@@ -644,9 +679,10 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
             const V eb = sgn * (EX[i0] * bx_ + EY[i0] * by_ + EZ[i0] * bz_);
             const V om = rate * (V(1) - V(KAPPA) * eb);
             const V q = (V)K.fsh[cls] - feq_signed<i0>(fe, sgn);
-            put(dd + (int64_t)(OFF_F + i0) * S + hc, Fv[s] - om * (Fv[s] + q));
             const V geq = (V)K.wp[cls] * ng * (V(1) + gc1 * eb + gc2 * eb * eb - gc3b2);
-            put(dd + (int64_t)(OFF_G + i0) * S + hc, (Gv[s] + wg * (geq - (V)K.gsh[cls])) * inv1wg);
+            if (active)
+                st2<NT>(dd + fg_index(K, i0, 0) + 2 * (int64_t)hc, Fv[s] - om * (Fv[s] + q),
+                        (Gv[s] + wg * (geq - (V)K.gsh[cls])) * inv1wg);
         }
     });
     const V cj = (V)(1.0 / (16.0 * 1.4142135623730951 * K.c)), ce = (V)(1.0 / (8.0 * 1.4142135623730951 * K.c));
@@ -1046,10 +1082,9 @@ __global__ __launch_bounds__(TPB) void k_init_ghost(FacePtrs in, Consts K, TS* _
         static_for<0>([&](auto ic) {
             constexpr int q = decltype(ic)::value;
             const double eb = EX[q] * beta[0] + EY[q] * beta[1] + EZ[q] * beta[2];
-            dd[(int64_t)(OFF_F + q) * K.stride + g] = static_cast<TS>(fe.template eq<q>() - fshift(K, q));
             const double wpi = q == 0 ? K.wp[0] : (q <= 6 ? K.wp[1] : K.wp[2]);
-            dd[(int64_t)(OFF_G + q) * K.stride + g] =
-                static_cast<TS>(wpi * n * gam * (1.0 + K.gc1 * eb + K.gc2 * eb * eb - K.gc3 * b2) - gshift(K, q));
+            st2<false>(dd + fg_index(K, q, g), fe.template eq<q>() - fshift(K, q),
+                       wpi * n * gam * (1.0 + K.gc1 * eb + K.gc2 * eb * eb - K.gc3 * b2) - gshift(K, q));
         });
 #pragma unroll
         for (int k = 0; k < QH; ++k) {
@@ -1131,10 +1166,9 @@ __global__ __launch_bounds__(TPB) void k_init_state(InPtrs in, Consts K, int til
     static_for<0>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const double eb = EX[i] * beta[0] + EY[i] * beta[1] + EZ[i] * beta[2];
-        dst[(int64_t)(OFF_F + i) * K.stride + cell] = static_cast<TS>(fe.template eq<i>() - fshift(K, i));
         const double wpi = i == 0 ? K.wp[0] : (i <= 6 ? K.wp[1] : K.wp[2]);
-        dst[(int64_t)(OFF_G + i) * K.stride + cell] =
-            static_cast<TS>(wpi * n * gam * (1.0 + K.gc1 * eb + K.gc2 * eb * eb - K.gc3 * b2) - gshift(K, i));
+        st2<false>(dst + fg_index(K, i, cell), fe.template eq<i>() - fshift(K, i),
+                   wpi * n * gam * (1.0 + K.gc1 * eb + K.gc2 * eb * eb - K.gc3 * b2) - gshift(K, i));
     });
     const double cj = 1.0 / (16.0 * 1.4142135623730951 * c), ce = 1.0 / (8.0 * 1.4142135623730951 * c);
 #pragma unroll
@@ -1167,11 +1201,13 @@ __global__ void k_export(const TS* __restrict__ s, const TE* __restrict__ se, do
     if (i >= K.N * NSTATE) return;
     const int64_t a = i / K.N, cell = i - a * K.N;
     if (a < OFF_E) {
-        double v = static_cast<double>(s[a * K.stride + cell]);
+        double v;
         if (a < OFF_G)
-            v += fshift(K, (int)a);
+            v = static_cast<double>(s[fg_index(K, (int)a, cell)]) + fshift(K, (int)a);
         else if (a < OFF_H)
-            v += gshift(K, (int)(a - OFF_G));
+            v = static_cast<double>(s[fg_index(K, (int)(a - OFF_G), cell) + 1]) + gshift(K, (int)(a - OFF_G));
+        else
+            v = static_cast<double>(s[a * K.stride + cell]);
         d[i] = v;
     } else {
         d[i] = static_cast<double>(se[(a - OFF_E) * K.stride + cell]);
@@ -1184,12 +1220,12 @@ __global__ void k_import(const double* __restrict__ s, TS* __restrict__ d, TE* _
     if (i >= K.N * NSTATE) return;
     const int64_t a = i / K.N, cell = i - a * K.N;
     if (a < OFF_E) {
-        double v = s[i];
         if (a < OFF_G)
-            v -= fshift(K, (int)a);
+            d[fg_index(K, (int)a, cell)] = static_cast<TS>(s[i] - fshift(K, (int)a));
         else if (a < OFF_H)
-            v -= gshift(K, (int)(a - OFF_G));
-        d[a * K.stride + cell] = static_cast<TS>(v);
+            d[fg_index(K, (int)(a - OFF_G), cell) + 1] = static_cast<TS>(s[i] - gshift(K, (int)(a - OFF_G)));
+        else
+            d[a * K.stride + cell] = static_cast<TS>(s[i]);
     } else {
         de[(a - OFF_E) * K.stride + cell] = static_cast<TE>(s[i]);
     }
