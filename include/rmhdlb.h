@@ -76,7 +76,9 @@ typedef struct {
     double sigma;                /* conductivity of Eq. Ohm (>= 0) */
     double nu;                   /* lattice nu = c / c_s (> 0); sqrt(27) makes every g weight positive */
     int32_t storage;             /* RMHDLB_STORE_* */
-    int32_t divb_fix;            /* 1: adjust the normal B on open faces so div B = 0 there; 0: off */
+    int32_t divb_fix;            /* 1: adjust the normal B on open faces so div B = 0 there; 0: off
+                                    (recommended: in runs of ~10^3 steps at sigma = 1e3 the adjustment
+                                    grew B at face edges until cells failed, see the design notes) */
     int32_t null_band;           /* reconnection-rate null search: rows with |y| <= null_band cells
                                     (cell centres y_j = j + 1/2 - ny/2); < 1 selects 64 */
     int32_t reserved[5];         /* must be zero */

@@ -78,7 +78,7 @@ def _vec(x):
 
 
 DEFAULTS = dict(dx=1.0, c=1.0, mu0=1.0, tau=1.0, tau_h=0.5, alpha=0.1, Gamma=4.0 / 3.0, sigma=1.0,
-                nu=27.0 ** 0.5, divb_fix=1, null_band=64)
+                nu=27.0 ** 0.5, divb_fix=0, null_band=64)
 
 
 def make_params(shape=(1, 1, 1), bc=None, **kw):

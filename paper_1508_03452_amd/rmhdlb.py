@@ -148,7 +148,7 @@ def make_params(shape, bc=None, storage="f64", **kw):
     for k in ("dx", "c", "mu0", "tau", "tau_h", "alpha", "Gamma", "sigma", "nu"):
         setattr(P, k, float(d[k]))
     P.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
-    P.divb_fix = int(d.get("divb_fix", 1))
+    P.divb_fix = int(d.get("divb_fix", 0))
     P.null_band = int(d.get("null_band", 64))
     return P
 

@@ -126,13 +126,13 @@ def test_random_3d_periodic_ragged_tiles():
 def test_random_3d_open_faces():
     """Open faces on every axis with the normal-B adjustment (div B = 0 on the faces)."""
     w = W.random_state(shape=(20, 9, 7), seed=3, vmax=0.05, Bmag=0.2, Emag=0.02, sigma=30.0,
-                       bc=(("open", "open"),) * 3)
+                       bc=(("open", "open"),) * 3, divb_fix=1)
     check_case(w, 10)
 
 
 def test_solenoidal_box_open_on_every_face_40_steps():
     w = W.random_state(shape=(20, 9, 7), seed=3, vmax=0.05, Bmag=0.1, sigma=30.0, bc=(("open", "open"),) * 3,
-                       solenoidal=True)
+                       solenoidal=True, divb_fix=1)
     check_case(w, 40)
 
 
@@ -285,12 +285,14 @@ def test_full_size_sampled_cells_one_step(name):
     assert worst <= TOL
 
 
-def test_full_size_sampled_face_cells_one_step():
-    """The flare box at full size: cells on the open x-low, y-high and z-high faces (normal-B
-    adjustment) and on the driven bottom face, each advanced one step by the oracle on a 5x5x5
-    window that keeps the face (and, for the bottom, the prescribed face fields)."""
+@pytest.mark.parametrize("divb_fix", [0, 1])
+def test_full_size_sampled_face_cells_one_step(divb_fix):
+    """The flare box at full size: cells on the open x-low, y-high and z-high faces (with and
+    without the normal-B adjustment) and on the driven bottom face, each advanced one step by the
+    oracle on a 5x5x5 window that keeps the face (and, for the bottom, the prescribed face fields)."""
     torch = _torch_cuda()
     w = W.flare()
+    w.params["divb_fix"] = divb_fix
     s = run_gpu(w, 3)
     st = s.get_state()
     s.step(1)
