@@ -494,9 +494,17 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 // value is shift + transport(d); the moments add the exact sums of the shifts;
 // the collisions write the new deviations directly.
 constexpr int PTPB = 256;  // threads of a fused-step block: 128 cells, two lanes each
+// Waves per SIMD the fused kernel is compiled for: two (the FP64 and FP32
+// forms, and FP16 with the learned guess, lose more to spills at three than
+// they gain), three for plain FP16 storage (measured 3.6 % faster on the
+// flare box; with the guess three waves were 31 % slower).
 #ifndef RMHDLB_WAVES
-#define RMHDLB_WAVES 2  // waves per SIMD the fused kernel is compiled for
+#define RMHDLB_WAVES 2
 #endif
+template <typename TS, int GM>
+constexpr int fused_waves() {
+    return (sizeof(TS) == 2 && GM == 0) ? 3 : RMHDLB_WAVES;
+}
 // f/g slots whose loads may be in flight together, per arithmetic width
 #ifndef RMHDLB_GROUP_F64
 #define RMHDLB_GROUP_F64 2
@@ -739,7 +747,7 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
 }
 
 template <bool NT, typename TS, typename TE, typename V, int GM, int PXT>
-__global__ __launch_bounds__(PTPB, RMHDLB_WAVES) void k_fused_step(const TS* __restrict__ sd, const TE* __restrict__ se,
+__global__ __launch_bounds__(PTPB, (fused_waves<TS, GM>())) void k_fused_step(const TS* __restrict__ sd, const TE* __restrict__ se,
                                                         TS* __restrict__ dd, TE* __restrict__ de,
                                                         const double* __restrict__ faceB,
                                                         const GuessTables* __restrict__ gt, Consts K,
@@ -769,7 +777,7 @@ __device__ __forceinline__ int find_instance(int ninst, int64_t v, Get first) {
 // table of block counts, so neighbouring tiles of one instance still share
 // an XCD.  parity selects which of each instance's buffers is read.
 template <bool NT, typename TS, typename TE, typename V, int PXT>
-__global__ __launch_bounds__(PTPB, RMHDLB_WAVES) void k_fused_batch(const BatchInst* __restrict__ I, int ninst,
+__global__ __launch_bounds__(PTPB, (fused_waves<TS, 0>())) void k_fused_batch(const BatchInst* __restrict__ I, int ninst,
                                                          int total, int parity) {
     const int b = tile_of_block(total);
     if (b >= total) return;
