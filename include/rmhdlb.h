@@ -244,12 +244,13 @@ int rmhdlb_mlp_eval(const float *w, const float *X, const float *Yt, int32_t n, 
  * The fused step runs blocks of 128 cells (two lanes per cell) shaped
  * px x (128 / px), px in {64, 32, 16}, each walking zb z-planes. */
 
-/* Time every (px, zb) shape (zb in {1, 2, 4, 8} up to nz) on the context's
- * current state with HIP events and keep the fastest for its later steps.
- * The state is not advanced (each timed step reads the current buffer and
- * writes the other).  Results are cached per process by grid size, storage
- * and boundary kinds; a cached shape is reused without timing.  The chosen
- * shape is returned in *px, *zb (either may be NULL).  Synchronises. */
+/* Time every (px, zb) shape (zb in {1, 2, 4, 8, 16} up to nz) on the
+ * context's current state with HIP events and keep the fastest for its later
+ * steps.  The state is not advanced (each timed step reads the current buffer
+ * and writes the other).  Results are cached per process by grid size,
+ * storage, boundary kinds and guess mode; a cached shape is reused without
+ * timing.  With the learned guess on only px = 64 is timed.  The chosen shape
+ * is returned in *px, *zb (either may be NULL).  Synchronises. */
 int rmhdlb_autotune(rmhdlb_ctx *ctx, int32_t *px, int32_t *zb);
 
 /* Set the shape directly: px in {64, 32, 16}, zb >= 1 (RMHDLB_EINVAL otherwise). */

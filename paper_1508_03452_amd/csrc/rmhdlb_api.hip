@@ -578,7 +578,7 @@ int rmhdlb_mlp_eval(const float* w, const float* X, const float* Yt, int32_t n, 
 
 namespace {
 
-typedef std::tuple<int, int, int, int, int, int> TuneKey;  // nx, ny, nz, storage, divb, driven
+typedef std::tuple<int, int, int, int, int, int, int> TuneKey;  // nx, ny, nz, storage, divb, driven, guess
 std::map<TuneKey, std::pair<int, int>> g_tune_cache;
 std::mutex g_tune_mutex;
 
@@ -610,7 +610,7 @@ extern "C" {
 
 int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out) {
     if (!C) return RMHDLB_EINVAL;
-    const TuneKey key(C->K.nx, C->K.ny, C->K.nz, C->storage, C->K.divb, C->K.drv);
+    const TuneKey key(C->K.nx, C->K.ny, C->K.nz, C->storage, C->K.divb, C->K.drv, C->guess_mode);
     std::pair<int, int> best(64, 4);
     bool cached = false;
     {
@@ -623,9 +623,9 @@ int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out) {
     }
     if (!cached) {
         float best_ms = 1e30f;
-        const int pxs[3] = {64, 32, 16}, zbs[4] = {1, 2, 4, 8};
+        const int pxs[3] = {64, 32, 16}, zbs[5] = {1, 2, 4, 8, 16};
         for (int pi = 0; pi < 3; ++pi)
-            for (int zi = 0; zi < 4; ++zi) {
+            for (int zi = 0; zi < 5; ++zi) {
                 if (zbs[zi] > C->K.nz && zbs[zi] != 1) continue;
                 if (C->guess_mode && pxs[pi] != 64) continue;  // the guess path has 64-wide tiles only
                 rmhd::StepTuning t;
