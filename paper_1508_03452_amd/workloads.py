@@ -108,6 +108,55 @@ def sheet(nx=1024, ny=4, nz=4, sigma=100.0, p=50.0, steps=4000, width_cells=2.0)
     return Workload("sheet", shape, bc, _params(sigma=sigma), fields, steps, meta=dict(t0=t0))
 
 
+def alfven_box(n_cells=400, eta=0.118591, sigma=1e5, B0=1.0, By=0.1, x0=-0.8, x1=0.0, Gamma=4.0 / 3.0):
+    """The Alfven-wave set-up of Sec. IV in the paper's units: [-1, 1] in n_cells cells, c = 1
+    (dx / dt = sqrt 2), open ends, n = p = 1, B = (B0, By, B_z) with B_z = eta B0 sin(2 pi (3 s^2 - 2 s^3)),
+    s = (x - x0) / (x1 - x0), inside (x0, x1) and 0 outside, u_z = -v_A B_z / B0 there, ideal-Ohm
+    E = -u x B and rho_c from Gauss's law (None: the solver takes eps0 div E).  meta: v_A from the
+    exact-wave formula of that section, the grid x, dt and the initial B_z."""
+    shape = (n_cells, 1, 1)
+    dx = 2.0 / n_cells
+    x, _, _ = _grid(shape, dx)
+    xs = x.ravel()
+    eps = 1.0 + 1.0 / (Gamma - 1.0)                  # n c^2 + p / (Gamma - 1) with n = p = c = 1
+    den = eps + 1.0 + B0 * B0 * (1.0 + eta * eta)
+    vA = np.sqrt(2.0 * B0 * B0 / den / (1.0 + np.sqrt(1.0 - (2.0 * eta * B0 * B0 / den) ** 2)))
+    sarg = (xs - x0) / (x1 - x0)
+    inside = (xs > x0) & (xs < x1)
+    Bz1 = np.where(inside, eta * B0 * np.sin(2.0 * np.pi * (3.0 * sarg ** 2 - 2.0 * sarg ** 3)), 0.0)
+    uz1 = -vA / B0 * Bz1
+    Bz = Bz1.reshape(1, 1, n_cells).copy()
+    uz = uz1.reshape(1, 1, n_cells).copy()
+    zero = _full(shape, 0.0)
+    Bx, Byf = _full(shape, B0), _full(shape, By)
+    # E = -u x B with u = (0, 0, u_z): E = (u_z B_y, -u_z B_x, 0)
+    E = (uz * Byf, -uz * Bx, zero.copy())
+    fields = dict(n=_full(shape, 1.0), p=_full(shape, 1.0), u=(zero.copy(), zero.copy(), uz),
+                  E=E, B=(Bx, Byf, Bz), rho_c=None)
+    bc = (("open", "open"), ("periodic", "periodic"), ("periodic", "periodic"))
+    return Workload("alfven_box", shape, bc, _params(sigma=sigma, dx=dx, Gamma=Gamma), fields, 0,
+                    meta=dict(vA=float(vA), x=xs.copy(), dt=dx / np.sqrt(2.0), Bz0=Bz1.copy(), x0=x0, x1=x1,
+                              eta=eta, B0=B0))
+
+
+def sheet_box(n_cells=100, sigma=100.0, t_start=1.0, p=50.0, half_width=1.5):
+    """The current-sheet set-up of Sec. IV (self-similar current sheets) in the paper's units: the
+    segment [-half_width, half_width] in n_cells cells (dx = 2 half_width / n_cells), c = 1 so that
+    dx / dt = sqrt(2), open ends, B_y = erf(sqrt(sigma / t_start) x / 2) (B0 = 1), n = 1, p = 50,
+    u = E = 0.  meta['t_start'] is the time the initial profile belongs to."""
+    shape = (n_cells, 1, 1)
+    dx = 2.0 * half_width / n_cells
+    x, _, _ = _grid(shape, dx)
+    By = np.vectorize(erf)(0.5 * np.sqrt(sigma / t_start) * x).reshape(1, 1, n_cells).copy()
+    zero = _full(shape, 0.0)
+    fields = dict(n=_full(shape, 1.0), p=_full(shape, p), u=(zero, zero.copy(), zero.copy()),
+                  E=(zero.copy(), zero.copy(), zero.copy()), B=(zero.copy(), By, zero.copy()),
+                  rho_c=zero.copy())
+    bc = (("open", "open"), ("periodic", "periodic"), ("periodic", "periodic"))
+    return Workload("sheet_box", shape, bc, _params(sigma=sigma, dx=dx), fields, 0,
+                    meta=dict(t_start=t_start, dt=dx / np.sqrt(2.0), x=x.ravel().copy()))
+
+
 def kh(nx=1024, ny=2048, nz=1, v0=0.2, ratio=10.0, sigma=1e3, B0=0.1, noise=1e-3, seed=2015, a=1.0, b=10.0,
        steps=20000):
     """Kelvin-Helmholtz shear layer with an antiparallel field (Sec. IV, KH)."""
