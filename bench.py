@@ -36,10 +36,10 @@ KERNEL_SOURCES = ("paper_1508_03452_amd/csrc/rmhdlb_kernels.hip", "paper_1508_03
 # (scaled by the copy-kernel calibration), keyed by (workload, storage, hash
 # of the kernel sources): a changed kernel reports null until re-measured.
 MEASURED_TRAFFIC = {
-    ("flare", "f64", "a2938690c429"): 72.45,    # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f32", "a2938690c429"): 30.73,    # profiles/fused_step_f32_flare256x256x512.md
-    ("flare", "f16", "a2938690c429"): 21.09,    # profiles/fused_step_f16_flare256x256x512.md
-    ("flare", "f16+guess", "a2938690c429"): 13.31,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f64", "f4fe36313db7"): 72.42,    # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f32", "f4fe36313db7"): 30.50,    # profiles/fused_step_f32_flare256x256x512.md
+    ("flare", "f16", "f4fe36313db7"): 20.88,    # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16+guess", "f4fe36313db7"): 13.33,  # profiles/fused_step_f16g_flare256x256x512.md
 }
 
 

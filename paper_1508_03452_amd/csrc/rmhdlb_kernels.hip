@@ -569,10 +569,34 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
             const vec2<V> c0 = ldv2<V>(fga, 2 * (int64_t)hc), m2 = ldv2<V>(fga, 2 * (int64_t)(hc + om2)),
                           m1 = ldv2<V>(fga, 2 * (int64_t)(hc + om1)), p1 = ldv2<V>(fga, 2 * (int64_t)(hc + op1));
             const V f0 = c0.x, fm2 = m2.x, fm1 = m1.x, fp1 = p1.x;
-            const V lap = (ldv<V>(fga, 2 * (int64_t)(hc + lap_xp)) + ldv<V>(fga, 2 * (int64_t)(hc + lap_xm))) +
-                          (ldv<V>(fga, 2 * (int64_t)(hc + lap_yp)) + ldv<V>(fga, 2 * (int64_t)(hc + lap_ym))) +
-                          (ldv<V>(fga, 2 * (int64_t)(hc + lap_zp)) + ldv<V>(fga, 2 * (int64_t)(hc + lap_zm))) -
-                          V(6) * f0;
+            // On an axis slot the upwind points x -+ e are also the Laplacian's
+            // neighbours along that axis (lane 1 walks -e): reuse them.
+            constexpr bool axis_slot = (ex != 0) + (ey != 0) + (ez != 0) == 1;
+            const V up = h ? fm1 : fp1, dn = h ? fp1 : fm1;  // f at x + e_i0 and x - e_i0
+            auto lap_at = [&](int off) { return ldv<V>(fga, 2 * (int64_t)(hc + off)); };
+            V lxp, lxm, lyp, lym, lzp, lzm;
+            if constexpr (axis_slot && ex != 0) {
+                lxp = up;
+                lxm = dn;
+            } else {
+                lxp = lap_at(lap_xp);
+                lxm = lap_at(lap_xm);
+            }
+            if constexpr (axis_slot && ey != 0) {
+                lyp = up;
+                lym = dn;
+            } else {
+                lyp = lap_at(lap_yp);
+                lym = lap_at(lap_ym);
+            }
+            if constexpr (axis_slot && ez != 0) {
+                lzp = up;
+                lzm = dn;
+            } else {
+                lzp = lap_at(lap_zp);
+                lzm = lap_at(lap_zm);
+            }
+            const V lap = (lxp + lxm) + (lyp + lym) + (lzp + lzm) - V(6) * f0;
             const V fv = f0 - cour * ((f0 + V(0.5) * minmod(f0 - fm1, fp1 - f0)) -
                                       (fm1 + V(0.5) * minmod(fm1 - fm2, f0 - fm1))) + kv * lap;
             const V g0 = c0.y, gm2 = m2.y, gm1 = m1.y, gp1 = p1.y;
