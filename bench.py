@@ -9,7 +9,9 @@ warm-up steps and an untimed launch-shape autotune, then K steps bracketed by
 synchronisations, with HIP events recorded on the stream the kernels are
 launched on.  The headline value is the plain FP64 form; the same box is then
 timed in the mixed + learned form (FP16-shifted storage, learned recovery
-guess trained untimed on the box) and reported beside it with its speed-up.
+guess trained untimed on the box) and reported beside it with its speed-up,
+and once more in FP16 storage without the guess (mixed_plain), which shows
+whether the network pays for itself on this workload.
 
 roofline: algorithmic HBM bytes of one step (read + write of the 66 state
 values per cell) divided by the measured average step duration, against the
@@ -36,10 +38,10 @@ KERNEL_SOURCES = ("paper_1508_03452_amd/csrc/rmhdlb_kernels.hip", "paper_1508_03
 # (scaled by the copy-kernel calibration), keyed by (workload, storage, hash
 # of the kernel sources): a changed kernel reports null until re-measured.
 MEASURED_TRAFFIC = {
-    ("flare", "f64", "f4fe36313db7"): 72.42,    # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f32", "f4fe36313db7"): 30.50,    # profiles/fused_step_f32_flare256x256x512.md
-    ("flare", "f16", "f4fe36313db7"): 20.88,    # profiles/fused_step_f16_flare256x256x512.md
-    ("flare", "f16+guess", "f4fe36313db7"): 13.33,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f64", "78d5f125eb5b"): 72.41,    # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f32", "78d5f125eb5b"): 30.36,    # profiles/fused_step_f32_flare256x256x512.md
+    ("flare", "f16", "78d5f125eb5b"): 20.93,    # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16+guess", "78d5f125eb5b"): 13.34,  # profiles/fused_step_f16g_flare256x256x512.md
 }
 
 
@@ -68,7 +70,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--single-form", action="store_true",
-                    help="time only the form given by --storage/--guess (no mixed+learned comparison)")
+                    help="time only the form given by --storage/--guess (no mixed forms beside it)")
     return ap.parse_args()
 
 
@@ -276,6 +278,16 @@ def main():
                             "within 2e-2 and the total energy within 2e-3 of FP64 while B and J drift O(1) of the "
                             "field scale, the flow amplifying rounding ~2e6-fold (tests/test_gpu_long_run.py)",
             **{k: v for k, v in info2.items() if k != "weights"}}
+        # the same storage without the guess: whether the network pays for itself here
+        ms3, _, s3, info3 = timed_form(w, "f16", False, args, stream)
+        s3.close()
+        del s3
+        torch.cuda.empty_cache()
+        out["mixed_plain"] = {
+            "storage": "f16 (shifted)", "recovery": "plain Newton",
+            "value": round(ncell / (ms3 * 1e-3) / 1e6, 2), "unit": "MLUPS", "ms_per_step": round(ms3, 4),
+            "speedup_vs_headline": round(ms / ms3, 3), "guess_speedup": round(ms3 / ms2, 3),
+            "mean_newton_iters": info3["mean_newton_iters"], "tile": info3["tile"]}
     out["copy_probe_gbs"] = copy_probe_gbs(stream)
     del w.fields
     if not args.no_cpu_baseline:

@@ -497,24 +497,33 @@ constexpr int PTPB = 256;  // threads of a fused-step block: 128 cells, two lane
 // Waves per SIMD the fused kernel is compiled for: two (the FP64 and FP32
 // forms, and FP16 with the learned guess, lose more to spills at three than
 // they gain), three for plain FP16 storage (measured 3.6 % faster on the
-// flare box; with the guess three waves were 31 % slower).
+// flare box than two, and 31 % faster than four; with the guess three waves
+// were 31 % slower).
 #ifndef RMHDLB_WAVES
 #define RMHDLB_WAVES 2
 #endif
+#ifndef RMHDLB_WAVES_F16
+#define RMHDLB_WAVES_F16 3
+#endif
 template <typename TS, int GM>
 constexpr int fused_waves() {
-    return (sizeof(TS) == 2 && GM == 0) ? 3 : RMHDLB_WAVES;
+    return (sizeof(TS) == 2 && GM == 0) ? RMHDLB_WAVES_F16 : RMHDLB_WAVES;
 }
-// f/g slots whose loads may be in flight together, per arithmetic width
+// f/g slots whose loads may be in flight together, per storage type
+// (measured on the flare box: 2 for FP64 and FP16; 3 for FP32, 1.7 % faster
+// there and 14 % slower for FP64)
 #ifndef RMHDLB_GROUP_F64
 #define RMHDLB_GROUP_F64 2
 #endif
 #ifndef RMHDLB_GROUP_F32
-#define RMHDLB_GROUP_F32 2
+#define RMHDLB_GROUP_F32 3
 #endif
-template <typename V>
+#ifndef RMHDLB_GROUP_F16
+#define RMHDLB_GROUP_F16 2
+#endif
+template <typename TS>
 constexpr int pin_group() {
-    return sizeof(V) == 8 ? RMHDLB_GROUP_F64 : RMHDLB_GROUP_F32;
+    return sizeof(TS) == 8 ? RMHDLB_GROUP_F64 : (sizeof(TS) == 4 ? RMHDLB_GROUP_F32 : RMHDLB_GROUP_F16);
 }
 
 // The two lanes of a cell are l and l ^ 32 of a wavefront: each half of the
@@ -607,7 +616,7 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
             // Keep each slot's arithmetic next to its loads: without this the
             // scheduler sinks all of it below every load of the cell, and the
             // ~150 load destinations in flight cost a wave its occupancy.
-            if constexpr (s % pin_group<V>() == 0 || s == 9) asm volatile("" : "+v"(Fv[s]), "+v"(Gv[s])::"memory");
+            if constexpr (s % pin_group<TS>() == 0 || s == 9) asm volatile("" : "+v"(Fv[s]), "+v"(Gv[s])::"memory");
             t00 += fv;
             n0 += gv;
             const V sf = sgn * fv;
