@@ -46,6 +46,7 @@ typedef struct {
     double alpha, Gamma, sigma, nu;
     int32_t divb_fix;  /* normal-B adjustment on open faces (Reading R22) */
     int32_t null_band; /* half-width in y-cells of the null-point search band (< 1: 64) */
+    int32_t collision; /* f collision: 0 explicit (Reading R4), 1 the printed semi-implicit form */
 } orc_params;
 
 /* ---------------------------------------------------------------- lattice */
@@ -714,9 +715,15 @@ static void collision_pass(orc_ctx *C)
                                    L->xi[i][3] * chi[3];
                     double om = pref * (xichi / (L->nu * L->nu)) / P->tau;
                     /* Reading R4: explicit in f; with rates proportional to xi_mu chi^mu
-                     * and the Landau-frame eigenpair this conserves T^{0 nu} exactly */
+                     * and the Landau-frame eigenpair this conserves T^{0 nu} exactly.
+                     * Optionally (collision = 1) Eq. rlb as printed, with f(x, t + dt)
+                     * in the collision term, in closed form: f' = (f + om f_eq) / (1 + om);
+                     * the direction-dependent rate makes it only approximately conservative */
                     double fi = f[(long)i * N + id];
-                    fn[(long)i * N + id] = fi - om * (fi - feq[i]);
+                    if (P->collision == 1)
+                        fn[(long)i * N + id] = (fi + om * feq[i]) / (1.0 + om);
+                    else
+                        fn[(long)i * N + id] = fi - om * (fi - feq[i]);
                     /* Eq. rlb with g(x, t + dt) in the collision, in closed form; the rate
                      * is the same for every direction, so sum_i g is conserved */
                     double gi = g[(long)i * N + id];
@@ -747,6 +754,7 @@ ORC_API int rmhdlb_oracle_create(const orc_params *P, void **out)
         if ((P->bc_lo[a] == BC_PERIODIC) != (P->bc_hi[a] == BC_PERIODIC)) return ORC_EINVAL;
     }
     if (P->divb_fix != 0 && P->divb_fix != 1) return ORC_EINVAL;
+    if (P->collision != 0 && P->collision != 1) return ORC_EINVAL;
     if (P->tau_h != 0.5) return ORC_EUNSUPPORTED; /* Eq. Ex_force holds for tau_h = 1/2 */
     orc_ctx *C = (orc_ctx *)calloc(1, sizeof(orc_ctx));
     if (!C) return ORC_ENOMEM;

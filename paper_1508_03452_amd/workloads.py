@@ -157,6 +157,29 @@ def sheet_box(n_cells=100, sigma=100.0, t_start=1.0, p=50.0, half_width=1.5):
                     meta=dict(t_start=t_start, dt=dx / np.sqrt(2.0), x=x.ravel().copy()))
 
 
+def kh_box(n_cells=512, U0=0.2, dn=1.8, sigma=100.0, B0=0.06, u_pert=0.01, c=2.5, null_band=8):
+    """The KH reconnection set-up of Sec. IV in the paper's units: [-0.5, 0.5]^2 in n_cells^2 cells,
+    dx / dt = sqrt(2) c with c = 2.5, x periodic, y open; u_x = (U0 c / 2) tanh(y / a) with a = dx,
+    n = 1 + (dn / 2) tanh(y / a), p = 1, B_x = B0 tanh(y / a), single-mode u_y =
+    u_pert sin(2 pi x) exp(-y^2 / b^2) with b = 10 dx, ideal-Ohm E = -u x B.  U0 is in units of c.
+    The null point is searched in the rows within null_band cells of y = 0."""
+    shape = (n_cells, n_cells, 1)
+    dx = 1.0 / n_cells
+    x, y, _ = _grid(shape, dx)
+    a, b = dx, 10.0 * dx
+    th = np.broadcast_to(np.tanh(y / a), (1, n_cells, n_cells)).copy()
+    ux = 0.5 * U0 * c * th
+    uy = np.broadcast_to(u_pert * np.sin(2.0 * np.pi * x) * np.exp(-(y / b) ** 2), (1, n_cells, n_cells)).copy()
+    n = 1.0 + 0.5 * dn * th
+    Bx = B0 * th
+    zero = _full(shape, 0.0)
+    # E = -u x B with u = (u_x, u_y, 0), B = (B_x, 0, 0): E = (0, 0, u_y B_x)
+    fields = dict(n=n, p=_full(shape, 1.0), u=(ux, uy, zero.copy()), E=(zero.copy(), zero.copy(), uy * Bx),
+                  B=(Bx, zero.copy(), zero.copy()), rho_c=zero.copy())
+    return Workload("kh_box", shape, KH_BC, _params(sigma=sigma, dx=dx, c=c, null_band=null_band), fields, 0,
+                    meta=dict(U0=U0, dn=dn, B0=B0, dt=dx / (np.sqrt(2.0) * c)))
+
+
 def kh(nx=1024, ny=2048, nz=1, v0=0.2, ratio=10.0, sigma=1e3, B0=0.1, noise=1e-3, seed=2015, a=1.0, b=10.0,
        steps=20000):
     """Kelvin-Helmholtz shear layer with an antiparallel field (Sec. IV, KH)."""
