@@ -81,8 +81,20 @@ typedef struct {
                                     grew B at face edges until cells failed, see the design notes) */
     int32_t null_band;           /* reconnection-rate null search: rows with |y| <= null_band cells
                                     (cell centres y_j = j + 1/2 - ny/2); < 1 selects 64 */
-    int32_t reserved[5];         /* must be zero */
+    int32_t collision;           /* RMHDLB_COLL_*: the f collision (see below) */
+    int32_t reserved[4];         /* must be zero */
 } rmhdlb_params;
+
+/* The f collision of Eq. rlb.  EXPLICIT (default): f' = f - omega (f - f_eq)
+ * on the transported f, which conserves T^{0 nu} exactly in every cell.
+ * PRINTED: the form the paper prints, with f(t + dt) in the collision term,
+ * in closed form f' = (f + omega f_eq) / (1 + omega); it is not exactly
+ * conservative (the rate depends on the direction) but stays stable in
+ * supersonic shear flows where the explicit form fails (the paper's KH runs
+ * at U0 = 0.4c and 0.6c).  PRINTED is built for 64-wide tiles without the
+ * learned guess: rmhdlb_set_guess(.., RMHDLB_GUESS_MLP) and batches with it
+ * return RMHDLB_EUNSUPPORTED, rmhdlb_set_tuning with px != 64 RMHDLB_EINVAL. */
+enum { RMHDLB_COLL_EXPLICIT = 0, RMHDLB_COLL_PRINTED = 1 };
 
 /* Initial primitive fields (Sec. IV): number density n, pressure p,
  * velocity u, electric field E, magnetic field B, charge density rho_c

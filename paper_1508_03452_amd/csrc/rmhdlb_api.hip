@@ -65,12 +65,13 @@ int validate(const rmhdlb_params* P) {
         if ((P->bc_lo[a] == RMHDLB_BC_PERIODIC) != (P->bc_hi[a] == RMHDLB_BC_PERIODIC)) return RMHDLB_EINVAL;
     }
     if (P->divb_fix != 0 && P->divb_fix != 1) return RMHDLB_EINVAL;
+    if (P->collision != RMHDLB_COLL_EXPLICIT && P->collision != RMHDLB_COLL_PRINTED) return RMHDLB_EINVAL;
     if (!(P->dx > 0) || !(P->c > 0) || !(P->mu0 > 0) || !(P->tau > 0) || !(P->alpha >= 0) || !(P->Gamma > 1) ||
         !(P->sigma >= 0) || !(P->nu > 0) || !isfinite(P->sigma) || !isfinite(P->alpha))
         return RMHDLB_EINVAL;
     if (P->storage != RMHDLB_STORE_F64 && P->storage != RMHDLB_STORE_F32 && P->storage != RMHDLB_STORE_F16)
         return RMHDLB_EINVAL;
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < 4; ++k)
         if (P->reserved[k] != 0) return RMHDLB_EINVAL;
     if (P->tau_h != 0.5) return RMHDLB_EUNSUPPORTED;  // the force form of Eq. Ex_force needs tau_h = 1/2
     return RMHDLB_OK;
@@ -97,6 +98,7 @@ Consts make_consts(const rmhdlb_params* P) {
     }
     K.divb = any_open;
     K.band = P->null_band >= 1 ? P->null_band : 64;
+    K.coll = P->collision;
     const int64_t fsz[3] = {(int64_t)P->ny * P->nz, (int64_t)P->nx * P->nz, (int64_t)P->nx * P->ny};
     K.fo[0] = 0;
     for (int f = 0; f < 6; ++f) K.fo[f + 1] = K.fo[f] + fsz[f >> 1];
@@ -454,6 +456,7 @@ int rmhdlb_set_guess_weights(rmhdlb_ctx* C, const rmhdlb_guess_weights* w) {
 int rmhdlb_set_guess(rmhdlb_ctx* C, int32_t mode) {
     if (!C || (mode != RMHDLB_GUESS_PLAIN && mode != RMHDLB_GUESS_MLP)) return RMHDLB_EINVAL;
     if (mode == RMHDLB_GUESS_MLP && !C->gt) return RMHDLB_EINVAL;
+    if (mode == RMHDLB_GUESS_MLP && C->K.coll) return RMHDLB_EUNSUPPORTED;  // not built for the printed collision
     C->guess_mode = mode;
     return RMHDLB_OK;
 }
@@ -627,7 +630,7 @@ int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out) {
         for (int pi = 0; pi < 3; ++pi)
             for (int zi = 0; zi < 5; ++zi) {
                 if (zbs[zi] > C->K.nz && zbs[zi] != 1) continue;
-                if (C->guess_mode && pxs[pi] != 64) continue;  // the guess path has 64-wide tiles only
+                if ((C->guess_mode || C->K.coll) && pxs[pi] != 64) continue;  // built for 64-wide tiles only
                 rmhd::StepTuning t;
                 t.px = pxs[pi];
                 t.zb = zbs[zi];
@@ -654,7 +657,7 @@ int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out) {
 
 int rmhdlb_set_tuning(rmhdlb_ctx* C, int32_t px, int32_t zb) {
     if (!C || (px != 64 && px != 32 && px != 16) || zb < 1) return RMHDLB_EINVAL;
-    if (C->guess_mode && px != 64) return RMHDLB_EINVAL;
+    if ((C->guess_mode || C->K.coll) && px != 64) return RMHDLB_EINVAL;
     C->tune.px = px;
     C->tune.zb = zb;
     return RMHDLB_OK;
@@ -762,6 +765,8 @@ int rmhdlb_batch_create(const rmhdlb_params* params, int32_t n, void* hip_stream
     if (!params || n < 1) return RMHDLB_EINVAL;
     for (int i = 1; i < n; ++i)
         if (params[i].storage != params[0].storage) return RMHDLB_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (params[i].collision != RMHDLB_COLL_EXPLICIT) return RMHDLB_EUNSUPPORTED;  // batches: explicit only
     rmhdlb_batch* B = new (std::nothrow) rmhdlb_batch();
     if (!B) return RMHDLB_ENOMEM;
     B->n = n;

@@ -57,6 +57,7 @@ struct Consts {
     int divb;            // 1: the normal B of open-face cells is adjusted so that div B = 0 there
     int open_lo[3], open_hi[3];  // face takes the div B adjustment (open, with at least 2 cells on the axis)
     int band;            // half-width in rows of the reconnection null search band
+    int coll;            // f collision: 0 explicit, 1 the printed semi-implicit form (host dispatch)
     int64_t fo[7];       // offsets of the six face arrays of adjusted normal B (x lo, x hi, y lo, ...), fo[6] = total
     int64_t N;           // cells
     int64_t stride;      // values per state array (ghost planes + N, rounded up)

@@ -536,7 +536,9 @@ __device__ __forceinline__ V pair_sum(V v) {
     return v + __shfl_xor(v, 32, 64);
 }
 
-template <bool NT, typename TS, typename TE, typename V, int GM>
+// CM: the f collision, 0 explicit (Reading R4), 1 the printed semi-implicit
+// form of Eq. rlb, f' = (f + omega f_eq) / (1 + omega).
+template <bool NT, typename TS, typename TE, typename V, int GM, int CM = 0>
 __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* __restrict__ se, TS* __restrict__ dd,
                                           TE* __restrict__ de, const double* __restrict__ faceB,
                                           const GuessTables* __restrict__ gt, const Consts& K, int cell,
@@ -707,7 +709,8 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
         const V q0 = (V)K.fsh[0] - fe.template eq<0>();
         const V geq0 = (V)K.wp[0] * ng * (V(1) - gc3b2);
         if (active)
-            st2<NT>(dd + fg_index(K, 0, cell), Fv[0] - rate * (Fv[0] + q0),
+            st2<NT>(dd + fg_index(K, 0, cell),
+                    CM == 0 ? Fv[0] - rate * (Fv[0] + q0) : (Fv[0] - rate * q0) / (V(1) + rate),
                     (Gv[0] + wg * (geq0 - (V)K.gsh[0])) * inv1wg);
     } else {
         put(dd + (int64_t)(OFF_H + QH) * S + cell, (V)(2.0 * M.rho) - Hv[12]);
@@ -722,7 +725,8 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
             const V q = (V)K.fsh[cls] - feq_signed<i0>(fe, sgn);
             const V geq = (V)K.wp[cls] * ng * (V(1) + gc1 * eb + gc2 * eb * eb - gc3b2);
             if (active)
-                st2<NT>(dd + fg_index(K, i0, 0) + 2 * (int64_t)hc, Fv[s] - om * (Fv[s] + q),
+                st2<NT>(dd + fg_index(K, i0, 0) + 2 * (int64_t)hc,
+                        CM == 0 ? Fv[s] - om * (Fv[s] + q) : (Fv[s] - om * q) / (V(1) + om),
                         (Gv[s] + wg * (geq - (V)K.gsh[cls])) * inv1wg);
         }
     });
@@ -751,7 +755,7 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
 // of the stencil meet in that XCD's L2.
 // With the learned guess the network runs on whole wavefronts, so lanes past
 // a ragged edge stay and compute a copy of the edge cell without storing it.
-template <bool NT, typename TS, typename TE, typename V, int GM, int PXT>
+template <bool NT, typename TS, typename TE, typename V, int GM, int PXT, int CM = 0>
 __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE* __restrict__ se,
                                             TS* __restrict__ dd, TE* __restrict__ de,
                                             const double* __restrict__ faceB, const GuessTables* __restrict__ gt,
@@ -774,12 +778,12 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
     for (int z = z0; z < z1; ++z) {
         const int cell = x + K.nx * (y + K.ny * z);
         const Nbr nb = make_nbr<true>(K, x, y, z);
-        pair_cell<NT, TS, TE, V, GM>(sd, se, dd, de, faceB, gt, K, cell, nb, h, x, y, z,
-                                     GM == GUESS_NONE ? true : active);
+        pair_cell<NT, TS, TE, V, GM, CM>(sd, se, dd, de, faceB, gt, K, cell, nb, h, x, y, z,
+                                         GM == GUESS_NONE ? true : active);
     }
 }
 
-template <bool NT, typename TS, typename TE, typename V, int GM, int PXT>
+template <bool NT, typename TS, typename TE, typename V, int GM, int PXT, int CM>
 __global__ __launch_bounds__(PTPB, (fused_waves<TS, GM>())) void k_fused_step(const TS* __restrict__ sd, const TE* __restrict__ se,
                                                         TS* __restrict__ dd, TE* __restrict__ de,
                                                         const double* __restrict__ faceB,
@@ -787,7 +791,7 @@ __global__ __launch_bounds__(PTPB, (fused_waves<TS, GM>())) void k_fused_step(co
                                                         int tiles_x, int ncol, int zb, int nblk) {
     const int b = tile_of_block(nblk);
     if (b >= nblk) return;  // uniform over the block
-    fused_block<NT, TS, TE, V, GM, PXT>(sd, se, dd, de, faceB, gt, K, tiles_x, ncol, zb, b);
+    fused_block<NT, TS, TE, V, GM, PXT, CM>(sd, se, dd, de, faceB, gt, K, tiles_x, ncol, zb, b);
 }
 
 // Index of the instance whose range [first[i], first[i + 1]) holds v (first
@@ -1345,7 +1349,7 @@ void step_geometry(const Consts& K, int px, int zb, int& tiles_x, int& ncol, int
     nblk = ncol * ((K.nz + zb - 1) / zb);
 }
 
-template <typename TS, int GM, int PXT>
+template <typename TS, int GM, int PXT, int CM = 0>
 static void launch_fused(const TS* sd, const void* se, TS* dd, void* de, double* faceB, const GuessTables* gt,
                          const Consts& K, int zb, hipStream_t s) {
     using TE = typename StoreTypes<TS>::E;
@@ -1353,7 +1357,7 @@ static void launch_fused(const TS* sd, const void* se, TS* dd, void* de, double*
     int tx, ncol, nblk;
     step_geometry(K, PXT, zb, tx, ncol, nblk);
     const int grid = ((nblk + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_fused_step<true, TS, TE, V, GM, PXT>), dim3(grid), dim3(PTPB), 0, s, sd, (const TE*)se, dd,
+    hipLaunchKernelGGL((k_fused_step<true, TS, TE, V, GM, PXT, CM>), dim3(grid), dim3(PTPB), 0, s, sd, (const TE*)se, dd,
                        (TE*)de, (const double*)faceB, gt, K, tx, ncol, zb, nblk);
 }
 
@@ -1365,7 +1369,10 @@ hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K
     const int zb = tune.zb > 0 ? (tune.zb < K.nz ? tune.zb : K.nz) : 1;
     const TS* sd = (const TS*)src.dist;
     TS* dd = (TS*)dst.dist;
-    if (gt)  // the guess path is built for 64-wide tiles only
+    if (K.coll) {  // the printed collision: 64-wide tiles, no guess
+        if (gt) return hipErrorNotSupported;
+        launch_fused<TS, GUESS_NONE, 64, 1>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+    } else if (gt)  // the guess path is built for 64-wide tiles only
         launch_fused<TS, GUESS_PAIR, 64>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
     else if (tune.px == 32)
         launch_fused<TS, GUESS_NONE, 32>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);

@@ -132,6 +132,42 @@ def test_random_3d_periodic_ragged_tiles():
     check_case(w, 12)
 
 
+def test_printed_collision_random_3d_ragged_tiles():
+    """The printed semi-implicit f collision (collision = 1), 12 steps of a ragged periodic 3-D state."""
+    w = W.random_state(shape=(70, 6, 3), seed=2, vmax=0.1, Bmag=0.2, Emag=0.02, sigma=3.0)
+    w.params["collision"] = 1
+    check_case(w, 12)
+
+
+def test_printed_collision_supersonic_kh():
+    """The paper's KH set-up at U0 = 0.6c on 64 x 64 cells (x periodic, y open) with the printed
+    collision, a 60-step prefix (the supersonic shear amplifies rounding about a million-fold over
+    300 steps); conditioning-derived bound."""
+    w = W.kh_box(n_cells=64, U0=0.6, sigma=100.0)
+    w.params["collision"] = 1
+    check_case(w, 60, conditioned=True)
+
+
+def test_printed_collision_limits():
+    """The printed collision has 64-wide tiles and no learned guess or batches."""
+    torch = _torch_cuda()
+    from paper_1508_03452_amd.rmhdlb import Batch, RmhdlbError
+    w = W.random_state(shape=(20, 9, 7), seed=3, vmax=0.05, Bmag=0.2, Emag=0.02, sigma=30.0)
+    w.params["collision"] = 1
+    s = run_gpu(w, 0)
+    with pytest.raises(RmhdlbError):
+        s.set_tuning(32, 4)
+    assert s.autotune()[0] == 64
+    with pytest.raises(RmhdlbError):
+        Batch([(w.shape, w.bc, w.params)], storage="f32", stream=torch.cuda.current_stream())
+    s.set_guess_weights(dict(w=W.mlp_init(11).astype(np.float32), mu_x=np.zeros(6), sd_x=np.ones(6),
+                             mu_t=np.zeros(2), sd_t=np.ones(2)))
+    with pytest.raises(RmhdlbError):
+        s.set_guess(True)
+    s.step(1)
+    assert s.moments(fields=())["diag"]["n_failed"] == 0
+
+
 def test_random_3d_open_faces():
     """Open faces on every axis with the normal-B adjustment (div B = 0 on the faces)."""
     w = W.random_state(shape=(20, 9, 7), seed=3, vmax=0.05, Bmag=0.2, Emag=0.02, sigma=30.0,

@@ -295,12 +295,14 @@ def _wave_fields(nx, kind, a=1e-4, B0=1.0):
     return dict(n=one, p=one, u=(z, uy, z), E=(z, z, uy * B0), B=(B0 * one, a * B0 * s, z), rho_c=z), vA
 
 
+@pytest.mark.parametrize("collision", [0, 1])
 @pytest.mark.parametrize("kind,tol", [("light", 1e-3), ("sound", 2e-3), ("alfven", 1e-2)])
-def test_linear_wave_speeds(kind, tol):
-    """Vacuum light (c), relativistic sound sqrt(Gamma p / (eps + p)) and Alfven B0 / sqrt(eps + p + B0^2)."""
+def test_linear_wave_speeds(kind, tol, collision):
+    """Vacuum light (c), relativistic sound sqrt(Gamma p / (eps + p)) and Alfven B0 / sqrt(eps + p + B0^2),
+    with either f collision."""
     nx = 128
     f, v = _wave_fields(nx, kind)
-    o = oracle.Oracle((nx, 1, 1), None, sigma=1e6 if kind == "alfven" else 0.0)
+    o = oracle.Oracle((nx, 1, 1), None, sigma=1e6 if kind == "alfven" else 0.0, collision=collision)
     o.init(f)
     key = "p" if kind == "sound" else "By"
     speed = _phase_speed(o, key, nx, 400, 50)
@@ -403,7 +405,7 @@ def test_printed_collision_survives_supersonic_shear():
     failed cell (the paper reports such runs; it notes the model's trouble at high speed)."""
     def first_failure(collision, steps):
         w = W.kh_box(n_cells=32, U0=0.6, sigma=100.0)
-        o = oracle.Oracle(w.shape, w.bc, collision=collision, **w.params)
+        o = oracle.Oracle(w.shape, w.bc, **dict(w.params, collision=collision))
         o.init(w.fields)
         for done in range(100, steps + 1, 100):
             o.step(100)
