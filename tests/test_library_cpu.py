@@ -58,10 +58,22 @@ def _create(**kw):
     (dict(sigma=-1.0), R.RMHDLB_EINVAL),
     (dict(c=0.0), R.RMHDLB_EINVAL),
     (dict(storage=7), R.RMHDLB_EINVAL),
+    (dict(collision=2), R.RMHDLB_EINVAL),
+    (dict(divb_fix=3), R.RMHDLB_EINVAL),
+    (dict(nu=0.0), R.RMHDLB_EINVAL),
 ])
 def test_parameter_validation_without_device(kw, code):
     rc, h = _create(**kw)
     assert rc == code and not h.value
+
+
+@pytest.mark.parametrize("shape", [(0, 8, 8), (8, -1, 8), (2048, 2048, 300)])
+def test_grid_size_limits(shape):
+    """Empty grids and grids whose cell indices overflow 32 bits (N > 2^30) are rejected before any
+    device call."""
+    P = R.make_params(shape)
+    h = ctypes.c_void_p()
+    assert R.load().rmhdlb_create(ctypes.byref(P), None, ctypes.byref(h)) == R.RMHDLB_EINVAL and not h.value
 
 
 def test_mixed_periodic_axis_rejected():
