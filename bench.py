@@ -89,9 +89,15 @@ def cpu_baseline(budget_s):
         o.step(2)
         steps += 2
     el = time.perf_counter() - t0
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": w.ncells * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"flare generator at 64x64x32 ({w.ncells} cells), {steps} steps, {el:.1f} s, "
-                      f"single-threaded FP64 C oracle on {os.cpu_count()} visible host cores"}
+                      f"single-threaded FP64 C oracle: 1 of {os.cpu_count()} visible host cores ({model})"}
 
 
 def sweep_main(args):

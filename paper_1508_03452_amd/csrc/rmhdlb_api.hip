@@ -300,7 +300,6 @@ int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** ou
     // tuning sweeps).
     C->tune.zb = 4;
     C->tune.px = 64;
-    if (const char* v = getenv("RMHDLB_ZB")) C->tune.zb = atoi(v) > 0 ? atoi(v) : 1;
     *out = C;
     return RMHDLB_OK;
 }
