@@ -82,8 +82,17 @@ typedef struct {
     int32_t null_band;           /* reconnection-rate null search: rows with |y| <= null_band cells
                                     (cell centres y_j = j + 1/2 - ny/2); < 1 selects 64 */
     int32_t collision;           /* RMHDLB_COLL_*: the f collision (see below) */
-    int32_t reserved[4];         /* must be zero */
+    int32_t flux;                /* RMHDLB_FLUX_*: the face values of the transport (see below) */
+    int32_t reserved[3];         /* must be zero */
 } rmhdlb_params;
+
+/* The face value h_i^a of the transport in Eq. rlb, which the paper takes
+ * from a reference it cites: the upwind value along the link of population i
+ * plus a minmod-limited slope term.  MUSCL (default): slope weight 1/2.
+ * LAX_WENDROFF: weight (1 - C)/2 with C the Courant number along a link,
+ * the limited Lax-Wendroff form, which translates quadratic profiles exactly
+ * where the limiter keeps the upwind-side slope. */
+enum { RMHDLB_FLUX_MUSCL = 0, RMHDLB_FLUX_LAX_WENDROFF = 1 };
 
 /* The f collision of Eq. rlb.  EXPLICIT (default): f' = f - omega (f - f_eq)
  * on the transported f, which conserves T^{0 nu} exactly in every cell.

@@ -33,6 +33,7 @@ class _Params(ctypes.Structure):
         ("alpha", ctypes.c_double), ("Gamma", ctypes.c_double), ("sigma", ctypes.c_double),
         ("nu", ctypes.c_double),
         ("divb_fix", ctypes.c_int32), ("null_band", ctypes.c_int32), ("collision", ctypes.c_int32),
+        ("flux", ctypes.c_int32),
     ]
 
 
@@ -78,7 +79,7 @@ def _vec(x):
 
 
 DEFAULTS = dict(dx=1.0, c=1.0, mu0=1.0, tau=1.0, tau_h=0.5, alpha=0.1, Gamma=4.0 / 3.0, sigma=1.0,
-                nu=27.0 ** 0.5, divb_fix=0, null_band=64, collision=0)
+                nu=27.0 ** 0.5, divb_fix=0, null_band=64, collision=0, flux=0)
 
 
 def make_params(shape=(1, 1, 1), bc=None, **kw):
@@ -96,6 +97,7 @@ def make_params(shape=(1, 1, 1), bc=None, **kw):
     P.divb_fix = int(d["divb_fix"])
     P.null_band = int(d["null_band"])
     P.collision = int(d["collision"])
+    P.flux = int(d["flux"])
     return P
 
 

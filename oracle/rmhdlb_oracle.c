@@ -47,6 +47,7 @@ typedef struct {
     int32_t divb_fix;  /* normal-B adjustment on open faces (Reading R22) */
     int32_t null_band; /* half-width in y-cells of the null-point search band (< 1: 64) */
     int32_t collision; /* f collision: 0 explicit (Reading R4), 1 the printed semi-implicit form */
+    int32_t flux;      /* face values: 0 MUSCL-minmod (Reading R2), 1 limited Lax-Wendroff */
 } orc_params;
 
 /* ---------------------------------------------------------------- lattice */
@@ -425,7 +426,9 @@ static inline double minmod(double a, double b)
  * is (c_0/c_t) c_a c dt/dx = sqrt(19/54) for every moving population
  * (Reading R17: time enters as x^0 = c t).  For the six axis populations this
  * is the printed axis-wise difference; for the face diagonals the axis-wise
- * unsplit form has C_x + C_y = 1.19 > 1 and is unstable.
+ * unsplit form has C_x + C_y = 1.19 > 1 and is unstable.  The alternative
+ * reading (flux = 1) is the limited Lax-Wendroff face value, whose slope term
+ * carries the factor (1 - C): exact translation of quadratic profiles.
  * Returns the flux difference (dt/dx)(c_0/c_t) [h(x + e_i/2) - h(x - e_i/2)]. */
 static double advection(const orc_ctx *C, const double *arr, const double *ghost, int i, int x, int y, int z)
 {
@@ -437,8 +440,9 @@ static double advection(const orc_ctx *C, const double *arr, const double *ghost
     double fm1 = value_at(C, arr, ghost, i, x - e[0], y - e[1], z - e[2]);
     double f0 = value_at(C, arr, ghost, i, x, y, z);
     double fp1 = value_at(C, arr, ghost, i, x + e[0], y + e[1], z + e[2]);
-    double face_plus = f0 + 0.5 * minmod(f0 - fm1, fp1 - f0);     /* face x + e_i/2, upwind cell x */
-    double face_minus = fm1 + 0.5 * minmod(fm1 - fm2, f0 - fm1);  /* face x - e_i/2, upwind cell x - e_i */
+    double s = C->P.flux == 1 ? 0.5 * (1.0 - cour) : 0.5;
+    double face_plus = f0 + s * minmod(f0 - fm1, fp1 - f0);     /* face x + e_i/2, upwind cell x */
+    double face_minus = fm1 + s * minmod(fm1 - fm2, f0 - fm1);  /* face x - e_i/2, upwind cell x - e_i */
     return cour * (face_plus - face_minus);
 }
 
@@ -755,6 +759,7 @@ ORC_API int rmhdlb_oracle_create(const orc_params *P, void **out)
     }
     if (P->divb_fix != 0 && P->divb_fix != 1) return ORC_EINVAL;
     if (P->collision != 0 && P->collision != 1) return ORC_EINVAL;
+    if (P->flux != 0 && P->flux != 1) return ORC_EINVAL;
     if (P->tau_h != 0.5) return ORC_EUNSUPPORTED; /* Eq. Ex_force holds for tau_h = 1/2 */
     orc_ctx *C = (orc_ctx *)calloc(1, sizeof(orc_ctx));
     if (!C) return ORC_ENOMEM;

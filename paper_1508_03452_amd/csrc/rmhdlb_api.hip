@@ -66,12 +66,13 @@ int validate(const rmhdlb_params* P) {
     }
     if (P->divb_fix != 0 && P->divb_fix != 1) return RMHDLB_EINVAL;
     if (P->collision != RMHDLB_COLL_EXPLICIT && P->collision != RMHDLB_COLL_PRINTED) return RMHDLB_EINVAL;
+    if (P->flux != RMHDLB_FLUX_MUSCL && P->flux != RMHDLB_FLUX_LAX_WENDROFF) return RMHDLB_EINVAL;
     if (!(P->dx > 0) || !(P->c > 0) || !(P->mu0 > 0) || !(P->tau > 0) || !(P->alpha >= 0) || !(P->Gamma > 1) ||
         !(P->sigma >= 0) || !(P->nu > 0) || !isfinite(P->sigma) || !isfinite(P->alpha))
         return RMHDLB_EINVAL;
     if (P->storage != RMHDLB_STORE_F64 && P->storage != RMHDLB_STORE_F32 && P->storage != RMHDLB_STORE_F16)
         return RMHDLB_EINVAL;
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 3; ++k)
         if (P->reserved[k] != 0) return RMHDLB_EINVAL;
     if (P->tau_h != 0.5) return RMHDLB_EUNSUPPORTED;  // the force form of Eq. Ex_force needs tau_h = 1/2
     return RMHDLB_OK;
@@ -110,6 +111,7 @@ Consts make_consts(const rmhdlb_params* P) {
     K.dx = P->dx;
     K.eps0 = 1.0 / (P->mu0 * P->c * P->c);
     K.cour = rmhd::KAPPA * P->c * dt / P->dx;
+    K.slope = P->flux == RMHDLB_FLUX_LAX_WENDROFF ? 0.5 * (1.0 - K.cour) : 0.5;
     K.kv = P->alpha * P->c * dt / P->dx;
     K.inv_tau = 1.0 / P->tau;
     const double ct_c0 = sqrt(27.0) / P->nu, ca = sqrt(19.0) / P->nu;

@@ -64,6 +64,7 @@ struct Consts {
     int64_t g0;          // ghost cells in front of cell 0 of every array
     double c, dx, eps0;
     double cour;         // Courant number along a link: kappa c dt / dx
+    double slope;        // weight of the limited slope in a face value: 1/2 (MUSCL) or (1 - cour)/2 (Lax-Wendroff)
     double kv;           // bulk-viscosity coefficient alpha c dt / dx
     double inv_tau;      // 1 / tau (tau in units of dt)
     double wg;           // rate of the g collision, (c_0 nu / c_t) / tau

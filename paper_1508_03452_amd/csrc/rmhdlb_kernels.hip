@@ -317,8 +317,8 @@ __device__ __forceinline__ void macroscopic(const TS* __restrict__ src, const TE
             const vec2<double> m2 = fg(om2), m1 = fg(om1), p1 = fg(op1);
             {
                 const double fm2 = m2.x, fm1 = m1.x, fp1 = p1.x;
-                const double face_p = f0 + 0.5 * minmod(f0 - fm1, fp1 - f0);
-                const double face_m = fm1 + 0.5 * minmod(fm1 - fm2, f0 - fm1);
+                const double face_p = f0 + K.slope * minmod(f0 - fm1, fp1 - f0);
+                const double face_m = fm1 + K.slope * minmod(fm1 - fm2, f0 - fm1);
                 const double lap = (fo(nb.at(1, 0, 0)) + fo(nb.at(-1, 0, 0))) +
                                    (fo(nb.at(0, 1, 0)) + fo(nb.at(0, -1, 0))) +
                                    (fo(nb.at(0, 0, 1)) + fo(nb.at(0, 0, -1))) - 6.0 * f0;
@@ -326,8 +326,8 @@ __device__ __forceinline__ void macroscopic(const TS* __restrict__ src, const TE
             }
             {
                 const double gm2 = m2.y, gm1 = m1.y, gp1 = p1.y;
-                const double face_p = g0 + 0.5 * minmod(g0 - gm1, gp1 - g0);
-                const double face_m = gm1 + 0.5 * minmod(gm1 - gm2, g0 - gm1);
+                const double face_p = g0 + K.slope * minmod(g0 - gm1, gp1 - g0);
+                const double face_m = gm1 + K.slope * minmod(gm1 - gm2, g0 - gm1);
                 gv = g0 - K.cour * (face_p - face_m);
             }
         }
@@ -553,7 +553,7 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
     // Array bases stay uniform (scalar registers); the lane's choice between
     // the two arrays of a pair is folded into its 32-bit element index.
     const int hc = cell + (h ? (int)S : 0);
-    const V cour = (V)K.cour, kv = (V)K.kv;
+    const V cour = (V)K.cour, kv = (V)K.kv, slope = (V)K.slope;
     V Fv[10], Gv[10], Hv[13];
     V t00 = 0, t0x = 0, t0y = 0, t0z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0, n0 = 0;
     // slot 0: f_0, g_0 (lane 0) and h_rest (lane 1)
@@ -608,11 +608,11 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
                 lzm = lap_at(lap_zm);
             }
             const V lap = (lxp + lxm) + (lyp + lym) + (lzp + lzm) - V(6) * f0;
-            const V fv = f0 - cour * ((f0 + V(0.5) * minmod(f0 - fm1, fp1 - f0)) -
-                                      (fm1 + V(0.5) * minmod(fm1 - fm2, f0 - fm1))) + kv * lap;
+            const V fv = f0 - cour * ((f0 + slope * minmod(f0 - fm1, fp1 - f0)) -
+                                      (fm1 + slope * minmod(fm1 - fm2, f0 - fm1))) + kv * lap;
             const V g0 = c0.y, gm2 = m2.y, gm1 = m1.y, gp1 = p1.y;
-            const V gv = g0 - cour * ((g0 + V(0.5) * minmod(g0 - gm1, gp1 - g0)) -
-                                      (gm1 + V(0.5) * minmod(gm1 - gm2, g0 - gm1)));
+            const V gv = g0 - cour * ((g0 + slope * minmod(g0 - gm1, gp1 - g0)) -
+                                      (gm1 + slope * minmod(gm1 - gm2, g0 - gm1)));
             Fv[s] = fv;
             Gv[s] = gv;
             // Keep each slot's arithmetic next to its loads: without this the

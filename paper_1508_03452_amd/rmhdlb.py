@@ -28,7 +28,7 @@ class rmhdlb_params(ctypes.Structure):
         ("tau", ctypes.c_double), ("tau_h", ctypes.c_double), ("alpha", ctypes.c_double),
         ("Gamma", ctypes.c_double), ("sigma", ctypes.c_double), ("nu", ctypes.c_double),
         ("storage", ctypes.c_int32), ("divb_fix", ctypes.c_int32), ("null_band", ctypes.c_int32),
-        ("collision", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4),
+        ("collision", ctypes.c_int32), ("flux", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -151,6 +151,7 @@ def make_params(shape, bc=None, storage="f64", **kw):
     P.divb_fix = int(d.get("divb_fix", 0))
     P.null_band = int(d.get("null_band", 64))
     P.collision = int(d.get("collision", 0))
+    P.flux = int(d.get("flux", 0))
     return P
 
 

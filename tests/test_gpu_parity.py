@@ -148,6 +148,21 @@ def test_printed_collision_supersonic_kh():
     check_case(w, 60, conditioned=True)
 
 
+def test_lax_wendroff_flux_random_3d_ragged_tiles():
+    """The limited Lax-Wendroff face values (flux = 1), 12 steps of a ragged periodic 3-D state."""
+    w = W.random_state(shape=(70, 6, 3), seed=2, vmax=0.1, Bmag=0.2, Emag=0.02, sigma=3.0)
+    w.params["flux"] = 1
+    check_case(w, 12)
+
+
+def test_lax_wendroff_flux_with_printed_collision_open_faces():
+    """Both alternative readings together on a box open on every face, 10 steps."""
+    w = W.random_state(shape=(20, 9, 7), seed=3, vmax=0.05, Bmag=0.2, Emag=0.02, sigma=30.0, solenoidal=True,
+                       bc=(("open", "open"),) * 3)
+    w.params.update(flux=1, collision=1)
+    check_case(w, 10)
+
+
 def test_printed_collision_limits():
     """The printed collision has 64-wide tiles and no learned guess or batches."""
     torch = _torch_cuda()

@@ -59,6 +59,7 @@ def _create(**kw):
     (dict(c=0.0), R.RMHDLB_EINVAL),
     (dict(storage=7), R.RMHDLB_EINVAL),
     (dict(collision=2), R.RMHDLB_EINVAL),
+    (dict(flux=2), R.RMHDLB_EINVAL),
     (dict(divb_fix=3), R.RMHDLB_EINVAL),
     (dict(nu=0.0), R.RMHDLB_EINVAL),
 ])

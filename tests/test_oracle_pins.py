@@ -416,6 +416,37 @@ def test_printed_collision_survives_supersonic_shear():
     assert first_failure(1, 1500) is None
 
 
+@pytest.mark.parametrize("flux", [0, 1])
+def test_transport_of_a_quadratic_profile(flux):
+    """One transport step of the +x population with the collision and the viscosity switched off
+    (tau -> infinity, alpha = 0) on a small quadratic profile eps (i - i0)^2 over a resting state.
+    Where the minmod limiter keeps the upwind-side slope (i > i0 + 1), the limited Lax-Wendroff face
+    value translates a quadratic exactly by the Courant number C (a property of the unlimited scheme
+    it reduces to there); the MUSCL face value of Reading R2 falls short by eps C^2."""
+    nx = 48
+    one = np.ones((1, 1, nx))
+    z = np.zeros_like(one)
+    o = oracle.Oracle((nx, 1, 1), None, tau=1e300, alpha=0.0, flux=flux)
+    o.init(dict(n=one, p=one, u=(z, z.copy(), z.copy()), E=(z.copy(), z.copy(), z.copy()),
+                B=(z.copy(), z.copy(), z.copy()), rho_c=z.copy()))
+    st = o.get_state()
+    i = np.arange(nx, dtype=np.float64)
+    i0, eps = 10.0, 1e-7
+    st2 = st.copy()
+    st2[1, 0, 0, :] += eps * (i - i0) ** 2                      # F of direction +x
+    o.set_state(st2)
+    o.step(1)
+    got = (o.get_state()[1, 0, 0, :] - st[1, 0, 0, :]) / eps
+    C = np.sqrt(19.0 / 54.0)
+    sel = (i >= i0 + 2) & (i < nx - 3)
+    exact = (i - C - i0) ** 2
+    err = np.abs(got - exact)[sel].max()
+    if flux == 1:
+        assert err < 1e-6, err
+    else:
+        assert abs(np.abs(got - exact)[sel].max() - C * C) < 1e-6 and abs(np.abs(got - exact)[sel].min() - C * C) < 1e-6
+
+
 def _sheet_box_run(n_cells, sigma, steps):
     w = W.sheet_box(n_cells, sigma)
     o = _run(w, steps)
