@@ -91,7 +91,8 @@ typedef struct {
  * plus a minmod-limited slope term.  MUSCL (default): slope weight 1/2.
  * LAX_WENDROFF: weight (1 - C)/2 with C the Courant number along a link,
  * the limited Lax-Wendroff form, which translates quadratic profiles exactly
- * where the limiter keeps the upwind-side slope. */
+ * where the limiter keeps the upwind-side slope.  Like the printed collision
+ * it is built for 64-wide tiles without the learned guess or batches. */
 enum { RMHDLB_FLUX_MUSCL = 0, RMHDLB_FLUX_LAX_WENDROFF = 1 };
 
 /* The f collision of Eq. rlb.  EXPLICIT (default): f' = f - omega (f - f_eq)

@@ -100,6 +100,7 @@ Consts make_consts(const rmhdlb_params* P) {
     K.divb = any_open;
     K.band = P->null_band >= 1 ? P->null_band : 64;
     K.coll = P->collision;
+    K.flux = P->flux;
     const int64_t fsz[3] = {(int64_t)P->ny * P->nz, (int64_t)P->nx * P->nz, (int64_t)P->nx * P->ny};
     K.fo[0] = 0;
     for (int f = 0; f < 6; ++f) K.fo[f + 1] = K.fo[f] + fsz[f >> 1];
@@ -457,7 +458,7 @@ int rmhdlb_set_guess_weights(rmhdlb_ctx* C, const rmhdlb_guess_weights* w) {
 int rmhdlb_set_guess(rmhdlb_ctx* C, int32_t mode) {
     if (!C || (mode != RMHDLB_GUESS_PLAIN && mode != RMHDLB_GUESS_MLP)) return RMHDLB_EINVAL;
     if (mode == RMHDLB_GUESS_MLP && !C->gt) return RMHDLB_EINVAL;
-    if (mode == RMHDLB_GUESS_MLP && C->K.coll) return RMHDLB_EUNSUPPORTED;  // not built for the printed collision
+    if (mode == RMHDLB_GUESS_MLP && (C->K.coll || C->K.flux)) return RMHDLB_EUNSUPPORTED;  // default readings only
     C->guess_mode = mode;
     return RMHDLB_OK;
 }
@@ -631,7 +632,7 @@ int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out) {
         for (int pi = 0; pi < 3; ++pi)
             for (int zi = 0; zi < 5; ++zi) {
                 if (zbs[zi] > C->K.nz && zbs[zi] != 1) continue;
-                if ((C->guess_mode || C->K.coll) && pxs[pi] != 64) continue;  // built for 64-wide tiles only
+                if ((C->guess_mode || C->K.coll || C->K.flux) && pxs[pi] != 64) continue;  // 64-wide tiles only
                 rmhd::StepTuning t;
                 t.px = pxs[pi];
                 t.zb = zbs[zi];
@@ -658,7 +659,7 @@ int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out) {
 
 int rmhdlb_set_tuning(rmhdlb_ctx* C, int32_t px, int32_t zb) {
     if (!C || (px != 64 && px != 32 && px != 16) || zb < 1) return RMHDLB_EINVAL;
-    if ((C->guess_mode || C->K.coll) && px != 64) return RMHDLB_EINVAL;
+    if ((C->guess_mode || C->K.coll || C->K.flux) && px != 64) return RMHDLB_EINVAL;
     C->tune.px = px;
     C->tune.zb = zb;
     return RMHDLB_OK;
@@ -767,7 +768,8 @@ int rmhdlb_batch_create(const rmhdlb_params* params, int32_t n, void* hip_stream
     for (int i = 1; i < n; ++i)
         if (params[i].storage != params[0].storage) return RMHDLB_EINVAL;
     for (int i = 0; i < n; ++i)
-        if (params[i].collision != RMHDLB_COLL_EXPLICIT) return RMHDLB_EUNSUPPORTED;  // batches: explicit only
+        if (params[i].collision != RMHDLB_COLL_EXPLICIT || params[i].flux != RMHDLB_FLUX_MUSCL)
+            return RMHDLB_EUNSUPPORTED;  // batches: the default readings only
     rmhdlb_batch* B = new (std::nothrow) rmhdlb_batch();
     if (!B) return RMHDLB_ENOMEM;
     B->n = n;

@@ -57,14 +57,12 @@ struct Consts {
     int divb;            // 1: the normal B of open-face cells is adjusted so that div B = 0 there
     int open_lo[3], open_hi[3];  // face takes the div B adjustment (open, with at least 2 cells on the axis)
     int band;            // half-width in rows of the reconnection null search band
-    int coll;            // f collision: 0 explicit, 1 the printed semi-implicit form (host dispatch)
     int64_t fo[7];       // offsets of the six face arrays of adjusted normal B (x lo, x hi, y lo, ...), fo[6] = total
     int64_t N;           // cells
     int64_t stride;      // values per state array (ghost planes + N, rounded up)
     int64_t g0;          // ghost cells in front of cell 0 of every array
     double c, dx, eps0;
     double cour;         // Courant number along a link: kappa c dt / dx
-    double slope;        // weight of the limited slope in a face value: 1/2 (MUSCL) or (1 - cour)/2 (Lax-Wendroff)
     double kv;           // bulk-viscosity coefficient alpha c dt / dx
     double inv_tau;      // 1 / tau (tau in units of dt)
     double wg;           // rate of the g collision, (c_0 nu / c_t) / tau
@@ -79,6 +77,10 @@ struct Consts {
     // over the directions with e^a != 0 (any axis a), gs0 = sum_i gsh_i.
     double fsh[3], gsh[3];
     double fs0, fsaa, gs0;
+    // the alternative readings (the host picks the kernel variant from coll, flux)
+    double slope;        // weight of the limited slope in a face value: 1/2 (MUSCL) or (1 - cour)/2 (Lax-Wendroff)
+    int coll;            // f collision: 0 explicit, 1 the printed semi-implicit form
+    int flux;            // face values: 0 MUSCL, 1 limited Lax-Wendroff
 };
 
 constexpr double KAPPA = 0.83887049280786108;   // sqrt(19/27)

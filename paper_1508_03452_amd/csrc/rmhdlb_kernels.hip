@@ -536,9 +536,10 @@ __device__ __forceinline__ V pair_sum(V v) {
     return v + __shfl_xor(v, 32, 64);
 }
 
-// CM: the f collision, 0 explicit (Reading R4), 1 the printed semi-implicit
-// form of Eq. rlb, f' = (f + omega f_eq) / (1 + omega).
-template <bool NT, typename TS, typename TE, typename V, int GM, int CM = 0>
+// VR: the alternative readings, bit 0 the printed semi-implicit f collision
+// of Eq. rlb, f' = (f + omega f_eq) / (1 + omega) (else explicit, Reading
+// R4); bit 1 the limited Lax-Wendroff face values (else MUSCL, Reading R2).
+template <bool NT, typename TS, typename TE, typename V, int GM, int VR = 0>
 __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* __restrict__ se, TS* __restrict__ dd,
                                           TE* __restrict__ de, const double* __restrict__ faceB,
                                           const GuessTables* __restrict__ gt, const Consts& K, int cell,
@@ -553,7 +554,8 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
     // Array bases stay uniform (scalar registers); the lane's choice between
     // the two arrays of a pair is folded into its 32-bit element index.
     const int hc = cell + (h ? (int)S : 0);
-    const V cour = (V)K.cour, kv = (V)K.kv, slope = (V)K.slope;
+    constexpr int CM = VR & 1;
+    const V cour = (V)K.cour, kv = (V)K.kv, slope = (VR & 2) ? (V)K.slope : V(0.5);
     V Fv[10], Gv[10], Hv[13];
     V t00 = 0, t0x = 0, t0y = 0, t0z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0, n0 = 0;
     // slot 0: f_0, g_0 (lane 0) and h_rest (lane 1)
@@ -755,7 +757,7 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
 // of the stencil meet in that XCD's L2.
 // With the learned guess the network runs on whole wavefronts, so lanes past
 // a ragged edge stay and compute a copy of the edge cell without storing it.
-template <bool NT, typename TS, typename TE, typename V, int GM, int PXT, int CM = 0>
+template <bool NT, typename TS, typename TE, typename V, int GM, int PXT, int VR = 0>
 __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE* __restrict__ se,
                                             TS* __restrict__ dd, TE* __restrict__ de,
                                             const double* __restrict__ faceB, const GuessTables* __restrict__ gt,
@@ -778,12 +780,12 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
     for (int z = z0; z < z1; ++z) {
         const int cell = x + K.nx * (y + K.ny * z);
         const Nbr nb = make_nbr<true>(K, x, y, z);
-        pair_cell<NT, TS, TE, V, GM, CM>(sd, se, dd, de, faceB, gt, K, cell, nb, h, x, y, z,
+        pair_cell<NT, TS, TE, V, GM, VR>(sd, se, dd, de, faceB, gt, K, cell, nb, h, x, y, z,
                                          GM == GUESS_NONE ? true : active);
     }
 }
 
-template <bool NT, typename TS, typename TE, typename V, int GM, int PXT, int CM>
+template <bool NT, typename TS, typename TE, typename V, int GM, int PXT, int VR>
 __global__ __launch_bounds__(PTPB, (fused_waves<TS, GM>())) void k_fused_step(const TS* __restrict__ sd, const TE* __restrict__ se,
                                                         TS* __restrict__ dd, TE* __restrict__ de,
                                                         const double* __restrict__ faceB,
@@ -791,7 +793,7 @@ __global__ __launch_bounds__(PTPB, (fused_waves<TS, GM>())) void k_fused_step(co
                                                         int tiles_x, int ncol, int zb, int nblk) {
     const int b = tile_of_block(nblk);
     if (b >= nblk) return;  // uniform over the block
-    fused_block<NT, TS, TE, V, GM, PXT, CM>(sd, se, dd, de, faceB, gt, K, tiles_x, ncol, zb, b);
+    fused_block<NT, TS, TE, V, GM, PXT, VR>(sd, se, dd, de, faceB, gt, K, tiles_x, ncol, zb, b);
 }
 
 // Index of the instance whose range [first[i], first[i + 1]) holds v (first
@@ -1349,7 +1351,7 @@ void step_geometry(const Consts& K, int px, int zb, int& tiles_x, int& ncol, int
     nblk = ncol * ((K.nz + zb - 1) / zb);
 }
 
-template <typename TS, int GM, int PXT, int CM = 0>
+template <typename TS, int GM, int PXT, int VR = 0>
 static void launch_fused(const TS* sd, const void* se, TS* dd, void* de, double* faceB, const GuessTables* gt,
                          const Consts& K, int zb, hipStream_t s) {
     using TE = typename StoreTypes<TS>::E;
@@ -1357,7 +1359,7 @@ static void launch_fused(const TS* sd, const void* se, TS* dd, void* de, double*
     int tx, ncol, nblk;
     step_geometry(K, PXT, zb, tx, ncol, nblk);
     const int grid = ((nblk + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_fused_step<true, TS, TE, V, GM, PXT, CM>), dim3(grid), dim3(PTPB), 0, s, sd, (const TE*)se, dd,
+    hipLaunchKernelGGL((k_fused_step<true, TS, TE, V, GM, PXT, VR>), dim3(grid), dim3(PTPB), 0, s, sd, (const TE*)se, dd,
                        (TE*)de, (const double*)faceB, gt, K, tx, ncol, zb, nblk);
 }
 
@@ -1369,9 +1371,15 @@ hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K
     const int zb = tune.zb > 0 ? (tune.zb < K.nz ? tune.zb : K.nz) : 1;
     const TS* sd = (const TS*)src.dist;
     TS* dd = (TS*)dst.dist;
-    if (K.coll) {  // the printed collision: 64-wide tiles, no guess
+    const int vr = (K.coll ? 1 : 0) | (K.flux ? 2 : 0);
+    if (vr) {  // the alternative readings: 64-wide tiles, no guess
         if (gt) return hipErrorNotSupported;
-        launch_fused<TS, GUESS_NONE, 64, 1>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+        if (vr == 1)
+            launch_fused<TS, GUESS_NONE, 64, 1>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+        else if (vr == 2)
+            launch_fused<TS, GUESS_NONE, 64, 2>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+        else
+            launch_fused<TS, GUESS_NONE, 64, 3>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
     } else if (gt)  // the guess path is built for 64-wide tiles only
         launch_fused<TS, GUESS_PAIR, 64>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
     else if (tune.px == 32)
