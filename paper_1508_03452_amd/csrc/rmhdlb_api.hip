@@ -299,8 +299,7 @@ int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** ou
     }
     C->cur = 0;
     C->step = 0;
-    // Launch shape: z-planes per block (overridable through RMHDLB_ZB for
-    // tuning sweeps).
+    // Launch shape until rmhdlb_autotune or rmhdlb_set_tuning picks another.
     C->tune.zb = 4;
     C->tune.px = 64;
     *out = C;
