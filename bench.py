@@ -190,8 +190,11 @@ def timed_form(w, storage, guess, args, stream):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     d = s.moments(fields=())["diag"]
+    hist = [int(v) for v in d["newton_hist"]]
+    while len(hist) > 1 and hist[-1] == 0:
+        hist.pop()
     info.update(failed_cells=d["n_failed"], mean_newton_iters=round(d["mean_iters"], 3),
-                guess_fallbacks=d["n_fallback"])
+                newton_hist=hist, guess_fallbacks=d["n_fallback"])
     return ev0.elapsed_time(ev1) / args.steps, wall, s, info
 
 
@@ -293,7 +296,8 @@ def main():
             "storage": "f16 (shifted)", "recovery": "plain Newton",
             "value": round(ncell / (ms3 * 1e-3) / 1e6, 2), "unit": "MLUPS", "ms_per_step": round(ms3, 4),
             "speedup_vs_headline": round(ms / ms3, 3), "guess_speedup": round(ms3 / ms2, 3),
-            "mean_newton_iters": info3["mean_newton_iters"], "tile": info3["tile"]}
+            "mean_newton_iters": info3["mean_newton_iters"], "newton_hist": info3["newton_hist"],
+            "tile": info3["tile"]}
     out["copy_probe_gbs"] = copy_probe_gbs(stream)
     del w.fields
     if not args.no_cpu_baseline:
