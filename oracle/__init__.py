@@ -65,6 +65,7 @@ def lib():
         L.rmhdlb_oracle_recover.argtypes = [ctypes.POINTER(_Params), dp, ctypes.c_double, dp, dp, dp]
         L.rmhdlb_oracle_ohm.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, ctypes.c_double, dp, dp]
         L.rmhdlb_oracle_set_driven.argtypes = [ctypes.c_void_p, dp, dp, dp * 3, dp * 3]
+        L.rmhdlb_oracle_set_force.argtypes = [ctypes.c_void_p, ctypes.POINTER(dp * 3), ctypes.c_double]
         L.rmhdlb_oracle_fluid_tensor.argtypes = [ctypes.c_void_p, dp, dp]
         _LIB = L
     return _LIB
@@ -192,6 +193,19 @@ class Oracle:
         rc = lib().rmhdlb_oracle_set_driven(self._h, arr(face["n"]), arr(face["p"]), u, B)
         if rc != 0:
             raise ValueError(f"oracle set_driven failed ({rc})")
+
+    def set_force(self, F, gate=0.0):
+        """External force density (Reading R26): F = (Fx, Fy, Fz) arrays on the grid, or None to switch it
+        off; it acts while the previous step's largest |beta| is below gate (<= 0: always)."""
+        if F is None:
+            rc = lib().rmhdlb_oracle_set_force(self._h, None, 0.0)
+        else:
+            arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), self.grid)) for a in F]
+            dp = ctypes.POINTER(ctypes.c_double)
+            ptrs = (dp * 3)(*[_ptr(a) for a in arrs])
+            rc = lib().rmhdlb_oracle_set_force(self._h, ctypes.byref(ptrs), float(gate))
+        if rc != 0:
+            raise ValueError(f"oracle set_force failed ({rc})")
 
     def get_state(self):
         n = lib().rmhdlb_oracle_state_len(self._h)

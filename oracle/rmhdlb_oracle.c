@@ -156,6 +156,9 @@ typedef struct {
     double *gf, *gg, *gh, *gE;
     double *Bt;       /* B of Eq. Cal_B from the streamed h of every cell, 3 arrays of N */
     double *Ez0;      /* initial E^z, for the reconnection rate */
+    double *force;    /* external force density (3 arrays of N) or NULL (Reading R26) */
+    double fgate;     /* the force acts while the previous step's max |beta| < fgate (<= 0: always) */
+    double vmax;      /* max |beta| over the cells at the last step's recovery */
     double B0;        /* max |B| of the initial fields */
 } orc_ctx;
 
@@ -736,6 +739,32 @@ static void collision_pass(orc_ctx *C)
                 for (int k = 0; k <= QH; k++) hn[(long)k * N + id] = hp[k] - (hp[k] - heq[k]) / P->tau_h;
                 for (int a = 0; a < 3; a++) En[(long)a * N + id] = m->E[a];
             }
+    /* Reading R26: an external force density F (the flare's driver, Sec. IV) enters
+     * as a source after the collision: c dt F^a into T^{0a} through the moving
+     * populations, (19/9) w_i (e_i . c dt F) / kappa (sum_i w_i e_i^a e_i^b =
+     * (9/19) delta^ab, no change of T^00 or T^ab), and the work c dt F . beta into
+     * T^00 through the rest population.  It acts while the largest |beta| of the
+     * previous step's recovery is below the gate (one-step lag). */
+    double vmax = 0.0;
+    for (long id = 0; id < N; id++) {
+        const orc_macro *m = &C->mac[id];
+        const double b = sqrt(m->beta[0] * m->beta[0] + m->beta[1] * m->beta[1] + m->beta[2] * m->beta[2]);
+        if (b > vmax) vmax = b;
+    }
+    if (C->force && (C->fgate <= 0.0 || C->vmax < C->fgate)) {
+        const double kap = sqrt(19.0 / 27.0), cdt = P->c * C->dt;
+        for (long id = 0; id < N; id++) {
+            const orc_macro *m = &C->mac[id];
+            double F[3];
+            for (int a = 0; a < 3; a++) F[a] = cdt * C->force[(long)a * N + id];
+            fn[id] += F[0] * m->beta[0] + F[1] * m->beta[1] + F[2] * m->beta[2];
+            for (int i = 1; i < Q19; i++) {
+                const double eF = L->e[i][0] * F[0] + L->e[i][1] * F[1] + L->e[i][2] * F[2];
+                fn[(long)i * N + id] += (19.0 / 9.0) * L->w[i] * eF / kap;
+            }
+        }
+    }
+    C->vmax = vmax;
     C->cur = dst;
     C->step++;
 }
@@ -803,6 +832,7 @@ ORC_API int rmhdlb_oracle_create(const orc_params *P, void **out)
         free(C->mac);
         free(C->Bt);
         free(C->Ez0);
+        free(C->force);
         free(C->gf);
         free(C->gg);
         free(C->gh);
@@ -830,6 +860,7 @@ ORC_API void rmhdlb_oracle_destroy(void *ctx)
     free(C->mac);
     free(C->Bt);
     free(C->Ez0);
+    free(C->force);
     free(C->gf);
     free(C->gg);
     free(C->gh);
@@ -897,6 +928,27 @@ ORC_API int rmhdlb_oracle_set_driven(void *ctx, const double *n, const double *p
  * and the previous-step E is the given E.  Reading R18: h* is laid out so that the first pull delivers
  * h_k = h_eq-form(J0, E'0, B0) with E'0 = E0 + (dt/2) mu0 c^2 J0, so the first
  * force-corrected E equals E0; h*_0 = rho_c. */
+/* External force density (Reading R26): three arrays of N values in cell
+ * order, copied; NULL switches the force off.  gate: the force acts while the
+ * previous step's largest |beta| is below it (<= 0: always). */
+ORC_API int rmhdlb_oracle_set_force(void *ctx, const double *const F[3], double gate)
+{
+    orc_ctx *C = (orc_ctx *)ctx;
+    if (!C) return ORC_EINVAL;
+    if (!F) {
+        free(C->force);
+        C->force = NULL;
+        return ORC_OK;
+    }
+    for (int a = 0; a < 3; a++)
+        if (!F[a]) return ORC_EINVAL;
+    if (!C->force) C->force = (double *)malloc(sizeof(double) * 3 * (size_t)C->N);
+    if (!C->force) return ORC_ENOMEM;
+    for (int a = 0; a < 3; a++) memcpy(C->force + (long)a * C->N, F[a], sizeof(double) * (size_t)C->N);
+    C->fgate = gate;
+    return ORC_OK;
+}
+
 ORC_API int rmhdlb_oracle_init(void *ctx, const double *n, const double *p, const double *const u[3],
                                const double *const E[3], const double *const B[3], const double *rhoc_in)
 {
@@ -998,6 +1050,7 @@ ORC_API int rmhdlb_oracle_init(void *ctx, const double *n, const double *p, cons
     /* a driven face starts from the fields of its first interior plane */
     if (P->bc_lo[2] == BC_DRIVEN && fill_ghosts(C, n, p, u, B) != ORC_OK) return ORC_EINVAL;
     C->step = 0;
+    C->vmax = 0.0;  /* the force gate starts open */
     return ORC_OK;
 }
 

@@ -447,6 +447,53 @@ def test_transport_of_a_quadratic_profile(flux):
         assert abs(np.abs(got - exact)[sel].max() - C * C) < 1e-6 and abs(np.abs(got - exact)[sel].min() - C * C) < 1e-6
 
 
+def _resting_box(shape=(6, 5, 4), **params):
+    nx, ny, nz = shape
+    one = np.ones((nz, ny, nx))
+    z = np.zeros_like(one)
+    o = oracle.Oracle(shape, None, **params)
+    o.init(dict(n=one, p=one, u=(z, z.copy(), z.copy()), E=(z.copy(), z.copy(), z.copy()),
+                B=(z.copy(), z.copy(), z.copy()), rho_c=z.copy()))
+    return o, one
+
+
+def test_external_force_adds_momentum_and_does_work():
+    """Reading R26 on a periodic resting box with a uniform force density F: every step adds N c dt F to
+    the total momentum (Newton's second law), and to the total energy the work c dt sum F . beta with
+    the velocity the step's recovery sees (zero in the first step, the moments of the state after it
+    in the second)."""
+    o, one = _resting_box(sigma=1.0)
+    F = np.array([0.01, -0.02, 0.005])
+    o.set_force(tuple(f * one for f in F), 0.0)
+    cdt = 1.0 / np.sqrt(2.0)                     # c dt with dx / dt = sqrt(2) c, c = dx = 1
+    d0 = o.diagnostics()
+    o.step(1)
+    d1, m1 = o.diagnostics(), o.moments()
+    assert np.allclose(d1["momentum"] - d0["momentum"], one.size * cdt * F, rtol=1e-12, atol=0)
+    assert abs(d1["energy"] - d0["energy"]) < 1e-12 * d0["energy"]
+    work = cdt * sum(F[a] * m1[k].sum() for a, k in enumerate(("ux", "uy", "uz")))   # c = 1: beta = u
+    o.step(1)
+    d2 = o.diagnostics()
+    assert np.allclose(d2["momentum"] - d1["momentum"], one.size * cdt * F, rtol=1e-12, atol=0)
+    assert abs((d2["energy"] - d1["energy"]) - work) < 1e-10 * abs(work)
+
+
+def test_external_force_gate_closes_with_one_step_lag():
+    """With a gate below any velocity the force still acts in the first two steps (the gate looks at the
+    previous step's recovery, at rest in steps 1 and 2) and no more from step 3 on."""
+    o, one = _resting_box(sigma=1.0)
+    F = np.array([0.01, 0.0, 0.0])
+    o.set_force(tuple(f * one for f in F), 1e-9)
+    P = [o.diagnostics()["momentum"][0]]
+    for _ in range(4):
+        o.step(1)
+        P.append(o.diagnostics()["momentum"][0])
+    dP = np.diff(P)
+    step = one.size * F[0] / np.sqrt(2.0)
+    assert abs(dP[0] - step) < 1e-12 * step and abs(dP[1] - step) < 1e-12 * step
+    assert abs(dP[2]) < 1e-12 * step and abs(dP[3]) < 1e-12 * step
+
+
 def _sheet_box_run(n_cells, sigma, steps):
     w = W.sheet_box(n_cells, sigma)
     o = _run(w, steps)
