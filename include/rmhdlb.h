@@ -195,6 +195,23 @@ int rmhdlb_moments(rmhdlb_ctx *ctx, rmhdlb_fields_out *out, rmhdlb_diag *diag);
  * device; this call synchronises the stream). */
 int rmhdlb_set_driven_face(rmhdlb_ctx *ctx, const rmhdlb_face_in *face);
 
+/* External force density (the flare driver of Sec. IV, stellar flare; the
+ * paper gives no lattice form, this library's reading): F[a] are device
+ * arrays of N = nx ny nz FP64 values in cell order (x fastest), copied on the
+ * context's stream; NULL switches the force off.  Each step adds, after the
+ * collision, c dt F^a to the momentum T^{0a} of a cell through its moving f
+ * populations, (19/9) w_i (e_i . c dt F) / kappa each (no change of T^00 or
+ * T^ab from these), and the work c dt F . beta to T^00 through the rest
+ * population, with beta of that step's recovery.  The force acts while the
+ * largest |beta| of the previous step's recovery over the box is below gate
+ * (gate <= 0: always); the gate opens again at rmhdlb_init_fields.  Built for
+ * 64-wide tiles with the default readings: RMHDLB_EUNSUPPORTED with the
+ * printed collision, the Lax-Wendroff faces or the learned guess on, and
+ * batches with a forced instance refuse to step.  RMHDLB_EINVAL for NULL
+ * entries or a non-finite gate, RMHDLB_ENOMEM if the buffers cannot be
+ * allocated. */
+int rmhdlb_set_force(rmhdlb_ctx *ctx, const double *const F[3], double gate);
+
 /* ---- learned recovery guess (not in the paper) ----------------------------
  * The recovery (Sec. III, coupling subsection) finds the timelike eigenpair
  * of the fluid tensor; this library solves it by Newton on the secular

@@ -40,6 +40,8 @@ struct rmhdlb_ctx {
     double* aux;       // aux[0] = max |B| of the initial fields
     double* result;    // NPART sums, max |div B|, R, null cell, B0
     rmhd::GuessTables* gt;  // inference tables of the learned guess (device), null until installed
+    double* force;     // external force density, 3 N doubles, null until set
+    double* vmax;      // vmax[0]: largest |beta| of the last forced step; then the per-wavefront partials
     int guess_mode;    // RMHDLB_GUESS_*
     int64_t step;
     rmhd::StepTuning tune;
@@ -239,6 +241,8 @@ void release(rmhdlb_ctx* C) {
     if (C->ez0) (void)hipFree(C->ez0);
     if (C->aux) (void)hipFree(C->aux);
     if (C->gt) (void)hipFree(C->gt);
+    if (C->force) (void)hipFree(C->force);
+    if (C->vmax) (void)hipFree(C->vmax);
     if (C->result) (void)hipFree(C->result);
     delete C;
 }
@@ -356,7 +360,43 @@ int rmhdlb_init_fields(rmhdlb_ctx* C, const rmhdlb_fields_in* in) {
         for (int b = 0; b < 2; ++b)
             if (RMHD_DISPATCH(C, launch_ghost)(fp, C->K, C->sb[b], C->stream) != hipSuccess) return RMHDLB_EDEVICE;
     }
+    if (C->K.forced && hipMemsetAsync(C->vmax, 0, sizeof(double), C->stream) != hipSuccess)
+        return RMHDLB_EDEVICE;  // the force gate starts open
     C->step = 0;
+    return RMHDLB_OK;
+}
+
+int rmhdlb_set_force(rmhdlb_ctx* C, const double* const F[3], double gate) {
+    if (!C || !isfinite(gate)) return RMHDLB_EINVAL;
+    if (!F) {
+        C->K.forced = 0;
+        return RMHDLB_OK;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (!F[a]) return RMHDLB_EINVAL;
+    if (C->K.coll || C->K.flux || C->guess_mode) return RMHDLB_EUNSUPPORTED;
+    const int64_t N = C->K.N;
+    // one partial per wavefront of the widest launch (64-wide tiles, one plane per block)
+    const int64_t nparts = 4 * (int64_t)((C->K.nx + 63) / 64) * ((C->K.ny + 1) / 2) * C->K.nz;
+    if (!C->force && hipMalloc((void**)&C->force, sizeof(double) * 3 * (size_t)N) != hipSuccess) {
+        C->force = nullptr;
+        return RMHDLB_ENOMEM;
+    }
+    if (!C->vmax && hipMalloc((void**)&C->vmax, sizeof(double) * (size_t)(1 + nparts)) != hipSuccess) {
+        C->vmax = nullptr;
+        return RMHDLB_ENOMEM;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (hipMemcpyAsync(C->force + a * N, F[a], sizeof(double) * (size_t)N, hipMemcpyDeviceToDevice, C->stream) !=
+            hipSuccess)
+            return RMHDLB_EDEVICE;
+    if (hipMemsetAsync(C->vmax, 0, sizeof(double) * (size_t)(1 + nparts), C->stream) != hipSuccess)
+        return RMHDLB_EDEVICE;
+    C->K.force = C->force;
+    C->K.vmax_prev = C->vmax;
+    C->K.vmax_part = C->vmax + 1;
+    C->K.fgate = gate;
+    C->K.forced = 1;
     return RMHDLB_OK;
 }
 
@@ -457,7 +497,8 @@ int rmhdlb_set_guess_weights(rmhdlb_ctx* C, const rmhdlb_guess_weights* w) {
 int rmhdlb_set_guess(rmhdlb_ctx* C, int32_t mode) {
     if (!C || (mode != RMHDLB_GUESS_PLAIN && mode != RMHDLB_GUESS_MLP)) return RMHDLB_EINVAL;
     if (mode == RMHDLB_GUESS_MLP && !C->gt) return RMHDLB_EINVAL;
-    if (mode == RMHDLB_GUESS_MLP && (C->K.coll || C->K.flux)) return RMHDLB_EUNSUPPORTED;  // default readings only
+    if (mode == RMHDLB_GUESS_MLP && (C->K.coll || C->K.flux || C->K.forced))
+        return RMHDLB_EUNSUPPORTED;  // default readings, no force
     C->guess_mode = mode;
     return RMHDLB_OK;
 }
@@ -631,7 +672,7 @@ int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out) {
         for (int pi = 0; pi < 3; ++pi)
             for (int zi = 0; zi < 5; ++zi) {
                 if (zbs[zi] > C->K.nz && zbs[zi] != 1) continue;
-                if ((C->guess_mode || C->K.coll || C->K.flux) && pxs[pi] != 64) continue;  // 64-wide tiles only
+                if ((C->guess_mode || C->K.coll || C->K.flux || C->K.forced) && pxs[pi] != 64) continue;  // 64 only
                 rmhd::StepTuning t;
                 t.px = pxs[pi];
                 t.zb = zbs[zi];
@@ -658,7 +699,7 @@ int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out) {
 
 int rmhdlb_set_tuning(rmhdlb_ctx* C, int32_t px, int32_t zb) {
     if (!C || (px != 64 && px != 32 && px != 16) || zb < 1) return RMHDLB_EINVAL;
-    if ((C->guess_mode || C->K.coll || C->K.flux) && px != 64) return RMHDLB_EINVAL;
+    if ((C->guess_mode || C->K.coll || C->K.flux || C->K.forced) && px != 64) return RMHDLB_EINVAL;
     C->tune.px = px;
     C->tune.zb = zb;
     return RMHDLB_OK;
@@ -813,7 +854,7 @@ int rmhdlb_batch_step(rmhdlb_batch* B, int64_t nsteps) {
     const int parity0 = B->ctx[0]->cur;
     for (rmhdlb_ctx* C : B->ctx) {
         if (C->cur != parity0) return RMHDLB_EINVAL;
-        if (C->guess_mode) return RMHDLB_EUNSUPPORTED;
+        if (C->guess_mode || C->K.forced) return RMHDLB_EUNSUPPORTED;
     }
     if (nsteps == 0) return RMHDLB_OK;
     int rc = batch_table(B);

@@ -81,6 +81,13 @@ struct Consts {
     double slope;        // weight of the limited slope in a face value: 1/2 (MUSCL) or (1 - cour)/2 (Lax-Wendroff)
     int coll;            // f collision: 0 explicit, 1 the printed semi-implicit form
     int flux;            // face values: 0 MUSCL, 1 limited Lax-Wendroff
+    // external force density (3 arrays of N, cell order) and its gate: on while
+    // the previous step's largest |beta| (*vmax_prev) is below fgate (<= 0: always)
+    int forced;
+    double fgate;
+    const double* force;
+    const double* vmax_prev;
+    double* vmax_part;   // largest |beta| per wavefront of the step, reduced after it
 };
 
 constexpr double KAPPA = 0.83887049280786108;   // sqrt(19/27)

@@ -543,7 +543,7 @@ template <bool NT, typename TS, typename TE, typename V, int GM, int VR = 0>
 __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* __restrict__ se, TS* __restrict__ dd,
                                           TE* __restrict__ de, const double* __restrict__ faceB,
                                           const GuessTables* __restrict__ gt, const Consts& K, int cell,
-                                          const Nbr& nb, int h, int x, int y, int z, bool active) {
+                                          const Nbr& nb, int h, int x, int y, int z, bool active, double& bmax) {
     // stores of this cell's new state (lanes that only take part in the
     // wavefront's network evaluation store nothing)
     auto put = [&](auto* p, auto v) {
@@ -707,13 +707,27 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
     const V gc1 = (V)K.gc1, gc2 = (V)K.gc2, gc3b2 = (V)(K.gc3 * (M.beta[0] * M.beta[0] + M.beta[1] * M.beta[1] +
                                                               M.beta[2] * M.beta[2]));
     const V bx_ = (V)M.beta[0], by_ = (V)M.beta[1], bz_ = (V)M.beta[2];
+    // External force (Reading R26): c dt F^a into T^{0a} through the moving
+    // populations, (19/9) w_i (e_i . c dt F) / kappa each, and the work
+    // c dt F . beta into T^00 through the rest population; on while the
+    // previous step's largest |beta| is below the gate.
+    double fw = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    if constexpr ((VR & 4) != 0) {
+        bmax = fmax(bmax, sqrt(M.beta[0] * M.beta[0] + M.beta[1] * M.beta[1] + M.beta[2] * M.beta[2]));
+        if (!(K.fgate > 0.0) || *K.vmax_prev < K.fgate) {
+            const double cdt = K.dx * INV_SQRT2;  // c dt
+            fx = cdt * K.force[cell];
+            fy = cdt * K.force[K.N + cell];
+            fz = cdt * K.force[2 * K.N + cell];
+            fw = fx * M.beta[0] + fy * M.beta[1] + fz * M.beta[2];
+        }
+    }
     if (h == 0) {
         const V q0 = (V)K.fsh[0] - fe.template eq<0>();
         const V geq0 = (V)K.wp[0] * ng * (V(1) - gc3b2);
-        if (active)
-            st2<NT>(dd + fg_index(K, 0, cell),
-                    CM == 0 ? Fv[0] - rate * (Fv[0] + q0) : (Fv[0] - rate * q0) / (V(1) + rate),
-                    (Gv[0] + wg * (geq0 - (V)K.gsh[0])) * inv1wg);
+        V f0n = CM == 0 ? Fv[0] - rate * (Fv[0] + q0) : (Fv[0] - rate * q0) / (V(1) + rate);
+        if constexpr ((VR & 4) != 0) f0n += (V)fw;
+        if (active) st2<NT>(dd + fg_index(K, 0, cell), f0n, (Gv[0] + wg * (geq0 - (V)K.gsh[0])) * inv1wg);
     } else {
         put(dd + (int64_t)(OFF_H + QH) * S + cell, (V)(2.0 * M.rho) - Hv[12]);
     }
@@ -726,10 +740,13 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
             const V om = rate * (V(1) - V(KAPPA) * eb);
             const V q = (V)K.fsh[cls] - feq_signed<i0>(fe, sgn);
             const V geq = (V)K.wp[cls] * ng * (V(1) + gc1 * eb + gc2 * eb * eb - gc3b2);
+            V fn = CM == 0 ? Fv[s] - om * (Fv[s] + q) : (Fv[s] - om * q) / (V(1) + om);
+            if constexpr ((VR & 4) != 0) {
+                constexpr double wcls = cls == 1 ? 99.0 / 722.0 : 9.0 / 361.0;  // D3Q19 weights
+                fn += (V)((19.0 / 9.0) * wcls / KAPPA * ((h ? -1.0 : 1.0) * (EX[i0] * fx + EY[i0] * fy + EZ[i0] * fz)));
+            }
             if (active)
-                st2<NT>(dd + fg_index(K, i0, 0) + 2 * (int64_t)hc,
-                        CM == 0 ? Fv[s] - om * (Fv[s] + q) : (Fv[s] - om * q) / (V(1) + om),
-                        (Gv[s] + wg * (geq - (V)K.gsh[cls])) * inv1wg);
+                st2<NT>(dd + fg_index(K, i0, 0) + 2 * (int64_t)hc, fn, (Gv[s] + wg * (geq - (V)K.gsh[cls])) * inv1wg);
         }
     });
     const V cj = (V)(1.0 / (16.0 * 1.4142135623730951 * K.c)), ce = (V)(1.0 / (8.0 * 1.4142135623730951 * K.c));
@@ -770,18 +787,27 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
     const int c = (threadIdx.x >> 6) * 32 + (lane & 31), h = lane >> 5;
     int x = tx * PXT + (c % PXT), y = ty * PYT + c / PXT;
     const bool active = x < K.nx && y < K.ny;
-    if constexpr (GM == GUESS_NONE) {
+    // with the force every lane stays (the wavefront's largest |beta| is
+    // reduced over all 64 lanes)
+    constexpr bool all_lanes = GM != GUESS_NONE || (VR & 4) != 0;
+    if constexpr (!all_lanes) {
         if (!active) return;  // both lanes of a pair leave together
     } else {
         x = min(x, K.nx - 1);
         y = min(y, K.ny - 1);
     }
     const int z0 = zc * zb, z1 = min(K.nz, z0 + zb);
+    double bmax = 0.0;
     for (int z = z0; z < z1; ++z) {
         const int cell = x + K.nx * (y + K.ny * z);
         const Nbr nb = make_nbr<true>(K, x, y, z);
         pair_cell<NT, TS, TE, V, GM, VR>(sd, se, dd, de, faceB, gt, K, cell, nb, h, x, y, z,
-                                         GM == GUESS_NONE ? true : active);
+                                         all_lanes ? active : true, bmax);
+    }
+    if constexpr ((VR & 4) != 0) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) bmax = fmax(bmax, __shfl_xor(bmax, o, 64));
+        if (lane == 0) K.vmax_part[(int64_t)b * (PTPB / 64) + (threadIdx.x >> 6)] = bmax;
     }
 }
 
@@ -1040,6 +1066,26 @@ __global__ __launch_bounds__(TPB) void k_null_reduce(const double* __restrict__ 
 }
 
 // Fixed-order reduction of the per-block partials by one block.
+// Largest |beta| of a forced step from its per-wavefront partials (which are
+// cleared for the next step); one block.
+__global__ __launch_bounds__(TPB) void k_vmax_reduce(double* __restrict__ part, int64_t n, double* __restrict__ out) {
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += TPB) {
+        m = fmax(m, part[i]);
+        part[i] = 0.0;
+    }
+    __shared__ double sh[TPB / 64];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = sh[0];
+        for (int w = 1; w < TPB / 64; ++w) r = fmax(r, sh[w]);
+        *out = r;
+    }
+}
+
 __global__ __launch_bounds__(TPB) void k_reduce(const double* __restrict__ part, int nblk, int width, int is_max,
                                                 double* __restrict__ out) {
     for (int j = 0; j < width; ++j) {
@@ -1372,7 +1418,14 @@ hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K
     const TS* sd = (const TS*)src.dist;
     TS* dd = (TS*)dst.dist;
     const int vr = (K.coll ? 1 : 0) | (K.flux ? 2 : 0);
-    if (vr) {  // the alternative readings: 64-wide tiles, no guess
+    if (K.forced) {  // the external force: 64-wide tiles, default readings, no guess
+        if (gt || vr) return hipErrorNotSupported;
+        launch_fused<TS, GUESS_NONE, 64, 4>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+        int tx, ncol, nblk;
+        step_geometry(K, 64, zb, tx, ncol, nblk);
+        hipLaunchKernelGGL(k_vmax_reduce, dim3(1), dim3(TPB), 0, s, K.vmax_part, (int64_t)nblk * (PTPB / 64),
+                           const_cast<double*>(K.vmax_prev));
+    } else if (vr) {  // the alternative readings: 64-wide tiles, no guess
         if (gt) return hipErrorNotSupported;
         if (vr == 1)
             launch_fused<TS, GUESS_NONE, 64, 1>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);

@@ -69,7 +69,8 @@ class rmhdlb_face_in(ctypes.Structure):
 SYMBOLS = ("rmhdlb_create", "rmhdlb_init_fields", "rmhdlb_step", "rmhdlb_moments", "rmhdlb_destroy",
            "rmhdlb_strerror", "rmhdlb_state_len", "rmhdlb_get_state", "rmhdlb_set_state", "rmhdlb_lattice_tables",
            "rmhdlb_set_driven_face", "rmhdlb_train_guess", "rmhdlb_set_guess_weights", "rmhdlb_set_guess",
-           "rmhdlb_guess_samples", "rmhdlb_mlp_eval", "rmhdlb_autotune", "rmhdlb_set_tuning", "rmhdlb_batch_create",
+           "rmhdlb_guess_samples", "rmhdlb_mlp_eval", "rmhdlb_autotune", "rmhdlb_set_tuning", "rmhdlb_set_force",
+           "rmhdlb_batch_create",
            "rmhdlb_batch_instance", "rmhdlb_batch_step", "rmhdlb_batch_autotune", "rmhdlb_batch_destroy")
 
 _LIB = None
@@ -109,6 +110,7 @@ def load():
     ip32 = ctypes.POINTER(ctypes.c_int32)
     L.rmhdlb_autotune.argtypes = [vp, ip32, ip32]
     L.rmhdlb_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.rmhdlb_set_force.argtypes = [vp, ctypes.POINTER(_dp * 3), ctypes.c_double]
     L.rmhdlb_batch_create.argtypes = [ctypes.POINTER(rmhdlb_params), ctypes.c_int32, vp, ctypes.POINTER(vp)]
     L.rmhdlb_batch_instance.argtypes = [vp, ctypes.c_int32]
     L.rmhdlb_batch_instance.restype = vp
@@ -308,6 +310,17 @@ class Solver:
         _check(load().rmhdlb_train_guess(self._h, ctypes.byref(o), w0.ctypes.data_as(fp), ctypes.byref(W),
                                          losses.ctypes.data_as(fp)), "rmhdlb_train_guess")
         return weights_to_dict(W), losses[:int(iters)]
+
+    def set_force(self, F, gate=0.0):
+        """External force density F = (Fx, Fy, Fz) on the grid (numpy or tensors), or None to switch it off;
+        it acts while the previous step's largest |beta| is below gate (<= 0: always)."""
+        if F is None:
+            _check(load().rmhdlb_set_force(self._h, None, 0.0), "rmhdlb_set_force")
+            return
+        keep = [self._dev(a) for a in F]
+        ptrs = (_dp * 3)(*[_dptr(t) for t in keep])
+        _check(load().rmhdlb_set_force(self._h, ctypes.byref(ptrs), float(gate)), "rmhdlb_set_force")
+        self.stream.synchronize()   # the copies read the temporaries above
 
     def set_guess_weights(self, d):
         _check(load().rmhdlb_set_guess_weights(self._h, ctypes.byref(weights_from_dict(d))), "rmhdlb_set_guess_weights")

@@ -41,6 +41,7 @@ class Workload:
     steps: int = 0
     meta: dict = field(default_factory=dict)
     driven: dict = None    # prescribed fields of a driven low-z face: n, p, u (3), B (3), each (ny, nx)
+    force: tuple = None    # external force density ((Fx, Fy, Fz), gate), or None
 
     @property
     def ncells(self):
@@ -253,6 +254,63 @@ def flare(nx=256, ny=256, nz=512, sigma=1e3, B0=0.06, seed=512, steps=10000, Lx=
     bc = (("open", "open"), ("open", "open"), ("driven", "open"))
     return Workload("flare", shape, bc, _params(sigma=sigma), fields, steps, meta=dict(h=h, B0=B0, v_drive=v_drive),
                     driven=driven)
+
+
+def flare_box(n=256, nz=None, sigma=100.0, B0=0.06, h=2.0, F0=0.05, gate=0.3, c=2.5):
+    """The stellar-flare set-up of Sec. IV in the paper's units: [-3, 3]^2 x [0, 6] in n x n x nz cells
+    (nz = n by default), c = 2.5 (dx / dt = 2.5 sqrt 2), all faces open, n = p = 1, u = 0, B = curl(psi e_y)
+    scaled to max |B| = B0 plus the rope's B^y (flux rope at height h), and the external force of that
+    section: F^x = F0 sin(pi x* / 3) cos(pi y / 6), F^y = F0 cos(pi x* / 3) sin(pi y / 6) in the two
+    sub-boxes z <= 0.2343 (x* = x for x < 0, x - 3 for x >= 0), acting while the largest |beta| is below
+    gate.  The paper obtains the initial E and J by iterating the code at fixed B and u; with u = 0 that
+    iteration converges to the steady resistive balance J = curl B / mu0, E = J / sigma, which is used
+    directly (central differences)."""
+    nz = n if nz is None else nz
+    shape = (n, n, nz)
+    dx = 6.0 / n
+    xs = (np.arange(n) + 0.5) * dx - 3.0
+    ys = xs.copy()
+    zs = (np.arange(nz) + 0.5) * dx
+    r0, cb = 0.5, 0.2534
+
+    def psi(X, Z):
+        pb = cb * np.log(((X + 0.3) ** 2 + (Z + 0.3) ** 2) * ((X - 0.3) ** 2 + (Z + 0.3) ** 2) /
+                         (((X + 1.5) ** 2 + (Z + 0.3) ** 2) * ((X - 1.5) ** 2 + (Z + 0.3) ** 2)))
+        pi_ = -r0 / 2.0 * np.log(X ** 2 + (Z + h) ** 2)
+        r = np.sqrt(X ** 2 + (Z - h) ** 2)
+        pl = np.where(r <= r0, r ** 2 / (2 * r0), r0 / 2 - r0 * np.log(r0) + r0 * np.log(np.maximum(r, 1e-300)))
+        return pb + pi_ + pl
+
+    X, Z = np.meshgrid(xs, zs, indexing="xy")        # (nz, nx)
+    d = 1e-4
+    bx = -(psi(X, Z + d) - psi(X, Z - d)) / (2 * d)
+    bz = (psi(X + d, Z) - psi(X - d, Z)) / (2 * d)
+    scale = B0 / np.sqrt(bx ** 2 + bz ** 2).max()
+    r = np.sqrt(X ** 2 + (Z - h) ** 2)
+    by = np.where(r <= r0, scale * np.sqrt(np.maximum(2.0 * (1.0 - r ** 2 / r0 ** 2), 0.0)), 0.0)
+    Bx = np.broadcast_to((bx * scale)[:, None, :], (nz, n, n)).copy()
+    By = np.broadcast_to(by[:, None, :], (nz, n, n)).copy()
+    Bz = np.broadcast_to((bz * scale)[:, None, :], (nz, n, n)).copy()
+    # J = curl B (mu0 = 1) by central differences (one-sided on the faces); the fields vary in x and z only
+    gx = lambda f: np.gradient(f, dx, axis=2)
+    gz = lambda f: np.gradient(f, dx, axis=0)
+    Jx = -gz(By)
+    Jy = gz(Bx) - gx(Bz)
+    Jz = gx(By)
+    zero = _full(shape, 0.0)
+    fields = dict(n=_full(shape, 1.0), p=_full(shape, 1.0), u=(zero, zero.copy(), zero.copy()),
+                  E=(Jx / sigma, Jy / sigma, Jz / sigma), B=(Bx, By, Bz), rho_c=None)
+    Xc = xs[None, None, :]
+    Yc = ys[None, :, None]
+    xstar = np.where(Xc < 0.0, Xc, Xc - 3.0)
+    band = (zs <= 0.2343)[:, None, None]
+    Fx = np.broadcast_to(np.where(band, F0 * np.sin(np.pi * xstar / 3.0) * np.cos(np.pi * Yc / 6.0), 0.0),
+                         (nz, n, n)).copy()
+    Fy = np.broadcast_to(np.where(band, F0 * np.cos(np.pi * xstar / 3.0) * np.sin(np.pi * Yc / 6.0), 0.0),
+                         (nz, n, n)).copy()
+    bc = (("open", "open"),) * 3
+    return Workload("flare_box", shape, bc, _params(sigma=sigma, dx=dx, c=c), fields, 0,
+                    meta=dict(h=h, B0=B0, F0=F0, dt=dx / (np.sqrt(2.0) * c)), force=((Fx, Fy, zero.copy()), gate))
 
 
 def random_state(shape=(8, 8, 8), seed=0, vmax=0.3, amp=0.05, Bmag=0.3, Emag=0.05, sigma=10.0, modes=3,

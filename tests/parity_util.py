@@ -40,6 +40,8 @@ def run_oracle(w, steps):
     o.init(w.fields)
     if w.driven is not None:
         o.set_driven(w.driven)
+    if w.force is not None:
+        o.set_force(*w.force)
     if steps:
         o.step(steps)
     return o
@@ -51,6 +53,8 @@ def run_gpu(w, steps, storage="f64"):
     s.init_fields(w.fields)
     if w.driven is not None:
         s.set_driven_face(w.driven)
+    if w.force is not None:
+        s.set_force(*w.force)
     if steps:
         s.step(steps)
     return s

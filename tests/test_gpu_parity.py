@@ -38,6 +38,8 @@ def oracle_sensitivity(w, steps, o_ref, symmetric):
     b.init(w.fields)
     if w.driven is not None:
         b.set_driven(w.driven)
+    if w.force is not None:
+        b.set_force(*w.force)
     st = b.get_state()
     rng = np.random.default_rng(1234)
     shp = (st.shape[0], 1, 1, st.shape[3]) if symmetric else st.shape
@@ -161,6 +163,44 @@ def test_lax_wendroff_flux_with_printed_collision_open_faces():
                        bc=(("open", "open"),) * 3)
     w.params.update(flux=1, collision=1)
     check_case(w, 10)
+
+
+def _random_force(w, seed, amp):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = w.shape
+    x, y, z = np.meshgrid(np.arange(nx) / nx, np.arange(ny) / ny, np.arange(nz) / nz, indexing="xy")
+    F = []
+    for a in range(3):
+        k = rng.integers(1, 3, size=3)
+        ph = rng.uniform(0, 2 * np.pi, size=3)
+        f = amp * np.sin(2 * np.pi * k[0] * x + ph[0]) * np.cos(2 * np.pi * k[1] * y + ph[1]) * np.sin(
+            2 * np.pi * k[2] * z + ph[2])
+        F.append(np.ascontiguousarray(np.transpose(f, (2, 0, 1))))      # (nz, ny, nx)
+    return tuple(F)
+
+
+def test_external_force_random_3d_ragged_tiles():
+    """The external force (Reading R26), always on, with a smooth random force field: 12 steps of a
+    ragged periodic 3-D state."""
+    w = W.random_state(shape=(70, 6, 3), seed=2, vmax=0.1, Bmag=0.2, Emag=0.02, sigma=3.0)
+    w.force = (_random_force(w, 5, 0.02), 0.0)
+    check_case(w, 12)
+
+
+def test_external_force_gate_closes():
+    """A gate below the state's velocities: the force acts in the first step only (the gate reads the
+    previous step's largest |beta|, zero before the first step), on a box open on every face."""
+    w = W.random_state(shape=(20, 9, 7), seed=3, vmax=0.05, Bmag=0.2, Emag=0.02, sigma=30.0, solenoidal=True,
+                       bc=(("open", "open"),) * 3)
+    w.force = (_random_force(w, 6, 0.05), 1e-6)
+    check_case(w, 8)
+
+
+def test_flare_set_up_of_the_paper_with_its_force():
+    """The stellar-flare set-up of Sec. IV at 32^3 (dx = 0.1875, c = 2.5, all faces open, initial E from
+    the steady resistive balance, the force in the bottom band), 40 steps."""
+    w = W.flare_box(n=32)
+    check_case(w, 40, conditioned=True)
 
 
 def test_printed_collision_limits():
