@@ -205,9 +205,9 @@ int rmhdlb_set_driven_face(rmhdlb_ctx *ctx, const rmhdlb_face_in *face);
  * population, with beta of that step's recovery.  The force acts while the
  * largest |beta| of the previous step's recovery over the box is below gate
  * (gate <= 0: always); the gate opens again at rmhdlb_init_fields.  Built for
- * 64-wide tiles with the default readings: RMHDLB_EUNSUPPORTED with the
- * printed collision, the Lax-Wendroff faces or the learned guess on, and
- * batches with a forced instance refuse to step.  RMHDLB_EINVAL for NULL
+ * 64-wide tiles with MUSCL faces and either collision: RMHDLB_EUNSUPPORTED
+ * with the Lax-Wendroff faces or the learned guess on, and batches with a
+ * forced instance refuse to step.  RMHDLB_EINVAL for NULL
  * entries or a non-finite gate, RMHDLB_ENOMEM if the buffers cannot be
  * allocated. */
 int rmhdlb_set_force(rmhdlb_ctx *ctx, const double *const F[3], double gate);

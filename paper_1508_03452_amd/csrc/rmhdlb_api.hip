@@ -374,7 +374,7 @@ int rmhdlb_set_force(rmhdlb_ctx* C, const double* const F[3], double gate) {
     }
     for (int a = 0; a < 3; ++a)
         if (!F[a]) return RMHDLB_EINVAL;
-    if (C->K.coll || C->K.flux || C->guess_mode) return RMHDLB_EUNSUPPORTED;
+    if (C->K.flux || C->guess_mode) return RMHDLB_EUNSUPPORTED;
     const int64_t N = C->K.N;
     // one partial per wavefront of the widest launch (64-wide tiles, one plane per block)
     const int64_t nparts = 4 * (int64_t)((C->K.nx + 63) / 64) * ((C->K.ny + 1) / 2) * C->K.nz;

@@ -1418,9 +1418,12 @@ hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K
     const TS* sd = (const TS*)src.dist;
     TS* dd = (TS*)dst.dist;
     const int vr = (K.coll ? 1 : 0) | (K.flux ? 2 : 0);
-    if (K.forced) {  // the external force: 64-wide tiles, default readings, no guess
-        if (gt || vr) return hipErrorNotSupported;
-        launch_fused<TS, GUESS_NONE, 64, 4>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+    if (K.forced) {  // the external force: 64-wide tiles, MUSCL faces, no guess
+        if (gt || K.flux) return hipErrorNotSupported;
+        if (K.coll)
+            launch_fused<TS, GUESS_NONE, 64, 5>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+        else
+            launch_fused<TS, GUESS_NONE, 64, 4>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
         int tx, ncol, nblk;
         step_geometry(K, 64, zb, tx, ncol, nblk);
         hipLaunchKernelGGL(k_vmax_reduce, dim3(1), dim3(TPB), 0, s, K.vmax_part, (int64_t)nblk * (PTPB / 64),

@@ -196,6 +196,14 @@ def test_external_force_gate_closes():
     check_case(w, 8)
 
 
+def test_external_force_with_printed_collision():
+    """The external force together with the printed semi-implicit collision, 12 steps."""
+    w = W.random_state(shape=(70, 6, 3), seed=2, vmax=0.1, Bmag=0.2, Emag=0.02, sigma=3.0)
+    w.params["collision"] = 1
+    w.force = (_random_force(w, 7, 0.02), 0.0)
+    check_case(w, 12)
+
+
 def test_flare_set_up_of_the_paper_with_its_force():
     """The stellar-flare set-up of Sec. IV at 32^3 (dx = 0.1875, c = 2.5, all faces open, initial E from
     the steady resistive balance, the force in the bottom band), 40 steps."""
