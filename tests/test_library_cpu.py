@@ -86,5 +86,6 @@ def test_mixed_periodic_axis_rejected():
 def test_null_arguments():
     L = R.load()
     assert L.rmhdlb_step(None, 1) == R.RMHDLB_EINVAL
+    assert L.rmhdlb_set_force(None, None, 0.0) == R.RMHDLB_EINVAL
     assert L.rmhdlb_destroy(None) == 0
     assert L.rmhdlb_state_len(None) == -1
