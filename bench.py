@@ -223,8 +223,8 @@ def main():
     if args.workload == "sweep" and args.gpus == 1:
         return sweep_main(args)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "described in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "the step runs on one GPU; --gpus must be 1 (the multi-GPU domain "
+                                   "decomposition is not implemented)"}))
         sys.exit(2)
     import torch
     from paper_1508_03452_amd import workloads as W

@@ -78,7 +78,8 @@ typedef struct {
     int32_t storage;             /* RMHDLB_STORE_* */
     int32_t divb_fix;            /* 1: adjust the normal B on open faces so div B = 0 there; 0: off
                                     (recommended: in runs of ~10^3 steps at sigma = 1e3 the adjustment
-                                    grew B at face edges until cells failed, see the design notes) */
+                                    grew B at face edges until cells failed: a 256 x 512 KH slab at
+                                    step 1200, the flare box by step 900) */
     int32_t null_band;           /* reconnection-rate null search: rows with |y| <= null_band cells
                                     (cell centres y_j = j + 1/2 - ny/2); < 1 selects 64 */
     int32_t collision;           /* RMHDLB_COLL_*: the f collision (see below) */

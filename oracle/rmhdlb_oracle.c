@@ -13,8 +13,7 @@
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (see oracle/build.py).
  *
  * Every place where the paper is silent, garbled or inconsistent with itself
- * is marked "Reading Rn" with the reading taken; the list is kept in the
- * design notes of the repository.
+ * is marked "Reading Rn" with the reading taken and the reason for it.
  *
  * Loop order is fixed: cells in x-fastest order, directions in table order.
  */

@@ -118,7 +118,7 @@ def test_printed_collision_carries_the_supersonic_kh_run():
 def test_forced_flare_set_up_runs():
     """The paper's flare set-up (128^3, body force in the bottom band, printed collision) over 2000 steps
     (t = 26.5): no failed cell, the force spins up the bottom shear (largest |beta| grows) and the
-    energy rises by the work done.  (Later the shear turns supersonic; see the design notes.)"""
+    energy rises by the work done.  (Later, near t = 32-42, the shear turns supersonic and cells fail.)"""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
