@@ -516,6 +516,22 @@ def test_mixed_driven_face(storage):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_mixed_alternative_readings(storage):
+    """The printed collision with the Lax-Wendroff faces in the reduced storage forms."""
+    w = W.random_state(shape=(70, 6, 3), seed=2, vmax=0.1, Bmag=0.2, Emag=0.02, sigma=3.0)
+    w.params.update(collision=1, flux=1)
+    _mixed_case(w, 12, storage)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_mixed_external_force(storage):
+    """The external force in the reduced storage forms (the source enters the stored deviations)."""
+    w = W.random_state(shape=(70, 6, 3), seed=2, vmax=0.1, Bmag=0.2, Emag=0.02, sigma=3.0)
+    w.force = (_random_force(w, 5, 0.02), 0.0)
+    _mixed_case(w, 12, storage)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_mixed_conserves_mass_exactly_in_fp64_sums(storage):
     """The collisions conserve N^0 exactly; with FP32 arithmetic per cell the
     total mass on a periodic box drifts only by rounding."""
