@@ -157,6 +157,13 @@ def sweep_main(args):
 ALG_BYTES = {"f64": (8, 8), "f32": (4, 4), "f16": (2, 4)}   # (distribution, E_prev) bytes per value
 
 
+def tile_text(shape):
+    px, zb, zg = shape
+    walk = (f"{zb} z-planes per block" if zg == 1 else
+            f"{zg} blocks per column walking chunks of {zg * zb} z-planes interleaved ({zb} planes each)")
+    return f"{px}x{128 // px} cells, {walk}"
+
+
 def alg_bytes_per_step(storage, ncell):
     """Read + write of the stored state: 63 distribution values and 3 E_prev values per cell."""
     dist_b, e_b = ALG_BYTES[storage]
@@ -174,15 +181,15 @@ def timed_form(w, storage, guess, args, stream):
     if w.driven is not None:
         s.set_driven_face(w.driven)
     s.step(args.warmup)
-    shape = (64, 4) if args.no_autotune else s.autotune()   # untimed; the state is not advanced
-    info = {"tile": f"{shape[0]}x{128 // shape[0]} cells, {shape[1]} z-planes per block"}
+    shape = (64, 4, 1) if args.no_autotune else s.autotune()   # untimed; the state is not advanced
+    info = {"tile": tile_text(shape)}
     if guess:
         t_tr = time.perf_counter()
         weights, losses = s.train_guess(W.mlp_init(11), n_samples=65536, iters=400, batch=512, lr=3e-3)
         s.set_guess(True)
         if not args.no_autotune:   # the guess path has 64-wide tiles only: tune again among those
             shape = s.autotune()
-            info["tile"] = f"{shape[0]}x{128 // shape[0]} cells, {shape[1]} z-planes per block"
+            info["tile"] = tile_text(shape)
         s.step(2)
         info["guess_training"] = {"samples": 65536, "iters": 400, "loss_first": float(losses[0]),
                                   "loss_last": float(losses[-1]), "train_s": round(time.perf_counter() - t_tr, 3)}

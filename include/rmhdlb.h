@@ -282,19 +282,30 @@ int rmhdlb_mlp_eval(const float *w, const float *X, const float *Yt, int32_t n, 
 
 /* ---- launch tuning and batched sweeps --------------------------------------
  * The fused step runs blocks of 128 cells (two lanes per cell) shaped
- * px x (128 / px), px in {64, 32, 16}, each walking zb z-planes. */
+ * px x (128 / px), px in {64, 32, 16}, each walking zb z-planes.  With
+ * zg > 1 the planes are taken in chunks of zg * zb per column, and the zg
+ * blocks of a chunk walk them interleaved (block r: planes r, r + zg, ...),
+ * so that they run at neighbouring planes together and share the
+ * z-neighbour planes in the L2 cache.  The shape changes the order of work
+ * only: results are bitwise the same for every shape. */
 
-/* Time every (px, zb) shape (zb in {1, 2, 4, 8, 16} up to nz) on the
- * context's current state with HIP events and keep the fastest for its later
- * steps.  The state is not advanced (each timed step reads the current buffer
- * and writes the other).  Results are cached per process by grid size,
- * storage, boundary kinds and guess mode; a cached shape is reused without
- * timing.  With the learned guess on only px = 64 is timed.  The chosen shape
- * is returned in *px, *zb (either may be NULL).  Synchronises. */
-int rmhdlb_autotune(rmhdlb_ctx *ctx, int32_t *px, int32_t *zb);
+/* Time the launch shapes on the context's current state with HIP events and
+ * keep the fastest for its later steps: every (px, zb) with zb in
+ * {1, 2, 4, 8, 16} up to nz and zg = 1, plus px = 64 with zb in {16, 32, 64}
+ * and zg in {2, 4} where zg * zb <= nz.  The state is not advanced (each
+ * timed step reads the current buffer and writes the other).  Results are
+ * cached per process by grid size, storage, boundary kinds, guess mode,
+ * collision, flux and force; a cached shape is reused without timing.  With
+ * the learned guess, the printed collision, the Lax-Wendroff flux or a force
+ * only px = 64 is timed, and with a force only zg = 1.  The chosen shape is
+ * returned in *px, *zb, *zg (any may be NULL).  Synchronises. */
+int rmhdlb_autotune(rmhdlb_ctx *ctx, int32_t *px, int32_t *zb, int32_t *zg);
 
-/* Set the shape directly: px in {64, 32, 16}, zb >= 1 (RMHDLB_EINVAL otherwise). */
-int rmhdlb_set_tuning(rmhdlb_ctx *ctx, int32_t px, int32_t zb);
+/* Set the shape directly: px in {64, 32, 16}, zb >= 1, 1 <= zg <= 64; px = 64
+ * with the learned guess, the printed collision or the Lax-Wendroff flux, and
+ * zg = 1 with a force (RMHDLB_EINVAL otherwise).  A force set later runs
+ * with zg = 1 whatever the tuning. */
+int rmhdlb_set_tuning(rmhdlb_ctx *ctx, int32_t px, int32_t zb, int32_t zg);
 
 /* A batch of independent instances (for example a parameter sweep) stepped
  * together: every step is one launch over the blocks of all instances (plus

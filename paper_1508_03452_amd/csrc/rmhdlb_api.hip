@@ -306,6 +306,7 @@ int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** ou
     // Launch shape until rmhdlb_autotune or rmhdlb_set_tuning picks another.
     C->tune.zb = 4;
     C->tune.px = 64;
+    C->tune.zg = 1;
     *out = C;
     return RMHDLB_OK;
 }
@@ -623,8 +624,9 @@ int rmhdlb_mlp_eval(const float* w, const float* X, const float* Yt, int32_t n, 
 
 namespace {
 
-typedef std::tuple<int, int, int, int, int, int, int> TuneKey;  // nx, ny, nz, storage, divb, driven, guess
-std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+// nx, ny, nz, storage, divb, driven, guess, collision, flux, force
+typedef std::tuple<int, int, int, int, int, int, int, int, int, int> TuneKey;
+std::map<TuneKey, rmhd::StepTuning> g_tune_cache;
 std::mutex g_tune_mutex;
 
 // Average duration (ms) of `reps` calls of fn on the stream after one warm-up.
@@ -653,10 +655,14 @@ int time_ms(hipStream_t st, int reps, Fn fn, float* ms) {
 
 extern "C" {
 
-int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out) {
+int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out, int32_t* zg_out) {
     if (!C) return RMHDLB_EINVAL;
-    const TuneKey key(C->K.nx, C->K.ny, C->K.nz, C->storage, C->K.divb, C->K.drv, C->guess_mode);
-    std::pair<int, int> best(64, 4);
+    const TuneKey key(C->K.nx, C->K.ny, C->K.nz, C->storage, C->K.divb, C->K.drv, C->guess_mode, C->K.coll,
+                      C->K.flux, C->K.forced);
+    rmhd::StepTuning best;
+    best.px = 64;
+    best.zb = 4;
+    best.zg = 1;
     bool cached = false;
     {
         std::lock_guard<std::mutex> g(g_tune_mutex);
@@ -667,41 +673,60 @@ int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out) {
         }
     }
     if (!cached) {
-        float best_ms = 1e30f;
-        const int pxs[3] = {64, 32, 16}, zbs[5] = {1, 2, 4, 8, 16};
-        for (int pi = 0; pi < 3; ++pi)
-            for (int zi = 0; zi < 5; ++zi) {
-                if (zbs[zi] > C->K.nz && zbs[zi] != 1) continue;
-                if ((C->guess_mode || C->K.coll || C->K.flux || C->K.forced) && pxs[pi] != 64) continue;  // 64 only
+        // Candidates: every tile width with zb in {1, 2, 4, 8, 16} walked by
+        // one block, and 64-wide tiles with long walks shared by 2 or 4
+        // interleaved blocks per column (chunks of up to 256 planes).
+        std::vector<rmhd::StepTuning> cand;
+        const bool only64 = C->guess_mode || C->K.coll || C->K.flux || C->K.forced;
+        for (int px : {64, 32, 16})
+            for (int zb : {1, 2, 4, 8, 16}) {
+                if ((zb > C->K.nz && zb != 1) || (only64 && px != 64)) continue;
                 rmhd::StepTuning t;
-                t.px = pxs[pi];
-                t.zb = zbs[zi];
-                float ms = 0.0f;
-                const int rc = time_ms(C->stream, 3, [&]() {
-                    return RMHD_DISPATCH(C, launch_step)(C->sb[C->cur], C->sb[1 - C->cur], C->K, t, C->faceB,
-                                                         C->guess_mode ? C->gt : nullptr, C->stream);
-                }, &ms);
-                if (rc != RMHDLB_OK) return rc;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = std::make_pair(t.px, t.zb);
-                }
+                t.px = px;
+                t.zb = zb;
+                t.zg = 1;
+                cand.push_back(t);
             }
+        if (!C->K.forced)
+            for (int zg : {2, 4})
+                for (int zb : {16, 32, 64}) {
+                    if (zg * zb > C->K.nz) continue;
+                    rmhd::StepTuning t;
+                    t.px = 64;
+                    t.zb = zb;
+                    t.zg = zg;
+                    cand.push_back(t);
+                }
+        float best_ms = 1e30f;
+        for (const rmhd::StepTuning& t : cand) {
+            float ms = 0.0f;
+            const int rc = time_ms(C->stream, 3, [&]() {
+                return RMHD_DISPATCH(C, launch_step)(C->sb[C->cur], C->sb[1 - C->cur], C->K, t, C->faceB,
+                                                     C->guess_mode ? C->gt : nullptr, C->stream);
+            }, &ms);
+            if (rc != RMHDLB_OK) return rc;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        }
         std::lock_guard<std::mutex> g(g_tune_mutex);
         g_tune_cache[key] = best;
     }
-    C->tune.px = best.first;
-    C->tune.zb = best.second;
-    if (px_out) *px_out = best.first;
-    if (zb_out) *zb_out = best.second;
+    C->tune = best;
+    if (px_out) *px_out = best.px;
+    if (zb_out) *zb_out = best.zb;
+    if (zg_out) *zg_out = best.zg;
     return RMHDLB_OK;
 }
 
-int rmhdlb_set_tuning(rmhdlb_ctx* C, int32_t px, int32_t zb) {
-    if (!C || (px != 64 && px != 32 && px != 16) || zb < 1) return RMHDLB_EINVAL;
+int rmhdlb_set_tuning(rmhdlb_ctx* C, int32_t px, int32_t zb, int32_t zg) {
+    if (!C || (px != 64 && px != 32 && px != 16) || zb < 1 || zg < 1 || zg > 64) return RMHDLB_EINVAL;
     if ((C->guess_mode || C->K.coll || C->K.flux || C->K.forced) && px != 64) return RMHDLB_EINVAL;
+    if (C->K.forced && zg != 1) return RMHDLB_EINVAL;
     C->tune.px = px;
     C->tune.zb = zb;
+    C->tune.zg = zg;
     return RMHDLB_OK;
 }
 
@@ -739,7 +764,7 @@ int batch_table(rmhdlb_batch* B) {
         }
         I.faceB = C->faceB;
         I.zb = std::max(1, std::min(C->tune.zb, C->K.nz));
-        rmhd::step_geometry(C->K, B->px, I.zb, I.tiles_x, I.ncol, I.nblk);
+        rmhd::step_geometry(C->K, B->px, I.zb, 1, I.tiles_x, I.ncol, I.nblk);
         I.blk0 = blk;
         I.face0 = face;
         blk += I.nblk;

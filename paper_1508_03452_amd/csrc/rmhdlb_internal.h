@@ -94,11 +94,13 @@ __device__ __forceinline__ double block_max_value(double v) {
 
 int num_tiles(const Consts& K);
 
-// Launch shape of the fused step: z-planes walked per block and the tile
-// width along x (64, 32 or 16 cells; the tile has 128 cells).
+// Launch shape of the fused step: z-planes walked per block, the tile width
+// along x (64, 32 or 16 cells; the tile has 128 cells) and the number of
+// blocks that walk a column's chunk of zg * zb planes interleaved.
 struct StepTuning {
     int zb;
     int px;
+    int zg = 1;
 };
 
 // One instance of a batched step: its constants, both state buffers (cell
@@ -193,9 +195,10 @@ hipError_t launch_ghost(const FacePtrs& in, const Consts& K, const StateBuf& dst
 hipError_t launch_init_ref(const InPtrs& in, const Consts& K, double* part, double* result, hipStream_t s);
 template <typename TS>
 hipError_t launch_face_b(const StateBuf& src, const Consts& K, double* faceB, hipStream_t s);
-// Launch geometry of the fused step for a tile width px and zb planes:
-// tiles along x, columns, blocks.
-void step_geometry(const Consts& K, int px, int zb, int& tiles_x, int& ncol, int& nblk);
+// Launch geometry of the fused step for a tile width px, zb planes per block
+// and zg blocks per column and chunk of zg * zb planes: tiles along x,
+// columns, blocks.
+void step_geometry(const Consts& K, int px, int zb, int zg, int& tiles_x, int& ncol, int& nblk);
 // One batched step (face pass of the instances that need it, then the fused
 // step of all) reading buffer `parity` of every instance.
 template <typename TS>

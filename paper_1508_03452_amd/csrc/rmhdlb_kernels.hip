@@ -767,20 +767,25 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
 // ------------------------------------------------------------------ kernels
 
 // One block owns a PXT x (128 / PXT) column of cells (two lanes per cell)
-// and walks zb consecutive z-planes.  Blocks are numbered column-fastest
-// within a z-chunk and XCD k receives the contiguous block range
-// [k P, (k + 1) P): the columns one XCD runs at the same time are neighbours
-// marching through the same planes, so the y-halo and the z-neighbour planes
-// of the stencil meet in that XCD's L2.
+// and walks zb z-planes.  A chunk of zg * zb planes is shared by zg blocks
+// per column: block r of the zg takes planes r, r + zg, r + 2 zg, ... of the
+// chunk, so that the zg blocks of a column run at neighbouring planes at the
+// same time and the z-neighbour planes of the stencil are fetched once into
+// L2 for all of them (zg = 1: one block walks zb consecutive planes).  Blocks
+// are numbered column-fastest within a chunk, the zg blocks of a column next
+// to each other, and XCD k receives the contiguous block range [k P, (k + 1) P):
+// the columns one XCD runs at the same time are neighbours marching through
+// the same planes, so the y-halo meets in that XCD's L2 as well.
 // With the learned guess the network runs on whole wavefronts, so lanes past
 // a ragged edge stay and compute a copy of the edge cell without storing it.
 template <bool NT, typename TS, typename TE, typename V, int GM, int PXT, int VR = 0>
 __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE* __restrict__ se,
                                             TS* __restrict__ dd, TE* __restrict__ de,
                                             const double* __restrict__ faceB, const GuessTables* __restrict__ gt,
-                                            const Consts& K, int tiles_x, int ncol, int zb, int b) {
+                                            const Consts& K, int tiles_x, int ncol, int zb, int zg, int b) {
     constexpr int PYT = 128 / PXT;
-    const int col = b % ncol, zc = b / ncol;
+    const int per = ncol * zg, zc = b / per, r = b % per;
+    const int col = r / zg, zoff = r % zg;
     const int tx = col % tiles_x, ty = col / tiles_x;
     // cell c of the tile is lane c % 32 (h = 0) and lane c % 32 + 32 (h = 1) of wavefront c / 32
     const int lane = threadIdx.x & 63;
@@ -796,9 +801,9 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
         x = min(x, K.nx - 1);
         y = min(y, K.ny - 1);
     }
-    const int z0 = zc * zb, z1 = min(K.nz, z0 + zb);
+    const int z0 = zc * zb * zg, z1 = min(K.nz, z0 + zb * zg);
     double bmax = 0.0;
-    for (int z = z0; z < z1; ++z) {
+    for (int z = z0 + zoff; z < z1; z += zg) {
         const int cell = x + K.nx * (y + K.ny * z);
         const Nbr nb = make_nbr<true>(K, x, y, z);
         pair_cell<NT, TS, TE, V, GM, VR>(sd, se, dd, de, faceB, gt, K, cell, nb, h, x, y, z,
@@ -816,10 +821,10 @@ __global__ __launch_bounds__(PTPB, (fused_waves<TS, GM>())) void k_fused_step(co
                                                         TS* __restrict__ dd, TE* __restrict__ de,
                                                         const double* __restrict__ faceB,
                                                         const GuessTables* __restrict__ gt, Consts K,
-                                                        int tiles_x, int ncol, int zb, int nblk) {
+                                                        int tiles_x, int ncol, int zb, int zg, int nblk) {
     const int b = tile_of_block(nblk);
     if (b >= nblk) return;  // uniform over the block
-    fused_block<NT, TS, TE, V, GM, PXT, VR>(sd, se, dd, de, faceB, gt, K, tiles_x, ncol, zb, b);
+    fused_block<NT, TS, TE, V, GM, PXT, VR>(sd, se, dd, de, faceB, gt, K, tiles_x, ncol, zb, zg, b);
 }
 
 // Index of the instance whose range [first[i], first[i + 1]) holds v (first
@@ -850,7 +855,7 @@ __global__ __launch_bounds__(PTPB, (fused_waves<TS, 0>())) void k_fused_batch(co
     const BatchInst& B = I[i];
     fused_block<NT, TS, TE, V, GUESS_NONE, PXT>(
         (const TS*)B.dist[parity], (const TE*)B.efield[parity], (TS*)B.dist[1 - parity], (TE*)B.efield[1 - parity],
-        B.faceB, nullptr, B.K, B.tiles_x, B.ncol, B.zb, (int)(b - B.blk0));
+        B.faceB, nullptr, B.K, B.tiles_x, B.ncol, B.zb, 1, (int)(b - B.blk0));
 }
 
 // B of Eq. Cal_B at a cell from the streamed h (population order, FP64).
@@ -1390,23 +1395,23 @@ hipError_t launch_face_b(const StateBuf& src, const Consts& K, double* faceB, hi
     return hipGetLastError();
 }
 
-void step_geometry(const Consts& K, int px, int zb, int& tiles_x, int& ncol, int& nblk) {
+void step_geometry(const Consts& K, int px, int zb, int zg, int& tiles_x, int& ncol, int& nblk) {
     const int py = 128 / px;
     tiles_x = (K.nx + px - 1) / px;
     ncol = tiles_x * ((K.ny + py - 1) / py);
-    nblk = ncol * ((K.nz + zb - 1) / zb);
+    nblk = ncol * zg * ((K.nz + zg * zb - 1) / (zg * zb));
 }
 
 template <typename TS, int GM, int PXT, int VR = 0>
 static void launch_fused(const TS* sd, const void* se, TS* dd, void* de, double* faceB, const GuessTables* gt,
-                         const Consts& K, int zb, hipStream_t s) {
+                         const Consts& K, int zb, int zg, hipStream_t s) {
     using TE = typename StoreTypes<TS>::E;
     using V = typename StoreTypes<TS>::V;
     int tx, ncol, nblk;
-    step_geometry(K, PXT, zb, tx, ncol, nblk);
+    step_geometry(K, PXT, zb, zg, tx, ncol, nblk);
     const int grid = ((nblk + 7) / 8) * 8;
     hipLaunchKernelGGL((k_fused_step<true, TS, TE, V, GM, PXT, VR>), dim3(grid), dim3(PTPB), 0, s, sd, (const TE*)se, dd,
-                       (TE*)de, (const double*)faceB, gt, K, tx, ncol, zb, nblk);
+                       (TE*)de, (const double*)faceB, gt, K, tx, ncol, zb, zg, nblk);
 }
 
 template <typename TS>
@@ -1415,35 +1420,38 @@ hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K
     hipError_t e = launch_face_b<TS>(src, K, faceB, s);
     if (e != hipSuccess) return e;
     const int zb = tune.zb > 0 ? (tune.zb < K.nz ? tune.zb : K.nz) : 1;
+    // interleaved walks: zg blocks per column and chunk (the force path keeps
+    // zg = 1, the geometry its per-wavefront maxima are sized for)
+    const int zg = (tune.zg > 1 && !K.forced) ? tune.zg : 1;
     const TS* sd = (const TS*)src.dist;
     TS* dd = (TS*)dst.dist;
     const int vr = (K.coll ? 1 : 0) | (K.flux ? 2 : 0);
     if (K.forced) {  // the external force: 64-wide tiles, MUSCL faces, no guess
         if (gt || K.flux) return hipErrorNotSupported;
         if (K.coll)
-            launch_fused<TS, GUESS_NONE, 64, 5>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+            launch_fused<TS, GUESS_NONE, 64, 5>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, 1, s);
         else
-            launch_fused<TS, GUESS_NONE, 64, 4>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+            launch_fused<TS, GUESS_NONE, 64, 4>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, 1, s);
         int tx, ncol, nblk;
-        step_geometry(K, 64, zb, tx, ncol, nblk);
+        step_geometry(K, 64, zb, 1, tx, ncol, nblk);
         hipLaunchKernelGGL(k_vmax_reduce, dim3(1), dim3(TPB), 0, s, K.vmax_part, (int64_t)nblk * (PTPB / 64),
                            const_cast<double*>(K.vmax_prev));
     } else if (vr) {  // the alternative readings: 64-wide tiles, no guess
         if (gt) return hipErrorNotSupported;
         if (vr == 1)
-            launch_fused<TS, GUESS_NONE, 64, 1>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+            launch_fused<TS, GUESS_NONE, 64, 1>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, zg, s);
         else if (vr == 2)
-            launch_fused<TS, GUESS_NONE, 64, 2>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+            launch_fused<TS, GUESS_NONE, 64, 2>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, zg, s);
         else
-            launch_fused<TS, GUESS_NONE, 64, 3>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+            launch_fused<TS, GUESS_NONE, 64, 3>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, zg, s);
     } else if (gt)  // the guess path is built for 64-wide tiles only
-        launch_fused<TS, GUESS_PAIR, 64>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+        launch_fused<TS, GUESS_PAIR, 64>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, zg, s);
     else if (tune.px == 32)
-        launch_fused<TS, GUESS_NONE, 32>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+        launch_fused<TS, GUESS_NONE, 32>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, zg, s);
     else if (tune.px == 16)
-        launch_fused<TS, GUESS_NONE, 16>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+        launch_fused<TS, GUESS_NONE, 16>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, zg, s);
     else
-        launch_fused<TS, GUESS_NONE, 64>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, s);
+        launch_fused<TS, GUESS_NONE, 64>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, zg, s);
     return hipGetLastError();
 }
 

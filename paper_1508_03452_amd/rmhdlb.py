@@ -108,8 +108,8 @@ def load():
     L.rmhdlb_guess_samples.argtypes = [vp, ctypes.c_int32, _dp, _dp]
     L.rmhdlb_mlp_eval.argtypes = [fp, fp, fp, ctypes.c_int32, fp, fp, fp, vp]
     ip32 = ctypes.POINTER(ctypes.c_int32)
-    L.rmhdlb_autotune.argtypes = [vp, ip32, ip32]
-    L.rmhdlb_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.rmhdlb_autotune.argtypes = [vp, ip32, ip32, ip32]
+    L.rmhdlb_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.rmhdlb_set_force.argtypes = [vp, ctypes.POINTER(_dp * 3), ctypes.c_double]
     L.rmhdlb_batch_create.argtypes = [ctypes.POINTER(rmhdlb_params), ctypes.c_int32, vp, ctypes.POINTER(vp)]
     L.rmhdlb_batch_instance.argtypes = [vp, ctypes.c_int32]
@@ -238,12 +238,14 @@ class Solver:
         self._h = ctypes.c_void_p()
 
     def autotune(self):
-        px, zb = ctypes.c_int32(), ctypes.c_int32()
-        _check(load().rmhdlb_autotune(self._h, ctypes.byref(px), ctypes.byref(zb)), "rmhdlb_autotune")
-        return int(px.value), int(zb.value)
+        """Time the launch shapes and keep the fastest: (px, zb, zg)."""
+        px, zb, zg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load().rmhdlb_autotune(self._h, ctypes.byref(px), ctypes.byref(zb), ctypes.byref(zg)),
+               "rmhdlb_autotune")
+        return int(px.value), int(zb.value), int(zg.value)
 
-    def set_tuning(self, px, zb):
-        _check(load().rmhdlb_set_tuning(self._h, int(px), int(zb)), "rmhdlb_set_tuning")
+    def set_tuning(self, px, zb, zg=1):
+        _check(load().rmhdlb_set_tuning(self._h, int(px), int(zb), int(zg)), "rmhdlb_set_tuning")
 
     def __del__(self):
         try:

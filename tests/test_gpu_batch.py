@@ -24,14 +24,17 @@ def _state(s):
     return s.get_state().cpu().numpy()
 
 
-@pytest.mark.parametrize("px,zb", [(32, 1), (16, 2), (64, 8)])
-def test_tile_shapes_give_identical_states(px, zb):
+# zg > 1: interleaved walks, with chunks of zg * zb planes that do not divide
+# nz = 9 (the last chunk is ragged and some walks are empty)
+@pytest.mark.parametrize("px,zb,zg", [(32, 1, 1), (16, 2, 1), (64, 8, 1), (64, 2, 2), (64, 2, 4), (32, 1, 4),
+                                      (64, 16, 2)])
+def test_tile_shapes_give_identical_states(px, zb, zg):
     _torch_cuda()
     w = W.random_state(shape=(70, 13, 9), seed=6, vmax=0.1, Bmag=0.2, Emag=0.02, sigma=3.0,
                        bc=(("open", "open"), ("periodic", "periodic"), ("open", "open")))
     a = run_gpu(w, 0)
     b = run_gpu(w, 0)
-    b.set_tuning(px, zb)
+    b.set_tuning(px, zb, zg)
     a.step(6)
     b.step(6)
     assert np.array_equal(_state(a), _state(b))
@@ -42,15 +45,46 @@ def test_autotune_picks_a_valid_shape_and_keeps_the_state():
     w = W.kh(nx=192, ny=256, v0=0.3, ratio=5.0, sigma=1e3)
     s = run_gpu(w, 2)
     before = _state(s)
-    px, zb = s.autotune()
-    print(f"[batch] autotune kh 192x256x1 -> px {px} zb {zb}", flush=True)
-    assert px in (64, 32, 16) and zb >= 1
+    px, zb, zg = s.autotune()
+    print(f"[batch] autotune kh 192x256x1 -> px {px} zb {zb} zg {zg}", flush=True)
+    assert px in (64, 32, 16) and zb >= 1 and zg == 1   # nz = 1: no interleaved walks
     assert np.array_equal(before, _state(s))   # timing does not advance the state
-    assert s.autotune() == (px, zb)            # cached
+    assert s.autotune() == (px, zb, zg)        # cached
     ref = run_gpu(w, 2)
     s.step(3)
     ref.step(3)
     assert np.array_equal(_state(s), _state(ref))
+
+
+def test_autotune_3d_with_interleaved_candidates():
+    """On a box deep enough for the interleaved walks the tuner times them
+    too; whatever it picks leaves the state alone and steps as the default."""
+    _torch_cuda()
+    w = W.random_state(shape=(64, 8, 64), seed=8, vmax=0.1, Bmag=0.2, Emag=0.02, sigma=3.0,
+                       bc=(("periodic", "periodic"), ("open", "open"), ("open", "open")))
+    s = run_gpu(w, 0)
+    before = _state(s)
+    px, zb, zg = s.autotune()
+    print(f"[batch] autotune random 64x8x64 -> px {px} zb {zb} zg {zg}", flush=True)
+    assert px in (64, 32, 16) and zb >= 1 and zg in (1, 2, 4) and (zg == 1 or px == 64)
+    assert np.array_equal(before, _state(s))
+    ref = run_gpu(w, 0)
+    s.step(4)
+    ref.step(4)
+    assert np.array_equal(_state(s), _state(ref))
+
+
+def test_interleaved_walks_not_with_force():
+    """With an external force the step keeps one walk per column (zg = 1)."""
+    _torch_cuda()
+    from paper_1508_03452_amd.rmhdlb import RmhdlbError
+    w = W.random_state(shape=(20, 9, 16), seed=4, vmax=0.05, Bmag=0.2, Emag=0.02, sigma=30.0)
+    s = run_gpu(w, 0)
+    nx, ny, nz = w.shape
+    s.set_force([np.full((nz, ny, nx), 0.01) for _ in range(3)], 0.0)
+    with pytest.raises(RmhdlbError):
+        s.set_tuning(64, 2, 2)
+    assert s.autotune()[2] == 1
 
 
 def _sweep_workloads(n=5, seed=3):
