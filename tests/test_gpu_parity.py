@@ -377,10 +377,19 @@ def test_full_size_sampled_cells_one_step(name):
     GPU's own next step."""
     torch = _torch_cuda()
     w = W.kh() if name == "kh" else W.flare()
-    s = run_gpu(w, 3)
+    s = run_gpu(w, 0)
+    shape = s.autotune()   # the launch shape bench.py times (the state is not advanced)
+    print(f"[parity] {name} full size, autotuned shape {shape}", flush=True)
+    s.step(3)
     st = s.get_state()
     s.step(1)
     st1 = s.get_state()
+    # the same four steps in the default shape (one block per column walk of
+    # 4 planes): the launch shape changes the order of work, not one bit
+    d = run_gpu(w, 4)
+    assert torch.equal(d.get_state(), st1)
+    d.close()
+    del d
     rng = np.random.default_rng(11)
     nx, ny, nz = w.shape
     worst = 0.0
@@ -415,7 +424,9 @@ def test_full_size_sampled_face_cells_one_step(divb_fix):
     torch = _torch_cuda()
     w = W.flare()
     w.params["divb_fix"] = divb_fix
-    s = run_gpu(w, 3)
+    s = run_gpu(w, 0)
+    print(f"[parity] flare faces divb_fix={divb_fix}, autotuned shape {s.autotune()}", flush=True)
+    s.step(3)
     st = s.get_state()
     s.step(1)
     st1 = s.get_state()
