@@ -27,6 +27,19 @@ __device__ __forceinline__ V ldv(const T* __restrict__ p, int64_t i) {
     return static_cast<V>(p[i]);
 }
 
+// Loads of values that no other cell of the step reads (each streamed h* is
+// pulled by exactly one cell): the non-temporal hint keeps them from
+// evicting the stencil lines that the neighbours' loads will hit.  Used for
+// 4- and 8-byte values only: a 2-byte array shares each cache line between
+// two wavefronts, and the hint then costs the second one a refetch.
+template <typename V, typename T>
+__device__ __forceinline__ V ldv_once(const T* __restrict__ p, int64_t i) {
+    if constexpr (sizeof(T) >= 4)
+        return static_cast<V>(__builtin_nontemporal_load(p + i));
+    else
+        return static_cast<V>(p[i]);
+}
+
 // Stores of the next state are never read again in this step: the
 // non-temporal hint keeps them from evicting the stencil lines from L2.
 template <bool NT, typename T, typename V>
@@ -561,7 +574,7 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
     // slot 0: f_0, g_0 (lane 0) and h_rest (lane 1)
     {
         const vec2<V> fg0 = ldv2<V>(sd, fg_index(K, 0, cell));
-        const V hr = ldv<V>(sd, (int64_t)(OFF_H + QH) * S + cell);
+        const V hr = ldv_once<V>(sd, (int64_t)(OFF_H + QH) * S + cell);
         Fv[0] = h ? V(0) : fg0.x;
         Gv[0] = h ? V(0) : fg0.y;
         Hv[12] = h ? hr : V(0);
@@ -639,7 +652,7 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
 #pragma unroll
     for (int m = 0; m < 12; ++m) {
         const int k0 = 2 * m;
-        const V v = ldv<V>(sd + (int64_t)(OFF_H + k0) * S, hc + nb.at(-SX[k0], -SY[k0], -SZ[k0]));
+        const V v = ldv_once<V>(sd + (int64_t)(OFF_H + k0) * S, hc + nb.at(-SX[k0], -SY[k0], -SZ[k0]));
         Hv[m] = v;
         hs += v;
         const V sv = sgn * v;
