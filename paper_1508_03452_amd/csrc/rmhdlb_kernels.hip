@@ -816,10 +816,19 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
     }
     const int z0 = zc * zb * zg, z1 = min(K.nz, z0 + zb * zg);
     double bmax = 0.0;
+    // In the forms whose cell code spills (FP64, and FP16 without the
+    // guess) the lane's coordinates are made opaque at every plane, so that
+    // the x- and y-parts of the neighbour table are recomputed per plane
+    // (a few integer operations) instead of being kept across the walk and
+    // spilled: that took 11 scratch reloads per plane out of the FP16 loop
+    // and 7 out of the FP64 one.  FP32 does not spill and keeps them.
+    constexpr bool opaque = sizeof(TS) == 8 || (sizeof(TS) == 2 && GM == GUESS_NONE);
     for (int z = z0 + zoff; z < z1; z += zg) {
-        const int cell = x + K.nx * (y + K.ny * z);
-        const Nbr nb = make_nbr<true>(K, x, y, z);
-        pair_cell<NT, TS, TE, V, GM, VR>(sd, se, dd, de, faceB, gt, K, cell, nb, h, x, y, z,
+        int xp = x, yp = y, hp = h;
+        if constexpr (opaque) asm volatile("" : "+v"(xp), "+v"(yp), "+v"(hp));
+        const int cell = xp + K.nx * (yp + K.ny * z);
+        const Nbr nb = make_nbr<true>(K, xp, yp, z);
+        pair_cell<NT, TS, TE, V, GM, VR>(sd, se, dd, de, faceB, gt, K, cell, nb, hp, xp, yp, z,
                                          all_lanes ? active : true, bmax);
     }
     if constexpr ((VR & 4) != 0) {
