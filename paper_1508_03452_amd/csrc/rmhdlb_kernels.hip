@@ -507,11 +507,11 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 // value is shift + transport(d); the moments add the exact sums of the shifts;
 // the collisions write the new deviations directly.
 constexpr int PTPB = 256;  // threads of a fused-step block: 128 cells, two lanes each
-// Waves per SIMD the fused kernel is compiled for: two (the FP64 and FP32
-// forms, and FP16 with the learned guess, lose more to spills at three than
-// they gain), three for plain FP16 storage (measured 3.6 % faster on the
-// flare box than two, and 31 % faster than four; with the guess three waves
-// were 31 % slower).
+// Waves per SIMD the fused kernel is compiled for: two for the FP64 and
+// FP32 forms (they lose more to spills at three than they gain: FP32 4 %
+// slower), three for FP16 storage (plain FP16 3.6 % faster on the flare box
+// than two and 31 % faster than four; with the learned guess, once the lane
+// coordinates are recomputed per plane, 2.5 % faster than two).
 #ifndef RMHDLB_WAVES
 #define RMHDLB_WAVES 2
 #endif
@@ -520,7 +520,7 @@ constexpr int PTPB = 256;  // threads of a fused-step block: 128 cells, two lane
 #endif
 template <typename TS, int GM>
 constexpr int fused_waves() {
-    return (sizeof(TS) == 2 && GM == 0) ? RMHDLB_WAVES_F16 : RMHDLB_WAVES;
+    return sizeof(TS) == 2 ? RMHDLB_WAVES_F16 : RMHDLB_WAVES;
 }
 // f/g slots whose loads may be in flight together, per storage type
 // (measured on the flare box: 2 for FP64 and FP16; 3 for FP32, 1.7 % faster
@@ -816,13 +816,14 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
     }
     const int z0 = zc * zb * zg, z1 = min(K.nz, z0 + zb * zg);
     double bmax = 0.0;
-    // In the forms whose cell code spills (FP64, and FP16 without the
-    // guess) the lane's coordinates are made opaque at every plane, so that
-    // the x- and y-parts of the neighbour table are recomputed per plane
-    // (a few integer operations) instead of being kept across the walk and
-    // spilled: that took 11 scratch reloads per plane out of the FP16 loop
-    // and 7 out of the FP64 one.  FP32 does not spill and keeps them.
-    constexpr bool opaque = sizeof(TS) == 8 || (sizeof(TS) == 2 && GM == GUESS_NONE);
+    // In the forms whose cell code spills (FP64, and FP16 at three waves)
+    // the lane's coordinates are made opaque at every plane, so that the x-
+    // and y-parts of the neighbour table are recomputed per plane (a few
+    // integer operations) instead of being kept across the walk and spilled:
+    // that took 11 scratch reloads per plane out of the plain FP16 loop and
+    // 7 out of the FP64 one.  FP32 does not spill and keeps them (recomputing
+    // them there measured 6 % slower).
+    constexpr bool opaque = sizeof(TS) != 4;
     for (int z = z0 + zoff; z < z1; z += zg) {
         int xp = x, yp = y, hp = h;
         if constexpr (opaque) asm volatile("" : "+v"(xp), "+v"(yp), "+v"(hp));
