@@ -38,10 +38,10 @@ KERNEL_SOURCES = ("paper_1508_03452_amd/csrc/rmhdlb_kernels.hip", "paper_1508_03
 # (scaled by the copy-kernel calibration), keyed by (workload, storage, hash
 # of the kernel sources): a changed kernel reports null until re-measured.
 MEASURED_TRAFFIC = {
-    ("flare", "f64", "4fd3ce3b7167"): 65.90,    # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f32", "4fd3ce3b7167"): 27.26,    # profiles/fused_step_f32_flare256x256x512.md
-    ("flare", "f16", "4fd3ce3b7167"): 16.35,    # profiles/fused_step_f16_flare256x256x512.md
-    ("flare", "f16+guess", "4fd3ce3b7167"): 12.52,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f64", "fc266c7367bd"): 64.87,    # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f32", "fc266c7367bd"): 27.12,    # profiles/fused_step_f32_flare256x256x512.md
+    ("flare", "f16", "fc266c7367bd"): 13.49,    # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16+guess", "fc266c7367bd"): 15.93,  # profiles/fused_step_f16g_flare256x256x512.md
 }
 
 
