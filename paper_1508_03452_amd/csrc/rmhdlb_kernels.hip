@@ -523,8 +523,9 @@ constexpr int fused_waves() {
     return sizeof(TS) == 2 ? RMHDLB_WAVES_F16 : RMHDLB_WAVES;
 }
 // f/g slots whose loads may be in flight together, per storage type
-// (measured on the flare box: 2 for FP64 and FP16; 3 for FP32, 1.7 % faster
-// there and 14 % slower for FP64)
+// (measured on the flare box: 2 for FP64, where 1 is 18 % and 3 is 25 %
+// slower; 3 for FP32, where 2 is 4 % and 4 is 8 % slower; 3 for FP16, 1.5 %
+// faster than 2 with and without the guess, and 1-2 % faster than 4, 5, 9)
 #ifndef RMHDLB_GROUP_F64
 #define RMHDLB_GROUP_F64 2
 #endif
@@ -532,7 +533,7 @@ constexpr int fused_waves() {
 #define RMHDLB_GROUP_F32 3
 #endif
 #ifndef RMHDLB_GROUP_F16
-#define RMHDLB_GROUP_F16 2
+#define RMHDLB_GROUP_F16 3
 #endif
 template <typename TS>
 constexpr int pin_group() {
