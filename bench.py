@@ -38,10 +38,10 @@ KERNEL_SOURCES = ("paper_1508_03452_amd/csrc/rmhdlb_kernels.hip", "paper_1508_03
 # (scaled by the copy-kernel calibration), keyed by (workload, storage, hash
 # of the kernel sources): a changed kernel reports null until re-measured.
 MEASURED_TRAFFIC = {
-    ("flare", "f64", "fc266c7367bd"): 64.87,    # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f32", "fc266c7367bd"): 27.12,    # profiles/fused_step_f32_flare256x256x512.md
-    ("flare", "f16", "fc266c7367bd"): 13.49,    # profiles/fused_step_f16_flare256x256x512.md
-    ("flare", "f16+guess", "fc266c7367bd"): 15.93,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f64", "6afb9bd9efd6"): 57.02,    # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f32", "6afb9bd9efd6"): 27.65,    # profiles/fused_step_f32_flare256x256x512.md
+    ("flare", "f16", "6afb9bd9efd6"): 13.82,    # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16+guess", "6afb9bd9efd6"): 16.13,  # profiles/fused_step_f16g_flare256x256x512.md
 }
 
 
