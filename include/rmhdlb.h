@@ -303,8 +303,9 @@ int rmhdlb_autotune(rmhdlb_ctx *ctx, int32_t *px, int32_t *zb, int32_t *zg);
 
 /* Set the shape directly: px in {64, 32, 16}, zb >= 1, 1 <= zg <= 64; px = 64
  * with the learned guess, the printed collision or the Lax-Wendroff flux, and
- * zg = 1 with a force (RMHDLB_EINVAL otherwise).  A force set later runs
- * with zg = 1 whatever the tuning. */
+ * zg = 1 with a force (RMHDLB_EINVAL otherwise).  zb above nz acts as nz, and
+ * zg above ceil(nz / zb) is reduced to it.  A force set later runs with
+ * zg = 1 whatever the tuning. */
 int rmhdlb_set_tuning(rmhdlb_ctx *ctx, int32_t px, int32_t zb, int32_t zg);
 
 /* A batch of independent instances (for example a parameter sweep) stepped

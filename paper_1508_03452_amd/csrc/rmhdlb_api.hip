@@ -724,9 +724,14 @@ int rmhdlb_set_tuning(rmhdlb_ctx* C, int32_t px, int32_t zb, int32_t zg) {
     if (!C || (px != 64 && px != 32 && px != 16) || zb < 1 || zg < 1 || zg > 64) return RMHDLB_EINVAL;
     if ((C->guess_mode || C->K.coll || C->K.flux || C->K.forced) && px != 64) return RMHDLB_EINVAL;
     if (C->K.forced && zg != 1) return RMHDLB_EINVAL;
+    // More blocks per column than the chunk has planes would only walk
+    // nothing: cap zg at ceil(nz / zb) (zb as the step clamps it to nz),
+    // which also keeps zg * zb within int range.
+    const int zbe = zb < C->K.nz ? zb : C->K.nz;
+    const int zg_max = (C->K.nz + zbe - 1) / zbe;
     C->tune.px = px;
     C->tune.zb = zb;
-    C->tune.zg = zg;
+    C->tune.zg = zg < zg_max ? zg : zg_max;
     return RMHDLB_OK;
 }
 
