@@ -35,14 +35,32 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS + % HBM peak, plain FP64 vs mixed+learned form at stated error"
 KERNEL_SOURCES = ("paper_1508_03452_amd/csrc/rmhdlb_kernels.hip", "paper_1508_03452_amd/csrc/rmhdlb_device.h")
 # HBM GB per launch of k_fused_step from rocprofv3 FETCH_SIZE + WRITE_SIZE
-# (scaled by the copy-kernel calibration), keyed by (workload, storage, hash
-# of the kernel sources): a changed kernel reports null until re-measured.
+# (scaled by the copy-kernel calibration), keyed by (workload, form, hash of
+# the kernel sources, launch shape "px,zb,zg"): the traffic depends on the
+# shape the autotuner picks, and a changed kernel or an unmeasured shape
+# reports null.
 MEASURED_TRAFFIC = {
-    ("flare", "f64", "6afb9bd9efd6"): 57.02,    # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f32", "6afb9bd9efd6"): 27.65,    # profiles/fused_step_f32_flare256x256x512.md
-    ("flare", "f16", "6afb9bd9efd6"): 13.82,    # profiles/fused_step_f16_flare256x256x512.md
-    ("flare", "f16+guess", "6afb9bd9efd6"): 16.13,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f64", "6afb9bd9efd6", "64,16,4"): 55.91,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "6afb9bd9efd6", "64,32,4"): 61.61,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "6afb9bd9efd6", "64,64,4"): 65.09,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "6afb9bd9efd6", "64,16,2"): 64.08,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "6afb9bd9efd6", "64,32,2"): 63.84,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "6afb9bd9efd6", "64,64,2"): 66.96,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "6afb9bd9efd6", "64,16,1"): 73.79,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f16+guess", "6afb9bd9efd6", "64,16,4"): 16.34,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "6afb9bd9efd6", "64,32,4"): 16.22,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "6afb9bd9efd6", "64,64,4"): 16.46,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "6afb9bd9efd6", "64,16,2"): 16.51,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "6afb9bd9efd6", "64,32,2"): 16.89,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "6afb9bd9efd6", "64,64,2"): 16.60,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "6afb9bd9efd6", "64,16,1"): 18.82,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f32", "6afb9bd9efd6", "64,64,4"): 27.65,  # profiles/fused_step_f32_flare256x256x512.md
+    ("flare", "f16", "6afb9bd9efd6", "64,16,4"): 13.82,  # profiles/fused_step_f16_flare256x256x512.md
 }
+
+
+def measured_traffic(workload, form, shape):
+    return MEASURED_TRAFFIC.get((workload, form, kernel_hash(), ",".join(str(v) for v in shape)))
 
 
 def kernel_hash():
@@ -65,6 +83,8 @@ def parse():
     ap.add_argument("--storage", default="f64", choices=["f64", "f32", "f16"])
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shape (64 x 2 tiles, 4 planes) instead of the autotuned one")
+    ap.add_argument("--tile", default=None,
+                    help="launch shape px,zb,zg to use instead of the autotuned one (e.g. 64,32,4)")
     ap.add_argument("--guess", action="store_true",
                     help="learned recovery guess: trained on the state after the warm-up (untimed), then used")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
@@ -181,15 +201,21 @@ def timed_form(w, storage, guess, args, stream):
     if w.driven is not None:
         s.set_driven_face(w.driven)
     s.step(args.warmup)
-    shape = (64, 4, 1) if args.no_autotune else s.autotune()   # untimed; the state is not advanced
-    info = {"tile": tile_text(shape)}
+    def choose_shape():
+        if args.tile:
+            shape = tuple(int(v) for v in args.tile.split(","))
+            s.set_tuning(*shape)
+            return shape
+        return (64, 4, 1) if args.no_autotune else s.autotune()   # untimed; the state is not advanced
+    shape = choose_shape()
+    info = {"tile": tile_text(shape), "launch_shape": list(shape)}
     if guess:
         t_tr = time.perf_counter()
         weights, losses = s.train_guess(W.mlp_init(11), n_samples=65536, iters=400, batch=512, lr=3e-3)
         s.set_guess(True)
         if not args.no_autotune:   # the guess path has 64-wide tiles only: tune again among those
-            shape = s.autotune()
-            info["tile"] = tile_text(shape)
+            shape = choose_shape()
+            info.update(tile=tile_text(shape), launch_shape=list(shape))
         s.step(2)
         info["guess_training"] = {"samples": 65536, "iters": 400, "loss_first": float(losses[0]),
                                   "loss_last": float(losses[-1]), "train_s": round(time.perf_counter() - t_tr, 3)}
@@ -253,7 +279,7 @@ def main():
     torch.cuda.empty_cache()
     alg_bytes = alg_bytes_per_step(args.storage, ncell)
     achieved = alg_bytes / (ms * 1e-3) / 1e9
-    traffic = MEASURED_TRAFFIC.get((args.workload, args.storage + ("+guess" if args.guess else ""), kernel_hash()))
+    traffic = measured_traffic(args.workload, args.storage + ("+guess" if args.guess else ""), info["launch_shape"])
     out = {
         "metric": METRIC,
         "value": round(ncell / (ms * 1e-3) / 1e6, 2),
@@ -294,7 +320,7 @@ def main():
             "speedup_vs_headline": round(ms / ms2, 3),
             "roofline": {"achieved": round(a2, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(a2 / HBM_PEAK_GBS, 4),
-                         "traffic": MEASURED_TRAFFIC.get((args.workload, "f16+guess", kernel_hash()))},
+                         "traffic": measured_traffic(args.workload, "f16+guess", info2["launch_shape"])},
             "stated_error": "per field vs the FP64 oracle over runs of up to 300 steps: <= 5e-3 on n, p, eps, u, E, "
                             "B and <= 5e-2 on J, rho_c (tests/test_gpu_parity.py, FP16 form; the guess changes "
                             "iteration counts, not the root); over 1000 steps of a 64^3 flare box n, p, u stay "
