@@ -55,7 +55,7 @@ MEASURED_TRAFFIC = {
     ("flare", "f16+guess", "6afb9bd9efd6", "64,64,2"): 16.60,  # profiles/fused_step_f16g_flare256x256x512.md
     ("flare", "f16+guess", "6afb9bd9efd6", "64,16,1"): 18.82,  # profiles/fused_step_f16g_flare256x256x512.md
     ("flare", "f32", "6afb9bd9efd6", "64,64,4"): 27.65,  # profiles/fused_step_f32_flare256x256x512.md
-    ("flare", "f16", "6afb9bd9efd6", "64,16,4"): 13.82,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16", "6afb9bd9efd6", "64,32,2"): 13.82,  # profiles/fused_step_f16_flare256x256x512.md
 }
 
 
