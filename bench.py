@@ -33,29 +33,30 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS + % HBM peak, plain FP64 vs mixed+learned form at stated error"
-KERNEL_SOURCES = ("paper_1508_03452_amd/csrc/rmhdlb_kernels.hip", "paper_1508_03452_amd/csrc/rmhdlb_device.h")
+KERNEL_SOURCES = ("paper_1508_03452_amd/csrc/rmhdlb_kernels.hip", "paper_1508_03452_amd/csrc/rmhdlb_device.h",
+                  "paper_1508_03452_amd/csrc/rmhdlb_internal.h", "paper_1508_03452_amd/csrc/rmhdlb_mlp.h")
 # HBM GB per launch of k_fused_step from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (scaled by the copy-kernel calibration), keyed by (workload, form, hash of
 # the kernel sources, launch shape "px,zb,zg"): the traffic depends on the
 # shape the autotuner picks, and a changed kernel or an unmeasured shape
 # reports null.
 MEASURED_TRAFFIC = {
-    ("flare", "f64", "6afb9bd9efd6", "64,16,4"): 55.91,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "6afb9bd9efd6", "64,32,4"): 61.61,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "6afb9bd9efd6", "64,64,4"): 65.09,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "6afb9bd9efd6", "64,16,2"): 64.08,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "6afb9bd9efd6", "64,32,2"): 63.84,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "6afb9bd9efd6", "64,64,2"): 66.96,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "6afb9bd9efd6", "64,16,1"): 73.79,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f16+guess", "6afb9bd9efd6", "64,16,4"): 16.34,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "6afb9bd9efd6", "64,32,4"): 16.22,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "6afb9bd9efd6", "64,64,4"): 16.46,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "6afb9bd9efd6", "64,16,2"): 16.51,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "6afb9bd9efd6", "64,32,2"): 16.89,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "6afb9bd9efd6", "64,64,2"): 16.60,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "6afb9bd9efd6", "64,16,1"): 18.82,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f32", "6afb9bd9efd6", "64,64,4"): 27.65,  # profiles/fused_step_f32_flare256x256x512.md
-    ("flare", "f16", "6afb9bd9efd6", "64,32,2"): 13.82,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f64", "cb337988654a", "64,16,4"): 55.91,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "cb337988654a", "64,32,4"): 61.61,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "cb337988654a", "64,64,4"): 65.09,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "cb337988654a", "64,16,2"): 64.08,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "cb337988654a", "64,32,2"): 63.84,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "cb337988654a", "64,64,2"): 66.96,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "cb337988654a", "64,16,1"): 73.79,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f16+guess", "cb337988654a", "64,16,4"): 16.34,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "cb337988654a", "64,32,4"): 16.22,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "cb337988654a", "64,64,4"): 16.46,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "cb337988654a", "64,16,2"): 16.51,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "cb337988654a", "64,32,2"): 16.89,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "cb337988654a", "64,64,2"): 16.60,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "cb337988654a", "64,16,1"): 18.82,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f32", "cb337988654a", "64,64,4"): 27.65,  # profiles/fused_step_f32_flare256x256x512.md
+    ("flare", "f16", "cb337988654a", "64,32,2"): 13.82,  # profiles/fused_step_f16_flare256x256x512.md
 }
 
 
