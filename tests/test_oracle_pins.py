@@ -92,18 +92,20 @@ def test_d3q13_geometry():
 
 # ----------------------------------------------------------- equilibria ---
 
-@pytest.mark.parametrize("c", [1.0, 2.5])
-def test_f_equilibrium_moments_are_total_tensor(c):
-    """Moments of f_eq reproduce T_fluid + T_EM (Eqs. El_total, EM_Fluid, EM components)."""
+@pytest.mark.parametrize("c,nu", [(1.0, 27 ** 0.5), (2.5, 27 ** 0.5), (1.0, 27 ** 0.25), (2.5, 4.5),
+                                  (1.0, 4.5)])
+def test_f_equilibrium_moments_are_total_tensor(c, nu):
+    """Moments of f_eq reproduce T_fluid + T_EM (Eqs. El_total, EM_Fluid, EM components), at every
+    lattice nu: xi^mu_i and the paper-variable f_eq both depend on nu, their moments must not."""
     rng = np.random.default_rng(7)
-    L = oracle.lattice(c=c)
+    L = oracle.lattice(c=c, nu=nu)
     xi = L["xi"]
     worst = 0.0
     for _ in range(200):
         n, p, beta, E, B = rand_state(rng)
         E = E * c
         eps = n * c * c + p / (4.0 / 3.0 - 1.0)
-        f, _ = oracle.equilibria(eps, p, n, beta, E, B, c=c)
+        f, _ = oracle.equilibria(eps, p, n, beta, E, B, c=c, nu=nu)
         T = np.einsum("im,in,i->mn", xi, xi, f)
         ref = t_fluid(eps, p, beta) + t_em(E, B, c=c)
         worst = max(worst, np.abs(T - ref).max() / np.abs(ref).max())
@@ -445,6 +447,103 @@ def test_transport_of_a_quadratic_profile(flux):
         assert err < 1e-6, err
     else:
         assert abs(np.abs(got - exact)[sel].max() - C * C) < 1e-6 and abs(np.abs(got - exact)[sel].min() - C * C) < 1e-6
+
+
+def _uniform_rest(shape, **params):
+    """Oracle on a periodic box holding a uniform fluid at rest (n = p = 1, no fields)."""
+    nx, ny, nz = shape
+    one = np.ones((nz, ny, nx))
+    z = np.zeros_like(one)
+    o = oracle.Oracle(shape, None, **params)
+    o.init(dict(n=one, p=one, u=(z, z.copy(), z.copy()), E=(z.copy(), z.copy(), z.copy()),
+                B=(z.copy(), z.copy(), z.copy()), rho_c=z.copy()))
+    return o
+
+
+@pytest.mark.parametrize("i,axis,alpha", [(1, 1, 0.1), (7, 2, 0.1), (15, 0, 0.05), (2, 2, 0.2)])
+def test_viscosity_damps_a_transverse_mode_at_the_closed_form_rate(i, axis, alpha):
+    """Reading R5 (the bulk-viscosity term of Eq. rlb as lambda_i times the 7-point Laplacian of f_i,
+    lambda_i = alpha dx, time as c dt): with the collisions off (tau -> infinity) a perturbation
+    delta sin(2 pi k / n) of population i != 0 that varies only along an axis perpendicular to e_i is
+    not transported (every point of its link stencil holds the same value) and is multiplied in one
+    step by exactly 1 - k_v 2 (1 - cos(2 pi / n)), k_v = alpha c dt / dx = alpha / sqrt 2.  The rest
+    population (lambda_0 = 0) and g (no viscosity) keep the same perturbation unchanged.  A wrong
+    coefficient, a missing or doubled stencil point or a viscosity on f_0 or g fails this."""
+    n = 8
+    shape = [1, 1, 1]
+    shape[axis] = n
+    o = _uniform_rest(tuple(shape), tau=1e300, sigma=0.0, alpha=alpha, dx=0.03, c=2.5)
+    base = o.get_state()
+    k = np.arange(n)
+    mode = np.sin(2 * np.pi * k / n)
+    sl = [0, 0, 0]
+    sl[2 - axis] = slice(None)                      # state arrays are (q, z, y, x)
+    delta = 1e-3
+    pert = base.copy()
+    for q in (i, 0, 19 + i):                        # f_i, f_0, g_i
+        pert[(q,) + tuple(sl)] += delta * mode
+    o.set_state(pert)
+    o.step(1)
+    got = (o.get_state() - base) / delta
+    factor = 1.0 - (alpha / np.sqrt(2.0)) * 2.0 * (1.0 - np.cos(2 * np.pi / n))
+    assert np.abs(got[(i,) + tuple(sl)] - factor * mode).max() < 1e-11
+    assert np.abs(got[(0,) + tuple(sl)] - mode).max() < 1e-11
+    assert np.abs(got[(19 + i,) + tuple(sl)] - mode).max() < 1e-11
+
+
+@pytest.mark.parametrize("nu,tau", [(27 ** 0.5, 1.0), (4.5, 1.0), (27 ** 0.5, 2.5), (4.5, 0.8)])
+def test_g_collision_relaxes_at_the_printed_rate(nu, tau):
+    """Eq. rlb for g with the rate of Reading R12, w_g = (c_0 nu / c_t) dt / tau = nu^2 / (sqrt 27 tau)
+    (c_t / c_0 = sqrt 27 / nu), in the closed implicit form g' = (g + w_g g_eq) / (1 + w_g): at rest in a
+    uniform periodic box, a uniform perturbation of G whose sum vanishes leaves N^0, the recovery and
+    g_eq unchanged and is not transported, so one step multiplies it by exactly 1 / (1 + w_g)."""
+    o = _uniform_rest((4, 4, 4), nu=nu, tau=tau, sigma=0.0)
+    base = o.get_state()
+    d = np.random.default_rng(11).normal(size=19)
+    d -= d.mean()
+    pert = base.copy()
+    pert[19:38] += 1e-3 * d[:, None, None, None]
+    o.set_state(pert)
+    o.step(1)
+    got = (o.get_state()[19:38] - base[19:38]) / 1e-3
+    wg = nu * nu / (np.sqrt(27.0) * tau)
+    assert np.abs(got - d[:, None, None, None] / (1.0 + wg)).max() < 1e-11
+    # f is untouched by a number perturbation
+    assert np.abs(o.get_state()[:19] - base[:19]).max() < 1e-15
+
+
+def test_convection_charge_is_gauss_law_of_the_previous_E():
+    """Reading R20: the charge of the convection current rho u in Eq. Ohm is Gauss's law (Eq. Gauss_E)
+    applied to the previous step's E by central differences, not the charge of the Maxwell populations.
+    With uniform u and B and E_x linear in x (slope b) on an open x axis, the current minus its
+    conduction part sigma gamma (E + u x B - (E.u) u / c^2) must be eps0 b u in every interior cell and
+    eps0 (b / 2) u in the two face cells (the ghost is a copy of the face cell, Reading R19), while
+    rho_c of the populations (Eq. Cal_rhoc) keeps the unrelated value it was given in the interior."""
+    nx, dx, c, sigma = 12, 0.5, 1.5, 2.0
+    bc = (("open", "open"), ("periodic", "periodic"), ("periodic", "periodic"))
+    o = oracle.Oracle((nx, 1, 1), bc, dx=dx, c=c, sigma=sigma)
+    one = np.ones((1, 1, nx))
+    x = (np.arange(nx) + 0.5) * dx
+    b = 0.04
+    u = (0.1 * one, 0.05 * one, -0.02 * one)
+    B = (0.2 * one, -0.1 * one, 0.3 * one)
+    E = (0.03 + b * x[None, None, :], 0.01 * one, -0.02 * one)
+    o.init(dict(n=one, p=one, u=u, E=E, B=B, rho_c=0.7 * one))
+    m = o.moments()
+    uu = np.stack([m["ux"], m["uy"], m["uz"]])[:, 0, 0, :]
+    EE = np.stack([m["Ex"], m["Ey"], m["Ez"]])[:, 0, 0, :]
+    BB = np.stack([m["Bx"], m["By"], m["Bz"]])[:, 0, 0, :]
+    JJ = np.stack([m["Jx"], m["Jy"], m["Jz"]])[:, 0, 0, :]
+    gam = 1.0 / np.sqrt(1.0 - (uu * uu).sum(0) / c ** 2)
+    uxB = np.cross(uu.T, BB.T).T
+    Eu = (EE * uu).sum(0) / c ** 2
+    conv = JJ - sigma * gam * (EE + uxB - Eu * uu)
+    eps0 = 1.0 / c ** 2
+    slope = np.full(nx, b)
+    slope[0] = slope[-1] = b / 2
+    assert np.abs(conv - eps0 * slope * uu).max() < 1e-13
+    # the populations' charge: the given 0.7 in the interior (the face cells pull copied h*)
+    assert np.abs(m["rho_c"][..., 1:-1] - 0.7).max() < 1e-13
 
 
 def _resting_box(shape=(6, 5, 4), **params):
