@@ -60,8 +60,14 @@ MEASURED_TRAFFIC = {
 }
 
 
+def shape_key(shape):
+    """"px,zb,zg" (and ",yw" when the block takes several row groups) of a launch shape."""
+    shape = tuple(shape) + (1,) * (4 - len(shape))
+    return ",".join(str(v) for v in (shape if shape[3] != 1 else shape[:3]))
+
+
 def measured_traffic(workload, form, shape):
-    return MEASURED_TRAFFIC.get((workload, form, kernel_hash(), ",".join(str(v) for v in shape)))
+    return MEASURED_TRAFFIC.get((workload, form, kernel_hash(), shape_key(shape)))
 
 
 def kernel_hash():
@@ -85,7 +91,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shape (64 x 2 tiles, 4 planes) instead of the autotuned one")
     ap.add_argument("--tile", default=None,
-                    help="launch shape px,zb,zg to use instead of the autotuned one (e.g. 64,32,4)")
+                    help="launch shape px,zb,zg[,yw] to use instead of the autotuned one (e.g. 64,32,4)")
     ap.add_argument("--guess", action="store_true",
                     help="learned recovery guess: trained on the state after the warm-up (untimed), then used")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle CPU baseline")
@@ -145,7 +151,7 @@ def sweep_main(args):
         del w
     ncell = sum(sp["nx"] * sp["ny"] for sp in specs)
     b.step(args.warmup)
-    px = b.autotune()
+    px, yw, waves = b.autotune()
     b.step(2)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -166,7 +172,8 @@ def sweep_main(args):
            "scaling": "weak", "vs_baseline": None, "dtype": f"{storage} storage, f32 arithmetic", "data": "synthetic",
            "config": {"workload": f"batched sweep: {len(specs)} KH slabs, nx, ny in 256..1024, {ncell} cells, "
                                   f"sigma 1e2..1e5, one launch per step, hipGraph replays",
-                      "storage": storage, "cells": ncell, "tile_px": px, "failed_cells": failed,
+                      "storage": storage, "cells": ncell, "tile": f"{px}x{128 // px * yw} cells",
+                      "waves_per_simd": waves, "failed_cells": failed,
                       "wall_s_timed": round(wall, 3)},
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_fused_batch",
@@ -179,10 +186,10 @@ ALG_BYTES = {"f64": (8, 8), "f32": (4, 4), "f16": (2, 4)}   # (distribution, E_p
 
 
 def tile_text(shape):
-    px, zb, zg = shape
+    px, zb, zg, yw = tuple(shape) + (1,) * (4 - len(shape))
     walk = (f"{zb} z-planes per block" if zg == 1 else
             f"{zg} blocks per column walking chunks of {zg * zb} z-planes interleaved ({zb} planes each)")
-    return f"{px}x{128 // px} cells, {walk}"
+    return f"{px}x{128 // px * yw} cells, {walk}"
 
 
 def alg_bytes_per_step(storage, ncell):
@@ -207,7 +214,10 @@ def timed_form(w, storage, guess, args, stream):
             shape = tuple(int(v) for v in args.tile.split(","))
             s.set_tuning(*shape)
             return shape
-        return (64, 4, 1) if args.no_autotune else s.autotune()   # untimed; the state is not advanced
+        if args.no_autotune:
+            s.set_tuning(64, 4, 1, 1)
+            return (64, 4, 1, 1)
+        return s.autotune()   # untimed; the state is not advanced
     shape = choose_shape()
     info = {"tile": tile_text(shape), "launch_shape": list(shape)}
     if guess:

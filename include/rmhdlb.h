@@ -43,7 +43,9 @@ enum {
     RMHDLB_ENOMEM = -2,      /* device allocation failed */
     RMHDLB_EDEVICE = -3,     /* HIP runtime or launch error */
     RMHDLB_ERECOVERY = -4,   /* primitive recovery failed in some cell (state holds NaN there) */
-    RMHDLB_EUNSUPPORTED = -5 /* parameter value outside what the method supports */
+    RMHDLB_EUNSUPPORTED = -5, /* parameter value outside what the method supports */
+    RMHDLB_ESTATE = -6        /* call out of order: no state yet (rmhdlb_init_fields or rmhdlb_set_state
+                                 not called), or instances of a batch at different time levels */
 };
 
 /* Face types.  Periodic pairs both faces of an axis.  Open: the ghosts are
@@ -84,8 +86,28 @@ typedef struct {
                                     (cell centres y_j = j + 1/2 - ny/2); < 1 selects 64 */
     int32_t collision;           /* RMHDLB_COLL_*: the f collision (see below) */
     int32_t flux;                /* RMHDLB_FLUX_*: the face values of the transport (see below) */
-    int32_t reserved[3];         /* must be zero */
+    int32_t b_prev;              /* RMHDLB_BPREV_*: the B of the recovery and of f_eq (see below) */
+    int32_t reserved[2];         /* must be zero */
+    void *workspace;             /* optional caller-owned DEVICE buffer that holds every buffer the context
+                                    needs (state, scratch, partial sums): at least rmhdlb_workspace_bytes
+                                    bytes, 256-byte aligned, on the current device, untouched by the caller
+                                    until rmhdlb_destroy.  NULL: rmhdlb_create allocates it (hipMalloc). */
+    size_t workspace_bytes;      /* size of *workspace (ignored when workspace is NULL) */
 } rmhdlb_params;
+
+/* Which magnetic field enters the recovery's fluid tensor T_fl = T - T_EM(E, B)
+ * and the T_EM part of f_eq (Sec. III, coupling subsection, which names the
+ * fields of the previous time step).  E is always the previous step's (the
+ * current one needs the velocity, through Eq. Ohm).  CURRENT (default): B of
+ * this step, a moment of the streamed h (Eq. Cal_B) known before the
+ * recovery; with it the Alfven speed is exact for every tau.  PREVIOUS: the
+ * previous step's B as the paper words it; the state then also carries B_prev
+ * (69 instead of 66 arrays).  PREVIOUS lags the field inertia by a step,
+ * which grows a mode in strongly magnetised states (B^2 of the order of
+ * eps + p); it is built for 64-wide tiles with the default collision and
+ * faces, without the learned guess, a force or batches
+ * (RMHDLB_EUNSUPPORTED). */
+enum { RMHDLB_BPREV_CURRENT = 0, RMHDLB_BPREV_PREVIOUS = 1 };
 
 /* The face value h_i^a of the transport in Eq. rlb, which the paper takes
  * from a reference it cites: the upwind value along the link of population i
@@ -154,11 +176,19 @@ typedef struct {
 
 typedef struct rmhdlb_ctx rmhdlb_ctx; /* opaque, owned by the library */
 
-/* Create a solver.  Validates *params (RMHDLB_EINVAL; tau_h != 1/2 gives
- * RMHDLB_EUNSUPPORTED), allocates the two state buffers on the current HIP
- * device (RMHDLB_ENOMEM) and keeps `hip_stream` (a hipStream_t, may be NULL).
- * On success *out owns the device memory until rmhdlb_destroy; on failure
- * *out is NULL and nothing stays allocated. */
+/* Bytes of device memory a context with these parameters needs for its two
+ * state buffers, scratch and partial sums: the size of params->workspace
+ * (256-byte alignment included).  The learned guess's tables and an external
+ * force, when set later, take memory of their own.  0 for invalid params. */
+size_t rmhdlb_workspace_bytes(const rmhdlb_params *params);
+
+/* Create a solver.  Validates *params (RMHDLB_EINVAL, also for a workspace
+ * smaller than rmhdlb_workspace_bytes or not 256-byte aligned; tau_h != 1/2
+ * gives RMHDLB_EUNSUPPORTED), takes its device memory from params->workspace
+ * or allocates it on the current HIP device (RMHDLB_ENOMEM), clears it on
+ * `hip_stream` (a hipStream_t, may be NULL) and keeps that stream.  On
+ * success *out uses the memory until rmhdlb_destroy (and frees it there if it
+ * allocated it); on failure *out is NULL and nothing stays allocated. */
 int rmhdlb_create(const rmhdlb_params *params, void *hip_stream, rmhdlb_ctx **out);
 
 /* Set the state from primitive fields (device pointers, see rmhdlb_fields_in).
@@ -173,7 +203,9 @@ int rmhdlb_init_fields(rmhdlb_ctx *ctx, const rmhdlb_fields_in *in);
 
 /* Queue nsteps >= 0 fused time steps on the context's stream and return
  * without waiting.  Only launch errors are reported here (RMHDLB_EDEVICE);
- * recovery failures are deferred to rmhdlb_moments. */
+ * recovery failures are deferred to rmhdlb_moments.  RMHDLB_ESTATE before the
+ * first rmhdlb_init_fields or rmhdlb_set_state (also from rmhdlb_moments,
+ * rmhdlb_get_state, rmhdlb_autotune and the guess training calls). */
 int rmhdlb_step(rmhdlb_ctx *ctx, int64_t nsteps);
 
 /* Primitive fields of the current state (what the next step computes first:
@@ -281,32 +313,37 @@ int rmhdlb_mlp_eval(const float *w, const float *X, const float *Yt, int32_t n, 
                     void *hip_stream);
 
 /* ---- launch tuning and batched sweeps --------------------------------------
- * The fused step runs blocks of 128 cells (two lanes per cell) shaped
- * px x (128 / px), px in {64, 32, 16}, each walking zb z-planes.  With
- * zg > 1 the planes are taken in chunks of zg * zb per column, and the zg
- * blocks of a chunk walk them interleaved (block r: planes r, r + zg, ...),
- * so that they run at neighbouring planes together and share the
- * z-neighbour planes in the L2 cache.  The shape changes the order of work
- * only: results are bitwise the same for every shape. */
+ * The fused step runs blocks of 256 threads, two lanes per cell, over row
+ * groups of px x (128 / px) cells, px in {64, 32, 16} (128 too in batches);
+ * a block takes yw such groups stacked along y (a tile of px x (128 / px) yw
+ * cells) and walks zb z-planes.  With zg > 1 the planes are taken in chunks
+ * of zg * zb per column, and the zg blocks of a chunk walk them interleaved
+ * (block r: planes r, r + zg, ...), so that they run at neighbouring planes
+ * together and share the z-neighbour planes in the L2 cache.  The shape
+ * changes the order of work only: results are bitwise the same for every
+ * shape. */
 
 /* Time the launch shapes on the context's current state with HIP events and
  * keep the fastest for its later steps: every (px, zb) with zb in
- * {1, 2, 4, 8, 16} up to nz and zg = 1, plus px = 64 with zb in {16, 32, 64}
- * and zg in {2, 4} where zg * zb <= nz.  The state is not advanced (each
- * timed step reads the current buffer and writes the other).  Results are
- * cached per process by grid size, storage, boundary kinds, guess mode,
- * collision, flux and force; a cached shape is reused without timing.  With
- * the learned guess, the printed collision, the Lax-Wendroff flux or a force
- * only px = 64 is timed, and with a force only zg = 1.  The chosen shape is
- * returned in *px, *zb, *zg (any may be NULL).  Synchronises. */
-int rmhdlb_autotune(rmhdlb_ctx *ctx, int32_t *px, int32_t *zb, int32_t *zg);
+ * {1, 2, 4, 8, 16} up to nz and zg = yw = 1, plus px = 64 with zb in
+ * {16, 32, 64} and zg in {2, 4} where zg * zb <= nz; on a slab (nz = 1) every
+ * px with yw in {1, 2, 4}.  The state is not advanced (each timed step reads
+ * the current buffer and writes the other).  Results are cached per process
+ * by grid size, storage, boundary kinds, guess mode, collision, flux, force
+ * and previous-B reading; a cached shape is reused without timing.  With the
+ * learned guess, the printed collision, the Lax-Wendroff flux, a force or the
+ * previous-B reading only px = 64 is timed, and with a force only zg = yw = 1.
+ * The chosen shape is returned in *px, *zb, *zg, *yw (any may be NULL).
+ * Synchronises.  RMHDLB_ESTATE before the state is set. */
+int rmhdlb_autotune(rmhdlb_ctx *ctx, int32_t *px, int32_t *zb, int32_t *zg, int32_t *yw);
 
-/* Set the shape directly: px in {64, 32, 16}, zb >= 1, 1 <= zg <= 64; px = 64
- * with the learned guess, the printed collision or the Lax-Wendroff flux, and
- * zg = 1 with a force (RMHDLB_EINVAL otherwise).  zb above nz acts as nz, and
- * zg above ceil(nz / zb) is reduced to it.  A force set later runs with
- * zg = 1 whatever the tuning. */
-int rmhdlb_set_tuning(rmhdlb_ctx *ctx, int32_t px, int32_t zb, int32_t zg);
+/* Set the shape directly: px in {64, 32, 16}, zb >= 1, 1 <= zg <= 64,
+ * 1 <= yw <= 8; px = 64 with the learned guess, the printed collision, the
+ * Lax-Wendroff flux or the previous-B reading, and zg = yw = 1 with a force
+ * (RMHDLB_EINVAL otherwise).  zb above nz acts as nz, and zg above
+ * ceil(nz / zb) is reduced to it.  A force set later runs with zg = yw = 1
+ * whatever the tuning. */
+int rmhdlb_set_tuning(rmhdlb_ctx *ctx, int32_t px, int32_t zb, int32_t zg, int32_t yw);
 
 /* A batch of independent instances (for example a parameter sweep) stepped
  * together: every step is one launch over the blocks of all instances (plus
@@ -326,14 +363,26 @@ int rmhdlb_batch_create(const rmhdlb_params *params, int32_t n, void *hip_stream
 /* Instance i (0 <= i < n) as a context owned by the batch (NULL if out of range). */
 rmhdlb_ctx *rmhdlb_batch_instance(rmhdlb_batch *batch, int32_t i);
 
-/* Queue nsteps batched steps.  Every instance must be at the same buffer
- * parity (stepped only through the batch since init_fields), else
- * RMHDLB_EINVAL. */
+/* Queue nsteps batched steps.  Every instance must hold a state and be at
+ * the same buffer parity (stepped only through the batch since init_fields),
+ * else RMHDLB_ESTATE.  Steps are replayed from hipGraphs captured on the
+ * batch's stream (64 steps per graph, then 2, then one eager launch); a graph
+ * is captured again whenever the launch geometry changed (an instance's
+ * tuning, the batch's tile shape). */
 int rmhdlb_batch_step(rmhdlb_batch *batch, int64_t nsteps);
 
-/* Time the tile widths px in {64, 32, 16} of the batched step (state not
- * advanced) and keep the fastest; *px receives it (may be NULL).  Synchronises. */
-int rmhdlb_batch_autotune(rmhdlb_batch *batch, int32_t *px);
+/* Time the tiles of the batched step (state not advanced) and keep the
+ * fastest: px x (128 / px) yw cells for (px, yw) in (64, 1), (32, 1), (16, 1)
+ * and the shapes 64 x 4 (64, 2), 32 x 8 (32, 2), 128 x 2 (128, 2), 16 x 16
+ * (16, 2), 64 x 8 (64, 4), each with the kernel compiled for 2 and (FP32
+ * storage) 3 waves per SIMD.  Cached per process by storage and the grids
+ * of the instances.  *px, *yw, *waves receive the choice (any may be NULL).
+ * Synchronises.  RMHDLB_ESTATE as for rmhdlb_batch_step. */
+int rmhdlb_batch_autotune(rmhdlb_batch *batch, int32_t *px, int32_t *yw, int32_t *waves);
+
+/* Set the batch's tile directly: px in {128, 64, 32, 16}, 1 <= yw <= 8,
+ * waves 2, or 3 with FP32 storage (RMHDLB_EINVAL otherwise). */
+int rmhdlb_batch_set_tuning(rmhdlb_batch *batch, int32_t px, int32_t yw, int32_t waves);
 
 /* Release the batch and its instances.  NULL is accepted. */
 int rmhdlb_batch_destroy(rmhdlb_batch *batch);
@@ -345,7 +394,8 @@ int rmhdlb_destroy(rmhdlb_ctx *ctx);
 const char *rmhdlb_strerror(int code);
 
 /* Number of FP64 values of the raw state: 66 * nx*ny*nz (F[19], G[19],
- * h*[24 moving + 1 rest], E_prev[3], each nx*ny*nz values, post-collision). */
+ * h*[24 moving + 1 rest], E_prev[3], each nx*ny*nz values, post-collision),
+ * 69 * nx*ny*nz with RMHDLB_BPREV_PREVIOUS (B_prev[3] after E_prev). */
 int64_t rmhdlb_state_len(const rmhdlb_ctx *ctx);
 
 /* Copy the raw state to / from a DEVICE buffer of rmhdlb_state_len FP64

@@ -33,7 +33,7 @@ class _Params(ctypes.Structure):
         ("alpha", ctypes.c_double), ("Gamma", ctypes.c_double), ("sigma", ctypes.c_double),
         ("nu", ctypes.c_double),
         ("divb_fix", ctypes.c_int32), ("null_band", ctypes.c_int32), ("collision", ctypes.c_int32),
-        ("flux", ctypes.c_int32),
+        ("flux", ctypes.c_int32), ("b_prev", ctypes.c_int32),
     ]
 
 
@@ -80,7 +80,7 @@ def _vec(x):
 
 
 DEFAULTS = dict(dx=1.0, c=1.0, mu0=1.0, tau=1.0, tau_h=0.5, alpha=0.1, Gamma=4.0 / 3.0, sigma=1.0,
-                nu=27.0 ** 0.5, divb_fix=0, null_band=64, collision=0, flux=0)
+                nu=27.0 ** 0.5, divb_fix=0, null_band=64, collision=0, flux=0, b_prev=0)
 
 
 def make_params(shape=(1, 1, 1), bc=None, **kw):
@@ -99,6 +99,7 @@ def make_params(shape=(1, 1, 1), bc=None, **kw):
     P.null_band = int(d["null_band"])
     P.collision = int(d["collision"])
     P.flux = int(d["flux"])
+    P.b_prev = int(d["b_prev"])
     return P
 
 
@@ -211,7 +212,7 @@ class Oracle:
         n = lib().rmhdlb_oracle_state_len(self._h)
         out = np.empty(n)
         lib().rmhdlb_oracle_get_state(self._h, _ptr(out))
-        return out.reshape((66,) + self.grid)
+        return out.reshape((-1,) + self.grid)
 
     def set_state(self, state):
         s = np.ascontiguousarray(state, dtype=np.float64).reshape(-1)

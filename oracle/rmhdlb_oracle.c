@@ -47,6 +47,7 @@ typedef struct {
     int32_t null_band; /* half-width in y-cells of the null-point search band (< 1: 64) */
     int32_t collision; /* f collision: 0 explicit (Reading R4), 1 the printed semi-implicit form */
     int32_t flux;      /* face values: 0 MUSCL-minmod (Reading R2), 1 limited Lax-Wendroff */
+    int32_t b_prev;    /* B of the recovery and of f_eq: 0 this step's (Reading R10), 1 the previous step's */
 } orc_params;
 
 /* ---------------------------------------------------------------- lattice */
@@ -144,6 +145,7 @@ typedef struct {
     long N;
     double dt, eps0;
     double *f[2], *g[2], *hs[2], *Ep[2];
+    double *Bp[2];    /* previous step's B (3 arrays of N) when b_prev = 1, else NULL */
     int cur;
     double *ftr, *gtr; /* transported f, g of the current step, [q*N + cell] */
     double *hpull;    /* pulled h of the current step, 25 per cell */
@@ -596,10 +598,15 @@ static void macroscopic_cell(orc_ctx *C, int x, int y, int z, orc_macro *m, cons
     /* Fluid tensor T_fl = T - T_EM.  Reading R10: E is the previous step's
      * (the current one needs the velocity through Ohm's law, Eq. Ex_force);
      * B is this step's, a moment of the streamed h (Eq. Cal_B) that does not
-     * depend on the recovery.  The same pair enters f_eq below. */
-    double Eprev[3], Tem[4][4], Tfl[4][4];
-    for (int a = 0; a < 3; a++) Eprev[a] = Ep[(long)a * N + id];
-    t_em(C->eps0, c, Eprev, B, Tem);
+     * depend on the recovery.  The same pair enters f_eq below.  With
+     * b_prev = 1, B is the previous step's as well, the paper's wording of
+     * the coupling subsection (Sec. III). */
+    double Eprev[3], Brec[3], Tem[4][4], Tfl[4][4];
+    for (int a = 0; a < 3; a++) {
+        Eprev[a] = Ep[(long)a * N + id];
+        Brec[a] = P->b_prev ? C->Bp[C->cur][(long)a * N + id] : B[a];
+    }
+    t_em(C->eps0, c, Eprev, Brec, Tem);
     for (int mu = 0; mu < 4; mu++)
         for (int nv = 0; nv < 4; nv++) m->Tfl[mu][nv] = Tfl[mu][nv] = m->T[mu][nv] - Tem[mu][nv];
 
@@ -701,9 +708,12 @@ static void collision_pass(orc_ctx *C)
                 double feq[Q19], geq[Q19], heq[QH + 1];
                 /* Reading R10: f_eq carries T_EM of the same E, B pair that the
                  * recovery subtracted, so the collision conserves T^{0 nu} exactly */
-                double Eprev[3];
-                for (int a = 0; a < 3; a++) Eprev[a] = C->Ep[C->cur][(long)a * N + id];
-                f_equilibrium(C, m->eps, m->p, m->beta, Eprev, m->B, feq);
+                double Eprev[3], Brec[3];
+                for (int a = 0; a < 3; a++) {
+                    Eprev[a] = C->Ep[C->cur][(long)a * N + id];
+                    Brec[a] = P->b_prev ? C->Bp[C->cur][(long)a * N + id] : m->B[a];
+                }
+                f_equilibrium(C, m->eps, m->p, m->beta, Eprev, Brec, feq);
                 g_equilibrium(C, m->n, m->beta, geq);
                 /* Reading R22: the Maxwell populations relax towards h_eq of the
                  * streamed B.  With tau_h = 1/2 the collision reflects h about h_eq,
@@ -737,6 +747,9 @@ static void collision_pass(orc_ctx *C)
                 }
                 for (int k = 0; k <= QH; k++) hn[(long)k * N + id] = hp[k] - (hp[k] - heq[k]) / P->tau_h;
                 for (int a = 0; a < 3; a++) En[(long)a * N + id] = m->E[a];
+                /* b_prev = 1: this step's B (as the fluid coupling used it) is the next one's previous B */
+                if (P->b_prev)
+                    for (int a = 0; a < 3; a++) C->Bp[dst][(long)a * N + id] = m->B[a];
             }
     /* Reading R26: an external force density F (the flare's driver, Sec. IV) enters
      * as a source after the collision: c dt F^a into T^{0a} through the moving
@@ -788,6 +801,7 @@ ORC_API int rmhdlb_oracle_create(const orc_params *P, void **out)
     if (P->divb_fix != 0 && P->divb_fix != 1) return ORC_EINVAL;
     if (P->collision != 0 && P->collision != 1) return ORC_EINVAL;
     if (P->flux != 0 && P->flux != 1) return ORC_EINVAL;
+    if (P->b_prev != 0 && P->b_prev != 1) return ORC_EINVAL;
     if (P->tau_h != 0.5) return ORC_EUNSUPPORTED; /* Eq. Ex_force holds for tau_h = 1/2 */
     orc_ctx *C = (orc_ctx *)calloc(1, sizeof(orc_ctx));
     if (!C) return ORC_ENOMEM;
@@ -801,6 +815,7 @@ ORC_API int rmhdlb_oracle_create(const orc_params *P, void **out)
         C->g[b] = (double *)calloc((size_t)Q19 * C->N, sizeof(double));
         C->hs[b] = (double *)calloc((size_t)(QH + 1) * C->N, sizeof(double));
         C->Ep[b] = (double *)calloc((size_t)3 * C->N, sizeof(double));
+        if (P->b_prev) C->Bp[b] = (double *)calloc((size_t)3 * C->N, sizeof(double));
     }
     C->ftr = (double *)calloc((size_t)Q19 * C->N, sizeof(double));
     C->gtr = (double *)calloc((size_t)Q19 * C->N, sizeof(double));
@@ -817,13 +832,14 @@ ORC_API int rmhdlb_oracle_create(const orc_params *P, void **out)
         C->gE = (double *)calloc(3 * plane2, sizeof(double));
         ok = ok && C->gf && C->gg && C->gh && C->gE;
     }
-    for (int b = 0; b < 2; b++) ok = ok && C->f[b] && C->g[b] && C->hs[b] && C->Ep[b];
+    for (int b = 0; b < 2; b++) ok = ok && C->f[b] && C->g[b] && C->hs[b] && C->Ep[b] && (!P->b_prev || C->Bp[b]);
     if (!ok) {
         for (int b = 0; b < 2; b++) {
             free(C->f[b]);
             free(C->g[b]);
             free(C->hs[b]);
             free(C->Ep[b]);
+            free(C->Bp[b]);
         }
         free(C->ftr);
         free(C->gtr);
@@ -852,6 +868,7 @@ ORC_API void rmhdlb_oracle_destroy(void *ctx)
         free(C->g[b]);
         free(C->hs[b]);
         free(C->Ep[b]);
+        free(C->Bp[b]);
     }
     free(C->ftr);
     free(C->gtr);
@@ -1035,6 +1052,8 @@ ORC_API int rmhdlb_oracle_init(void *ctx, const double *n, const double *p, cons
                 }
                 hs[(long)QH * N + id] = rhoc[id];
                 for (int a = 0; a < 3; a++) Ep[(long)a * N + id] = EE[a];
+                if (P->b_prev)
+                    for (int a = 0; a < 3; a++) C->Bp[cur][(long)a * N + id] = BB[a];
             }
     free(rhoc);
     free(J);
@@ -1195,8 +1214,8 @@ ORC_API int rmhdlb_oracle_diagnostics(void *ctx, double d[13])
 }
 
 /* Raw (post-collision) state in normalised variables F = (c_t/c_0)^2 f,
- * G = (c_t/c_0) g, in the order F[19], G[19], h*[25], E_prev[3], each
- * nx*ny*nz doubles. */
+ * G = (c_t/c_0) g, in the order F[19], G[19], h*[25], E_prev[3] (then
+ * B_prev[3] when b_prev = 1), each nx*ny*nz doubles. */
 ORC_API int rmhdlb_oracle_get_state(void *ctx, double *out)
 {
     orc_ctx *C = (orc_ctx *)ctx;
@@ -1209,6 +1228,8 @@ ORC_API int rmhdlb_oracle_get_state(void *ctx, double *out)
     for (long k = 0; k < Q19 * N; k++) out[o++] = r1 * C->g[b][k];
     for (long k = 0; k < (QH + 1) * N; k++) out[o++] = C->hs[b][k];
     for (long k = 0; k < 3 * N; k++) out[o++] = C->Ep[b][k];
+    if (C->P.b_prev)
+        for (long k = 0; k < 3 * N; k++) out[o++] = C->Bp[b][k];
     return ORC_OK;
 }
 
@@ -1224,13 +1245,15 @@ ORC_API int rmhdlb_oracle_set_state(void *ctx, const double *in)
     for (long k = 0; k < Q19 * N; k++) C->g[b][k] = in[o++] / r1;
     for (long k = 0; k < (QH + 1) * N; k++) C->hs[b][k] = in[o++];
     for (long k = 0; k < 3 * N; k++) C->Ep[b][k] = in[o++];
+    if (C->P.b_prev)
+        for (long k = 0; k < 3 * N; k++) C->Bp[b][k] = in[o++];
     return ORC_OK;
 }
 
 ORC_API long rmhdlb_oracle_state_len(void *ctx)
 {
     orc_ctx *C = (orc_ctx *)ctx;
-    return C ? (long)NSTATE * C->N : -1;
+    return C ? (long)(NSTATE + (C->P.b_prev ? 3 : 0)) * C->N : -1;
 }
 
 /* ---- single-cell entry points, used by the tests that pin the oracle ---- */

@@ -1,8 +1,10 @@
 // rmhdlb_api.hip -- implementation of the C ABI declared in include/rmhdlb.h.
 //
-// Owns parameter validation, the two device state buffers and the scratch
-// memory, the per-run constants and the launch sequence.  No host
-// synchronisation except in rmhdlb_moments and the state copies.
+// Owns parameter validation, the layout of the device memory of a context
+// (two state buffers, scratch, partial sums: one block, the caller's
+// workspace or one allocation), the per-run constants and the launch
+// sequence.  No host synchronisation except in rmhdlb_moments and the state
+// copies.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -28,7 +30,10 @@ struct rmhdlb_ctx {
     hipStream_t stream;
     Consts K;
     int storage;       // RMHDLB_STORE_*
-    void* buf[2];      // state buffers (distributions, then E_prev)
+    void* mem;         // the block every buffer below (to result) is carved from
+    bool own_mem;      // mem was allocated by rmhdlb_create (else the caller's workspace)
+    bool has_state;    // rmhdlb_init_fields or rmhdlb_set_state has run
+    void* buf[2];      // state buffers (distributions, then E_prev and, with the previous-B reading, B_prev)
     rmhd::StateBuf sb[2];
     int cur;
     double* scratch;   // 6 N doubles: initial J0 and E'0, then B and E^z of the moments pass
@@ -55,6 +60,7 @@ struct rmhdlb_ctx {
 
 namespace {
 
+// Parameters without the workspace fields.
 int validate(const rmhdlb_params* P) {
     if (!P) return RMHDLB_EINVAL;
     if (P->nx < 1 || P->ny < 1 || P->nz < 1) return RMHDLB_EINVAL;
@@ -69,14 +75,17 @@ int validate(const rmhdlb_params* P) {
     if (P->divb_fix != 0 && P->divb_fix != 1) return RMHDLB_EINVAL;
     if (P->collision != RMHDLB_COLL_EXPLICIT && P->collision != RMHDLB_COLL_PRINTED) return RMHDLB_EINVAL;
     if (P->flux != RMHDLB_FLUX_MUSCL && P->flux != RMHDLB_FLUX_LAX_WENDROFF) return RMHDLB_EINVAL;
+    if (P->b_prev != RMHDLB_BPREV_CURRENT && P->b_prev != RMHDLB_BPREV_PREVIOUS) return RMHDLB_EINVAL;
     if (!(P->dx > 0) || !(P->c > 0) || !(P->mu0 > 0) || !(P->tau > 0) || !(P->alpha >= 0) || !(P->Gamma > 1) ||
         !(P->sigma >= 0) || !(P->nu > 0) || !isfinite(P->sigma) || !isfinite(P->alpha))
         return RMHDLB_EINVAL;
     if (P->storage != RMHDLB_STORE_F64 && P->storage != RMHDLB_STORE_F32 && P->storage != RMHDLB_STORE_F16)
         return RMHDLB_EINVAL;
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 2; ++k)
         if (P->reserved[k] != 0) return RMHDLB_EINVAL;
     if (P->tau_h != 0.5) return RMHDLB_EUNSUPPORTED;  // the force form of Eq. Ex_force needs tau_h = 1/2
+    if (P->b_prev == RMHDLB_BPREV_PREVIOUS && (P->collision != RMHDLB_COLL_EXPLICIT || P->flux != RMHDLB_FLUX_MUSCL))
+        return RMHDLB_EUNSUPPORTED;  // the previous-B reading is built with the default collision and faces
     return RMHDLB_OK;
 }
 
@@ -103,6 +112,7 @@ Consts make_consts(const rmhdlb_params* P) {
     K.band = P->null_band >= 1 ? P->null_band : 64;
     K.coll = P->collision;
     K.flux = P->flux;
+    K.bprev = P->b_prev;
     const int64_t fsz[3] = {(int64_t)P->ny * P->nz, (int64_t)P->nx * P->nz, (int64_t)P->nx * P->ny};
     K.fo[0] = 0;
     for (int f = 0; f < 6; ++f) K.fo[f + 1] = K.fo[f] + fsz[f >> 1];
@@ -140,8 +150,34 @@ size_t efield_offset(int storage, int64_t stride) {
     const size_t b = (size_t)(rmhd::NSTATE - 3) * (size_t)stride * dist_elem(storage);
     return (b + 255) / 256 * 256;
 }
-size_t buffer_bytes(int storage, int64_t stride) {
-    return efield_offset(storage, stride) + 3 * (size_t)stride * efield_elem(storage);
+// The field block holds E_prev (3 arrays) and, with the previous-B reading, B_prev (3 more).
+size_t buffer_bytes(const Consts& K, int storage) {
+    return efield_offset(storage, K.stride) + (size_t)(K.bprev ? 6 : 3) * (size_t)K.stride * efield_elem(storage);
+}
+
+// The device memory of a context: the buffers below, each at a 256-byte
+// aligned offset of one block.
+enum { M_BUF0, M_BUF1, M_SCRATCH, M_PART, M_PART2, M_NULLP, M_FACEB, M_EZ0, M_AUX, M_RESULT, M_COUNT };
+
+size_t mem_layout(const Consts& K, int storage, size_t off[M_COUNT]) {
+    const size_t nt = (size_t)rmhd::num_tiles(K);
+    const size_t nred = (size_t)((K.N + 255) / 256);  // blocks of the init-reference reduction
+    size_t sz[M_COUNT];
+    sz[M_BUF0] = sz[M_BUF1] = buffer_bytes(K, storage);
+    sz[M_SCRATCH] = sizeof(double) * 6 * (size_t)K.N;  // initial J0 and E'0, then B and E^z of the moments pass
+    sz[M_PART] = sizeof(double) * std::max(std::max((size_t)rmhd::NPART * nt, 2 * nred), (size_t)K.nx * K.ny);
+    sz[M_PART2] = sizeof(double) * std::max(nt, nred);
+    sz[M_NULLP] = sizeof(double) * 2 * nt;
+    sz[M_FACEB] = sizeof(double) * (size_t)std::max<int64_t>(K.fo[6], 1);
+    sz[M_EZ0] = sizeof(double) * (size_t)K.N;
+    sz[M_AUX] = sizeof(double) * 4;
+    sz[M_RESULT] = sizeof(double) * RESULT_LEN;
+    size_t total = 0;
+    for (int i = 0; i < M_COUNT; ++i) {
+        off[i] = total;
+        total += (sz[i] + 255) / 256 * 256;
+    }
+    return total;
 }
 
 // Shifts of the stored f and g: w_i E_ref and w'_i N_ref rounded to the
@@ -231,19 +267,10 @@ bool dalloc(Tp** p, size_t n) {
 
 void release(rmhdlb_ctx* C) {
     if (!C) return;
-    for (int b = 0; b < 2; ++b)
-        if (C->buf[b]) (void)hipFree(C->buf[b]);
-    if (C->scratch) (void)hipFree(C->scratch);
-    if (C->part) (void)hipFree(C->part);
-    if (C->part2) (void)hipFree(C->part2);
-    if (C->nullp) (void)hipFree(C->nullp);
-    if (C->faceB) (void)hipFree(C->faceB);
-    if (C->ez0) (void)hipFree(C->ez0);
-    if (C->aux) (void)hipFree(C->aux);
+    if (C->own_mem && C->mem) (void)hipFree(C->mem);
     if (C->gt) (void)hipFree(C->gt);
     if (C->force) (void)hipFree(C->force);
     if (C->vmax) (void)hipFree(C->vmax);
-    if (C->result) (void)hipFree(C->result);
     delete C;
 }
 
@@ -259,8 +286,15 @@ const char* rmhdlb_strerror(int code) {
         case RMHDLB_EDEVICE: return "HIP runtime or launch error";
         case RMHDLB_ERECOVERY: return "primitive recovery failed in some cells";
         case RMHDLB_EUNSUPPORTED: return "unsupported parameter value";
+        case RMHDLB_ESTATE: return "call out of order (no state yet, or batch instances at different time levels)";
         default: return "unknown error";
     }
+}
+
+size_t rmhdlb_workspace_bytes(const rmhdlb_params* params) {
+    if (validate(params) != RMHDLB_OK) return 0;
+    size_t off[M_COUNT];
+    return mem_layout(make_consts(params), params->storage, off);
 }
 
 int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** out) {
@@ -268,39 +302,49 @@ int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** ou
     *out = nullptr;
     const int v = validate(params);
     if (v != RMHDLB_OK) return v;
+    const Consts K = make_consts(params);
+    size_t off[M_COUNT];
+    const size_t total = mem_layout(K, params->storage, off);
+    if (params->workspace && (params->workspace_bytes < total || ((uintptr_t)params->workspace & 255) != 0))
+        return RMHDLB_EINVAL;
     rmhdlb_ctx* C = new (std::nothrow) rmhdlb_ctx();
     if (!C) return RMHDLB_ENOMEM;
     C->P = *params;
     C->stream = (hipStream_t)hip_stream;
-    C->K = make_consts(params);
+    C->K = K;
     C->storage = params->storage;
-    const size_t bytes = buffer_bytes(C->storage, C->K.stride);
-    const int nt = rmhd::num_tiles(C->K);
-    const size_t nred = (size_t)((C->K.N + 255) / 256);  // blocks of the init-reference reduction
-    bool ok = true;
-    const int64_t g0 = ghost_cells(C->K);
-    for (int b = 0; b < 2 && ok; ++b) {
-        // zeroed once so that ghost planes and padding hold defined values
-        ok = hipMalloc(&C->buf[b], bytes) == hipSuccess && hipMemset(C->buf[b], 0, bytes) == hipSuccess;
-        if (ok) {
-            C->sb[b].dist = (char*)C->buf[b] + g0 * dist_elem(C->storage);
-            C->sb[b].efield = (char*)C->buf[b] + efield_offset(C->storage, C->K.stride) + g0 * efield_elem(C->storage);
-        }
-    }
-    const size_t npart = std::max(std::max((size_t)rmhd::NPART * nt, 2 * nred), (size_t)C->K.nx * C->K.ny);
-    ok = ok && hipMalloc((void**)&C->scratch, sizeof(double) * 6 * (size_t)C->K.N) == hipSuccess;
-    ok = ok && hipMalloc((void**)&C->part, sizeof(double) * npart) == hipSuccess;
-    ok = ok && hipMalloc((void**)&C->part2, sizeof(double) * std::max((size_t)nt, nred)) == hipSuccess;
-    ok = ok && hipMalloc((void**)&C->nullp, sizeof(double) * 2 * (size_t)nt) == hipSuccess;
-    ok = ok && hipMalloc((void**)&C->faceB, sizeof(double) * (size_t)std::max<int64_t>(C->K.fo[6], 1)) == hipSuccess;
-    ok = ok && hipMalloc((void**)&C->ez0, sizeof(double) * (size_t)C->K.N) == hipSuccess;
-    ok = ok && hipMalloc((void**)&C->aux, sizeof(double) * 4) == hipSuccess;
-    ok = ok && hipMalloc((void**)&C->result, sizeof(double) * RESULT_LEN) == hipSuccess;
-    if (!ok) {
+    if (params->workspace) {
+        C->mem = params->workspace;
+        C->own_mem = false;
+    } else if (hipMalloc(&C->mem, total) != hipSuccess) {
         (void)hipGetLastError();
+        C->mem = nullptr;
         release(C);
         return RMHDLB_ENOMEM;
+    } else {
+        C->own_mem = true;
     }
+    // cleared once so that ghost planes and padding hold defined values
+    if (hipMemsetAsync(C->mem, 0, total, C->stream) != hipSuccess) {
+        release(C);
+        return RMHDLB_EDEVICE;
+    }
+    char* base = (char*)C->mem;
+    const int64_t g0 = ghost_cells(C->K);
+    for (int b = 0; b < 2; ++b) {
+        C->buf[b] = base + off[M_BUF0 + b];
+        C->sb[b].dist = (char*)C->buf[b] + g0 * dist_elem(C->storage);
+        C->sb[b].efield = (char*)C->buf[b] + efield_offset(C->storage, C->K.stride) + g0 * efield_elem(C->storage);
+    }
+    C->scratch = (double*)(base + off[M_SCRATCH]);
+    C->part = (double*)(base + off[M_PART]);
+    C->part2 = (double*)(base + off[M_PART2]);
+    C->nullp = (double*)(base + off[M_NULLP]);
+    C->faceB = (double*)(base + off[M_FACEB]);
+    C->ez0 = (double*)(base + off[M_EZ0]);
+    C->aux = (double*)(base + off[M_AUX]);
+    C->result = (double*)(base + off[M_RESULT]);
+    C->has_state = false;
     C->cur = 0;
     C->step = 0;
     // Launch shape until rmhdlb_autotune or rmhdlb_set_tuning picks another.
@@ -364,6 +408,7 @@ int rmhdlb_init_fields(rmhdlb_ctx* C, const rmhdlb_fields_in* in) {
     if (C->K.forced && hipMemsetAsync(C->vmax, 0, sizeof(double), C->stream) != hipSuccess)
         return RMHDLB_EDEVICE;  // the force gate starts open
     C->step = 0;
+    C->has_state = true;
     return RMHDLB_OK;
 }
 
@@ -375,7 +420,7 @@ int rmhdlb_set_force(rmhdlb_ctx* C, const double* const F[3], double gate) {
     }
     for (int a = 0; a < 3; ++a)
         if (!F[a]) return RMHDLB_EINVAL;
-    if (C->K.flux || C->guess_mode) return RMHDLB_EUNSUPPORTED;
+    if (C->K.flux || C->guess_mode || C->K.bprev) return RMHDLB_EUNSUPPORTED;
     const int64_t N = C->K.N;
     // one partial per wavefront of the widest launch (64-wide tiles, one plane per block)
     const int64_t nparts = 4 * (int64_t)((C->K.nx + 63) / 64) * ((C->K.ny + 1) / 2) * C->K.nz;
@@ -424,6 +469,7 @@ int rmhdlb_set_driven_face(rmhdlb_ctx* C, const rmhdlb_face_in* face) {
 
 int rmhdlb_step(rmhdlb_ctx* C, int64_t nsteps) {
     if (!C || nsteps < 0) return RMHDLB_EINVAL;
+    if (!C->has_state) return RMHDLB_ESTATE;
     for (int64_t s = 0; s < nsteps; ++s) {
         hipError_t e = RMHD_DISPATCH(C, launch_step)(C->sb[C->cur], C->sb[1 - C->cur], C->K, C->tune, C->faceB,
                                                      C->guess_mode ? C->gt : nullptr, C->stream);
@@ -436,6 +482,7 @@ int rmhdlb_step(rmhdlb_ctx* C, int64_t nsteps) {
 
 int rmhdlb_moments(rmhdlb_ctx* C, rmhdlb_fields_out* out, rmhdlb_diag* diag) {
     if (!C) return RMHDLB_EINVAL;
+    if (!C->has_state) return RMHDLB_ESTATE;
     rmhd::OutPtrs op;
     memset(&op, 0, sizeof(op));
     if (out) {
@@ -498,7 +545,7 @@ int rmhdlb_set_guess_weights(rmhdlb_ctx* C, const rmhdlb_guess_weights* w) {
 int rmhdlb_set_guess(rmhdlb_ctx* C, int32_t mode) {
     if (!C || (mode != RMHDLB_GUESS_PLAIN && mode != RMHDLB_GUESS_MLP)) return RMHDLB_EINVAL;
     if (mode == RMHDLB_GUESS_MLP && !C->gt) return RMHDLB_EINVAL;
-    if (mode == RMHDLB_GUESS_MLP && (C->K.coll || C->K.flux || C->K.forced))
+    if (mode == RMHDLB_GUESS_MLP && (C->K.coll || C->K.flux || C->K.forced || C->K.bprev))
         return RMHDLB_EUNSUPPORTED;  // default readings, no force
     C->guess_mode = mode;
     return RMHDLB_OK;
@@ -517,6 +564,8 @@ static int sample_cells(rmhdlb_ctx* C, int ns, double* F, double* T, double* par
 
 int rmhdlb_guess_samples(rmhdlb_ctx* C, int32_t ns, double* F, double* T) {
     if (!C || !F || !T || ns < 1 || ns > C->K.N) return RMHDLB_EINVAL;
+    if (!C->has_state) return RMHDLB_ESTATE;
+    if (C->K.bprev) return RMHDLB_EUNSUPPORTED;
     double* part = nullptr;
     if (!dalloc(&part, (size_t)rmhd::SAMPLE_SUMS * ((ns + 255) / 256))) return RMHDLB_ENOMEM;
     double sums[rmhd::SAMPLE_SUMS];
@@ -528,6 +577,8 @@ int rmhdlb_guess_samples(rmhdlb_ctx* C, int32_t ns, double* F, double* T) {
 int rmhdlb_train_guess(rmhdlb_ctx* C, const rmhdlb_train_opts* o, const float* init_w, rmhdlb_guess_weights* out,
                        float* losses) {
     if (!C || !o || !init_w) return RMHDLB_EINVAL;
+    if (!C->has_state) return RMHDLB_ESTATE;
+    if (C->K.bprev) return RMHDLB_EUNSUPPORTED;
     const int ns = o->n_samples;
     if (ns < 128 || ns > C->K.N || o->batch < 128 || o->batch % 128 != 0 || o->batch > ns || o->iters < 0 ||
         o->stride < 1 || !(o->lr > 0.0f) || !isfinite(o->lr) || o->reserved[0] || o->reserved[1] || o->reserved[2])
@@ -624,8 +675,8 @@ int rmhdlb_mlp_eval(const float* w, const float* X, const float* Yt, int32_t n, 
 
 namespace {
 
-// nx, ny, nz, storage, divb, driven, guess, collision, flux, force
-typedef std::tuple<int, int, int, int, int, int, int, int, int, int> TuneKey;
+// nx, ny, nz, storage, divb, driven, guess, collision, flux, force, previous B
+typedef std::tuple<int, int, int, int, int, int, int, int, int, int, int> TuneKey;
 std::map<TuneKey, rmhd::StepTuning> g_tune_cache;
 std::mutex g_tune_mutex;
 
@@ -655,14 +706,16 @@ int time_ms(hipStream_t st, int reps, Fn fn, float* ms) {
 
 extern "C" {
 
-int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out, int32_t* zg_out) {
+int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out, int32_t* zg_out, int32_t* yw_out) {
     if (!C) return RMHDLB_EINVAL;
+    if (!C->has_state) return RMHDLB_ESTATE;
     const TuneKey key(C->K.nx, C->K.ny, C->K.nz, C->storage, C->K.divb, C->K.drv, C->guess_mode, C->K.coll,
-                      C->K.flux, C->K.forced);
+                      C->K.flux, C->K.forced, C->K.bprev);
     rmhd::StepTuning best;
     best.px = 64;
     best.zb = 4;
     best.zg = 1;
+    best.yw = 1;
     bool cached = false;
     {
         std::lock_guard<std::mutex> g(g_tune_mutex);
@@ -675,18 +728,22 @@ int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out, int32_t* zg
     if (!cached) {
         // Candidates: every tile width with zb in {1, 2, 4, 8, 16} walked by
         // one block, and 64-wide tiles with long walks shared by 2 or 4
-        // interleaved blocks per column (chunks of up to 256 planes).
+        // interleaved blocks per column (chunks of up to 256 planes).  On a
+        // slab (nz = 1) the blocks instead take 1, 2 or 4 row groups.
         std::vector<rmhd::StepTuning> cand;
-        const bool only64 = C->guess_mode || C->K.coll || C->K.flux || C->K.forced;
+        const bool only64 = C->guess_mode || C->K.coll || C->K.flux || C->K.forced || C->K.bprev;
         for (int px : {64, 32, 16})
-            for (int zb : {1, 2, 4, 8, 16}) {
-                if ((zb > C->K.nz && zb != 1) || (only64 && px != 64)) continue;
-                rmhd::StepTuning t;
-                t.px = px;
-                t.zb = zb;
-                t.zg = 1;
-                cand.push_back(t);
-            }
+            for (int zb : {1, 2, 4, 8, 16})
+                for (int yw : {1, 2, 4}) {
+                    if ((zb > C->K.nz && zb != 1) || (only64 && px != 64)) continue;
+                    if (yw > 1 && (C->K.nz > 1 || C->K.forced)) continue;
+                    rmhd::StepTuning t;
+                    t.px = px;
+                    t.zb = zb;
+                    t.zg = 1;
+                    t.yw = yw;
+                    cand.push_back(t);
+                }
         if (!C->K.forced)
             for (int zg : {2, 4})
                 for (int zb : {16, 32, 64}) {
@@ -717,13 +774,15 @@ int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out, int32_t* zg
     if (px_out) *px_out = best.px;
     if (zb_out) *zb_out = best.zb;
     if (zg_out) *zg_out = best.zg;
+    if (yw_out) *yw_out = best.yw;
     return RMHDLB_OK;
 }
 
-int rmhdlb_set_tuning(rmhdlb_ctx* C, int32_t px, int32_t zb, int32_t zg) {
-    if (!C || (px != 64 && px != 32 && px != 16) || zb < 1 || zg < 1 || zg > 64) return RMHDLB_EINVAL;
-    if ((C->guess_mode || C->K.coll || C->K.flux || C->K.forced) && px != 64) return RMHDLB_EINVAL;
-    if (C->K.forced && zg != 1) return RMHDLB_EINVAL;
+int rmhdlb_set_tuning(rmhdlb_ctx* C, int32_t px, int32_t zb, int32_t zg, int32_t yw) {
+    if (!C || (px != 64 && px != 32 && px != 16) || zb < 1 || zg < 1 || zg > 64 || yw < 1 || yw > 8)
+        return RMHDLB_EINVAL;
+    if ((C->guess_mode || C->K.coll || C->K.flux || C->K.forced || C->K.bprev) && px != 64) return RMHDLB_EINVAL;
+    if (C->K.forced && (zg != 1 || yw != 1)) return RMHDLB_EINVAL;
     // More blocks per column than the chunk has planes would only walk
     // nothing: cap zg at ceil(nz / zb) (zb as the step clamps it to nz),
     // which also keeps zg * zb within int range.
@@ -732,6 +791,7 @@ int rmhdlb_set_tuning(rmhdlb_ctx* C, int32_t px, int32_t zb, int32_t zg) {
     C->tune.px = px;
     C->tune.zb = zb;
     C->tune.zg = zg < zg_max ? zg : zg_max;
+    C->tune.yw = yw;
     return RMHDLB_OK;
 }
 
@@ -739,21 +799,49 @@ int rmhdlb_set_tuning(rmhdlb_ctx* C, int32_t px, int32_t zb, int32_t zg) {
 
 // ---------------------------------------------------------------- batches
 
+// Steps per captured graph of a batch: long replays for long sweeps, a
+// two-step graph for the rest (each starts and ends at buffer parity 0).
+constexpr int GRAPH_LONG = 64;
+
+// Launch dimensions baked into a captured graph: the graph must be captured
+// again when any of them changes.
+struct BatchGeom {
+    int px = 0, yw = 0, waves = 0, total_blocks = -1;
+    int64_t total_face = -1;
+    bool operator==(const BatchGeom& o) const {
+        return px == o.px && yw == o.yw && waves == o.waves && total_blocks == o.total_blocks &&
+               total_face == o.total_face;
+    }
+};
+
 struct rmhdlb_batch {
     int n;
     std::vector<rmhdlb_ctx*> ctx;
     hipStream_t stream;
     int storage;
-    int px;
+    int px;     // tile width (128, 64, 32, 16)
+    int yw;     // row groups per block (the tile is px x (128 / px) yw cells on a slab)
+    int waves;  // occupancy variant of the FP32 kernel (2 or 3 waves per SIMD)
     std::vector<rmhd::BatchInst> host;
     rmhd::BatchInst* dev;
     int total_blocks;
     int64_t total_face;
-    hipGraphExec_t exec;  // two captured steps (parity 0 then 1), or null
-    int graph_px;         // tile width the graph was captured with
+    hipGraphExec_t exec_long;  // GRAPH_LONG steps from parity 0, or null
+    hipGraphExec_t exec_pair;  // two steps from parity 0, or null
+    BatchGeom graph_geom;      // the geometry both graphs were captured with
 };
 
 namespace {
+
+BatchGeom batch_geom(const rmhdlb_batch* B) {
+    BatchGeom g;
+    g.px = B->px;
+    g.yw = B->yw;
+    g.waves = B->waves;
+    g.total_blocks = B->total_blocks;
+    g.total_face = B->total_face;
+    return g;
+}
 
 // Per-instance table of the batched launches from the instances' current
 // constants and buffers.
@@ -769,7 +857,8 @@ int batch_table(rmhdlb_batch* B) {
         }
         I.faceB = C->faceB;
         I.zb = std::max(1, std::min(C->tune.zb, C->K.nz));
-        rmhd::step_geometry(C->K, B->px, I.zb, 1, I.tiles_x, I.ncol, I.nblk);
+        I.yw = B->yw;
+        rmhd::step_geometry(C->K, B->px, I.zb, 1, I.yw, I.tiles_x, I.ncol, I.nblk);
         I.blk0 = blk;
         I.face0 = face;
         blk += I.nblk;
@@ -787,45 +876,63 @@ int batch_table(rmhdlb_batch* B) {
 hipError_t batch_launch(rmhdlb_batch* B, int parity) {
     switch (B->storage) {
         case RMHDLB_STORE_F64:
-            return rmhd::launch_batch<double>(B->dev, B->n, B->total_blocks, B->total_face, B->px, parity, B->stream);
+            return rmhd::launch_batch<double>(B->dev, B->n, B->total_blocks, B->total_face, B->px, B->waves, parity,
+                                              B->stream);
         case RMHDLB_STORE_F32:
-            return rmhd::launch_batch<float>(B->dev, B->n, B->total_blocks, B->total_face, B->px, parity, B->stream);
+            return rmhd::launch_batch<float>(B->dev, B->n, B->total_blocks, B->total_face, B->px, B->waves, parity,
+                                             B->stream);
         default:
-            return rmhd::launch_batch<_Float16>(B->dev, B->n, B->total_blocks, B->total_face, B->px, parity,
-                                                B->stream);
+            return rmhd::launch_batch<_Float16>(B->dev, B->n, B->total_blocks, B->total_face, B->px, B->waves,
+                                                parity, B->stream);
     }
 }
 
-void drop_graph(rmhdlb_batch* B) {
-    if (B->exec) (void)hipGraphExecDestroy(B->exec);
-    B->exec = nullptr;
+void drop_graphs(rmhdlb_batch* B) {
+    if (B->exec_long) (void)hipGraphExecDestroy(B->exec_long);
+    if (B->exec_pair) (void)hipGraphExecDestroy(B->exec_pair);
+    B->exec_long = B->exec_pair = nullptr;
 }
 
-// Capture two steps (parity 0, then 1) into an executable graph; on any
-// failure the batch steps eagerly.
-void capture_graph(rmhdlb_batch* B) {
-    drop_graph(B);
-    if (!B->stream) return;  // the legacy default stream cannot be captured
+// Capture nsteps (even) steps from parity 0 into an executable graph; null
+// on any failure (the batch then steps eagerly).
+hipGraphExec_t capture_steps(rmhdlb_batch* B, int nsteps) {
+    if (!B->stream) return nullptr;  // the legacy default stream cannot be captured
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipGetLastError();
-        return;
+        return nullptr;
     }
-    const bool ok = batch_launch(B, 0) == hipSuccess && batch_launch(B, 1) == hipSuccess;
+    bool ok = true;
+    for (int k = 0; k < nsteps && ok; ++k) ok = batch_launch(B, k & 1) == hipSuccess;
     if (hipStreamEndCapture(B->stream, &g) != hipSuccess || !ok || !g) {
         (void)hipGetLastError();
         if (g) (void)hipGraphDestroy(g);
-        return;
+        return nullptr;
     }
     hipGraphExec_t e = nullptr;
-    if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) == hipSuccess) {
-        B->exec = e;
-        B->graph_px = B->px;
-    } else {
+    if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
         (void)hipGetLastError();
+        e = nullptr;
     }
     (void)hipGraphDestroy(g);
+    return e;
 }
+
+int check_batch_state(rmhdlb_batch* B) {
+    const int parity0 = B->ctx[0]->cur;
+    for (rmhdlb_ctx* C : B->ctx) {
+        if (!C->has_state || C->cur != parity0) return RMHDLB_ESTATE;
+        if (C->guess_mode || C->K.forced) return RMHDLB_EUNSUPPORTED;
+    }
+    return RMHDLB_OK;
+}
+
+// Batch tuning cache: storage and every instance's grid.
+typedef std::pair<int, std::vector<std::tuple<int, int, int>>> BatchKey;
+struct BatchShape {
+    int px, yw, waves;
+};
+std::map<BatchKey, BatchShape> g_batch_cache;
 
 }  // namespace
 
@@ -838,7 +945,8 @@ int rmhdlb_batch_create(const rmhdlb_params* params, int32_t n, void* hip_stream
     for (int i = 1; i < n; ++i)
         if (params[i].storage != params[0].storage) return RMHDLB_EINVAL;
     for (int i = 0; i < n; ++i)
-        if (params[i].collision != RMHDLB_COLL_EXPLICIT || params[i].flux != RMHDLB_FLUX_MUSCL)
+        if (params[i].collision != RMHDLB_COLL_EXPLICIT || params[i].flux != RMHDLB_FLUX_MUSCL ||
+            params[i].b_prev != RMHDLB_BPREV_CURRENT)
             return RMHDLB_EUNSUPPORTED;  // batches: the default readings only
     rmhdlb_batch* B = new (std::nothrow) rmhdlb_batch();
     if (!B) return RMHDLB_ENOMEM;
@@ -846,9 +954,12 @@ int rmhdlb_batch_create(const rmhdlb_params* params, int32_t n, void* hip_stream
     B->stream = (hipStream_t)hip_stream;
     B->storage = params[0].storage;
     B->px = 64;
+    B->yw = 1;
+    B->waves = 2;
     B->dev = nullptr;
-    B->exec = nullptr;
-    B->graph_px = 0;
+    B->exec_long = B->exec_pair = nullptr;
+    B->total_blocks = 0;
+    B->total_face = 0;
     B->ctx.assign(n, nullptr);
     B->host.resize(n);
     int rc = RMHDLB_OK;
@@ -872,7 +983,7 @@ rmhdlb_ctx* rmhdlb_batch_instance(rmhdlb_batch* B, int32_t i) {
 int rmhdlb_batch_destroy(rmhdlb_batch* B) {
     if (!B) return RMHDLB_OK;
     if (B->stream) (void)hipStreamSynchronize(B->stream);
-    drop_graph(B);
+    drop_graphs(B);
     for (rmhdlb_ctx* C : B->ctx) rmhdlb_destroy(C);
     if (B->dev) (void)hipFree(B->dev);
     delete B;
@@ -881,25 +992,32 @@ int rmhdlb_batch_destroy(rmhdlb_batch* B) {
 
 int rmhdlb_batch_step(rmhdlb_batch* B, int64_t nsteps) {
     if (!B || nsteps < 0) return RMHDLB_EINVAL;
-    const int parity0 = B->ctx[0]->cur;
-    for (rmhdlb_ctx* C : B->ctx) {
-        if (C->cur != parity0) return RMHDLB_EINVAL;
-        if (C->guess_mode || C->K.forced) return RMHDLB_EUNSUPPORTED;
-    }
-    if (nsteps == 0) return RMHDLB_OK;
-    int rc = batch_table(B);
+    int rc = check_batch_state(B);
     if (rc != RMHDLB_OK) return rc;
-    int parity = parity0;
+    if (nsteps == 0) return RMHDLB_OK;
+    rc = batch_table(B);
+    if (rc != RMHDLB_OK) return rc;
+    // an instance's tuning or the batch's shape may have changed the grid since the capture
+    if (!(batch_geom(B) == B->graph_geom)) {
+        drop_graphs(B);
+        B->graph_geom = batch_geom(B);
+    }
+    int parity = B->ctx[0]->cur;
     int64_t left = nsteps;
     if (parity == 1) {
         if (batch_launch(B, 1) != hipSuccess) return RMHDLB_EDEVICE;
         parity = 0;
         --left;
     }
-    if (left >= 2 && (!B->exec || B->graph_px != B->px)) capture_graph(B);
+    if (left >= GRAPH_LONG && !B->exec_long) B->exec_long = capture_steps(B, GRAPH_LONG);
+    while (left >= GRAPH_LONG && B->exec_long) {
+        if (hipGraphLaunch(B->exec_long, B->stream) != hipSuccess) return RMHDLB_EDEVICE;
+        left -= GRAPH_LONG;
+    }
+    if (left >= 2 && !B->exec_pair) B->exec_pair = capture_steps(B, 2);
     while (left >= 2) {
-        if (B->exec) {
-            if (hipGraphLaunch(B->exec, B->stream) != hipSuccess) return RMHDLB_EDEVICE;
+        if (B->exec_pair) {
+            if (hipGraphLaunch(B->exec_pair, B->stream) != hipSuccess) return RMHDLB_EDEVICE;
         } else if (batch_launch(B, 0) != hipSuccess || batch_launch(B, 1) != hipSuccess) {
             return RMHDLB_EDEVICE;
         }
@@ -916,35 +1034,73 @@ int rmhdlb_batch_step(rmhdlb_batch* B, int64_t nsteps) {
     return RMHDLB_OK;
 }
 
-int rmhdlb_batch_autotune(rmhdlb_batch* B, int32_t* px_out) {
-    if (!B) return RMHDLB_EINVAL;
-    const int parity = B->ctx[0]->cur;
-    for (rmhdlb_ctx* C : B->ctx)
-        if (C->cur != parity) return RMHDLB_EINVAL;
-    const int pxs[3] = {64, 32, 16};
-    float best_ms = 1e30f;
-    int best = 64;
-    for (int pi = 0; pi < 3; ++pi) {
-        B->px = pxs[pi];
-        int rc = batch_table(B);
-        if (rc != RMHDLB_OK) return rc;
-        float ms = 0.0f;
-        rc = time_ms(B->stream, 3, [&]() { return batch_launch(B, parity); }, &ms);
-        if (rc != RMHDLB_OK) return rc;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = pxs[pi];
-        }
-    }
-    B->px = best;
-    if (px_out) *px_out = best;
+int rmhdlb_batch_set_tuning(rmhdlb_batch* B, int32_t px, int32_t yw, int32_t waves) {
+    if (!B || (px != 128 && px != 64 && px != 32 && px != 16) || yw < 1 || yw > 8 || (waves != 2 && waves != 3))
+        return RMHDLB_EINVAL;
+    if (waves == 3 && B->storage != RMHDLB_STORE_F32) return RMHDLB_EINVAL;
+    B->px = px;
+    B->yw = yw;
+    B->waves = waves;
     return RMHDLB_OK;
 }
 
-int64_t rmhdlb_state_len(const rmhdlb_ctx* C) { return C ? (int64_t)rmhd::NSTATE * C->K.N : -1; }
+int rmhdlb_batch_autotune(rmhdlb_batch* B, int32_t* px_out, int32_t* yw_out, int32_t* waves_out) {
+    if (!B) return RMHDLB_EINVAL;
+    int rc = check_batch_state(B);
+    if (rc != RMHDLB_OK) return rc;
+    const int parity = B->ctx[0]->cur;
+    BatchKey key;
+    key.first = B->storage;
+    for (rmhdlb_ctx* C : B->ctx) key.second.emplace_back(C->K.nx, C->K.ny, C->K.nz);
+    BatchShape best{64, 1, 2};
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mutex);
+        auto it = g_batch_cache.find(key);
+        if (it != g_batch_cache.end()) {
+            best = it->second;
+            cached = true;
+        }
+    }
+    if (!cached) {
+        // tiles px x (128 / px) yw: 64x2, 32x4, 16x8, 64x4, 32x8, 128x2, 16x16, 64x8, times the
+        // occupancy variants of the storage type
+        const BatchShape shapes[8] = {{64, 1, 0}, {32, 1, 0}, {16, 1, 0}, {64, 2, 0},
+                                      {32, 2, 0}, {128, 2, 0}, {16, 2, 0}, {64, 4, 0}};
+        float best_ms = 1e30f;
+        for (const BatchShape& sh : shapes)
+            for (int waves : {2, 3}) {
+                if (waves == 3 && B->storage != RMHDLB_STORE_F32) continue;
+                B->px = sh.px;
+                B->yw = sh.yw;
+                B->waves = waves;
+                rc = batch_table(B);
+                if (rc != RMHDLB_OK) return rc;
+                float ms = 0.0f;
+                rc = time_ms(B->stream, 3, [&]() { return batch_launch(B, parity); }, &ms);
+                if (rc != RMHDLB_OK) return rc;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = BatchShape{sh.px, sh.yw, waves};
+                }
+            }
+        std::lock_guard<std::mutex> g(g_tune_mutex);
+        g_batch_cache[key] = best;
+    }
+    B->px = best.px;
+    B->yw = best.yw;
+    B->waves = best.waves;
+    if (px_out) *px_out = best.px;
+    if (yw_out) *yw_out = best.yw;
+    if (waves_out) *waves_out = best.waves;
+    return RMHDLB_OK;
+}
+
+int64_t rmhdlb_state_len(const rmhdlb_ctx* C) { return C ? (int64_t)rmhd::state_arrays(C->K) * C->K.N : -1; }
 
 int rmhdlb_get_state(rmhdlb_ctx* C, double* dst) {
     if (!C || !dst) return RMHDLB_EINVAL;
+    if (!C->has_state) return RMHDLB_ESTATE;
     hipError_t e = RMHD_DISPATCH(C, launch_export)(C->sb[C->cur], dst, C->K, C->stream);
     if (e != hipSuccess || hipStreamSynchronize(C->stream) != hipSuccess) return RMHDLB_EDEVICE;
     return RMHDLB_OK;
@@ -954,6 +1110,7 @@ int rmhdlb_set_state(rmhdlb_ctx* C, const double* src) {
     if (!C || !src) return RMHDLB_EINVAL;
     hipError_t e = RMHD_DISPATCH(C, launch_import)(src, C->sb[C->cur], C->K, C->stream);
     if (e != hipSuccess || hipStreamSynchronize(C->stream) != hipSuccess) return RMHDLB_EDEVICE;
+    C->has_state = true;
     return RMHDLB_OK;
 }
 

@@ -81,6 +81,8 @@ struct Consts {
     double slope;        // weight of the limited slope in a face value: 1/2 (MUSCL) or (1 - cour)/2 (Lax-Wendroff)
     int coll;            // f collision: 0 explicit, 1 the printed semi-implicit form
     int flux;            // face values: 0 MUSCL, 1 limited Lax-Wendroff
+    int bprev;           // 1: the previous step's B in the recovery and f_eq; the field block then holds
+                         // E_prev[3] and B_prev[3] (else E_prev[3] only)
     // external force density (3 arrays of N, cell order) and its gate: on while
     // the previous step's largest |beta| (*vmax_prev) is below fgate (<= 0: always)
     int forced;

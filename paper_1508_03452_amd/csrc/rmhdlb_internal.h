@@ -94,13 +94,19 @@ __device__ __forceinline__ double block_max_value(double v) {
 
 int num_tiles(const Consts& K);
 
+// Arrays of the raw (interface) state: F[19], G[19], h*[25], E_prev[3], and
+// B_prev[3] with the previous-B reading.
+__host__ __device__ inline int state_arrays(const Consts& K) { return NSTATE + (K.bprev ? 3 : 0); }
+
 // Launch shape of the fused step: z-planes walked per block, the tile width
-// along x (64, 32 or 16 cells; the tile has 128 cells) and the number of
-// blocks that walk a column's chunk of zg * zb planes interleaved.
+// along x (64, 32 or 16 cells; a row group has 128 cells), the number of
+// blocks that walk a column's chunk of zg * zb planes interleaved, and the
+// row groups per block stacked along y.
 struct StepTuning {
     int zb;
     int px;
     int zg = 1;
+    int yw = 1;
 };
 
 // One instance of a batched step: its constants, both state buffers (cell
@@ -111,7 +117,7 @@ struct BatchInst {
     void* dist[2];
     void* efield[2];
     double* faceB;
-    int tiles_x, ncol, zb, nblk;
+    int tiles_x, ncol, zb, yw, nblk;
     int64_t blk0;
     int64_t face0;
 };
@@ -198,12 +204,13 @@ hipError_t launch_face_b(const StateBuf& src, const Consts& K, double* faceB, hi
 // Launch geometry of the fused step for a tile width px, zb planes per block
 // and zg blocks per column and chunk of zg * zb planes: tiles along x,
 // columns, blocks.
-void step_geometry(const Consts& K, int px, int zb, int zg, int& tiles_x, int& ncol, int& nblk);
+void step_geometry(const Consts& K, int px, int zb, int zg, int yw, int& tiles_x, int& ncol, int& nblk);
 // One batched step (face pass of the instances that need it, then the fused
-// step of all) reading buffer `parity` of every instance.
+// step of all) reading buffer `parity` of every instance; px the tile width
+// (128, 64, 32, 16), waves the occupancy variant (FP32: 2 or 3).
 template <typename TS>
-hipError_t launch_batch(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face, int px, int parity,
-                        hipStream_t s);
+hipError_t launch_batch(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face, int px, int waves,
+                        int parity, hipStream_t s);
 template <typename TS>
 hipError_t launch_guess_samples(const StateBuf& src, const Consts& K, double* faceB, int ns, double* F, double* T,
                                 double* part, double* result, hipStream_t s);

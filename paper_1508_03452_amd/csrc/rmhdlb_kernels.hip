@@ -186,13 +186,12 @@ struct Macro : CellSol {
 };
 
 // Fluid tensor T_fl = T - T_EM of the recovery: E_f = T_fl^00, S = T_fl^0a,
-// Pi = T_fl^ab (xx, yy, zz, xy, xz, yz), with E_prev and this step's B.
-__device__ __forceinline__ void fluid_tensor(const Consts& K, const CellSol& M, double& Ef, double S[3],
-                                             double Pi[6]) {
-    // fluid tensor with E_prev and this step's B
+// Pi = T_fl^ab (xx, yy, zz, xy, xz, yz), with E_prev and the recovery's B
+// (this step's, or with the previous-B reading the previous step's).
+__device__ __forceinline__ void fluid_tensor(const Consts& K, const CellSol& M, const double (&B)[3], double& Ef,
+                                             double S[3], double Pi[6]) {
     const double c = K.c, c2 = c * c;
     const double* E = M.Ep;
-    const double* B = M.B;
     const double E2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2];
     const double B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
     const double U = 0.5 * (E2 + c2 * B2);
@@ -250,14 +249,16 @@ __device__ __forceinline__ double guess_lambda(const GuessTables* __restrict__ g
 
 // Recovery and the Ohm-coupled E, J of one cell from its moments (M.T00,
 // M.T0, M.Tab, M.N0, M.Epr, M.B, M.Ep, M.rho_g): fills eps, p, n, gam, beta,
-// E, J, iters, fallback, ok.  With a guess mode every lane of the wavefront
-// must call it together.
+// E, J, iters, fallback, ok.  Brec is the B of the recovery's T_EM (M.B, or
+// the previous step's B); the Ohm solve always takes M.B.  With a guess mode
+// every lane of the wavefront must call it together.
 template <int GM = GUESS_NONE>
-__device__ __forceinline__ void solve_cell(const Consts& K, CellSol& M, const GuessTables* __restrict__ gt = nullptr) {
+__device__ __forceinline__ void solve_cell(const Consts& K, CellSol& M, const double (&Brec)[3],
+                                           const GuessTables* __restrict__ gt = nullptr) {
     const double c = K.c, c2 = c * c;
     const double* B = M.B;
     double Ef, S[3], Pi[6];
-    fluid_tensor(K, M, Ef, S, Pi);
+    fluid_tensor(K, M, Brec, Ef, S, Pi);
     double lam;
     if constexpr (GM == GUESS_NONE) {
         M.iters = recover(Ef, S, Pi, lam, M.beta);
@@ -407,7 +408,14 @@ __device__ __forceinline__ void macroscopic(const TS* __restrict__ src, const TE
                (ld(e2, nb.at(0, 0, 1)) - ld(e2, nb.at(0, 0, -1))));
 
     if (K.divb) apply_face_b(K, faceB, x, y, z, M.B);
-    solve_cell<GM>(K, M, gt);
+    if (K.bprev) {
+        double Bp[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Bp[a] = ld(esrc + (int64_t)(3 + a) * K.stride + cell, 0);
+        solve_cell<GM>(K, M, Bp, gt);
+    } else {
+        solve_cell<GM>(K, M, M.B, gt);
+    }
 }
 
 // f_eq of Eq. Dis_fun_EM in normalised variables (F = (c_t/c_0)^2 f), with
@@ -552,7 +560,9 @@ __device__ __forceinline__ V pair_sum(V v) {
 
 // VR: the alternative readings, bit 0 the printed semi-implicit f collision
 // of Eq. rlb, f' = (f + omega f_eq) / (1 + omega) (else explicit, Reading
-// R4); bit 1 the limited Lax-Wendroff face values (else MUSCL, Reading R2).
+// R4); bit 1 the limited Lax-Wendroff face values (else MUSCL, Reading R2);
+// bit 2 the external force; bit 3 the previous step's B in the recovery and
+// f_eq (else this step's, Reading R10), carried in the field block.
 template <bool NT, typename TS, typename TE, typename V, int GM, int VR = 0>
 __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* __restrict__ se, TS* __restrict__ dd,
                                           TE* __restrict__ de, const double* __restrict__ faceB,
@@ -710,11 +720,19 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
     M.rho = (double)pair_sum(Hv[12] + hs);
     M.rho_g = K.eps0 * K.inv_2dx * pair_sum(gpart);
     if (K.divb) apply_face_b(K, faceB, x, y, z, M.B);
-    solve_cell<GM>(K, M, gt);
+    FeqCellT<V> fe;
+    if constexpr ((VR & 8) != 0) {
+        double Bp[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Bp[a] = ld(se + (int64_t)(3 + a) * S + cell, 0);
+        solve_cell<GM>(K, M, Bp, gt);
+        fe.setup(M.eps, M.p, M.gam, M.beta, M.Ep, Bp, K.c, K.eps0);
+    } else {
+        solve_cell<GM>(K, M, M.B, gt);
+        fe.setup(M.eps, M.p, M.gam, M.beta, M.Ep, M.B, K.c, K.eps0);
+    }
 
     // collisions and stores (new deviations)
-    FeqCellT<V> fe;
-    fe.setup(M.eps, M.p, M.gam, M.beta, M.Ep, M.B, K.c, K.eps0);
     const V rate = (V)(M.gam * K.inv_tau);
     const V wg = (V)K.wg, inv1wg = (V)(1.0 / (1.0 + K.wg));
     const V ng = (V)(M.n * M.gam);
@@ -775,13 +793,17 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
     if (h == 0) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) put(de + (int64_t)a * S + cell, M.E[a]);
+    } else if constexpr ((VR & 8) != 0) {  // this step's coupling B is the next one's previous B
+#pragma unroll
+        for (int a = 0; a < 3; ++a) put(de + (int64_t)(3 + a) * S + cell, M.B[a]);
     }
 }
 
 // ------------------------------------------------------------------ kernels
 
-// One block owns a PXT x (128 / PXT) column of cells (two lanes per cell)
-// and walks zb z-planes.  A chunk of zg * zb planes is shared by zg blocks
+// One block owns a PXT x (128 / PXT) group of rows of cells (two lanes per
+// cell), yw such groups stacked along y (a tile of PXT x (128 / PXT) yw
+// cells), and walks zb z-planes, the yw groups of a plane one after another.  A chunk of zg * zb planes is shared by zg blocks
 // per column: block r of the zg takes planes r, r + zg, r + 2 zg, ... of the
 // chunk, so that the zg blocks of a column run at neighbouring planes at the
 // same time and the z-neighbour planes of the stencil are fetched once into
@@ -796,24 +818,28 @@ template <bool NT, typename TS, typename TE, typename V, int GM, int PXT, int VR
 __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE* __restrict__ se,
                                             TS* __restrict__ dd, TE* __restrict__ de,
                                             const double* __restrict__ faceB, const GuessTables* __restrict__ gt,
-                                            const Consts& K, int tiles_x, int ncol, int zb, int zg, int b) {
+                                            const Consts& K, int tiles_x, int ncol, int zb, int zg, int yw, int b) {
     constexpr int PYT = 128 / PXT;
     const int per = ncol * zg, zc = b / per, r = b % per;
     const int col = r / zg, zoff = r % zg;
     const int tx = col % tiles_x, ty = col / tiles_x;
-    // cell c of the tile is lane c % 32 (h = 0) and lane c % 32 + 32 (h = 1) of wavefront c / 32
+    // cell c of a row group is lane c % 32 (h = 0) and lane c % 32 + 32 (h = 1) of wavefront c / 32
     const int lane = threadIdx.x & 63;
     const int c = (threadIdx.x >> 6) * 32 + (lane & 31), h = lane >> 5;
-    int x = tx * PXT + (c % PXT), y = ty * PYT + c / PXT;
-    const bool active = x < K.nx && y < K.ny;
+    const int xr = tx * PXT + (c % PXT);
+    int x = xr;
+    const int ybase = ty * PYT * yw + c / PXT;
     // with the force every lane stays (the wavefront's largest |beta| is
     // reduced over all 64 lanes)
     constexpr bool all_lanes = GM != GUESS_NONE || (VR & 4) != 0;
+    // row groups of this lane that lie inside the grid (the later groups are further along y)
+    int ng = yw;
+    if (ybase >= K.ny) ng = 0;
+    else if (ybase + (yw - 1) * PYT >= K.ny) ng = (K.ny - 1 - ybase) / PYT + 1;
     if constexpr (!all_lanes) {
-        if (!active) return;  // both lanes of a pair leave together
+        if (x >= K.nx || ng == 0) return;  // both lanes of a pair leave together
     } else {
         x = min(x, K.nx - 1);
-        y = min(y, K.ny - 1);
     }
     const int z0 = zc * zb * zg, z1 = min(K.nz, z0 + zb * zg);
     double bmax = 0.0;
@@ -825,13 +851,18 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
     // 7 out of the FP64 one.  FP32 does not spill and keeps them (recomputing
     // them there measured 6 % slower).
     constexpr bool opaque = sizeof(TS) != 4;
+    const int groups = all_lanes ? yw : ng;
     for (int z = z0 + zoff; z < z1; z += zg) {
-        int xp = x, yp = y, hp = h;
-        if constexpr (opaque) asm volatile("" : "+v"(xp), "+v"(yp), "+v"(hp));
-        const int cell = xp + K.nx * (yp + K.ny * z);
-        const Nbr nb = make_nbr<true>(K, xp, yp, z);
-        pair_cell<NT, TS, TE, V, GM, VR>(sd, se, dd, de, faceB, gt, K, cell, nb, hp, xp, yp, z,
-                                         all_lanes ? active : true, bmax);
+        for (int j = 0; j < groups; ++j) {
+            const int yj = ybase + j * PYT;
+            const bool active = xr < K.nx && yj < K.ny;
+            int xp = x, yp = all_lanes ? min(yj, K.ny - 1) : yj, hp = h;
+            if constexpr (opaque) asm volatile("" : "+v"(xp), "+v"(yp), "+v"(hp));
+            const int cell = xp + K.nx * (yp + K.ny * z);
+            const Nbr nb = make_nbr<true>(K, xp, yp, z);
+            pair_cell<NT, TS, TE, V, GM, VR>(sd, se, dd, de, faceB, gt, K, cell, nb, hp, xp, yp, z,
+                                             all_lanes ? active : true, bmax);
+        }
     }
     if constexpr ((VR & 4) != 0) {
 #pragma unroll
@@ -845,10 +876,10 @@ __global__ __launch_bounds__(PTPB, (fused_waves<TS, GM>())) void k_fused_step(co
                                                         TS* __restrict__ dd, TE* __restrict__ de,
                                                         const double* __restrict__ faceB,
                                                         const GuessTables* __restrict__ gt, Consts K,
-                                                        int tiles_x, int ncol, int zb, int zg, int nblk) {
+                                                        int tiles_x, int ncol, int zb, int zg, int yw, int nblk) {
     const int b = tile_of_block(nblk);
     if (b >= nblk) return;  // uniform over the block
-    fused_block<NT, TS, TE, V, GM, PXT, VR>(sd, se, dd, de, faceB, gt, K, tiles_x, ncol, zb, zg, b);
+    fused_block<NT, TS, TE, V, GM, PXT, VR>(sd, se, dd, de, faceB, gt, K, tiles_x, ncol, zb, zg, yw, b);
 }
 
 // Index of the instance whose range [first[i], first[i + 1]) holds v (first
@@ -869,17 +900,19 @@ __device__ __forceinline__ int find_instance(int ninst, int64_t v, Get first) {
 // Batched step: the blocks of every instance in one launch.  Block b is
 // mapped XCD-aware over the whole batch, then to its instance by the prefix
 // table of block counts, so neighbouring tiles of one instance still share
-// an XCD.  parity selects which of each instance's buffers is read.
-template <bool NT, typename TS, typename TE, typename V, int PXT>
-__global__ __launch_bounds__(PTPB, (fused_waves<TS, 0>())) void k_fused_batch(const BatchInst* __restrict__ I, int ninst,
-                                                         int total, int parity) {
+// an XCD.  parity selects which of each instance's buffers is read.  WV:
+// waves per SIMD the kernel is compiled for (the occupancy the batch tuner
+// sweeps).
+template <bool NT, typename TS, typename TE, typename V, int PXT, int WV>
+__global__ __launch_bounds__(PTPB, WV) void k_fused_batch(const BatchInst* __restrict__ I, int ninst, int total,
+                                                          int parity) {
     const int b = tile_of_block(total);
     if (b >= total) return;
     const int i = find_instance(ninst, b, [&](int j) { return I[j].blk0; });
     const BatchInst& B = I[i];
     fused_block<NT, TS, TE, V, GUESS_NONE, PXT>(
         (const TS*)B.dist[parity], (const TE*)B.efield[parity], (TS*)B.dist[1 - parity], (TE*)B.efield[1 - parity],
-        B.faceB, nullptr, B.K, B.tiles_x, B.ncol, B.zb, 1, (int)(b - B.blk0));
+        B.faceB, nullptr, B.K, B.tiles_x, B.ncol, B.zb, 1, B.yw, (int)(b - B.blk0));
 }
 
 // B of Eq. Cal_B at a cell from the streamed h (population order, FP64).
@@ -1218,6 +1251,9 @@ __global__ __launch_bounds__(TPB) void k_init_ghost(FacePtrs in, Consts K, TS* _
         dd[(int64_t)(OFF_H + QH) * K.stride + g] = static_cast<TS>(0.0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) de[(int64_t)a * K.stride + g] = static_cast<TE>(E[a]);
+        if (K.bprev)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) de[(int64_t)(3 + a) * K.stride + g] = static_cast<TE>(Bv[a]);
     }
 }
 
@@ -1314,13 +1350,16 @@ __global__ __launch_bounds__(TPB) void k_init_state(InPtrs in, Consts K, int til
     dst[(int64_t)(OFF_H + QH) * K.stride + cell] = static_cast<TS>(rho);
 #pragma unroll
     for (int a = 0; a < 3; ++a) edst[(int64_t)a * K.stride + cell] = static_cast<TE>(Ep[a]);
+    if (K.bprev)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) edst[(int64_t)(3 + a) * K.stride + cell] = static_cast<TE>(Bv[a]);
 }
 
 // Raw state conversion to / from the FP64 interface layout (shifts added back).
 template <typename TS, typename TE>
 __global__ void k_export(const TS* __restrict__ s, const TE* __restrict__ se, double* __restrict__ d, Consts K) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= K.N * NSTATE) return;
+    if (i >= K.N * state_arrays(K)) return;
     const int64_t a = i / K.N, cell = i - a * K.N;
     if (a < OFF_E) {
         double v;
@@ -1339,7 +1378,7 @@ __global__ void k_export(const TS* __restrict__ s, const TE* __restrict__ se, do
 template <typename TS, typename TE>
 __global__ void k_import(const double* __restrict__ s, TS* __restrict__ d, TE* __restrict__ de, Consts K) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= K.N * NSTATE) return;
+    if (i >= K.N * state_arrays(K)) return;
     const int64_t a = i / K.N, cell = i - a * K.N;
     if (a < OFF_E) {
         if (a < OFF_G)
@@ -1371,7 +1410,7 @@ __global__ __launch_bounds__(256) void k_guess_samples(const TS* __restrict__ sr
         Macro M;
         macroscopic<GUESS_NONE>(src, esrc, faceB, nullptr, K, (int)cell, nb, x, y, z, M);
         double Ef, S[3], Pi[6];
-        fluid_tensor(K, M, Ef, S, Pi);
+        fluid_tensor(K, M, M.B, Ef, S, Pi);  // the guess is not offered with the previous-B reading
         double f[6];
         mlp_features(Ef, S, Pi, M.N0, f);
         const double t0 = M.eps / Ef;
@@ -1419,8 +1458,8 @@ hipError_t launch_face_b(const StateBuf& src, const Consts& K, double* faceB, hi
     return hipGetLastError();
 }
 
-void step_geometry(const Consts& K, int px, int zb, int zg, int& tiles_x, int& ncol, int& nblk) {
-    const int py = 128 / px;
+void step_geometry(const Consts& K, int px, int zb, int zg, int yw, int& tiles_x, int& ncol, int& nblk) {
+    const int py = 128 / px * yw;
     tiles_x = (K.nx + px - 1) / px;
     ncol = tiles_x * ((K.ny + py - 1) / py);
     nblk = ncol * zg * ((K.nz + zg * zb - 1) / (zg * zb));
@@ -1428,14 +1467,14 @@ void step_geometry(const Consts& K, int px, int zb, int zg, int& tiles_x, int& n
 
 template <typename TS, int GM, int PXT, int VR = 0>
 static void launch_fused(const TS* sd, const void* se, TS* dd, void* de, double* faceB, const GuessTables* gt,
-                         const Consts& K, int zb, int zg, hipStream_t s) {
+                         const Consts& K, int zb, int zg, int yw, hipStream_t s) {
     using TE = typename StoreTypes<TS>::E;
     using V = typename StoreTypes<TS>::V;
     int tx, ncol, nblk;
-    step_geometry(K, PXT, zb, zg, tx, ncol, nblk);
+    step_geometry(K, PXT, zb, zg, yw, tx, ncol, nblk);
     const int grid = ((nblk + 7) / 8) * 8;
     hipLaunchKernelGGL((k_fused_step<true, TS, TE, V, GM, PXT, VR>), dim3(grid), dim3(PTPB), 0, s, sd, (const TE*)se, dd,
-                       (TE*)de, (const double*)faceB, gt, K, tx, ncol, zb, zg, nblk);
+                       (TE*)de, (const double*)faceB, gt, K, tx, ncol, zb, zg, yw, nblk);
 }
 
 template <typename TS>
@@ -1450,53 +1489,78 @@ hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K
     const TS* sd = (const TS*)src.dist;
     TS* dd = (TS*)dst.dist;
     const int vr = (K.coll ? 1 : 0) | (K.flux ? 2 : 0);
-    if (K.forced) {  // the external force: 64-wide tiles, MUSCL faces, no guess
+    const int yw = tune.yw > 1 && !K.forced ? tune.yw : 1;  // the force's partial maxima are sized for yw = 1
+    const void* se = src.efield;
+    void* de = dst.efield;
+    if (K.bprev) {  // the previous-B reading: 64-wide tiles, default collision and faces, no guess or force
+        if (gt || vr || K.forced) return hipErrorNotSupported;
+        launch_fused<TS, GUESS_NONE, 64, 8>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
+    } else if (K.forced) {  // the external force: 64-wide tiles, MUSCL faces, no guess
         if (gt || K.flux) return hipErrorNotSupported;
         if (K.coll)
-            launch_fused<TS, GUESS_NONE, 64, 5>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, 1, s);
+            launch_fused<TS, GUESS_NONE, 64, 5>(sd, se, dd, de, faceB, gt, K, zb, 1, 1, s);
         else
-            launch_fused<TS, GUESS_NONE, 64, 4>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, 1, s);
+            launch_fused<TS, GUESS_NONE, 64, 4>(sd, se, dd, de, faceB, gt, K, zb, 1, 1, s);
         int tx, ncol, nblk;
-        step_geometry(K, 64, zb, 1, tx, ncol, nblk);
+        step_geometry(K, 64, zb, 1, 1, tx, ncol, nblk);
         hipLaunchKernelGGL(k_vmax_reduce, dim3(1), dim3(TPB), 0, s, K.vmax_part, (int64_t)nblk * (PTPB / 64),
                            const_cast<double*>(K.vmax_prev));
     } else if (vr) {  // the alternative readings: 64-wide tiles, no guess
         if (gt) return hipErrorNotSupported;
         if (vr == 1)
-            launch_fused<TS, GUESS_NONE, 64, 1>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, zg, s);
+            launch_fused<TS, GUESS_NONE, 64, 1>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
         else if (vr == 2)
-            launch_fused<TS, GUESS_NONE, 64, 2>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, zg, s);
+            launch_fused<TS, GUESS_NONE, 64, 2>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
         else
-            launch_fused<TS, GUESS_NONE, 64, 3>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, zg, s);
+            launch_fused<TS, GUESS_NONE, 64, 3>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
     } else if (gt)  // the guess path is built for 64-wide tiles only
-        launch_fused<TS, GUESS_PAIR, 64>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, zg, s);
+        launch_fused<TS, GUESS_PAIR, 64>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
     else if (tune.px == 32)
-        launch_fused<TS, GUESS_NONE, 32>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, zg, s);
+        launch_fused<TS, GUESS_NONE, 32>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
     else if (tune.px == 16)
-        launch_fused<TS, GUESS_NONE, 16>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, zg, s);
+        launch_fused<TS, GUESS_NONE, 16>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
     else
-        launch_fused<TS, GUESS_NONE, 64>(sd, src.efield, dd, dst.efield, faceB, gt, K, zb, zg, s);
+        launch_fused<TS, GUESS_NONE, 64>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
     return hipGetLastError();
 }
 
-template <typename TS>
-hipError_t launch_batch(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face, int px, int parity,
-                        hipStream_t s) {
+template <typename TS, int PXT, int WV>
+static void launch_batch_fused(const BatchInst* dev, int ninst, int total_blocks, int parity, hipStream_t s) {
     using TE = typename StoreTypes<TS>::E;
     using V = typename StoreTypes<TS>::V;
+    const int grid = ((total_blocks + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_fused_batch<true, TS, TE, V, PXT, WV>), dim3(grid), dim3(PTPB), 0, s, dev, ninst,
+                       total_blocks, parity);
+}
+
+template <typename TS, int WV>
+static void launch_batch_px(const BatchInst* dev, int ninst, int total_blocks, int px, int parity, hipStream_t s) {
+    if (px == 128)
+        launch_batch_fused<TS, 128, WV>(dev, ninst, total_blocks, parity, s);
+    else if (px == 32)
+        launch_batch_fused<TS, 32, WV>(dev, ninst, total_blocks, parity, s);
+    else if (px == 16)
+        launch_batch_fused<TS, 16, WV>(dev, ninst, total_blocks, parity, s);
+    else
+        launch_batch_fused<TS, 64, WV>(dev, ninst, total_blocks, parity, s);
+}
+
+template <typename TS>
+hipError_t launch_batch(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face, int px, int waves,
+                        int parity, hipStream_t s) {
     if (total_face > 0)
         hipLaunchKernelGGL((k_face_b_batch<TS>), dim3((unsigned)((total_face + 255) / 256)), dim3(256), 0, s, dev,
                            ninst, total_face, parity);
-    const int grid = ((total_blocks + 7) / 8) * 8;
-    if (px == 32)
-        hipLaunchKernelGGL((k_fused_batch<true, TS, TE, V, 32>), dim3(grid), dim3(PTPB), 0, s, dev, ninst,
-                           total_blocks, parity);
-    else if (px == 16)
-        hipLaunchKernelGGL((k_fused_batch<true, TS, TE, V, 16>), dim3(grid), dim3(PTPB), 0, s, dev, ninst,
-                           total_blocks, parity);
-    else
-        hipLaunchKernelGGL((k_fused_batch<true, TS, TE, V, 64>), dim3(grid), dim3(PTPB), 0, s, dev, ninst,
-                           total_blocks, parity);
+    // FP32 storage (the sweep's) is built for two and three waves per SIMD;
+    // FP64 and FP16 for their single-instance counts
+    if constexpr (sizeof(TS) == 4) {
+        if (waves == 3)
+            launch_batch_px<TS, 3>(dev, ninst, total_blocks, px, parity, s);
+        else
+            launch_batch_px<TS, 2>(dev, ninst, total_blocks, px, parity, s);
+    } else {
+        launch_batch_px<TS, fused_waves<TS, 0>()>(dev, ninst, total_blocks, px, parity, s);
+    }
     return hipGetLastError();
 }
 
@@ -1569,7 +1633,7 @@ hipError_t launch_init(const InPtrs& in, const Consts& K, double* scr, const Sta
 template <typename TS>
 hipError_t launch_export(const StateBuf& src, double* dst, const Consts& K, hipStream_t s) {
     using TE = typename StoreTypes<TS>::E;
-    const int64_t total = K.N * NSTATE;
+    const int64_t total = K.N * state_arrays(K);
     const int64_t blocks = (total + 255) / 256;
     hipLaunchKernelGGL((k_export<TS, TE>), dim3((unsigned)blocks), dim3(256), 0, s, (const TS*)src.dist,
                        (const TE*)src.efield, dst, K);
@@ -1579,7 +1643,7 @@ hipError_t launch_export(const StateBuf& src, double* dst, const Consts& K, hipS
 template <typename TS>
 hipError_t launch_import(const double* src, const StateBuf& dst, const Consts& K, hipStream_t s) {
     using TE = typename StoreTypes<TS>::E;
-    const int64_t total = K.N * NSTATE;
+    const int64_t total = K.N * state_arrays(K);
     const int64_t blocks = (total + 255) / 256;
     hipLaunchKernelGGL((k_import<TS, TE>), dim3((unsigned)blocks), dim3(256), 0, s, src, (TS*)dst.dist,
                        (TE*)dst.efield, K);
@@ -1606,7 +1670,7 @@ hipError_t launch_guess_samples(const StateBuf& src, const Consts& K, double* fa
                                            const GuessTables*, hipStream_t);                                          \
     template hipError_t launch_init<TS>(const InPtrs&, const Consts&, double*, const StateBuf&, hipStream_t);         \
     template hipError_t launch_ghost<TS>(const FacePtrs&, const Consts&, const StateBuf&, hipStream_t);               \
-    template hipError_t launch_batch<TS>(const BatchInst*, int, int, int64_t, int, int, hipStream_t);                 \
+    template hipError_t launch_batch<TS>(const BatchInst*, int, int, int64_t, int, int, int, hipStream_t);            \
     template hipError_t launch_guess_samples<TS>(const StateBuf&, const Consts&, double*, int, double*, double*,      \
                                                  double*, double*, hipStream_t);                                      \
     template hipError_t launch_export<TS>(const StateBuf&, double*, const Consts&, hipStream_t);                      \

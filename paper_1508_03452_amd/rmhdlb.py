@@ -1,8 +1,9 @@
 """Thin ctypes binding of the C ABI in include/rmhdlb.h.
 
 Argument marshalling only: every step of the method runs in the HIP library
-(librmhdlb.so).  PyTorch provides device memory and the stream.  If the
-library is missing this module raises; there is no other code path.
+(librmhdlb.so).  PyTorch provides the device memory (each context's workspace
+is a torch tensor of rmhdlb_workspace_bytes) and the stream.  If the library
+is missing this module raises; there is no other code path.
 """
 import ctypes
 import os
@@ -13,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librmhdlb.so")
 
 RMHDLB_OK, RMHDLB_EINVAL, RMHDLB_ENOMEM, RMHDLB_EDEVICE, RMHDLB_ERECOVERY, RMHDLB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+RMHDLB_ESTATE = -6
 BC = {"periodic": 0, "open": 1, "driven": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 OUT_FIELDS = ("n", "p", "eps", "ux", "uy", "uz", "Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho_c")
@@ -28,7 +30,8 @@ class rmhdlb_params(ctypes.Structure):
         ("tau", ctypes.c_double), ("tau_h", ctypes.c_double), ("alpha", ctypes.c_double),
         ("Gamma", ctypes.c_double), ("sigma", ctypes.c_double), ("nu", ctypes.c_double),
         ("storage", ctypes.c_int32), ("divb_fix", ctypes.c_int32), ("null_band", ctypes.c_int32),
-        ("collision", ctypes.c_int32), ("flux", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+        ("collision", ctypes.c_int32), ("flux", ctypes.c_int32), ("b_prev", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
     ]
 
 
@@ -70,8 +73,8 @@ SYMBOLS = ("rmhdlb_create", "rmhdlb_init_fields", "rmhdlb_step", "rmhdlb_moments
            "rmhdlb_strerror", "rmhdlb_state_len", "rmhdlb_get_state", "rmhdlb_set_state", "rmhdlb_lattice_tables",
            "rmhdlb_set_driven_face", "rmhdlb_train_guess", "rmhdlb_set_guess_weights", "rmhdlb_set_guess",
            "rmhdlb_guess_samples", "rmhdlb_mlp_eval", "rmhdlb_autotune", "rmhdlb_set_tuning", "rmhdlb_set_force",
-           "rmhdlb_batch_create",
-           "rmhdlb_batch_instance", "rmhdlb_batch_step", "rmhdlb_batch_autotune", "rmhdlb_batch_destroy")
+           "rmhdlb_batch_create", "rmhdlb_batch_instance", "rmhdlb_batch_step", "rmhdlb_batch_autotune",
+           "rmhdlb_batch_set_tuning", "rmhdlb_batch_destroy", "rmhdlb_workspace_bytes")
 
 _LIB = None
 
@@ -87,6 +90,8 @@ def load():
     L = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     L.rmhdlb_create.argtypes = [ctypes.POINTER(rmhdlb_params), vp, ctypes.POINTER(vp)]
+    L.rmhdlb_workspace_bytes.argtypes = [ctypes.POINTER(rmhdlb_params)]
+    L.rmhdlb_workspace_bytes.restype = ctypes.c_size_t
     L.rmhdlb_init_fields.argtypes = [vp, ctypes.POINTER(rmhdlb_fields_in)]
     L.rmhdlb_step.argtypes = [vp, ctypes.c_int64]
     L.rmhdlb_moments.argtypes = [vp, ctypes.POINTER(rmhdlb_fields_out), ctypes.POINTER(rmhdlb_diag)]
@@ -108,14 +113,15 @@ def load():
     L.rmhdlb_guess_samples.argtypes = [vp, ctypes.c_int32, _dp, _dp]
     L.rmhdlb_mlp_eval.argtypes = [fp, fp, fp, ctypes.c_int32, fp, fp, fp, vp]
     ip32 = ctypes.POINTER(ctypes.c_int32)
-    L.rmhdlb_autotune.argtypes = [vp, ip32, ip32, ip32]
-    L.rmhdlb_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.rmhdlb_autotune.argtypes = [vp, ip32, ip32, ip32, ip32]
+    L.rmhdlb_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.rmhdlb_set_force.argtypes = [vp, ctypes.POINTER(_dp * 3), ctypes.c_double]
     L.rmhdlb_batch_create.argtypes = [ctypes.POINTER(rmhdlb_params), ctypes.c_int32, vp, ctypes.POINTER(vp)]
     L.rmhdlb_batch_instance.argtypes = [vp, ctypes.c_int32]
     L.rmhdlb_batch_instance.restype = vp
     L.rmhdlb_batch_step.argtypes = [vp, ctypes.c_int64]
-    L.rmhdlb_batch_autotune.argtypes = [vp, ip32]
+    L.rmhdlb_batch_autotune.argtypes = [vp, ip32, ip32, ip32]
+    L.rmhdlb_batch_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.rmhdlb_batch_destroy.argtypes = [vp]
     _LIB = L
     return L
@@ -154,7 +160,25 @@ def make_params(shape, bc=None, storage="f64", **kw):
     P.null_band = int(d.get("null_band", 64))
     P.collision = int(d.get("collision", 0))
     P.flux = int(d.get("flux", 0))
+    P.b_prev = int(d.get("b_prev", 0))
     return P
+
+
+def workspace_bytes(P):
+    """Device bytes a context with parameters P needs (0 for invalid parameters)."""
+    return int(load().rmhdlb_workspace_bytes(ctypes.byref(P)))
+
+
+def attach_workspace(P, torch):
+    """Allocate the context's device memory as a torch tensor and point P at it; returns the tensor (keep it
+    alive as long as the context).  None when P is invalid (rmhdlb_create then reports why)."""
+    nbytes = workspace_bytes(P)
+    if nbytes == 0:
+        return None
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    P.workspace = ctypes.c_void_p(ws.data_ptr())
+    P.workspace_bytes = nbytes
+    return ws
 
 
 def lattice_tables():
@@ -214,9 +238,11 @@ def mlp_eval(w, X, Yt, stream=None):
 
 
 class Solver:
-    """One rmhdlb context on the current torch device and stream.  shape = (nx, ny, nz)."""
+    """One rmhdlb context on the current torch device and stream.  shape = (nx, ny, nz).
+    workspace: "torch" (default) allocates the context's device memory as a torch tensor and passes it to
+    rmhdlb_create; "library" lets the library allocate it."""
 
-    def __init__(self, shape, bc=None, storage="f64", stream=None, _handle=None, **params):
+    def __init__(self, shape, bc=None, storage="f64", stream=None, _handle=None, workspace="torch", **params):
         import torch
         self.torch = torch
         self.shape = tuple(int(v) for v in shape)
@@ -225,9 +251,14 @@ class Solver:
         self.P = make_params(self.shape, bc, storage, **params)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._owned = _handle is None
+        self.workspace = None
         if _handle is not None:   # an instance owned by a Batch
             self._h = ctypes.c_void_p(_handle)
             return
+        if workspace == "torch":
+            self.workspace = attach_workspace(self.P, torch)
+        elif workspace != "library":
+            raise ValueError(f"workspace must be 'torch' or 'library', not {workspace!r}")
         self._h = ctypes.c_void_p()
         _check(load().rmhdlb_create(ctypes.byref(self.P), ctypes.c_void_p(self.stream.cuda_stream),
                                     ctypes.byref(self._h)), "rmhdlb_create")
@@ -238,14 +269,14 @@ class Solver:
         self._h = ctypes.c_void_p()
 
     def autotune(self):
-        """Time the launch shapes and keep the fastest: (px, zb, zg)."""
-        px, zb, zg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(load().rmhdlb_autotune(self._h, ctypes.byref(px), ctypes.byref(zb), ctypes.byref(zg)),
-               "rmhdlb_autotune")
-        return int(px.value), int(zb.value), int(zg.value)
+        """Time the launch shapes and keep the fastest: (px, zb, zg, yw)."""
+        px, zb, zg, yw = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load().rmhdlb_autotune(self._h, ctypes.byref(px), ctypes.byref(zb), ctypes.byref(zg),
+                                      ctypes.byref(yw)), "rmhdlb_autotune")
+        return int(px.value), int(zb.value), int(zg.value), int(yw.value)
 
-    def set_tuning(self, px, zb, zg=1):
-        _check(load().rmhdlb_set_tuning(self._h, int(px), int(zb), int(zg)), "rmhdlb_set_tuning")
+    def set_tuning(self, px, zb, zg=1, yw=1):
+        _check(load().rmhdlb_set_tuning(self._h, int(px), int(zb), int(zg), int(yw)), "rmhdlb_set_tuning")
 
     def __del__(self):
         try:
@@ -370,7 +401,7 @@ class Solver:
     def get_state(self):
         t = self.torch.empty(self.state_len(), dtype=self.torch.float64, device="cuda")
         _check(load().rmhdlb_get_state(self._h, _dptr(t)), "rmhdlb_get_state")
-        return t.reshape((66,) + self.grid)
+        return t.reshape((-1,) + self.grid)
 
     def set_state(self, state):
         t = self._dev_flat(state)
@@ -384,17 +415,21 @@ class Solver:
 
 
 class Batch:
-    """Independent instances stepped together (one launch per step over all of them, captured into a
-    hipGraph on a non-default stream).  specs: list of (shape, bc, params dict)."""
+    """Independent instances stepped together (one launch per step over all of them, replayed from hipGraphs
+    on a non-default stream).  specs: list of (shape, bc, params dict); each instance's device memory is a
+    torch tensor unless workspace="library"."""
 
-    def __init__(self, specs, storage="f32", stream=None):
+    def __init__(self, specs, storage="f32", stream=None, workspace="torch"):
         import torch
         self.torch = torch
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         n = len(specs)
         arr = (rmhdlb_params * n)()
+        self.workspaces = []
         for i, (shape, bc, params) in enumerate(specs):
             arr[i] = make_params(shape, bc, storage, **params)
+            if workspace == "torch":
+                self.workspaces.append(attach_workspace(arr[i], torch))
         self._h = ctypes.c_void_p()
         _check(load().rmhdlb_batch_create(arr, n, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._h)),
                "rmhdlb_batch_create")
@@ -405,9 +440,14 @@ class Batch:
         _check(load().rmhdlb_batch_step(self._h, int(nsteps)), "rmhdlb_batch_step")
 
     def autotune(self):
-        px = ctypes.c_int32()
-        _check(load().rmhdlb_batch_autotune(self._h, ctypes.byref(px)), "rmhdlb_batch_autotune")
-        return int(px.value)
+        """Time the batch's tile shapes and occupancies and keep the fastest: (px, yw, waves)."""
+        px, yw, wv = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load().rmhdlb_batch_autotune(self._h, ctypes.byref(px), ctypes.byref(yw), ctypes.byref(wv)),
+               "rmhdlb_batch_autotune")
+        return int(px.value), int(yw.value), int(wv.value)
+
+    def set_tuning(self, px, yw=1, waves=2):
+        _check(load().rmhdlb_batch_set_tuning(self._h, int(px), int(yw), int(waves)), "rmhdlb_batch_set_tuning")
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -28,7 +28,7 @@ from math import erf, sqrt
 import numpy as np
 
 DEFAULT_PARAMS = dict(dx=1.0, c=1.0, mu0=1.0, tau=1.0, tau_h=0.5, alpha=0.1, Gamma=4.0 / 3.0, sigma=1.0,
-                      nu=27.0 ** 0.5, divb_fix=0, null_band=64, collision=0, flux=0)
+                      nu=27.0 ** 0.5, divb_fix=0, null_band=64, collision=0, flux=0, b_prev=0)
 
 
 @dataclass

@@ -6,10 +6,13 @@ import oracle
 VEC = ("u", "E", "B", "J")
 
 
-def field_errors(ref, got, scale_B):
+def field_errors(ref, got, scale_B, eps_ref=None):
     """Per-field error: max |got - ref| / max(max |ref|, floor).  Floors: c for
-    velocities, the field scale for E, B, J (their natural size in the run)."""
+    velocities, the field scale for E, B, J (their natural size in the run),
+    the energy scale eps_ref (default: max |eps| of ref) for p and eps."""
     errs = {}
+    if eps_ref is None and "eps" in ref:
+        eps_ref = float(np.abs(ref["eps"]).max())
     for k, r in ref.items():
         if k not in got or k in ("n_failed",):
             continue
@@ -18,6 +21,8 @@ def field_errors(ref, got, scale_B):
             floor = 1.0
         elif (k[0] in "EBJ" and len(k) == 2) or k == "rho_c":
             floor = scale_B             # rho_c ~ eps0 div E ~ eps0 c |B| / dx
+        elif k in ("p", "eps") and eps_ref is not None:
+            floor = eps_ref
         else:
             floor = 1e-300
         den = max(np.abs(r).max(), floor)
@@ -26,8 +31,11 @@ def field_errors(ref, got, scale_B):
 
 
 def state_errors(ref, got):
-    """Per-group error of the raw state (F, G, h*, E_prev), relative to each group's max."""
+    """Per-group error of the raw state (F, G, h*, E_prev and, with the previous-B reading, B_prev),
+    relative to each group's max."""
     groups = dict(F=slice(0, 19), G=slice(19, 38), h=slice(38, 63), E=slice(63, 66))
+    if ref.shape[0] == 69:
+        groups["Bp"] = slice(66, 69)
     out = {}
     for k, s in groups.items():
         r, g = ref[s], got[s]

@@ -25,16 +25,19 @@ def _state(s):
 
 
 # zg > 1: interleaved walks, with chunks of zg * zb planes that do not divide
-# nz = 9 (the last chunk is ragged and some walks are empty)
-@pytest.mark.parametrize("px,zb,zg", [(32, 1, 1), (16, 2, 1), (64, 8, 1), (64, 2, 2), (64, 2, 4), (32, 1, 4),
-                                      (64, 16, 2)])
-def test_tile_shapes_give_identical_states(px, zb, zg):
+# nz = 9 (the last chunk is ragged and some walks are empty); yw > 1: row
+# groups stacked along y, with ny = 13 leaving the last tile's groups partly
+# or wholly outside the grid
+@pytest.mark.parametrize("px,zb,zg,yw", [(32, 1, 1, 1), (16, 2, 1, 1), (64, 8, 1, 1), (64, 2, 2, 1), (64, 2, 4, 1),
+                                         (32, 1, 4, 1), (64, 16, 2, 1), (64, 1, 1, 2), (32, 2, 1, 2),
+                                         (16, 1, 1, 4), (64, 4, 2, 4)])
+def test_tile_shapes_give_identical_states(px, zb, zg, yw):
     _torch_cuda()
     w = W.random_state(shape=(70, 13, 9), seed=6, vmax=0.1, Bmag=0.2, Emag=0.02, sigma=3.0,
                        bc=(("open", "open"), ("periodic", "periodic"), ("open", "open")))
     a = run_gpu(w, 0)
     b = run_gpu(w, 0)
-    b.set_tuning(px, zb, zg)
+    b.set_tuning(px, zb, zg, yw)
     a.step(6)
     b.step(6)
     assert np.array_equal(_state(a), _state(b))
@@ -45,11 +48,11 @@ def test_autotune_picks_a_valid_shape_and_keeps_the_state():
     w = W.kh(nx=192, ny=256, v0=0.3, ratio=5.0, sigma=1e3)
     s = run_gpu(w, 2)
     before = _state(s)
-    px, zb, zg = s.autotune()
-    print(f"[batch] autotune kh 192x256x1 -> px {px} zb {zb} zg {zg}", flush=True)
-    assert px in (64, 32, 16) and zb >= 1 and zg == 1   # nz = 1: no interleaved walks
+    px, zb, zg, yw = s.autotune()
+    print(f"[batch] autotune kh 192x256x1 -> px {px} zb {zb} zg {zg} yw {yw}", flush=True)
+    assert px in (64, 32, 16) and zb >= 1 and zg == 1 and yw in (1, 2, 4)   # nz = 1: no interleaved walks
     assert np.array_equal(before, _state(s))   # timing does not advance the state
-    assert s.autotune() == (px, zb, zg)        # cached
+    assert s.autotune() == (px, zb, zg, yw)    # cached
     ref = run_gpu(w, 2)
     s.step(3)
     ref.step(3)
@@ -64,9 +67,9 @@ def test_autotune_3d_with_interleaved_candidates():
                        bc=(("periodic", "periodic"), ("open", "open"), ("open", "open")))
     s = run_gpu(w, 0)
     before = _state(s)
-    px, zb, zg = s.autotune()
-    print(f"[batch] autotune random 64x8x64 -> px {px} zb {zb} zg {zg}", flush=True)
-    assert px in (64, 32, 16) and zb >= 1 and zg in (1, 2, 4) and (zg == 1 or px == 64)
+    px, zb, zg, yw = s.autotune()
+    print(f"[batch] autotune random 64x8x64 -> px {px} zb {zb} zg {zg} yw {yw}", flush=True)
+    assert px in (64, 32, 16) and zb >= 1 and zg in (1, 2, 4) and (zg == 1 or px == 64) and yw == 1
     assert np.array_equal(before, _state(s))
     ref = run_gpu(w, 0)
     s.step(4)
@@ -151,12 +154,73 @@ def test_batch_rejects_mixed_parity_and_autotunes():
     st = torch.cuda.Stream()
     b = _batch(ws, "f32", st)
     before = [_state(s) for s in b.instances]
-    px = b.autotune()
-    print(f"[batch] batch autotune -> px {px}", flush=True)
-    assert px in (64, 32, 16)
+    px, yw, waves = b.autotune()
+    print(f"[batch] batch autotune -> px {px} yw {yw} waves {waves}", flush=True)
+    assert (px, yw) in BATCH_TILES and waves in (2, 3)
     for s, x in zip(b.instances, before):
         assert np.array_equal(_state(s), x)   # timing does not advance the state
+    assert b.autotune() == (px, yw, waves)    # cached
     b.instances[0].step(1)                    # one instance stepped alone: parities differ
-    with pytest.raises(RmhdlbError):
+    from paper_1508_03452_amd.rmhdlb import RMHDLB_ESTATE
+    with pytest.raises(RmhdlbError) as e:
         b.step(1)
+    assert e.value.code == RMHDLB_ESTATE
+    b.close()
+
+
+# the batch tuner's tiles: px x (128 / px) yw cells
+BATCH_TILES = ((64, 1), (32, 1), (16, 1), (64, 2), (32, 2), (128, 2), (16, 2), (64, 4))
+
+
+@pytest.mark.parametrize("px,yw", BATCH_TILES)
+@pytest.mark.parametrize("waves", [2, 3])
+def test_batch_tiles_and_occupancies_match_instances(px, yw, waves):
+    """Every tile shape and occupancy variant of the batched FP32 step gives each instance exactly the
+    state of stepping it alone (uneven slabs with ragged tiles in x and y, and a 3-D open box)."""
+    torch = _torch_cuda()
+    ws = _sweep_workloads(n=4, seed=6)
+    st = torch.cuda.Stream()
+    b = _batch(ws, "f32", st)
+    b.set_tuning(px, yw, waves)
+    b.step(5)
+    st.synchronize()
+    for w, s in zip(ws, b.instances):
+        ref = run_gpu(w, 5, storage="f32")
+        assert np.array_equal(_state(s), _state(ref)), (w.shape, px, yw, waves)
+    b.close()
+
+
+def test_batch_long_graph_replays_match_instances():
+    """131 batched steps from parity 0: two replays of the captured 64-step graph, one of the two-step
+    graph and one eager step, against each instance stepped alone (eager launches)."""
+    torch = _torch_cuda()
+    ws = _sweep_workloads(n=3, seed=7)
+    st = torch.cuda.Stream()
+    b = _batch(ws, "f32", st)
+    b.step(131)
+    st.synchronize()
+    for w, s in zip(ws, b.instances):
+        ref = run_gpu(w, 131, storage="f32")
+        assert np.array_equal(_state(s), _state(ref)), w.shape
+        assert s.moments(fields=())["diag"]["step"] == 131
+    b.close()
+
+
+def test_batch_recaptures_when_an_instance_is_retuned():
+    """The captured graphs hold the launch grid.  Retuning an instance of the batch (its z-walk, which
+    changes its block count) must make the batch capture again: the steps after the retune still equal
+    each instance stepped alone (a stale graph would skip the added blocks)."""
+    torch = _torch_cuda()
+    ws = _sweep_workloads(n=2, seed=8)            # two slabs and the 3-D box (nz = 7) last
+    st = torch.cuda.Stream()
+    b = _batch(ws, "f32", st)
+    b.step(4)                                     # captures the two-step graph with zb = 4
+    b.instances[-1].set_tuning(64, 1)             # zb = 1: seven blocks per column instead of two
+    b.step(4)
+    b.instances[-1].set_tuning(64, 8)
+    b.step(70)                                    # and the long graph with yet another grid
+    st.synchronize()
+    for w, s in zip(ws, b.instances):
+        ref = run_gpu(w, 78, storage="f32")
+        assert np.array_equal(_state(s), _state(ref)), w.shape
     b.close()

@@ -3,14 +3,16 @@
 Plain FP64 path, per-field error = max |gpu - oracle| / max(max |oracle|,
 floor), floors c for u and the run's field scale for E, B, J, rho_c.
 
-Tolerance: 1e-12 at the stated step counts.  For the longer runs the bound is
-max(1e-12, 4 s) per field, where s is the oracle's own sensitivity: the
-difference between two oracle runs whose initial states differ by one ulp
-(relative 2^-52 noise, keeping the workload's symmetry).  No implementation
-can agree with the oracle more closely than the oracle agrees with itself
-under rounding; for the stiff high-sigma and shear-layer runs that floor
-passes 1e-12 after a few hundred steps.  Diagnostics (sums in another order)
-agree to 1e-13 relative.
+Tolerance: 1e-12 at the stated step counts.  For the longer runs the bound
+of a field is 4 s where the oracle's own sensitivity s exceeds 1e-12, else
+1e-12: s is the difference between two oracle runs whose initial states
+differ by one ulp (relative 2^-52 noise, keeping the workload's symmetry).
+No implementation can agree with the oracle more closely than the oracle
+agrees with itself under rounding; for the stiff high-sigma and shear-layer
+runs that floor passes 1e-12 after a few hundred steps.  Floors of the
+per-field error: c for u, the field scale for E, B, J, rho_c, the largest
+eps for p and eps.  Diagnostics (sums in another order) agree to 1e-13
+relative.
 """
 import numpy as np
 import pytest
@@ -63,8 +65,8 @@ def check_case(w, steps, conditioned=False, symmetric=False):
     ctol = 1e-12 * max(1.0, w.ncells * 1e-3)
     if conditioned:
         fs, ss, cs = oracle_sensitivity(w, steps, o, symmetric)
-        ftol = {k: max(TOL, 4 * v) for k, v in fs.items()}
-        stol = {k: max(TOL, 4 * v) for k, v in ss.items()}
+        ftol = {k: 4 * v if v > TOL else TOL for k, v in fs.items()}
+        stol = {k: 4 * v if v > TOL else TOL for k, v in ss.items()}
         # the charge is the sum of the rho_c field: its bound follows from the per-cell one
         rho_den = max(np.abs(mo["rho_c"]).max(), field_scale(w))
         ctol = max(ctol, 4 * cs, ftol["rho_c"] * rho_den * w.ncells)
@@ -229,6 +231,86 @@ def test_printed_collision_limits():
         s.set_guess(True)
     s.step(1)
     assert s.moments(fields=())["diag"]["n_failed"] == 0
+
+
+def test_previous_B_reading_random_3d_ragged_tiles():
+    """The previous step's B in the recovery and f_eq (b_prev = 1, the paper's wording), carried as
+    B_prev in the state: 12 steps of the ragged periodic 3-D state, every state group to 1e-12."""
+    w = W.random_state(shape=(70, 6, 3), seed=2, vmax=0.1, Bmag=0.2, Emag=0.02, sigma=3.0)
+    w.params["b_prev"] = 1
+    check_case(w, 12)
+
+
+def test_previous_B_reading_driven_and_open_faces():
+    """b_prev = 1 with the driven low-z face and open y faces (the ghost planes carry B_prev too)."""
+    w = _driven_case()
+    w.params["b_prev"] = 1
+    check_case(w, 15)
+
+
+def test_previous_B_reading_limits():
+    """The previous-B reading has 64-wide tiles and no learned guess, force or batches."""
+    torch = _torch_cuda()
+    from paper_1508_03452_amd.rmhdlb import Batch, RmhdlbError
+    w = W.random_state(shape=(20, 9, 7), seed=3, vmax=0.05, Bmag=0.2, Emag=0.02, sigma=30.0)
+    w.params["b_prev"] = 1
+    s = run_gpu(w, 0)
+    assert s.state_len() == 69 * w.ncells
+    with pytest.raises(RmhdlbError):
+        s.set_tuning(32, 4)
+    assert s.autotune()[0] == 64
+    with pytest.raises(RmhdlbError):
+        Batch([(w.shape, w.bc, w.params)], storage="f32", stream=torch.cuda.current_stream())
+    with pytest.raises(RmhdlbError):
+        s.set_force(_random_force(w, 5, 0.02), 0.0)
+    s.step(1)
+    assert s.moments(fields=())["diag"]["n_failed"] == 0
+
+
+@pytest.mark.parametrize("nu", [4.5, 27 ** 0.25])
+def test_lattice_nu_other_than_sqrt27(nu):
+    """nu enters the g weights, the g equilibrium's coefficients and the g collision rate
+    nu^2 / (sqrt 27 tau) (Readings R1, R12): a 12-step parity run at nu = 4.5 and at 27^(1/4) (where two
+    g weights are negative; stable over these steps)."""
+    w = W.random_state(shape=(70, 6, 3), seed=2, vmax=0.1, Bmag=0.2, Emag=0.02, sigma=3.0)
+    w.params["nu"] = nu
+    check_case(w, 12)
+
+
+def test_torch_and_library_workspaces_step_identically():
+    """The same run with the device memory allocated by torch (the binding's default: a workspace
+    tensor of rmhdlb_workspace_bytes) and by the library itself: bitwise the same states."""
+    torch = _torch_cuda()
+    from paper_1508_03452_amd.rmhdlb import Solver
+    w = _driven_case()
+    states = []
+    for ws in ("torch", "library"):
+        s = Solver(w.shape, w.bc, workspace=ws, **w.params)
+        assert (s.workspace is not None) == (ws == "torch")
+        s.init_fields(w.fields)
+        s.set_driven_face(w.driven)
+        s.step(9)
+        states.append(s.get_state())
+    assert torch.equal(states[0], states[1])
+
+
+def test_calls_before_the_state_is_set_report_estate():
+    """rmhdlb_step, rmhdlb_moments, rmhdlb_get_state and rmhdlb_autotune before rmhdlb_init_fields (or
+    rmhdlb_set_state) return RMHDLB_ESTATE; set_state then makes the context usable."""
+    _torch_cuda()
+    from paper_1508_03452_amd.rmhdlb import RMHDLB_ESTATE, RmhdlbError, Solver
+    w = W.random_state(shape=(8, 6, 4), seed=5, vmax=0.05)
+    s = Solver(w.shape, w.bc, **w.params)
+    for call in (lambda: s.step(1), lambda: s.moments(), lambda: s.get_state(), lambda: s.autotune()):
+        with pytest.raises(RmhdlbError) as e:
+            call()
+        assert e.value.code == RMHDLB_ESTATE
+    ref = run_gpu(w, 0)
+    s.set_state(ref.get_state())
+    s.step(2)
+    ref.step(2)
+    import torch
+    assert torch.equal(s.get_state(), ref.get_state())
 
 
 def test_random_3d_open_faces():

@@ -62,6 +62,9 @@ def _create(**kw):
     (dict(flux=2), R.RMHDLB_EINVAL),
     (dict(divb_fix=3), R.RMHDLB_EINVAL),
     (dict(nu=0.0), R.RMHDLB_EINVAL),
+    (dict(b_prev=2), R.RMHDLB_EINVAL),
+    (dict(b_prev=1, collision=1), R.RMHDLB_EUNSUPPORTED),
+    (dict(b_prev=1, flux=1), R.RMHDLB_EUNSUPPORTED),
 ])
 def test_parameter_validation_without_device(kw, code):
     rc, h = _create(**kw)
@@ -89,3 +92,28 @@ def test_null_arguments():
     assert L.rmhdlb_set_force(None, None, 0.0) == R.RMHDLB_EINVAL
     assert L.rmhdlb_destroy(None) == 0
     assert L.rmhdlb_state_len(None) == -1
+
+
+def test_workspace_bytes():
+    """The workspace query: zero for invalid parameters, at least the two state buffers, smaller for the
+    narrower storage types, and the previous-B reading adds exactly its three B_prev arrays to each of
+    the two buffers (64 x 4 x 4 cells: arrays of 1024 values, FP64)."""
+    ws = {st: R.workspace_bytes(R.make_params((64, 4, 4), storage=st)) for st in ("f64", "f32", "f16")}
+    assert ws["f64"] > ws["f32"] > ws["f16"] > 0
+    assert ws["f64"] >= 2 * 66 * 1024 * 8
+    bp = R.workspace_bytes(R.make_params((64, 4, 4), b_prev=1))
+    assert bp - ws["f64"] == 2 * 3 * 1024 * 8
+    assert R.workspace_bytes(R.make_params((64, 4, 4), tau=0.0)) == 0
+    assert R.workspace_bytes(R.make_params((0, 4, 4))) == 0
+
+
+@pytest.mark.parametrize("short,offset", [(1, 0), (0, 8)])
+def test_workspace_too_small_or_misaligned_is_rejected(short, offset):
+    """A caller workspace below rmhdlb_workspace_bytes, or not 256-byte aligned, is refused before any
+    device call (the pointer is never dereferenced)."""
+    P = R.make_params((8, 8, 8))
+    need = R.workspace_bytes(P)
+    P.workspace = ctypes.c_void_p(1 << 20 | offset)
+    P.workspace_bytes = need - short
+    h = ctypes.c_void_p()
+    assert R.load().rmhdlb_create(ctypes.byref(P), None, ctypes.byref(h)) == R.RMHDLB_EINVAL and not h.value
