@@ -754,6 +754,13 @@ int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out, int32_t* zg
                     t.zg = zg;
                     cand.push_back(t);
                 }
+        // A forced step also reduces its largest |beta| into the gate's
+        // lagged value: keep the value of the last real step across the timing.
+        double gate_prev = 0.0;
+        if (C->K.forced && (hipMemcpyAsync(&gate_prev, C->K.vmax_prev, sizeof(double), hipMemcpyDeviceToHost,
+                                           C->stream) != hipSuccess ||
+                            hipStreamSynchronize(C->stream) != hipSuccess))
+            return RMHDLB_EDEVICE;
         float best_ms = 1e30f;
         for (const rmhd::StepTuning& t : cand) {
             float ms = 0.0f;
@@ -767,6 +774,10 @@ int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out, int32_t* zg
                 best = t;
             }
         }
+        if (C->K.forced && (hipMemcpyAsync(const_cast<double*>(C->K.vmax_prev), &gate_prev, sizeof(double),
+                                           hipMemcpyHostToDevice, C->stream) != hipSuccess ||
+                            hipStreamSynchronize(C->stream) != hipSuccess))
+            return RMHDLB_EDEVICE;
         std::lock_guard<std::mutex> g(g_tune_mutex);
         g_tune_cache[key] = best;
     }

@@ -208,8 +208,11 @@ def flare(nx=256, ny=256, nz=512, sigma=1e3, B0=0.06, seed=512, steps=10000, Lx=
     U[1.8, 2.2] with the seed.  Density n = max(0.05, exp(-z/2)), p = 1,
     u = 0, E = 0.  Physical box [-Lx/2, Lx/2]^2 x [0, Lz].  The bottom face is
     driven (ghost planes at the fields of the first plane with the shear
-    u_x = v_drive tanh(y / 0.5) (1 + 1e-3 U[-1, 1]), same seed); the other
-    faces are open.
+    u_x = v_drive tanh(y / 0.5) sin^2(pi (x + Lx/2) / Lx) (1 + 1e-3 U[-1, 1]),
+    same seed); the other faces are open.  The sin^2 window takes the drive
+    to zero at the x faces, as the paper's flare force vanishes at the side
+    faces: a drive that pushes the fluid through an open (copy) face grows B
+    without bound at that corner of the bottom plane.
     """
     shape = (nx, ny, nz)
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -247,7 +250,8 @@ def flare(nx=256, ny=256, nz=512, sigma=1e3, B0=0.06, seed=512, steps=10000, Lx=
     # with the density, pressure and field of that plane
     ys = (np.arange(ny) + 0.5) * (Lx / ny) - Lx / 2.0
     jitter = 1.0 + 1e-3 * rng.uniform(-1.0, 1.0, size=(ny, nx))
-    ux = v_drive * np.tanh(ys / 0.5)[:, None] * jitter
+    window = np.sin(np.pi * (xs + Lx / 2.0) / Lx) ** 2
+    ux = v_drive * np.tanh(ys / 0.5)[:, None] * window[None, :] * jitter
     fz = np.zeros((ny, nx))
     driven = dict(n=n[0].copy(), p=np.ones((ny, nx)), u=(ux, fz, fz.copy()),
                   B=(Bx[0].copy(), By[0].copy(), Bz[0].copy()))

@@ -3,13 +3,16 @@
 Plain FP64 path, per-field error = max |gpu - oracle| / max(max |oracle|,
 floor), floors c for u and the run's field scale for E, B, J, rho_c.
 
-Tolerance: 1e-12 at the stated step counts.  For the longer runs the bound
-of a field is 4 s where the oracle's own sensitivity s exceeds 1e-12, else
-1e-12: s is the difference between two oracle runs whose initial states
-differ by one ulp (relative 2^-52 noise, keeping the workload's symmetry).
-No implementation can agree with the oracle more closely than the oracle
-agrees with itself under rounding; for the stiff high-sigma and shear-layer
-runs that floor passes 1e-12 after a few hundred steps.  Floors of the
+Tolerance: 1e-12 at the stated step counts.  For the longer stiff or
+shearing runs ("conditioned") the bound of a field is max(1e-12, 4 s), where
+s is the oracle's own sensitivity: the difference between two oracle runs
+whose initial states differ by one ulp (relative 2^-52 noise, keeping the
+workload's symmetry).  No implementation can agree with the oracle more
+closely than the oracle agrees with itself under rounding, and an
+implementation that rounds differently at every step lands about one to two
+s away (one-ulp noise injected at every step of the oracle gives the same s
+as one initial ulp); for the stiff high-sigma and shear-layer runs that
+floor passes 1e-12 after a few hundred steps.  Floors of the
 per-field error: c for u, the field scale for E, B, J, rho_c, the largest
 eps for p and eps.  Diagnostics (sums in another order) agree to 1e-13
 relative.
@@ -65,8 +68,8 @@ def check_case(w, steps, conditioned=False, symmetric=False):
     ctol = 1e-12 * max(1.0, w.ncells * 1e-3)
     if conditioned:
         fs, ss, cs = oracle_sensitivity(w, steps, o, symmetric)
-        ftol = {k: 4 * v if v > TOL else TOL for k, v in fs.items()}
-        stol = {k: 4 * v if v > TOL else TOL for k, v in ss.items()}
+        ftol = {k: max(TOL, 4 * v) for k, v in fs.items()}
+        stol = {k: max(TOL, 4 * v) for k, v in ss.items()}
         # the charge is the sum of the rho_c field: its bound follows from the per-cell one
         rho_den = max(np.abs(mo["rho_c"]).max(), field_scale(w))
         ctol = max(ctol, 4 * cs, ftol["rho_c"] * rho_den * w.ncells)
@@ -196,6 +199,24 @@ def test_external_force_gate_closes():
                        bc=(("open", "open"),) * 3)
     w.force = (_random_force(w, 6, 0.05), 1e-6)
     check_case(w, 8)
+
+
+def test_autotune_keeps_the_force_gate():
+    """Timing a forced context runs forced steps, whose per-step maximum of |beta| feeds the gate of the
+    next step: the tuner must leave the gate at the value of the last real step (open right after init).
+    The gated run of test_external_force_gate_closes, autotuned before its first step, still equals the
+    oracle."""
+    _torch_cuda()
+    w = W.random_state(shape=(20, 9, 7), seed=3, vmax=0.05, Bmag=0.2, Emag=0.02, sigma=30.0, solenoidal=True,
+                       bc=(("open", "open"),) * 3)
+    w.force = (_random_force(w, 6, 0.05), 1e-6)
+    s = run_gpu(w, 0)
+    print(f"[parity] forced gate, autotuned shape {s.autotune()}", flush=True)
+    s.step(8)
+    o = run_oracle(w, 8)
+    serr = state_errors(o.get_state(), s.get_state().cpu().numpy())
+    print(f"[parity] state {serr}", flush=True)
+    assert max(serr.values()) <= TOL, serr
 
 
 def test_external_force_with_printed_collision():
