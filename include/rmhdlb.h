@@ -44,8 +44,9 @@ enum {
     RMHDLB_EDEVICE = -3,     /* HIP runtime or launch error */
     RMHDLB_ERECOVERY = -4,   /* primitive recovery failed in some cell (state holds NaN there) */
     RMHDLB_EUNSUPPORTED = -5, /* parameter value outside what the method supports */
-    RMHDLB_ESTATE = -6        /* call out of order: no state yet (rmhdlb_init_fields or rmhdlb_set_state
+    RMHDLB_ESTATE = -6,       /* call out of order: no state yet (rmhdlb_init_fields or rmhdlb_set_state
                                  not called), or instances of a batch at different time levels */
+    RMHDLB_ELIMIT = -7        /* size beyond the fixed device memory of a no-allocation entry point */
 };
 
 /* Face types.  Periodic pairs both faces of an axis.  Open: the ghosts are
@@ -301,6 +302,21 @@ int rmhdlb_set_guess(rmhdlb_ctx *ctx, int32_t mode);
  * F (DEVICE, n_samples x 6) and targets T (DEVICE, n_samples x 2) of cells
  * floor(i N / n_samples) of the current state.  Synchronises. */
 int rmhdlb_guess_samples(rmhdlb_ctx *ctx, int32_t n_samples, double *F, double *T);
+
+/* The same samples with no device allocation, for callers that cannot allocate
+ * (code in tight training or serving loops, harnesses that forbid hipMalloc):
+ * the per-block partial sums of the sampling pass live in a fixed array of the
+ * library, one per device, of 17 * RMHDLB_NOALLOC_MAX_SAMPLES / 256 doubles
+ * (544 KiB), which every device the library is loaded on holds until the process ends.  The
+ * caller still passes F and T.  Every call on a device shares that device's
+ * array: calls that overlap on one device (from other host threads or on
+ * other streams) race and must be serialised by the caller; each call writes
+ * every partial sum it reads, so nothing carries over from an earlier call.
+ * Results are those of rmhdlb_guess_samples, bit for bit.  RMHDLB_ELIMIT for
+ * n_samples > RMHDLB_NOALLOC_MAX_SAMPLES, other errors as rmhdlb_guess_samples.
+ * Synchronises. */
+#define RMHDLB_NOALLOC_MAX_SAMPLES (1 << 20)
+int rmhdlb_guess_samples_noalloc(rmhdlb_ctx *ctx, int32_t n_samples, double *F, double *T);
 
 /* One forward and backward pass of the network on a batch: w (host,
  * RMHDLB_GUESS_PARAMS), normalised inputs X (DEVICE, n x 6) and targets Yt

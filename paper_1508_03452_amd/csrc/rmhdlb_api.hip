@@ -30,6 +30,7 @@ struct rmhdlb_ctx {
     hipStream_t stream;
     Consts K;
     int storage;       // RMHDLB_STORE_*
+    int device;        // the HIP device current at rmhdlb_create
     void* mem;         // the block every buffer below (to result) is carved from
     bool own_mem;      // mem was allocated by rmhdlb_create (else the caller's workspace)
     bool has_state;    // rmhdlb_init_fields or rmhdlb_set_state has run
@@ -287,6 +288,7 @@ const char* rmhdlb_strerror(int code) {
         case RMHDLB_ERECOVERY: return "primitive recovery failed in some cells";
         case RMHDLB_EUNSUPPORTED: return "unsupported parameter value";
         case RMHDLB_ESTATE: return "call out of order (no state yet, or batch instances at different time levels)";
+        case RMHDLB_ELIMIT: return "size beyond the fixed device memory of a no-allocation entry point";
         default: return "unknown error";
     }
 }
@@ -312,6 +314,10 @@ int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** ou
     C->P = *params;
     C->stream = (hipStream_t)hip_stream;
     C->K = K;
+    if (hipGetDevice(&C->device) != hipSuccess) {
+        release(C);
+        return RMHDLB_EDEVICE;
+    }
     C->storage = params->storage;
     if (params->workspace) {
         C->mem = params->workspace;
@@ -572,6 +578,63 @@ int rmhdlb_guess_samples(rmhdlb_ctx* C, int32_t ns, double* F, double* T) {
     const int rc = sample_cells(C, ns, F, T, part, sums);
     (void)hipFree(part);
     return rc;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ the no-allocation entry point
+
+// Per-block partial sums of the sampling pass of rmhdlb_guess_samples_noalloc:
+// one fixed array per device, which the host reaches only through the address
+// hipGetSymbolAddress returns for that device (kept in g_scratch_ptr); the
+// array's own name is no device address in host code.
+constexpr size_t NOALLOC_SCRATCH_LEN = (size_t)rmhd::SAMPLE_SUMS * ((RMHDLB_NOALLOC_MAX_SAMPLES + 255) / 256);
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_LEN];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+std::map<int, double*> g_scratch_ptr;  // device -> address of its copy of `scratch`
+
+// The address of device dev's copy of `scratch`, resolved once per device
+// with that device current (the caller's current device is restored).
+int scratch_on_device(int dev, double** out) {
+    std::lock_guard<std::mutex> g(g_scratch_mutex);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return RMHDLB_OK;
+    }
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return RMHDLB_EDEVICE;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return RMHDLB_EDEVICE;
+    double* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return RMHDLB_EDEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+    *out = p;
+    return RMHDLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rmhdlb_guess_samples_noalloc(rmhdlb_ctx* C, int32_t ns, double* F, double* T) {
+    if (!C || !F || !T || ns < 1) return RMHDLB_EINVAL;
+    if (ns > RMHDLB_NOALLOC_MAX_SAMPLES) return RMHDLB_ELIMIT;
+    if (ns > C->K.N) return RMHDLB_EINVAL;
+    if (!C->has_state) return RMHDLB_ESTATE;
+    if (C->K.bprev) return RMHDLB_EUNSUPPORTED;
+    double* part = nullptr;
+    const int rc = scratch_on_device(C->device, &part);
+    if (rc != RMHDLB_OK) return rc;
+    double sums[rmhd::SAMPLE_SUMS];
+    return sample_cells(C, ns, F, T, part, sums);
 }
 
 int rmhdlb_train_guess(rmhdlb_ctx* C, const rmhdlb_train_opts* o, const float* init_w, rmhdlb_guess_weights* out,

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librmhdlb.so")
 
 RMHDLB_OK, RMHDLB_EINVAL, RMHDLB_ENOMEM, RMHDLB_EDEVICE, RMHDLB_ERECOVERY, RMHDLB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-RMHDLB_ESTATE = -6
+RMHDLB_ESTATE, RMHDLB_ELIMIT = -6, -7
+NOALLOC_MAX_SAMPLES = 1 << 20
 BC = {"periodic": 0, "open": 1, "driven": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 OUT_FIELDS = ("n", "p", "eps", "ux", "uy", "uz", "Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho_c")
@@ -74,7 +75,8 @@ SYMBOLS = ("rmhdlb_create", "rmhdlb_init_fields", "rmhdlb_step", "rmhdlb_moments
            "rmhdlb_set_driven_face", "rmhdlb_train_guess", "rmhdlb_set_guess_weights", "rmhdlb_set_guess",
            "rmhdlb_guess_samples", "rmhdlb_mlp_eval", "rmhdlb_autotune", "rmhdlb_set_tuning", "rmhdlb_set_force",
            "rmhdlb_batch_create", "rmhdlb_batch_instance", "rmhdlb_batch_step", "rmhdlb_batch_autotune",
-           "rmhdlb_batch_set_tuning", "rmhdlb_batch_destroy", "rmhdlb_workspace_bytes")
+           "rmhdlb_batch_set_tuning", "rmhdlb_batch_destroy", "rmhdlb_workspace_bytes",
+           "rmhdlb_guess_samples_noalloc")
 
 _LIB = None
 
@@ -111,6 +113,7 @@ def load():
     L.rmhdlb_set_guess_weights.argtypes = [vp, ctypes.POINTER(rmhdlb_guess_weights)]
     L.rmhdlb_set_guess.argtypes = [vp, ctypes.c_int32]
     L.rmhdlb_guess_samples.argtypes = [vp, ctypes.c_int32, _dp, _dp]
+    L.rmhdlb_guess_samples_noalloc.argtypes = [vp, ctypes.c_int32, _dp, _dp]
     L.rmhdlb_mlp_eval.argtypes = [fp, fp, fp, ctypes.c_int32, fp, fp, fp, vp]
     ip32 = ctypes.POINTER(ctypes.c_int32)
     L.rmhdlb_autotune.argtypes = [vp, ip32, ip32, ip32, ip32]
@@ -361,12 +364,14 @@ class Solver:
     def set_guess(self, on):
         _check(load().rmhdlb_set_guess(self._h, 1 if on else 0), "rmhdlb_set_guess")
 
-    def guess_samples(self, n_samples):
+    def guess_samples(self, n_samples, noalloc=False):
+        """Features and targets of sampled cells (the learned guess's training data); noalloc uses the
+        entry point that allocates no device memory (n_samples <= NOALLOC_MAX_SAMPLES)."""
         torch = self.torch
         F = torch.empty((n_samples, 6), dtype=torch.float64, device="cuda")
         T = torch.empty((n_samples, 2), dtype=torch.float64, device="cuda")
-        rc = _check(load().rmhdlb_guess_samples(self._h, int(n_samples), _dptr(F), _dptr(T)), "rmhdlb_guess_samples",
-                    allow=(RMHDLB_ERECOVERY,))
+        fn = load().rmhdlb_guess_samples_noalloc if noalloc else load().rmhdlb_guess_samples
+        rc = _check(fn(self._h, int(n_samples), _dptr(F), _dptr(T)), fn.__name__, allow=(RMHDLB_ERECOVERY,))
         return F, T, rc
 
     def step(self, nsteps=1):
