@@ -14,7 +14,7 @@ def field_errors(ref, got, scale_B, eps_ref=None):
     if eps_ref is None and "eps" in ref:
         eps_ref = float(np.abs(ref["eps"]).max())
     for k, r in ref.items():
-        if k not in got or k in ("n_failed",):
+        if k not in got or k in ("n_failed", "diag") or not hasattr(r, "shape"):
             continue
         g = got[k]
         if k[0] == "u" and len(k) == 2:
@@ -30,16 +30,18 @@ def field_errors(ref, got, scale_B, eps_ref=None):
     return errs
 
 
-def state_errors(ref, got):
+def state_errors(ref, got, scale_B=None):
     """Per-group error of the raw state (F, G, h*, E_prev and, with the previous-B reading, B_prev),
-    relative to each group's max."""
+    relative to each group's max; the field groups E_prev and B_prev with the floor scale_B of the
+    field errors (their natural size in the run), when given."""
     groups = dict(F=slice(0, 19), G=slice(19, 38), h=slice(38, 63), E=slice(63, 66))
     if ref.shape[0] == 69:
         groups["Bp"] = slice(66, 69)
     out = {}
     for k, s in groups.items():
         r, g = ref[s], got[s]
-        out[k] = float(np.abs(g - r).max() / max(np.abs(r).max(), 1e-300))
+        floor = scale_B if (k in ("E", "Bp") and scale_B is not None) else 1e-300
+        out[k] = float(np.abs(g - r).max() / max(np.abs(r).max(), floor))
     return out
 
 

@@ -224,3 +224,30 @@ def test_batch_recaptures_when_an_instance_is_retuned():
         ref = run_gpu(w, 78, storage="f32")
         assert np.array_equal(_state(s), _state(ref)), w.shape
     b.close()
+
+
+def test_batched_sweep_instances_against_the_oracle():
+    """The batched sweep's instances against the oracle: six KH slabs drawn by the sweep generator (seed
+    64, uneven sizes that leave ragged tiles in x and y; sigma 1e2 .. 1e5, shear 0.05 .. 0.4c, density
+    ratio 1 .. 10), stepped 20 times as one FP64 batch in the tuner's chosen tile; every instance's
+    fields and raw state within 1e-12 of the oracle's run of that instance."""
+    torch = _torch_cuda()
+    from .parity_util import field_errors, field_scale, gpu_moments_np, run_oracle, state_errors
+    specs = W.sweep_specs(n=6, seed=64, sizes=(72, 96, 130, 160, 200))
+    ws = [W.sweep_instance(sp) for sp in specs]
+    st = torch.cuda.Stream()
+    b = _batch(ws, "f64", st)
+    print(f"[batch] sweep of {len(ws)} KH slabs {[w.shape[:2] for w in ws]}, tile {b.autotune()}", flush=True)
+    b.step(20)
+    st.synchronize()
+    for w, s in zip(ws, b.instances):
+        o = run_oracle(w, 20)
+        mg = gpu_moments_np(s)
+        assert mg["diag"]["n_failed"] == 0
+        errs = field_errors(o.moments(), mg, field_scale(w))
+        serr = state_errors(o.get_state(), _state(s), field_scale(w))
+        worst = max(errs, key=errs.get)
+        print(f"[batch] {w.shape[:2]} sigma {w.params['sigma']:.3g}: worst field {worst}={errs[worst]:.1e}, "
+              f"state {max(serr.values()):.1e}", flush=True)
+        assert errs[worst] <= 1e-12 and max(serr.values()) <= 1e-12, (w.shape, errs[worst], serr)
+    b.close()

@@ -1,13 +1,14 @@
-"""Long-run behaviour of the storage forms on a 64^3 instance of the flare box (driven bottom face,
-open faces elsewhere), 1000 steps on the GPU through the C ABI.
+"""Long runs on the GPU through the C ABI, against the oracle: the 64^3 instance of the flare box (driven
+bottom face, open faces elsewhere) after 1000 steps in every storage form, the current sheet at its
+stated 4000 steps, and the paper's supersonic KH and forced flare set-ups.
 
-The plain FP64 path is pinned to the oracle elsewhere (1e-12 per step; 1.6e-10 in B after 1000 steps
-of this instance, rounding order only).  Here it is the reference for the reduced-precision forms,
-and its own sensitivity is measured: a one-ulp change of the initial density grows to ~3e-10 in B
-after 1000 steps, i.e. the flow amplifies rounding about two-million-fold.  The FP32 and FP16 forms
-round at 6e-8 and (on deviations) ~5e-4 every step, so their pointwise B and J drift to a sizeable
-fraction of the field scale while n, p, u and the total energy stay close; the bounds below state
-that."""
+The flare box's flow amplifies rounding about a million-fold over 1000 steps (the oracle's own one-ulp
+sensitivity is stored with its fields), so the plain FP64 path agrees with the oracle to that
+conditioning, and the FP32 and FP16 forms, which round at 6e-8 and (on deviations) ~5e-4 every step,
+keep n, p, u and the total energy close while their pointwise B drifts to a fraction of the field
+scale; the bounds below state that."""
+import os
+
 import numpy as np
 import pytest
 
@@ -15,69 +16,77 @@ from paper_1508_03452_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-KEEP = ("n", "p", "ux", "uy", "uz", "Bx", "By", "Bz", "Ez", "Jz")
+GOLD_FLARE64 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "flare64_oracle.npz")
+GOLD_FIELDS = ("n", "p", "eps", "ux", "uy", "uz", "Ex", "Ey", "Ez", "Bx", "By", "Bz")
+# Stated bounds of the reduced forms against the FP64 oracle after 1000 steps of this box (measured
+# against the FP64 GPU path: FP32 n, p, u <= 2.8e-3, E <= 2.3e-3, B <= 8.1e-2, total energy 5.5e-7;
+# FP16 and FP16 + guess n, p, u <= 6.4e-3, E <= 1.7e-2, B <= 2.6e-1, total energy 5.0e-4): the flow
+# amplifies rounding about a million-fold (the oracle's own one-ulp sensitivity stored with it is
+# 1.5e-10 in B), so the pointwise field of the reduced forms drifts while the bulk stays close.
+FLARE64_TOL = {"f32": {"fluid": 5e-3, "E": 5e-3, "B": 0.2, "energy": 1e-5},
+               "f16": {"fluid": 1.5e-2, "E": 4e-2, "B": 0.5, "energy": 1e-3}}
 
 
-def _run(w, storage, steps, perturb=False, guess=False):
-    import torch
-    from paper_1508_03452_amd.rmhdlb import Solver
-    fields = dict(w.fields)
-    if perturb:
-        fields["n"] = np.nextafter(np.asarray(w.fields["n"]), np.inf)
-    s = Solver(w.shape, w.bc, storage=storage, **w.params)
-    s.init_fields(fields)
-    s.set_driven_face(w.driven)
-    done = 0
-    if guess:
-        s.step(20)
-        done = 20
-        s.train_guess(W.mlp_init(11), n_samples=32768, iters=400, batch=512, lr=3e-3)
-        s.set_guess(True)
-    s.step(steps - done)
-    m = s.moments()
-    out = {k: m[k].cpu().numpy().astype(np.float64) for k in KEEP}
-    d = m["diag"]
-    s.close()
-    torch.cuda.synchronize()
-    return out, d
-
-
-def _errors(got, ref, scale):
-    e = {}
-    for k in KEEP:
-        floor = 1.0 if k[0] == "u" else (scale if k[0] in "BEJ" else 1e-300)
-        e[k] = float(np.abs(got[k] - ref[k]).max() / max(np.abs(ref[k]).max(), floor))
-    return e
-
-
-def test_storage_forms_over_1000_steps():
+def test_flare64_against_the_oracle_after_1000_steps():
+    """The accuracy sub-box of the flare workload (64^3 cells of the same generator: driven bottom face,
+    open faces elsewhere, sigma = 1e3), 1000 steps on the GPU in every form, against the FP64 oracle's
+    fields after the same 1000 steps (tests/golden/flare64_oracle.npz, written by make_flare64.py from
+    the oracle alone; six z-planes at every second cell).  FP64 within max(1e-12, 4 s) per field, s the
+    oracle's own one-ulp sensitivity stored with it; FP32, FP16 and FP16 + learned guess within the
+    stated bounds; global energy and mass against the oracle's sums."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    from paper_1508_03452_amd.rmhdlb import Solver
+    g = np.load(GOLD_FLARE64)
+    steps = int(g["steps"])
+    planes = [int(v) for v in g["planes"]]
+    scale = float(g["field_scale"])
+    eps_ref = float(g["max_eps"])
     w = W.flare(nx=64, ny=64, nz=64, Lz=12.0)
-    w.params["divb_fix"] = 0
-    scale = max(max(np.abs(b).max() for b in w.fields["B"]), 1e-3)
-    steps = 1000
-    ref, dref = _run(w, "f64", steps)
-    assert dref["n_failed"] == 0
-    sens, _ = _run(w, "f64", steps, perturb=True)
-    es = _errors(sens, ref, scale)
-    print(f"[long] FP64 one-ulp sensitivity after {steps} steps: " +
-          " ".join(f"{k} {v:.1e}" for k, v in es.items()), flush=True)
-    assert max(es.values()) < 1e-8   # measured 2.7e-10 (B)
-    bounds = {"f32": (2e-3, 1e-4), "f16": (2e-2, 2e-3)}
-    for name, storage, guess in (("f32", "f32", False), ("f16", "f16", False), ("f16+guess", "f16", True)):
-        got, d = _run(w, storage, steps, guess=guess)
+
+    def floor(k):
+        return 1.0 if k[0] == "u" else (scale if k[0] in "EB" else (eps_ref if k in ("p", "eps") else 1e-300))
+
+    res = {}
+    for name, storage, guess in (("f64", "f64", False), ("f32", "f32", False), ("f16", "f16", False),
+                                 ("f16+guess", "f16", True)):
+        s = Solver(w.shape, w.bc, storage=storage, **w.params)
+        s.init_fields(w.fields)
+        s.set_driven_face(w.driven)
+        done = 0
+        if guess:
+            s.step(20)
+            done = 20
+            s.train_guess(W.mlp_init(11), n_samples=32768, iters=400, batch=512, lr=3e-3)
+            s.set_guess(True)
+        s.step(steps - done)
+        m = s.moments(fields=GOLD_FIELDS)
+        d = m["diag"]
+        s.close()
         assert d["n_failed"] == 0, name
-        e = _errors(got, ref, scale)
-        de = abs(d["energy"] - dref["energy"]) / abs(dref["energy"])
-        print(f"[long] {name} after {steps} steps vs FP64: " + " ".join(f"{k} {v:.1e}" for k, v in e.items()) +
-              f"; total energy {de:.1e}", flush=True)
-        fb, eb = bounds[storage]
-        for k in ("n", "p", "ux", "uy", "uz"):
-            assert e[k] <= fb, (name, k, e[k])   # measured FP32 <= 8e-4, FP16 <= 7.3e-3
-        assert de <= eb, (name, de)              # measured FP32 2.4e-5, FP16 5.8e-4
-        assert max(e[k] for k in ("Bx", "By", "Bz")) < 2.0   # O(1) of the field scale: amplified rounding
+        e = {}
+        for k in GOLD_FIELDS:
+            got = m[k].cpu().numpy()[planes, ::2, ::2]
+            e[k] = float(np.abs(got - g[k]).max() / max(float(g["max_" + k]), floor(k)))
+        de = abs(d["energy"] - float(g["diag_energy"])) / abs(float(g["diag_energy"]))
+        dm = abs(d["mass"] - float(g["diag_mass"])) / abs(float(g["diag_mass"]))
+        res[name] = (e, de, dm)
+        print(f"[long] flare 64^3 {name} after {steps} steps vs the FP64 oracle: " +
+              " ".join(f"{k} {v:.1e}" for k, v in e.items()) + f"; total energy {de:.1e}, mass {dm:.1e}",
+              flush=True)
+    e, de, dm = res["f64"]
+    tol = {k: max(1e-12, 4 * float(g["sens_" + k])) for k in GOLD_FIELDS}
+    bad = {k: (v, tol[k]) for k, v in e.items() if v > tol[k]}
+    assert not bad, bad
+    assert de <= 1e-12 and dm <= 1e-12, (de, dm)
+    for name in ("f32", "f16", "f16+guess"):
+        e, de, _ = res[name]
+        b = FLARE64_TOL[name.split("+")[0]]
+        for k, v in e.items():
+            cls = "B" if k[0] == "B" else ("E" if k[0] == "E" else "fluid")
+            assert v <= b[cls], (name, k, v)
+        assert de <= b["energy"], (name, de)
 
 
 def _first_failure(w, steps, every=200):
@@ -140,3 +149,105 @@ def test_forced_flare_set_up_runs():
     assert all(b2 > b1 for b1, b2 in zip(bmax, bmax[1:])) and 0.05 < bmax[-1] < 0.3
     assert m["diag"]["energy"] > e0
     s.close()
+
+
+# ------------------------------------------------ the current sheet at its stated length
+
+SHEET_FIELDS = ("n", "p", "eps", "ux", "uy", "uz", "Ex", "Ey", "Ez", "Bx", "By", "Bz", "Jx", "Jy", "Jz", "rho_c")
+
+
+def _sheet_line_oracle(w, steps, perturb=False):
+    """The oracle on the sheet's 1024 x 1 x 1 line: the state is uniform in y and z on periodic axes, so
+    the line evolves bit for bit as the full 1024 x 4 x 4 grid (pinned on the CPU).  perturb: every state
+    value scaled by 1 +- 2^-52 (one ulp, uniform in y and z), for the oracle's own sensitivity."""
+    import oracle
+    nx = w.shape[0]
+    line = lambda a: np.ascontiguousarray(np.asarray(a)[:1, :1, :])
+    f = {k: line(w.fields[k]) for k in ("n", "p", "rho_c")}
+    for k in ("u", "E", "B"):
+        f[k] = tuple(line(a) for a in w.fields[k])
+    o = oracle.Oracle((nx, 1, 1), w.bc, **w.params)
+    o.init(f)
+    if perturb:
+        st = o.get_state()
+        sgn = np.random.default_rng(77).choice([-1.0, 1.0], size=st.shape)
+        o.set_state(st * (1 + 2.0 ** -52 * sgn))
+    for _ in range(steps // 500):
+        o.step(500)
+    o.step(steps % 500)
+    m = o.moments()
+    assert m["n_failed"] == 0
+    return {k: m[k] for k in SHEET_FIELDS}
+
+
+@pytest.mark.parametrize("sigma", [10.0, 100.0, 1000.0])
+def test_current_sheet_full_length_against_the_oracle(sigma):
+    """The resistive current sheet at its stated size and length: 1024 x 4 x 4 cells, x open, p = 50,
+    4000 steps (t = 2828), sigma = 10, 100, 1000.  The plain FP64 GPU path against the oracle per field
+    within max(1e-12, 4 s), s the oracle's own one-ulp sensitivity at this length; the FP32 and
+    FP16-shifted forms within their stated bounds; B_y of every form against the erf diffusion profile
+    erf(x / (2 sqrt((t0 + t) / sigma))) over |x| <= 256, no worse than the oracle's own distance to it
+    by more than the form's bound."""
+    import torch
+    from math import erf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from .parity_util import field_errors, gpu_moments_np, run_gpu
+    steps = 4000
+    w = W.sheet(sigma=sigma)
+    print(f"[sheet] sigma {sigma}: oracle line 1024x1x1, {steps} steps", flush=True)
+    ref = _sheet_line_oracle(w, steps)
+    per = _sheet_line_oracle(w, steps, perturb=True)
+    sens = field_errors(ref, per, 1.0)
+    tol = {k: max(1e-12, 4 * v) for k, v in sens.items()}
+    x = np.arange(w.shape[0]) + 0.5 - w.shape[0] / 2
+    t = w.meta["t0"] + steps / np.sqrt(2.0)
+    an = np.array([erf(v / (2.0 * np.sqrt(t / sigma))) for v in x])
+    band = np.abs(x) <= 256
+    e_orc = float(np.abs(ref["By"][0, 0] - an)[band].max())
+    results = {}
+    for storage in ("f64", "f32", "f16"):
+        s = run_gpu(w, steps, storage=storage)
+        mg = gpu_moments_np(s)
+        s.close()
+        assert mg["diag"]["n_failed"] == 0
+        # every (y, z) column of the 4 x 4 cross-section against the line
+        got = {k: mg[k] for k in SHEET_FIELDS}
+        line = {k: np.broadcast_to(v, got[k].shape) for k, v in ref.items()}
+        errs = field_errors(line, got, 1.0)
+        e_an = float(np.abs(mg["By"] - an[None, None, :])[..., band].max())
+        results[storage] = (errs, e_an)
+        print(f"[sheet] sigma {sigma} {storage}: " + " ".join(f"{k}={v:.1e}" for k, v in errs.items()) +
+              f"; erf distance {e_an:.3e} (oracle {e_orc:.3e})", flush=True)
+    print("[sheet] oracle self-sensitivity: " + " ".join(f"{k}={v:.1e}" for k, v in sens.items()), flush=True)
+    errs, e_an = results["f64"]
+    bad = {k: (v, tol[k]) for k, v in errs.items() if v > tol[k]}
+    assert not bad, bad
+    assert abs(e_an - e_orc) <= 1e-10
+    for storage in ("f32", "f16"):
+        errs, e_an = results[storage]
+        tols = SHEET_LONG_TOL[storage]
+        bad = {k: v for k, v in errs.items() if tols[_sheet_class(k)] is not None and v > tols[_sheet_class(k)]}
+        assert not bad, (storage, bad)
+        assert e_an <= e_orc + tols["B"], (storage, e_an, e_orc)
+
+
+# Stated per-field bounds of the reduced forms on the 4000-step sheet (against the FP64 oracle): the
+# primary fields n, p, eps, u, E, B; the current J (sigma times a nearly cancelling sum); the charge of
+# the Maxwell populations, rho_c, whose mode is undamped and carries every step's storage rounding.
+# Measured over sigma = 10, 100, 1000 (largest): FP32 B 1.4e-4, n 3.9e-5, J 6.2e-5, rho_c 1.5e-2; FP16 n
+# 2.4e-3, p, eps, u, E <= 2.3e-3, B 5.6e-2, J 1.1e-1.  rho_c in FP16 is not bounded: the populations'
+# charge mode grows slowly (about 0.3 % per step at sigma = 1000; its rounding is amplified about
+# 4e5-fold over these steps, 4e-11 in FP64) and FP16 storage rounds it every step; the dynamics never read
+# that charge (E, B and J do not see a common offset of the Maxwell populations, and the convection
+# current takes Gauss's law), so it is reported, not bounded.
+SHEET_LONG_TOL = {"f32": {"primary": 3e-4, "B": 3e-4, "J": 2e-4, "rho_c": 5e-2},
+                  "f16": {"primary": 5e-3, "B": 1e-1, "J": 2.5e-1, "rho_c": None}}
+
+
+def _sheet_class(k):
+    if k[0] == "J":
+        return "J"
+    if k == "rho_c":
+        return "rho_c"
+    return "B" if k[0] == "B" and len(k) == 2 else "primary"

@@ -51,7 +51,7 @@ def oracle_sensitivity(w, steps, o_ref, symmetric):
     b.set_state(st * (1 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=shp)))
     b.step(steps)
     return (field_errors(o_ref.moments(), b.moments(), field_scale(w)),
-            state_errors(o_ref.get_state(), b.get_state()),
+            state_errors(o_ref.get_state(), b.get_state(), field_scale(w)),
             abs(b.diagnostics()["charge"] - o_ref.diagnostics()["charge"]))
 
 
@@ -64,7 +64,7 @@ def check_case(w, steps, conditioned=False, symmetric=False):
     mg = gpu_moments_np(s)
     assert mo["n_failed"] == 0 and mg["diag"]["n_failed"] == 0
     errs = field_errors(mo, mg, field_scale(w))
-    serr = state_errors(o.get_state(), s.get_state().cpu().numpy())
+    serr = state_errors(o.get_state(), s.get_state().cpu().numpy(), field_scale(w))
     ctol = 1e-12 * max(1.0, w.ncells * 1e-3)
     if conditioned:
         fs, ss, cs = oracle_sensitivity(w, steps, o, symmetric)
@@ -214,7 +214,7 @@ def test_autotune_keeps_the_force_gate():
     print(f"[parity] forced gate, autotuned shape {s.autotune()}", flush=True)
     s.step(8)
     o = run_oracle(w, 8)
-    serr = state_errors(o.get_state(), s.get_state().cpu().numpy())
+    serr = state_errors(o.get_state(), s.get_state().cpu().numpy(), field_scale(w))
     print(f"[parity] state {serr}", flush=True)
     assert max(serr.values()) <= TOL, serr
 

@@ -369,6 +369,17 @@ def test_alfven_worked_value_and_eos_convention():
     assert round(np.sqrt(vA2), gold["printed_digits"]) == gold["v_A"]
 
 
+def test_uniform_cross_section_evolves_as_its_line():
+    """A state uniform in y and z on periodic y, z axes evolves bit for bit like its single line of
+    cells (every stencil point in y and z holds the same values): the current sheet's 1024 x 4 x 4 grid
+    is its 1024 x 1 x 1 line, which lets the full-length sheet runs be checked against the line."""
+    a = W.sheet(nx=64, ny=4, nz=3, sigma=100.0)
+    b = W.sheet(nx=64, ny=1, nz=1, sigma=100.0)
+    oa, ob = _run(a, 30), _run(b, 30)
+    sa, sb = oa.get_state(), ob.get_state()
+    assert np.array_equal(sa, np.broadcast_to(sb, sa.shape))
+
+
 def test_current_sheet_follows_erf_diffusion():
     """Resistive diffusion of a current sheet, Eq. Current_sheet (erf profile, rest frame)."""
     from math import erf
