@@ -15,9 +15,12 @@ whether the network pays for itself on this workload.
 
 roofline: algorithmic HBM bytes of one step (read + write of the 66 state
 values per cell) divided by the measured average step duration, against the
-MI355X HBM peak of 8 TB/s.  traffic: HBM bytes per step from rocprofv3
-FETCH_SIZE / WRITE_SIZE counters (profiles/), scaled by the copy-kernel
-calibration factor, or null when not measured for this kernel version.
+MI355X HBM peak of 8 TB/s.  traffic: bytes past the L2 cache per step from
+rocprofv3 FETCH_SIZE / WRITE_SIZE counters (profiles/), scaled by the factor
+the library's copy kernel (known bytes) reads under the same counters, or
+null when not measured for this kernel version and launch shape.
+copy_probe_gbs: the rate of that copy kernel on this GPU, the achievable
+bandwidth the step is read against.
 
 cpu_baseline: the oracle (plain single-threaded FP64 C) on a bounded sample
 of the same workload, timed on this host.
@@ -98,6 +101,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--single-form", action="store_true",
                     help="time only the form given by --storage/--guess (no mixed forms beside it)")
+    ap.add_argument("--copy-only", type=float, default=0.0,
+                    help="only run 3 copies of this many GiB with the library's copy kernel (counter calibration)")
     ap.add_argument("--history", type=int, default=0,
                     help="instead of timing: run --steps steps of the workload in the --storage form and report "
                          "the diagnostics every HISTORY steps (energy, largest |B| and |u| with their cells, "
@@ -171,7 +176,7 @@ def run_sweep(steps, warmup, storage="f32"):
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     info = {"workload": f"batched sweep: {len(specs)} KH slabs, nx, ny in 256..1024, {ncell} cells, "
                         f"sigma 1e2..1e5, one launch per step, hipGraph replays (64 steps per graph)",
-            "storage": storage, "cells": ncell, "tile": f"{px}x{128 // px * yw} cells", "waves_per_simd": waves,
+            "storage": storage, "cells": ncell, "tile": f"{px}x{(256 if storage == 'f32' else 128) // px * yw} cells", "waves_per_simd": waves,
             "failed_cells": failed, "wall_s_timed": round(wall, 3),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_fused_batch",
@@ -257,11 +262,14 @@ def accuracy_study(steps=1000):
 ALG_BYTES = {"f64": (8, 8), "f32": (4, 4), "f16": (2, 4)}   # (distribution, E_prev) bytes per value
 
 
-def tile_text(shape):
+def tile_text(shape, storage="f64"):
+    """A launch shape in words; a row group has 128 cells with FP64 and FP16 storage (two lanes per cell)
+    and 256 with FP32 (one lane per cell)."""
     px, zb, zg, yw = tuple(shape) + (1,) * (4 - len(shape))
     walk = (f"{zb} z-planes per block" if zg == 1 else
             f"{zg} blocks per column walking chunks of {zg * zb} z-planes interleaved ({zb} planes each)")
-    return f"{px}x{128 // px * yw} cells, {walk}"
+    rows = (256 if storage == "f32" else 128) // px * yw
+    return f"{px}x{rows} cells, {walk}"
 
 
 def alg_bytes_per_step(storage, ncell, b_prev=False):
@@ -292,14 +300,14 @@ def timed_form(w, storage, guess, args, stream):
             return (64, 4, 1, 1)
         return s.autotune()   # untimed; the state is not advanced
     shape = choose_shape()
-    info = {"tile": tile_text(shape), "launch_shape": list(shape)}
+    info = {"tile": tile_text(shape, storage), "launch_shape": list(shape)}
     if guess:
         t_tr = time.perf_counter()
         weights, losses = s.train_guess(W.mlp_init(11), n_samples=65536, iters=400, batch=512, lr=3e-3)
         s.set_guess(True)
         if not args.no_autotune:   # the guess path has 64-wide tiles only: tune again among those
             shape = choose_shape()
-            info.update(tile=tile_text(shape), launch_shape=list(shape))
+            info.update(tile=tile_text(shape, storage), launch_shape=list(shape))
         s.step(2)
         info["guess_training"] = {"samples": 65536, "iters": 400, "loss_first": float(losses[0]),
                                   "loss_last": float(losses[-1]), "train_s": round(time.perf_counter() - t_tr, 3)}
@@ -323,23 +331,43 @@ def timed_form(w, storage, guess, args, stream):
 
 
 def copy_probe_gbs(stream, gib=4.0, reps=10):
-    """Achievable HBM bandwidth of a plain device copy (read + write bytes / time)."""
+    """Achievable HBM bandwidth: the library's plain copy kernel (rmhdlb_device_copy: 16-byte lanes,
+    non-temporal loads and stores) over gib GiB, read + write bytes / time, HIP events on the stream."""
     import torch
+    from paper_1508_03452_amd.rmhdlb import device_copy
     n = int(gib * (1 << 30) // 8)
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
+    device_copy(b, a, stream)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        b.copy_(a)
+        device_copy(b, a, stream)
     e1.record(stream)
     torch.cuda.synchronize()
     gbs = 2 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    assert torch.equal(a, b)
     del a, b
     torch.cuda.empty_cache()
     return round(gbs, 1)
+
+
+def copy_only(gib, reps):
+    """--copy-only: reps copies of gib GiB with the library's copy kernel and nothing else, the known
+    traffic (gib GiB read and gib GiB written per dispatch) that calibrates the rocprofv3 counters."""
+    import torch
+    from paper_1508_03452_amd.rmhdlb import device_copy
+    torch.cuda.set_device(0)
+    n = int(gib * (1 << 30) // 8)
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    for _ in range(reps):
+        device_copy(b, a, st)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_only": {"bytes_read_per_dispatch": n * 8, "bytes_written_per_dispatch": n * 8,
+                                    "dispatches": reps, "kernel": "rmhd::k_copy16"}}), flush=True)
 
 
 def history_main(args):
@@ -382,6 +410,8 @@ def history_main(args):
 
 def main():
     args = parse()
+    if args.copy_only > 0:
+        return copy_only(args.copy_only, 3)
     if args.history > 0:
         if args.gpus != 1:
             print(json.dumps({"error": "the step runs on one GPU; --gpus must be 1"}))

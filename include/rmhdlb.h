@@ -329,9 +329,10 @@ int rmhdlb_mlp_eval(const float *w, const float *X, const float *Yt, int32_t n, 
                     void *hip_stream);
 
 /* ---- launch tuning and batched sweeps --------------------------------------
- * The fused step runs blocks of 256 threads, two lanes per cell, over row
- * groups of px x (128 / px) cells, px in {64, 32, 16} (128 too in batches);
- * a block takes yw such groups stacked along y (a tile of px x (128 / px) yw
+ * The fused step runs blocks of 256 threads over row groups of px x (R / px)
+ * cells, px in {64, 32, 16} (128 too in batches): R = 128 with FP64 and
+ * FP16 storage (two lanes per cell), R = 256 with FP32 (one lane per cell);
+ * a block takes yw such groups stacked along y (a tile of px x (R / px) yw
  * cells) and walks zb z-planes.  With zg > 1 the planes are taken in chunks
  * of zg * zb per column, and the zg blocks of a chunk walk them interleaved
  * (block r: planes r, r + zg, ...), so that they run at neighbouring planes
@@ -388,10 +389,11 @@ rmhdlb_ctx *rmhdlb_batch_instance(rmhdlb_batch *batch, int32_t i);
 int rmhdlb_batch_step(rmhdlb_batch *batch, int64_t nsteps);
 
 /* Time the tiles of the batched step (state not advanced) and keep the
- * fastest: px x (128 / px) yw cells for (px, yw) in (64, 1), (32, 1), (16, 1)
- * and the shapes 64 x 4 (64, 2), 32 x 8 (32, 2), 128 x 2 (128, 2), 16 x 16
- * (16, 2), 64 x 8 (64, 4), each with the kernel compiled for 2 and (FP32
- * storage) 3 waves per SIMD.  Cached per process by storage and the grids
+ * fastest: px x (R / px) yw cells, R = 128 cells per row group with FP64
+ * and FP16 storage (two lanes per cell) and 256 with FP32 (one lane per
+ * cell), so that the shapes 64 x 4, 32 x 8, 128 x 2, 16 x 16 and 64 x 8 are
+ * among them for every storage type (eight shapes in all), each with the
+ * kernel compiled for 2 and (FP32 storage) 3 waves per SIMD.  Cached per process by storage and the grids
  * of the instances.  *px, *yw, *waves receive the choice (any may be NULL).
  * Synchronises.  RMHDLB_ESTATE as for rmhdlb_batch_step. */
 int rmhdlb_batch_autotune(rmhdlb_batch *batch, int32_t *px, int32_t *yw, int32_t *waves);
@@ -402,6 +404,15 @@ int rmhdlb_batch_set_tuning(rmhdlb_batch *batch, int32_t px, int32_t yw, int32_t
 
 /* Release the batch and its instances.  NULL is accepted. */
 int rmhdlb_batch_destroy(rmhdlb_batch *batch);
+
+/* A plain device copy of `bytes` bytes from src to dst (both DEVICE pointers
+ * on the current device, 16-byte aligned, not overlapping; bytes a multiple
+ * of 16, else RMHDLB_EINVAL), queued on hip_stream: one 16-byte load and
+ * store per lane with non-temporal hints, the access pattern of the step's
+ * streams.  Not part of the method: the achievable HBM rate the step's
+ * roofline fraction is read against, and the reference that calibrates
+ * traffic counters (its bytes read and written are known exactly). */
+int rmhdlb_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
 
 /* Release the context and its device memory.  NULL is accepted. */
 int rmhdlb_destroy(rmhdlb_ctx *ctx);

@@ -147,8 +147,11 @@ size_t dist_elem(int storage) {
     return storage == RMHDLB_STORE_F64 ? 8 : (storage == RMHDLB_STORE_F32 ? 4 : 2);
 }
 size_t efield_elem(int storage) { return storage == RMHDLB_STORE_F64 ? 8 : 4; }
+// The distribution block: 63 arrays of `stride` values in the pair layout (FP64, FP16), 65 in the quad
+// layout (FP32: the rest slot is a quad with two unused values).
 size_t efield_offset(int storage, int64_t stride) {
-    const size_t b = (size_t)(rmhd::NSTATE - 3) * (size_t)stride * dist_elem(storage);
+    const int arrays = rmhd::quad_storage(storage) ? rmhd::QUAD_DIST_ARRAYS : rmhd::PAIR_DIST_ARRAYS;
+    const size_t b = (size_t)arrays * (size_t)stride * dist_elem(storage);
     return (b + 255) / 256 * 256;
 }
 // The field block holds E_prev (3 arrays) and, with the previous-B reading, B_prev (3 more).
@@ -359,6 +362,15 @@ int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** ou
     C->tune.zg = 1;
     *out = C;
     return RMHDLB_OK;
+}
+
+int rmhdlb_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+    if (!dst || !src || bytes % 16 != 0 || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15)) return RMHDLB_EINVAL;
+    const uintptr_t d = (uintptr_t)dst, s0 = (uintptr_t)src;
+    if (d < s0 + bytes && s0 < d + bytes) return RMHDLB_EINVAL;  // overlapping
+    return rmhd::launch_copy16(src, dst, (int64_t)(bytes / 16), (hipStream_t)hip_stream) == hipSuccess
+               ? RMHDLB_OK
+               : RMHDLB_EDEVICE;
 }
 
 int rmhdlb_destroy(rmhdlb_ctx* ctx) {
@@ -932,7 +944,8 @@ int batch_table(rmhdlb_batch* B) {
         I.faceB = C->faceB;
         I.zb = std::max(1, std::min(C->tune.zb, C->K.nz));
         I.yw = B->yw;
-        rmhd::step_geometry(C->K, B->px, I.zb, 1, I.yw, I.tiles_x, I.ncol, I.nblk);
+        rmhd::step_geometry(C->K, B->px, I.zb, 1, I.yw, rmhd::cells_per_block(rmhd::quad_storage(B->storage)),
+                            I.tiles_x, I.ncol, I.nblk);
         I.blk0 = blk;
         I.face0 = face;
         blk += I.nblk;
@@ -1137,13 +1150,18 @@ int rmhdlb_batch_autotune(rmhdlb_batch* B, int32_t* px_out, int32_t* yw_out, int
         }
     }
     if (!cached) {
-        // tiles px x (128 / px) yw: 64x2, 32x4, 16x8, 64x4, 32x8, 128x2, 16x16, 64x8, times the
-        // occupancy variants of the storage type
-        const BatchShape shapes[8] = {{64, 1, 0}, {32, 1, 0}, {16, 1, 0}, {64, 2, 0},
-                                      {32, 2, 0}, {128, 2, 0}, {16, 2, 0}, {64, 4, 0}};
+        // tiles px x (cells per row group / px) yw, times the occupancy variants of the storage type:
+        // pair layout (FP64, FP16: 128 cells) 64x2, 32x4, 16x8, 64x4, 32x8, 128x2, 16x16, 64x8; quad
+        // layout (FP32: 256 cells) 64x4, 32x8, 16x16, 128x2, 64x8, 32x16, 128x4, 16x32
+        const BatchShape pair_shapes[8] = {{64, 1, 0}, {32, 1, 0}, {16, 1, 0}, {64, 2, 0},
+                                           {32, 2, 0}, {128, 2, 0}, {16, 2, 0}, {64, 4, 0}};
+        const BatchShape quad_shapes[8] = {{64, 1, 0}, {32, 1, 0}, {16, 1, 0}, {128, 1, 0},
+                                           {64, 2, 0}, {32, 2, 0}, {128, 2, 0}, {16, 2, 0}};
+        const BatchShape* shapes = rmhd::quad_storage(B->storage) ? quad_shapes : pair_shapes;
         float best_ms = 1e30f;
-        for (const BatchShape& sh : shapes)
+        for (int si = 0; si < 8; ++si)
             for (int waves : {2, 3}) {
+                const BatchShape& sh = shapes[si];
                 if (waves == 3 && B->storage != RMHDLB_STORE_F32) continue;
                 B->px = sh.px;
                 B->yw = sh.yw;

@@ -92,6 +92,51 @@ struct Consts {
     double* vmax_part;   // largest |beta| per wavefront of the step, reduced after it
 };
 
+// Layout of the distributions in a state buffer.  Element indices are
+// relative to the buffer's distribution pointer, which sits g0 elements into
+// the buffer (the ghost planes of a driven face take the g0 positions in
+// front of cell 0 of every array; position p = g0 + c of cell c).
+//  - FP64 and FP16 (pair layout): direction i as pairs (f_i, g_i), pair of
+//    cell c at 2 (i S + p); Maxwell population k as its own array at
+//    (38 + k) S + p.
+//  - FP32 (quad layout): direction slot s = 1..9 holds the opposite
+//    directions 2s - 1 (e) and 2s (-e) as quads (f_{2s-1}, g_{2s-1}, f_{2s},
+//    g_{2s}) at 4 (s S + p), slot 0 the rest pair (f_0, g_0, 0, 0); the moving
+//    Maxwell populations 2m and 2m + 1, which stream from the same cell, as
+//    pairs at 40 S + 2 (m S + p), the rest one at 64 S + p.  One lane then
+//    reads both directions of a slot, and both populations of a pair, with one
+//    load per stencil point.
+constexpr int QUAD_SLOTS = 10;           // quad layout: 40 S elements of f and g
+constexpr int QUAD_DIST_ARRAYS = 65;     // quad layout: distribution block of 65 S elements
+constexpr int PAIR_DIST_ARRAYS = 63;     // pair layout: 38 S of f, g and 25 S of h
+__host__ __device__ inline int64_t quad_index(const Consts& K, int slot, int64_t c) {
+    return 4 * ((int64_t)slot * K.stride + c) + 3 * K.g0;
+}
+__host__ __device__ inline int64_t hpair_index(const Consts& K, int m, int64_t c) {
+    return 4 * (int64_t)QUAD_SLOTS * K.stride + 2 * ((int64_t)m * K.stride + c) + K.g0;
+}
+__host__ __device__ inline int64_t hrest_quad_index(const Consts& K, int64_t c) {
+    return (4 * (int64_t)QUAD_SLOTS + QH) * K.stride + c;
+}
+// Direction i of the quad layout: its slot and its position (0 or 2) in the quad.
+__host__ __device__ constexpr int quad_slot(int i) { return (i + 1) / 2; }
+__host__ __device__ constexpr int quad_pos(int i) { return (i == 0 || (i & 1)) ? 0 : 2; }
+
+// The pairings the quad layout relies on: slot s holds e_{2s-1} and its opposite; the Maxwell
+// populations 2m and 2m + 1 share the streaming offset and have opposite e and b.
+__host__ __device__ constexpr bool quad_pairings_hold() {
+    for (int s = 1; s <= 9; ++s)
+        if (EX[2 * s] != -EX[2 * s - 1] || EY[2 * s] != -EY[2 * s - 1] || EZ[2 * s] != -EZ[2 * s - 1]) return false;
+    for (int m = 0; m < 12; ++m) {
+        const int a = 2 * m, b = 2 * m + 1;
+        if (SX[a] != SX[b] || SY[a] != SY[b] || SZ[a] != SZ[b]) return false;
+        if (EHX[a] != -EHX[b] || EHY[a] != -EHY[b] || EHZ[a] != -EHZ[b]) return false;
+        if (BHX[a] != -BHX[b] || BHY[a] != -BHY[b] || BHZ[a] != -BHZ[b]) return false;
+    }
+    return true;
+}
+static_assert(quad_pairings_hold(), "the lattice tables no longer pair opposite directions");
+
 constexpr double KAPPA = 0.83887049280786108;   // sqrt(19/27)
 constexpr double KAPPA2 = 19.0 / 27.0;
 constexpr double SQRT19_3 = 2.5166114784235836; // sqrt(19/3)

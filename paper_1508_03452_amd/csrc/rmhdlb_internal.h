@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rmhdlb.h"
 #include "rmhdlb_device.h"
 
 namespace rmhd {
@@ -204,7 +205,11 @@ hipError_t launch_face_b(const StateBuf& src, const Consts& K, double* faceB, hi
 // Launch geometry of the fused step for a tile width px, zb planes per block
 // and zg blocks per column and chunk of zg * zb planes: tiles along x,
 // columns, blocks.
-void step_geometry(const Consts& K, int px, int zb, int zg, int yw, int& tiles_x, int& ncol, int& nblk);
+void step_geometry(const Consts& K, int px, int zb, int zg, int yw, int cpb, int& tiles_x, int& ncol, int& nblk);
+// Cells per row group of a fused-step block: 128 in the pair layout (FP64 and FP16 storage, two lanes
+// per cell), 256 in the quad layout (FP32 storage, one lane per cell).
+inline int cells_per_block(bool quad) { return quad ? 256 : 128; }
+inline bool quad_storage(int32_t storage) { return storage == RMHDLB_STORE_F32; }
 // One batched step (face pass of the instances that need it, then the fused
 // step of all) reading buffer `parity` of every instance; px the tile width
 // (128, 64, 32, 16), waves the occupancy variant (FP32: 2 or 3).
@@ -219,6 +224,8 @@ hipError_t launch_guess_normalise(const double* F, const double* T, int ns, cons
 hipError_t launch_train(const TrainArgs& A, hipStream_t s);
 template <typename TS>
 hipError_t launch_init(const InPtrs& in, const Consts& K, double* scr, const StateBuf& dst, hipStream_t s);
+// Plain copy of n16 16-byte words (the HBM reference rate).
+hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
 template <typename TS>
 hipError_t launch_export(const StateBuf& src, double* dst, const Consts& K, hipStream_t s);
 template <typename TS>

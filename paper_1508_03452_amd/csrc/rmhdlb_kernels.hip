@@ -1,11 +1,12 @@
 // rmhdlb_kernels.hip -- gfx950 kernels of the resistive relativistic MHD
 // lattice Boltzmann step (arXiv:1508.03452, Sec. III).
 //
-// Layout in HBM: structure of arrays, one array per population, x fastest.
-// A state buffer holds the 63 distribution arrays (F[0..18], G[0..18],
-// h*[0..24]) of storage type TS, then (256-byte aligned) the 3 E_prev arrays
-// of type TE (TS, or FP32 when TS is FP16); two buffers, read one and write
-// the other.  The stored state is post-collision.  On the FP32 and FP16
+// Layout in HBM: structure of arrays, x fastest.  A state buffer holds the
+// distributions F[0..18], G[0..18], h*[0..24] of storage type TS, interleaved
+// as (f_i, g_i) pairs (FP64 and FP16, 63 arrays) or as quads of opposite
+// directions (FP32, 65 arrays; the layouts are described in rmhdlb_device.h),
+// then (256-byte aligned) the 3 E_prev arrays of type TE (TS, or FP32 when TS
+// is FP16); two buffers, read one and write the other.  The stored state is post-collision.  On the FP32 and FP16
 // storage paths F and G are stored as deviations from w_i E_ref and
 // w'_i N_ref (references from the initial fields) and the step runs in FP32
 // arithmetic, with the recovery and the Ohm solve in FP64.
@@ -79,6 +80,35 @@ __device__ __forceinline__ void st2(T* __restrict__ p, V f, V g) {
         __builtin_nontemporal_store(v, reinterpret_cast<vec2<T>*>(p));
     else
         *reinterpret_cast<vec2<T>*>(p) = v;
+}
+
+// FP32 storage uses the quad layout, FP64 and FP16 the pair layout (see
+// rmhdlb_device.h): one lane per cell runs FP32 1.4x faster than two, and
+// FP16 3 % slower (its narrower loads leave fewer to save, and a lane that
+// carries the whole cell holds FP16 to 2 waves per SIMD instead of 3).  Element indices of f_i, g_i and h_k of cell c (c may be a
+// ghost cell of a driven face, down to -g0), for the kernels that read or
+// write single values.
+template <typename TS>
+constexpr bool quad_layout() {
+    return sizeof(TS) == 4;
+}
+template <typename TS>
+__device__ __forceinline__ int64_t f_at(const Consts& K, int i, int64_t c) {
+    if constexpr (quad_layout<TS>())
+        return quad_index(K, quad_slot(i), c) + quad_pos(i);
+    else
+        return fg_index(K, i, c);
+}
+template <typename TS>
+__device__ __forceinline__ int64_t g_at(const Consts& K, int i, int64_t c) {
+    return f_at<TS>(K, i, c) + 1;
+}
+template <typename TS>
+__device__ __forceinline__ int64_t h_at(const Consts& K, int k, int64_t c) {
+    if constexpr (quad_layout<TS>())
+        return k < QH ? hpair_index(K, k / 2, c) + (k & 1) : hrest_quad_index(K, c);
+    else
+        return (int64_t)(OFF_H + k) * K.stride + c;
 }
 
 // Shift of the stored f, g of direction i (0 on the plain FP64 path).
@@ -319,9 +349,13 @@ __device__ __forceinline__ void macroscopic(const TS* __restrict__ src, const TE
     double t0x = 0, t0y = 0, t0z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const TS* __restrict__ fga = src + fg_index(K, i, cell);
-        auto fg = [&](int o) { return ldv2<double>(fga, 2 * (int64_t)o); };
-        auto fo = [&](int o) { return ld(fga, 2 * (int64_t)o); };
+        auto fg = [&](int o) {
+            vec2<double> r;
+            r.x = ld(src, f_at<TS>(K, i, (int64_t)cell + o));
+            r.y = ld(src, g_at<TS>(K, i, (int64_t)cell + o));
+            return r;
+        };
+        auto fo = [&](int o) { return ld(src, f_at<TS>(K, i, (int64_t)cell + o)); };
         const vec2<double> c0 = fg(0);
         const double f0 = c0.x, g0 = c0.y;
         double fv = f0, gv = g0;
@@ -375,8 +409,7 @@ __device__ __forceinline__ void macroscopic(const TS* __restrict__ src, const TE
     double ehx = 0, ehy = 0, ehz = 0, bx = 0, by = 0, bz = 0, hs = 0;
 #pragma unroll
     for (int k = 0; k < QH; ++k) {
-        const TS* __restrict__ ha = src + (int64_t)(OFF_H + k) * K.stride + cell;
-        const double h = ld(ha, nb.at(-SX[k], -SY[k], -SZ[k]));
+        const double h = ld(src, h_at<TS>(K, k, (int64_t)cell + nb.at(-SX[k], -SY[k], -SZ[k])));
         M.H[k] = h;
         hs += h;
         if (EHX[k]) ehx += EHX[k] * h;
@@ -386,7 +419,7 @@ __device__ __forceinline__ void macroscopic(const TS* __restrict__ src, const TE
         if (BHY[k]) by += BHY[k] * h;
         if (BHZ[k]) bz += BHZ[k] * h;
     }
-    M.H[QH] = ld(src + (int64_t)(OFF_H + QH) * K.stride + cell, 0);
+    M.H[QH] = ld(src, h_at<TS>(K, QH, cell));
     const double ec = K.c * INV_SQRT2;  // |e_k| / |ehat_k|
     M.Epr[0] = ec * ehx;
     M.Epr[1] = ec * ehy;
@@ -799,6 +832,276 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
     }
 }
 
+// ---------------------------------------------------- one lane per cell
+
+template <typename T>
+using vec4 = T __attribute__((ext_vector_type(4)));
+
+template <typename V, typename T>
+__device__ __forceinline__ vec4<V> ldv4(const T* __restrict__ p, int64_t i) {
+    const vec4<T> v = *reinterpret_cast<const vec4<T>*>(p + i);
+    vec4<V> r;
+    r.x = static_cast<V>(v.x);
+    r.y = static_cast<V>(v.y);
+    r.z = static_cast<V>(v.z);
+    r.w = static_cast<V>(v.w);
+    return r;
+}
+
+template <bool NT, typename T, typename V>
+__device__ __forceinline__ void st4(T* __restrict__ p, V a, V b, V c, V d) {
+    vec4<T> v;
+    v.x = static_cast<T>(a);
+    v.y = static_cast<T>(b);
+    v.z = static_cast<T>(c);
+    v.w = static_cast<T>(d);
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, reinterpret_cast<vec4<T>*>(p));
+    else
+        *reinterpret_cast<vec4<T>*>(p) = v;
+}
+
+// f/g slots whose loads may be in flight together in the one-lane-per-cell step
+#ifndef RMHDLB_QGROUP
+#define RMHDLB_QGROUP 1
+#endif
+
+// The fused step of one cell in one lane (FP32 storage, quad layout):
+// slot s = 1..9 carries the opposite directions i0 = 2s - 1 (+e) and
+// i1 = 2s (-e), and one load per point of the link x - 2e .. x + 2e and of the
+// Laplacian serves both; the Maxwell populations 2m, 2m + 1 come from one load
+// of the cell they stream from.  The arithmetic per direction is that of
+// pair_cell (the readings it implements are listed there); only the
+// assignment of work to lanes and the order of the moment sums differ.
+template <bool NT, typename TS, typename TE, typename V, int GM, int VR = 0>
+__device__ __forceinline__ void quad_cell(const TS* __restrict__ sd, const TE* __restrict__ se, TS* __restrict__ dd,
+                                          TE* __restrict__ de, const double* __restrict__ faceB,
+                                          const GuessTables* __restrict__ gt, const Consts& K, int cell,
+                                          const Nbr& nb, int x, int y, int z, bool active, double& bmax) {
+    auto put = [&](auto* p, auto v) {
+        if (active) st<NT>(p, v);
+    };
+    const int64_t S = K.stride;
+    constexpr int CM = VR & 1;
+    const V cour = (V)K.cour, kv = (V)K.kv, slope = (VR & 2) ? (V)K.slope : V(0.5);
+    V Fv[Q], Gv[Q], Hv[QH + 1];
+    V t00, t0x = 0, t0y = 0, t0z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0, n0;
+    {
+        const vec2<V> fg0 = ldv2<V>(sd, quad_index(K, 0, cell));
+        Fv[0] = fg0.x;
+        Gv[0] = fg0.y;
+        t00 = Fv[0];
+        n0 = Gv[0];
+    }
+    const int lap_xp = nb.at(1, 0, 0), lap_xm = nb.at(-1, 0, 0), lap_yp = nb.at(0, 1, 0), lap_ym = nb.at(0, -1, 0),
+              lap_zp = nb.at(0, 0, 1), lap_zm = nb.at(0, 0, -1);
+    static_for<1>([&](auto ic) {
+        constexpr int s = decltype(ic)::value;
+        if constexpr (s <= 9) {
+            constexpr int i0 = 2 * s - 1, i1 = 2 * s;
+            constexpr int ex = EX[i0], ey = EY[i0], ez = EZ[i0];
+            const TS* __restrict__ qa = sd + quad_index(K, s, 0);  // uniform base of slot s
+            auto ldq = [&](int off) { return ldv4<V>(qa, 4 * (int64_t)(cell + off)); };
+            const vec4<V> q0 = ldq(0), qm2 = ldq(nb.at(-2 * ex, -2 * ey, -2 * ez)), qm1 = ldq(nb.at(-ex, -ey, -ez)),
+                          qp1 = ldq(nb.at(ex, ey, ez)), qp2 = ldq(nb.at(2 * ex, 2 * ey, 2 * ez));
+            // the Laplacian's six neighbours (f of both directions); on an axis slot two of them are the
+            // link points x -+ e
+            constexpr bool axis_slot = (ex != 0) + (ey != 0) + (ez != 0) == 1;
+            vec4<V> lxp, lxm, lyp, lym, lzp, lzm;
+            if constexpr (axis_slot && ex != 0) {
+                lxp = qp1;
+                lxm = qm1;
+            } else {
+                lxp = ldq(lap_xp);
+                lxm = ldq(lap_xm);
+            }
+            if constexpr (axis_slot && ey != 0) {
+                lyp = qp1;
+                lym = qm1;
+            } else {
+                lyp = ldq(lap_yp);
+                lym = ldq(lap_ym);
+            }
+            if constexpr (axis_slot && ez != 0) {
+                lzp = qp1;
+                lzm = qm1;
+            } else {
+                lzp = ldq(lap_zp);
+                lzm = ldq(lap_zm);
+            }
+            // +e: upwind stencil x - 2e, x - e, x, x + e; -e: x + 2e, x + e, x, x - e
+            const V lap0 = (lxp.x + lxm.x) + (lyp.x + lym.x) + (lzp.x + lzm.x) - V(6) * q0.x;
+            const V lap1 = (lxp.z + lxm.z) + (lyp.z + lym.z) + (lzp.z + lzm.z) - V(6) * q0.z;
+            const V fv0 = q0.x - cour * ((q0.x + slope * minmod(q0.x - qm1.x, qp1.x - q0.x)) -
+                                         (qm1.x + slope * minmod(qm1.x - qm2.x, q0.x - qm1.x))) + kv * lap0;
+            const V fv1 = q0.z - cour * ((q0.z + slope * minmod(q0.z - qp1.z, qm1.z - q0.z)) -
+                                         (qp1.z + slope * minmod(qp1.z - qp2.z, q0.z - qp1.z))) + kv * lap1;
+            const V gv0 = q0.y - cour * ((q0.y + slope * minmod(q0.y - qm1.y, qp1.y - q0.y)) -
+                                         (qm1.y + slope * minmod(qm1.y - qm2.y, q0.y - qm1.y)));
+            const V gv1 = q0.w - cour * ((q0.w + slope * minmod(q0.w - qp1.w, qm1.w - q0.w)) -
+                                         (qp1.w + slope * minmod(qp1.w - qp2.w, q0.w - qp1.w)));
+            Fv[i0] = fv0;
+            Fv[i1] = fv1;
+            Gv[i0] = gv0;
+            Gv[i1] = gv1;
+            if constexpr (s % RMHDLB_QGROUP == 0 || s == 9)
+                asm volatile("" : "+v"(Fv[i0]), "+v"(Fv[i1]), "+v"(Gv[i0]), "+v"(Gv[i1])::"memory");
+            const V sum = fv0 + fv1, dif = fv0 - fv1;
+            t00 += sum;
+            n0 += gv0 + gv1;
+            if (ex) t0x += ex * dif;
+            if (ey) t0y += ey * dif;
+            if (ez) t0z += ez * dif;
+            if (ex) txx += sum;
+            if (ey) tyy += sum;
+            if (ez) tzz += sum;
+            if (ex * ey) txy += (ex * ey) * sum;
+            if (ex * ez) txz += (ex * ez) * sum;
+            if (ey * ez) tyz += (ey * ez) * sum;
+        }
+    });
+    // stream h (Eq. LB_Maxwell): the pair 2m, 2m + 1 from its common source cell
+    V ehx = 0, ehy = 0, ehz = 0, bx = 0, by = 0, bz = 0, hs = 0;
+#pragma unroll
+    for (int m = 0; m < 12; ++m) {
+        const int k0 = 2 * m;
+        const vec2<V> v = ldv2<V>(sd, hpair_index(K, m, (int64_t)cell + nb.at(-SX[k0], -SY[k0], -SZ[k0])));
+        Hv[k0] = v.x;
+        Hv[k0 + 1] = v.y;
+        hs += v.x + v.y;
+        const V d = v.x - v.y;  // population 2m + 1 has the opposite e and b
+        if (EHX[k0]) ehx += EHX[k0] * d;
+        if (EHY[k0]) ehy += EHY[k0] * d;
+        if (EHZ[k0]) ehz += EHZ[k0] * d;
+        if (BHX[k0]) bx += BHX[k0] * d;
+        if (BHY[k0]) by += BHY[k0] * d;
+        if (BHZ[k0]) bz += BHZ[k0] * d;
+    }
+    Hv[QH] = ldv<V>(sd, hrest_quad_index(K, cell));
+    CellSol M;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) M.Ep[a] = ld(se + (int64_t)a * S + cell, 0);
+    {
+        const TE* ex_ = se + cell;
+        const TE* ey_ = se + S + cell;
+        const TE* ez_ = se + 2 * S + cell;
+        const double dv = ((ld(ex_, lap_xp) - ld(ex_, lap_xm)) + (ld(ey_, lap_yp) - ld(ey_, lap_ym))) +
+                          (ld(ez_, lap_zp) - ld(ez_, lap_zm));
+        M.rho_g = K.eps0 * K.inv_2dx * dv;
+    }
+    M.T00 = K.fs0 + (double)t00;
+    M.N0 = K.gs0 + (double)n0;
+    M.T0[0] = KAPPA * (double)t0x;
+    M.T0[1] = KAPPA * (double)t0y;
+    M.T0[2] = KAPPA * (double)t0z;
+    M.Tab[0] = KAPPA2 * (K.fsaa + (double)txx);
+    M.Tab[1] = KAPPA2 * (K.fsaa + (double)tyy);
+    M.Tab[2] = KAPPA2 * (K.fsaa + (double)tzz);
+    M.Tab[3] = KAPPA2 * (double)txy;
+    M.Tab[4] = KAPPA2 * (double)txz;
+    M.Tab[5] = KAPPA2 * (double)tyz;
+    const double ec = K.c * INV_SQRT2;
+    M.Epr[0] = ec * (double)ehx;
+    M.Epr[1] = ec * (double)ehy;
+    M.Epr[2] = ec * (double)ehz;
+    M.B[0] = (double)bx;
+    M.B[1] = (double)by;
+    M.B[2] = (double)bz;
+    // h* = 2 h_eq - h: the B part of h_eq (of the streamed B) now
+    {
+        const V sb0 = (V)M.B[0], sb1 = (V)M.B[1], sb2 = (V)M.B[2];
+#pragma unroll
+        for (int m = 0; m < 12; ++m) {
+            const int k0 = 2 * m;
+            const V bb = V(0.25) * (BHX[k0] * sb0 + BHY[k0] * sb1 + BHZ[k0] * sb2);
+            Hv[k0] -= bb;
+            Hv[k0 + 1] += bb;
+        }
+    }
+    M.rho = (double)(Hv[QH] + hs);
+    if (K.divb) apply_face_b(K, faceB, x, y, z, M.B);
+    FeqCellT<V> fe;
+    if constexpr ((VR & 8) != 0) {
+        double Bp[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Bp[a] = ld(se + (int64_t)(3 + a) * S + cell, 0);
+        solve_cell<GM>(K, M, Bp, gt);
+        fe.setup(M.eps, M.p, M.gam, M.beta, M.Ep, Bp, K.c, K.eps0);
+    } else {
+        solve_cell<GM>(K, M, M.B, gt);
+        fe.setup(M.eps, M.p, M.gam, M.beta, M.Ep, M.B, K.c, K.eps0);
+    }
+
+    // collisions and stores (new deviations)
+    const V rate = (V)(M.gam * K.inv_tau);
+    const V wg = (V)K.wg, inv1wg = (V)(1.0 / (1.0 + K.wg));
+    const V ng = (V)(M.n * M.gam);
+    const V gc1 = (V)K.gc1, gc2 = (V)K.gc2, gc3b2 = (V)(K.gc3 * (M.beta[0] * M.beta[0] + M.beta[1] * M.beta[1] +
+                                                              M.beta[2] * M.beta[2]));
+    const V bx_ = (V)M.beta[0], by_ = (V)M.beta[1], bz_ = (V)M.beta[2];
+    double fw = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    if constexpr ((VR & 4) != 0) {
+        bmax = fmax(bmax, sqrt(M.beta[0] * M.beta[0] + M.beta[1] * M.beta[1] + M.beta[2] * M.beta[2]));
+        if (!(K.fgate > 0.0) || *K.vmax_prev < K.fgate) {
+            const double cdt = K.dx * INV_SQRT2;  // c dt
+            fx = cdt * K.force[cell];
+            fy = cdt * K.force[K.N + cell];
+            fz = cdt * K.force[2 * K.N + cell];
+            fw = fx * M.beta[0] + fy * M.beta[1] + fz * M.beta[2];
+        }
+    }
+    {
+        const V q0 = (V)K.fsh[0] - fe.template eq<0>();
+        const V geq0 = (V)K.wp[0] * ng * (V(1) - gc3b2);
+        V f0n = CM == 0 ? Fv[0] - rate * (Fv[0] + q0) : (Fv[0] - rate * q0) / (V(1) + rate);
+        if constexpr ((VR & 4) != 0) f0n += (V)fw;
+        if (active) st2<NT>(dd + quad_index(K, 0, cell), f0n, (Gv[0] + wg * (geq0 - (V)K.gsh[0])) * inv1wg);
+    }
+    put(dd + hrest_quad_index(K, cell), (V)(2.0 * M.rho) - Hv[QH]);
+    static_for<1>([&](auto ic) {
+        constexpr int s = decltype(ic)::value;
+        if constexpr (s <= 9) {
+            constexpr int i0 = 2 * s - 1, i1 = 2 * s;
+            constexpr int cls = i0 <= 6 ? 1 : 2;
+            const V eb = EX[i0] * bx_ + EY[i0] * by_ + EZ[i0] * bz_;  // e_i0 . beta; -eb for i1
+            const V q_0 = (V)K.fsh[cls] - feq_signed<i0>(fe, V(1));
+            const V q_1 = (V)K.fsh[cls] - feq_signed<i0>(fe, V(-1));
+            const V om0 = rate * (V(1) - V(KAPPA) * eb), om1 = rate * (V(1) + V(KAPPA) * eb);
+            const V ebb = gc2 * eb * eb - gc3b2;
+            const V geq_0 = (V)K.wp[cls] * ng * (V(1) + gc1 * eb + ebb);
+            const V geq_1 = (V)K.wp[cls] * ng * (V(1) - gc1 * eb + ebb);
+            V fn0 = CM == 0 ? Fv[i0] - om0 * (Fv[i0] + q_0) : (Fv[i0] - om0 * q_0) / (V(1) + om0);
+            V fn1 = CM == 0 ? Fv[i1] - om1 * (Fv[i1] + q_1) : (Fv[i1] - om1 * q_1) / (V(1) + om1);
+            if constexpr ((VR & 4) != 0) {
+                constexpr double wcls = cls == 1 ? 99.0 / 722.0 : 9.0 / 361.0;  // D3Q19 weights
+                const double fe_ = (19.0 / 9.0) * wcls / KAPPA * (EX[i0] * fx + EY[i0] * fy + EZ[i0] * fz);
+                fn0 += (V)fe_;
+                fn1 += (V)(-fe_);
+            }
+            if (active)
+                st4<NT>(dd + quad_index(K, s, cell), fn0, (Gv[i0] + wg * (geq_0 - (V)K.gsh[cls])) * inv1wg, fn1,
+                        (Gv[i1] + wg * (geq_1 - (V)K.gsh[cls])) * inv1wg);
+        }
+    });
+    const V cj = (V)(1.0 / (16.0 * 1.4142135623730951 * K.c)), ce = (V)(1.0 / (8.0 * 1.4142135623730951 * K.c));
+    const V J0 = (V)M.J[0], J1 = (V)M.J[1], J2 = (V)M.J[2];
+    const V E0 = (V)M.E[0], E1 = (V)M.E[1], E2 = (V)M.E[2];
+#pragma unroll
+    for (int m = 0; m < 12; ++m) {
+        const int k0 = 2 * m;
+        const V hj = cj * (SX[k0] * J0 + SY[k0] * J1 + SZ[k0] * J2);
+        const V he = ce * (EHX[k0] * E0 + EHY[k0] * E1 + EHZ[k0] * E2);
+        if (active)
+            st2<NT>(dd + hpair_index(K, m, cell), V(2) * (hj + he) - Hv[k0], V(2) * (hj - he) - Hv[k0 + 1]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) put(de + (int64_t)a * S + cell, M.E[a]);
+    if constexpr ((VR & 8) != 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) put(de + (int64_t)(3 + a) * S + cell, M.B[a]);
+    }
+}
+
 // ------------------------------------------------------------------ kernels
 
 // One block owns a PXT x (128 / PXT) group of rows of cells (two lanes per
@@ -819,13 +1122,17 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
                                             TS* __restrict__ dd, TE* __restrict__ de,
                                             const double* __restrict__ faceB, const GuessTables* __restrict__ gt,
                                             const Consts& K, int tiles_x, int ncol, int zb, int zg, int yw, int b) {
-    constexpr int PYT = 128 / PXT;
+    // pair layout (FP64, FP16): 128 cells per row group, two lanes each; quad layout (FP32): 256 cells,
+    // one lane each
+    constexpr bool ONE = quad_layout<TS>();
+    constexpr int PYT = (ONE ? 256 : 128) / PXT;
     const int per = ncol * zg, zc = b / per, r = b % per;
     const int col = r / zg, zoff = r % zg;
     const int tx = col % tiles_x, ty = col / tiles_x;
-    // cell c of a row group is lane c % 32 (h = 0) and lane c % 32 + 32 (h = 1) of wavefront c / 32
+    // pair layout: cell c of a row group is lane c % 32 (h = 0) and lane c % 32 + 32 (h = 1) of
+    // wavefront c / 32; quad layout: cell c is thread c
     const int lane = threadIdx.x & 63;
-    const int c = (threadIdx.x >> 6) * 32 + (lane & 31), h = lane >> 5;
+    const int c = ONE ? (int)threadIdx.x : (int)(threadIdx.x >> 6) * 32 + (lane & 31), h = ONE ? 0 : lane >> 5;
     const int xr = tx * PXT + (c % PXT);
     int x = xr;
     const int ybase = ty * PYT * yw + c / PXT;
@@ -860,8 +1167,12 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
             if constexpr (opaque) asm volatile("" : "+v"(xp), "+v"(yp), "+v"(hp));
             const int cell = xp + K.nx * (yp + K.ny * z);
             const Nbr nb = make_nbr<true>(K, xp, yp, z);
-            pair_cell<NT, TS, TE, V, GM, VR>(sd, se, dd, de, faceB, gt, K, cell, nb, hp, xp, yp, z,
-                                             all_lanes ? active : true, bmax);
+            if constexpr (ONE)
+                quad_cell<NT, TS, TE, V, GM, VR>(sd, se, dd, de, faceB, gt, K, cell, nb, xp, yp, z,
+                                                 all_lanes ? active : true, bmax);
+            else
+                pair_cell<NT, TS, TE, V, GM, VR>(sd, se, dd, de, faceB, gt, K, cell, nb, hp, xp, yp, z,
+                                                 all_lanes ? active : true, bmax);
         }
     }
     if constexpr ((VR & 4) != 0) {
@@ -925,7 +1236,7 @@ __device__ __forceinline__ double streamed_B(const TS* __restrict__ src, const C
 #pragma unroll
     for (int k = 0; k < QH; ++k) {
         const int bk = comp == 0 ? BHX[k] : (comp == 1 ? BHY[k] : BHZ[k]);
-        if (bk) b += bk * ld(src + (int64_t)(OFF_H + k) * K.stride + cell, nb.at(-SX[k], -SY[k], -SZ[k]));
+        if (bk) b += bk * ld(src, h_at<TS>(K, k, (int64_t)cell + nb.at(-SX[k], -SY[k], -SZ[k])));
     }
     return b;
 }
@@ -1238,17 +1549,18 @@ __global__ __launch_bounds__(TPB) void k_init_ghost(FacePtrs in, Consts K, TS* _
             constexpr int q = decltype(ic)::value;
             const double eb = EX[q] * beta[0] + EY[q] * beta[1] + EZ[q] * beta[2];
             const double wpi = q == 0 ? K.wp[0] : (q <= 6 ? K.wp[1] : K.wp[2]);
-            st2<false>(dd + fg_index(K, q, g), fe.template eq<q>() - fshift(K, q),
-                       wpi * n * gam * (1.0 + K.gc1 * eb + K.gc2 * eb * eb - K.gc3 * b2) - gshift(K, q));
+            dd[f_at<TS>(K, q, g)] = static_cast<TS>(fe.template eq<q>() - fshift(K, q));
+            dd[g_at<TS>(K, q, g)] =
+                static_cast<TS>(wpi * n * gam * (1.0 + K.gc1 * eb + K.gc2 * eb * eb - K.gc3 * b2) - gshift(K, q));
         });
 #pragma unroll
         for (int k = 0; k < QH; ++k) {
             const double heq = cj * (SX[k] * J[0] + SY[k] * J[1] + SZ[k] * J[2]) +
                                ce * (EHX[k] * Epr[0] + EHY[k] * Epr[1] + EHZ[k] * Epr[2]) +
                                0.125 * (BHX[k] * Bv[0] + BHY[k] * Bv[1] + BHZ[k] * Bv[2]);
-            dd[(int64_t)(OFF_H + k) * K.stride + g] = static_cast<TS>(heq);
+            dd[h_at<TS>(K, k, g)] = static_cast<TS>(heq);
         }
-        dd[(int64_t)(OFF_H + QH) * K.stride + g] = static_cast<TS>(0.0);
+        dd[h_at<TS>(K, QH, g)] = static_cast<TS>(0.0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) de[(int64_t)a * K.stride + g] = static_cast<TE>(E[a]);
         if (K.bprev)
@@ -1325,8 +1637,9 @@ __global__ __launch_bounds__(TPB) void k_init_state(InPtrs in, Consts K, int til
         constexpr int i = decltype(ic)::value;
         const double eb = EX[i] * beta[0] + EY[i] * beta[1] + EZ[i] * beta[2];
         const double wpi = i == 0 ? K.wp[0] : (i <= 6 ? K.wp[1] : K.wp[2]);
-        st2<false>(dst + fg_index(K, i, cell), fe.template eq<i>() - fshift(K, i),
-                   wpi * n * gam * (1.0 + K.gc1 * eb + K.gc2 * eb * eb - K.gc3 * b2) - gshift(K, i));
+        dst[f_at<TS>(K, i, cell)] = static_cast<TS>(fe.template eq<i>() - fshift(K, i));
+        dst[g_at<TS>(K, i, cell)] =
+            static_cast<TS>(wpi * n * gam * (1.0 + K.gc1 * eb + K.gc2 * eb * eb - K.gc3 * b2) - gshift(K, i));
     });
     const double cj = 1.0 / (16.0 * 1.4142135623730951 * c), ce = 1.0 / (8.0 * 1.4142135623730951 * c);
 #pragma unroll
@@ -1336,7 +1649,7 @@ __global__ __launch_bounds__(TPB) void k_init_state(InPtrs in, Consts K, int til
         const double P0 = scr[3 * K.N + t], P1 = scr[4 * K.N + t], P2 = scr[5 * K.N + t];
         const double heq = cj * (SX[k] * J0 + SY[k] * J1 + SZ[k] * J2) + ce * (EHX[k] * P0 + EHY[k] * P1 + EHZ[k] * P2) +
                            0.125 * (BHX[k] * in.B[0][t] + BHY[k] * in.B[1][t] + BHZ[k] * in.B[2][t]);
-        dst[(int64_t)(OFF_H + k) * K.stride + cell] = static_cast<TS>(heq);
+        dst[h_at<TS>(K, k, cell)] = static_cast<TS>(heq);
     }
     double rho;
     if (in.rho_c) {
@@ -1347,7 +1660,7 @@ __global__ __launch_bounds__(TPB) void k_init_state(InPtrs in, Consts K, int til
                (in.E[1][cell + nb.at(0, 1, 0)] - in.E[1][cell + nb.at(0, -1, 0)]) +
                (in.E[2][cell + nb.at(0, 0, 1)] - in.E[2][cell + nb.at(0, 0, -1)]));
     }
-    dst[(int64_t)(OFF_H + QH) * K.stride + cell] = static_cast<TS>(rho);
+    dst[h_at<TS>(K, QH, cell)] = static_cast<TS>(rho);
 #pragma unroll
     for (int a = 0; a < 3; ++a) edst[(int64_t)a * K.stride + cell] = static_cast<TE>(Ep[a]);
     if (K.bprev)
@@ -1364,11 +1677,11 @@ __global__ void k_export(const TS* __restrict__ s, const TE* __restrict__ se, do
     if (a < OFF_E) {
         double v;
         if (a < OFF_G)
-            v = static_cast<double>(s[fg_index(K, (int)a, cell)]) + fshift(K, (int)a);
+            v = static_cast<double>(s[f_at<TS>(K, (int)a, cell)]) + fshift(K, (int)a);
         else if (a < OFF_H)
-            v = static_cast<double>(s[fg_index(K, (int)(a - OFF_G), cell) + 1]) + gshift(K, (int)(a - OFF_G));
+            v = static_cast<double>(s[g_at<TS>(K, (int)(a - OFF_G), cell)]) + gshift(K, (int)(a - OFF_G));
         else
-            v = static_cast<double>(s[a * K.stride + cell]);
+            v = static_cast<double>(s[h_at<TS>(K, (int)(a - OFF_H), cell)]);
         d[i] = v;
     } else {
         d[i] = static_cast<double>(se[(a - OFF_E) * K.stride + cell]);
@@ -1382,11 +1695,11 @@ __global__ void k_import(const double* __restrict__ s, TS* __restrict__ d, TE* _
     const int64_t a = i / K.N, cell = i - a * K.N;
     if (a < OFF_E) {
         if (a < OFF_G)
-            d[fg_index(K, (int)a, cell)] = static_cast<TS>(s[i] - fshift(K, (int)a));
+            d[f_at<TS>(K, (int)a, cell)] = static_cast<TS>(s[i] - fshift(K, (int)a));
         else if (a < OFF_H)
-            d[fg_index(K, (int)(a - OFF_G), cell) + 1] = static_cast<TS>(s[i] - gshift(K, (int)(a - OFF_G)));
+            d[g_at<TS>(K, (int)(a - OFF_G), cell)] = static_cast<TS>(s[i] - gshift(K, (int)(a - OFF_G)));
         else
-            d[a * K.stride + cell] = static_cast<TS>(s[i]);
+            d[h_at<TS>(K, (int)(a - OFF_H), cell)] = static_cast<TS>(s[i]);
     } else {
         de[(a - OFF_E) * K.stride + cell] = static_cast<TE>(s[i]);
     }
@@ -1435,7 +1748,32 @@ __global__ __launch_bounds__(256) void k_guess_samples(const TS* __restrict__ sr
     block_sum<SAMPLE_SUMS>(acc, part + (int64_t)blockIdx.x * SAMPLE_SUMS);
 }
 
+// Plain copy of n 16-byte words, four per lane in flight, with the non-temporal
+// hints of the step's streamed loads and stores (the reference rate of HBM).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ src, u32x4* __restrict__ dst, int64_t n) {
+    const int64_t base = (int64_t)blockIdx.x * (256 * 4) + threadIdx.x;
+    u32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = base + (int64_t)u * 256;
+        if (i < n) v[u] = __builtin_nontemporal_load(src + i);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = base + (int64_t)u * 256;
+        if (i < n) __builtin_nontemporal_store(v[u], dst + i);
+    }
+}
+
 // ------------------------------------------------------------ host launchers
+
+hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s) {
+    const int64_t blocks = (n16 + 1023) / 1024;
+    if (blocks > 0)
+        hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s, (const u32x4*)src, (u32x4*)dst, n16);
+    return hipGetLastError();
+}
 
 static inline void grid_of(const Consts& K, int& tiles_x, int& tiles_y, int& ntiles, int& nblocks) {
     tiles_x = (K.nx + TX - 1) / TX;
@@ -1458,8 +1796,8 @@ hipError_t launch_face_b(const StateBuf& src, const Consts& K, double* faceB, hi
     return hipGetLastError();
 }
 
-void step_geometry(const Consts& K, int px, int zb, int zg, int yw, int& tiles_x, int& ncol, int& nblk) {
-    const int py = 128 / px * yw;
+void step_geometry(const Consts& K, int px, int zb, int zg, int yw, int cpb, int& tiles_x, int& ncol, int& nblk) {
+    const int py = cpb / px * yw;
     tiles_x = (K.nx + px - 1) / px;
     ncol = tiles_x * ((K.ny + py - 1) / py);
     nblk = ncol * zg * ((K.nz + zg * zb - 1) / (zg * zb));
@@ -1471,7 +1809,7 @@ static void launch_fused(const TS* sd, const void* se, TS* dd, void* de, double*
     using TE = typename StoreTypes<TS>::E;
     using V = typename StoreTypes<TS>::V;
     int tx, ncol, nblk;
-    step_geometry(K, PXT, zb, zg, yw, tx, ncol, nblk);
+    step_geometry(K, PXT, zb, zg, yw, cells_per_block(quad_layout<TS>()), tx, ncol, nblk);
     const int grid = ((nblk + 7) / 8) * 8;
     hipLaunchKernelGGL((k_fused_step<true, TS, TE, V, GM, PXT, VR>), dim3(grid), dim3(PTPB), 0, s, sd, (const TE*)se, dd,
                        (TE*)de, (const double*)faceB, gt, K, tx, ncol, zb, zg, yw, nblk);
@@ -1502,7 +1840,7 @@ hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K
         else
             launch_fused<TS, GUESS_NONE, 64, 4>(sd, se, dd, de, faceB, gt, K, zb, 1, 1, s);
         int tx, ncol, nblk;
-        step_geometry(K, 64, zb, 1, 1, tx, ncol, nblk);
+        step_geometry(K, 64, zb, 1, 1, cells_per_block(quad_layout<TS>()), tx, ncol, nblk);
         hipLaunchKernelGGL(k_vmax_reduce, dim3(1), dim3(TPB), 0, s, K.vmax_part, (int64_t)nblk * (PTPB / 64),
                            const_cast<double*>(K.vmax_prev));
     } else if (vr) {  // the alternative readings: 64-wide tiles, no guess
@@ -1513,8 +1851,12 @@ hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K
             launch_fused<TS, GUESS_NONE, 64, 2>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
         else
             launch_fused<TS, GUESS_NONE, 64, 3>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
-    } else if (gt)  // the guess path is built for 64-wide tiles only
-        launch_fused<TS, GUESS_PAIR, 64>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
+    } else if (gt) {  // the guess path is built for 64-wide tiles only; one cell per lane in the quad layout
+        if constexpr (quad_layout<TS>())
+            launch_fused<TS, GUESS_SINGLE, 64>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
+        else
+            launch_fused<TS, GUESS_PAIR, 64>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
+    }
     else if (tune.px == 32)
         launch_fused<TS, GUESS_NONE, 32>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
     else if (tune.px == 16)

@@ -76,7 +76,7 @@ SYMBOLS = ("rmhdlb_create", "rmhdlb_init_fields", "rmhdlb_step", "rmhdlb_moments
            "rmhdlb_guess_samples", "rmhdlb_mlp_eval", "rmhdlb_autotune", "rmhdlb_set_tuning", "rmhdlb_set_force",
            "rmhdlb_batch_create", "rmhdlb_batch_instance", "rmhdlb_batch_step", "rmhdlb_batch_autotune",
            "rmhdlb_batch_set_tuning", "rmhdlb_batch_destroy", "rmhdlb_workspace_bytes",
-           "rmhdlb_guess_samples_noalloc")
+           "rmhdlb_guess_samples_noalloc", "rmhdlb_device_copy")
 
 _LIB = None
 
@@ -126,6 +126,7 @@ def load():
     L.rmhdlb_batch_autotune.argtypes = [vp, ip32, ip32, ip32]
     L.rmhdlb_batch_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.rmhdlb_batch_destroy.argtypes = [vp]
+    L.rmhdlb_device_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     _LIB = L
     return L
 
@@ -209,6 +210,16 @@ def _fptr(t):
         return ctypes.POINTER(ctypes.c_float)()
     assert t.dtype == torch.float32 and t.is_cuda and t.is_contiguous()
     return ctypes.cast(ctypes.c_void_p(t.data_ptr()), ctypes.POINTER(ctypes.c_float))
+
+
+def device_copy(dst, src, stream=None):
+    """Copy the bytes of a contiguous CUDA tensor src into dst (same size) with the library's copy kernel."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes and src.is_contiguous() and dst.is_contiguous()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(load().rmhdlb_device_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                                     ctypes.c_void_p(st.cuda_stream)), "rmhdlb_device_copy")
 
 
 def weights_to_dict(W):

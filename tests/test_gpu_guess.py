@@ -88,10 +88,11 @@ def test_training_reduces_the_loss():
     assert np.isfinite(weights["w"]).all() and (weights["sd_x"] > 0).all()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f16"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 def test_step_with_learned_guess_matches_the_plain_oracle(storage):
     """Newton from the network's guess reaches the same root: the FP64 state agrees with the plain
-    oracle to the plain bound; the FP16-shifted form stays within its stated bound.  The iteration
+    oracle to the plain bound; the FP32 (one lane per cell) and FP16-shifted forms stay within their
+    stated bounds.  The iteration
     counts with and without the guess are reported (the gain test)."""
     _torch_cuda()
     w = W.kh(nx=96, ny=160, v0=0.4, ratio=10.0, sigma=1e3)
@@ -116,7 +117,7 @@ def test_step_with_learned_guess_matches_the_plain_oracle(storage):
         assert errs[worst] <= TOL, (worst, errs[worst])
     else:
         e_plain = field_errors(mo, mp, field_scale(w))
-        # same stated bound as the plain FP16 form (the root is the same; only rounding differs)
+        # same stated bound as the plain form of this storage (the root is the same; only rounding differs)
         for k in errs:
             assert errs[k] <= max(5e-2 if k in ("Jx", "Jy", "Jz", "rho_c") else 5e-3, 2 * e_plain[k]), k
     assert dg["n_fallback"] < 0.05 * w.ncells

@@ -658,3 +658,25 @@ def test_mixed_conserves_mass_exactly_in_fp64_sums(storage):
     drift = abs(d1["mass"] - d0["mass"]) / d0["mass"]
     print(f"[mixed] {storage} mass drift over 50 steps {drift:.1e}", flush=True)
     assert drift <= (1e-6 if storage == "f32" else 1e-3)
+
+
+def test_device_copy_copies_and_checks_its_arguments():
+    """rmhdlb_device_copy, the plain copy kernel the benchmark reads the HBM rate from: exact copies of a
+    ragged length (not a multiple of the 1024 words a block moves), and RMHDLB_EINVAL for a length or an
+    address that is not 16-byte aligned and for overlapping ranges, with nothing written."""
+    torch = _torch_cuda()
+    from paper_1508_03452_amd.rmhdlb import RMHDLB_EINVAL, device_copy, load
+    import ctypes
+    a = torch.arange(3 * 1024 * 16 + 6, dtype=torch.float64, device="cuda")       # 49158 doubles, 16 B multiple
+    b = torch.zeros_like(a)
+    device_copy(b, a)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    L = load()
+    c = torch.zeros_like(a)
+    p = lambda t, off=0: ctypes.c_void_p(t.data_ptr() + off)
+    assert L.rmhdlb_device_copy(p(c), p(a), 8, None) == RMHDLB_EINVAL           # not a multiple of 16
+    assert L.rmhdlb_device_copy(p(c, 8), p(a), 16, None) == RMHDLB_EINVAL       # misaligned destination
+    assert L.rmhdlb_device_copy(p(a, 16), p(a), 64, None) == RMHDLB_EINVAL      # overlapping
+    torch.cuda.synchronize()
+    assert not c.any()
