@@ -31,6 +31,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -44,22 +46,7 @@ KERNEL_SOURCES = ("paper_1508_03452_amd/csrc/rmhdlb_kernels.hip", "paper_1508_03
 # shape the autotuner picks, and a changed kernel or an unmeasured shape
 # reports null.
 MEASURED_TRAFFIC = {
-    ("flare", "f64", "cb337988654a", "64,16,4"): 55.91,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "cb337988654a", "64,32,4"): 61.61,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "cb337988654a", "64,64,4"): 65.09,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "cb337988654a", "64,16,2"): 64.08,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "cb337988654a", "64,32,2"): 63.84,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "cb337988654a", "64,64,2"): 66.96,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "cb337988654a", "64,16,1"): 73.79,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f16+guess", "cb337988654a", "64,16,4"): 16.34,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "cb337988654a", "64,32,4"): 16.22,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "cb337988654a", "64,64,4"): 16.46,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "cb337988654a", "64,16,2"): 16.51,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "cb337988654a", "64,32,2"): 16.89,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "cb337988654a", "64,64,2"): 16.60,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "cb337988654a", "64,16,1"): 18.82,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f32", "cb337988654a", "64,64,4"): 27.65,  # profiles/fused_step_f32_flare256x256x512.md
-    ("flare", "f16", "cb337988654a", "64,32,2"): 13.82,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f32", "02ecb1bf1d03", "64,64,4"): 26.42,  # profiles/fused_step_f32_flare256x256x512.md
 }
 
 
@@ -87,9 +74,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="flare", choices=["flare", "kh", "sweep"],
+    ap.add_argument("--workload", default="flare", choices=["flare", "kh", "sweep", "khsweep"],
                     help="flare: the 256x256x512 box (headline); kh: the 1024x2048 slab; sweep: 64 KH slabs "
-                         "of uneven sizes stepped as one batch")
+                         "of uneven sizes stepped as one batch; khsweep: not a timing but the reconnection "
+                         "study of the KH set-up in the paper's units, the rate at the null against sigma "
+                         "(one JSON line with the series and the fits)")
+    ap.add_argument("--sigmas", default="20,40,60,80,100", help="khsweep: the conductivities")
+    ap.add_argument("--kh-u0", type=float, default=0.2, help="khsweep: shear speed U0 in units of c")
+    ap.add_argument("--kh-dn", type=float, default=1.8, help="khsweep: density jump across the layer")
+    ap.add_argument("--kh-cells", type=int, default=512, help="khsweep: cells per side")
+    ap.add_argument("--kh-every", type=float, default=0.25, help="khsweep: time between samples of the rate")
+    ap.add_argument("--kh-t-end", type=float, default=23.2, help="khsweep: time the runs stop at")
     ap.add_argument("--storage", default="f64", choices=["f64", "f32", "f16"])
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shape (64 x 2 tiles, 4 planes) instead of the autotuned one")
@@ -187,12 +182,48 @@ def run_sweep(steps, warmup, storage="f32"):
     return ncell / (ms * 1e-3) / 1e6, ms, info
 
 
+def launch_modes(storage="f32", steps=128):
+    """Step cadence of a batch of small slabs (64 KH slabs of 64..192 cells a side, 1.1 M cells), where
+    the cost of launching shows: one eager launch per step (rmhdlb_batch_step with one step), replays
+    of the 2-step graph and replays of the 64-step graph, each over the same `steps` steps on the same
+    batch (ms per step from HIP events on the batch's stream)."""
+    import torch
+    from paper_1508_03452_amd import workloads as W
+    from paper_1508_03452_amd.rmhdlb import Batch
+    specs = W.sweep_specs(sizes=tuple(range(64, 193, 32)))
+    st = torch.cuda.Stream()
+    b = Batch([W.sweep_layout(sp) for sp in specs], storage=storage, stream=st)
+    for sp, inst in zip(specs, b.instances):
+        inst.init_fields(W.sweep_instance(sp).fields)
+    b.step(64 + 2)            # captures both graphs; an even count keeps the buffer parity at 0, where they apply
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(per_call):
+        torch.cuda.synchronize()
+        ev0.record(st)
+        for _ in range(steps // per_call):
+            b.step(per_call)
+        ev1.record(st)
+        torch.cuda.synchronize()
+        return round(ev0.elapsed_time(ev1) / steps, 4)
+
+    out = {"workload": f"{len(specs)} KH slabs, nx, ny in 64..192, {sum(sp['nx'] * sp['ny'] for sp in specs)} "
+                       f"cells, {storage}", "steps": steps,
+           "ms_per_step": {"eager": timed(1), "graph_2_steps": timed(2), "graph_64_steps": timed(64)}}
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def sweep_main(args):
     """--workload sweep: the batched sweep as the headline line."""
     import torch
     torch.cuda.set_device(0)
     storage = "f32" if args.storage == "f64" else args.storage
     mlups, ms, info = run_sweep(args.steps, args.warmup, storage)
+    info["launch_modes"] = launch_modes(storage)
     roof = info.pop("roofline")
     out = {"metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
@@ -210,7 +241,6 @@ def accuracy_study(steps=1000):
     oracle's fields stored under tests/golden), per field as max |form - FP64| / max(max |FP64|, floor):
     floors c for u, the field scale for E, B, J.  Also the FP64 path's own one-ulp sensitivity: the change
     of the same run from an initial density one ulp larger, the accuracy rounding alone leaves."""
-    import numpy as np
     import torch
     from paper_1508_03452_amd import workloads as W
     from paper_1508_03452_amd.rmhdlb import Solver
@@ -408,6 +438,84 @@ def history_main(args):
           flush=True)
 
 
+KH_WINDOW = (2.0, 8.0)   # time window of the mean reconnection rate
+
+
+def fit_rates(sigmas, rates):
+    """Fits of the mean reconnection rate |R| against the conductivity: the power law |R| = a sigma^k
+    (least squares in log |R| against log sigma; the Sweet-Parker scaling has k = -1/2) and
+    |R| = b / ln sigma (the Petschek-like slow dependence; least squares through the origin in
+    1 / ln sigma).  Each with its largest relative residual, so the two can be told apart."""
+    s = np.asarray(sigmas, dtype=np.float64)
+    r = np.abs(np.asarray(rates, dtype=np.float64))
+    if len(s) < 3 or not np.all(r > 0):
+        return None
+    A = np.stack([np.log(s), np.ones_like(s)], axis=1)
+    k, loga = np.linalg.lstsq(A, np.log(r), rcond=None)[0]
+    a = float(np.exp(loga))
+    x = 1.0 / np.log(s)
+    b = float(x @ r / (x @ x))
+    return {"power_law": {"k": round(float(k), 4), "a": a,
+                          "max_rel_residual": round(float(np.max(np.abs(a * s ** k / r - 1.0))), 4)},
+            "inv_log": {"b": b, "max_rel_residual": round(float(np.max(np.abs(b * x / r - 1.0))), 4)}}
+
+
+def window_mean(series, window=KH_WINDOW):
+    vals = [r for t, r in series if window[0] <= t <= window[1]]
+    return float(np.mean(vals)) if vals else None
+
+
+def khsweep_main(args):
+    """The KH reconnection study (Sec. IV, KH): the set-up in the paper's units for each sigma, with the
+    explicit and the printed f collision, run to t_end in FP64; the rate R = (E^z - E^z_0) / B0 at the
+    null is sampled every kh_every; the mean over t in [2, 8] is fitted against sigma (fit_rates), over
+    all sigmas and over those from the one of largest |R| on."""
+    import torch
+    from paper_1508_03452_amd import workloads as W
+    from paper_1508_03452_amd.rmhdlb import Solver
+    torch.cuda.set_device(0)
+    sigmas = [float(v) for v in args.sigmas.split(",")]
+    cases, fits = [], {}
+    for cname, coll in (("explicit", 0), ("printed", 1)):
+        means = []
+        for sg in sigmas:
+            w = W.kh_box(n_cells=args.kh_cells, U0=args.kh_u0, dn=args.kh_dn, sigma=sg)
+            s = Solver(w.shape, w.bc, storage="f64", **dict(w.params, collision=coll))
+            s.init_fields(w.fields)
+            dt = float(w.meta["dt"])
+            total = int(round(args.kh_t_end / dt))
+            every = max(1, int(round(args.kh_every / dt)))
+            series, done, failed, t0 = [], 0, 0, time.perf_counter()
+            while done < total:
+                n = min(every, total - done)
+                s.step(n)
+                done += n
+                d = s.moments(fields=())["diag"]
+                if d["n_failed"]:
+                    failed = d["n_failed"]
+                    break
+                series.append((round(done * dt, 4), d["recon_rate"]))
+            s.close()
+            mean = window_mean(series) if (not failed or done * dt > KH_WINDOW[1]) else None
+            rec = {"collision": cname, "sigma": sg, "steps": done, "t_reached": round(done * dt, 3),
+                   "failed_cells": failed, "mean_R_t2_8": mean, "R_end": None if failed else series[-1][1],
+                   "wall_s": round(time.perf_counter() - t0, 2), "series": series}
+            cases.append(rec)
+            print(f"[khsweep] {cname} sigma={sg:g}: t={rec['t_reached']} failed={failed} "
+                  f"mean R(2..8)={mean} R(end)={rec['R_end']}", file=sys.stderr, flush=True)
+            if mean is not None:
+                means.append((sg, mean))
+        fits[cname] = {"all": fit_rates([m[0] for m in means], [m[1] for m in means])}
+        if means:
+            # the rate need not fall over the whole range: fit the branch from the largest |R| on as well
+            ip = int(np.argmax([abs(m[1]) for m in means]))
+            fits[cname]["from_peak"] = {"sigma_peak": means[ip][0],
+                                        "fit": fit_rates([m[0] for m in means[ip:]], [m[1] for m in means[ip:]])}
+    print(json.dumps({"workload": f"KH reconnection set-up {args.kh_cells}^2, U0 = {args.kh_u0}c, "
+                                  f"density jump {args.kh_dn}, FP64", "window": list(KH_WINDOW),
+                      "t_end": args.kh_t_end, "fits": fits, "cases": cases}), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_only > 0:
@@ -419,6 +527,11 @@ def main():
         return history_main(args)
     if args.workload == "sweep" and args.gpus == 1:
         return sweep_main(args)
+    if args.workload == "khsweep":
+        if args.gpus != 1:
+            print(json.dumps({"error": "the step runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        return khsweep_main(args)
     if args.gpus != 1:
         print(json.dumps({"error": "the step runs on one GPU; --gpus must be 1 (the multi-GPU domain "
                                    "decomposition is not implemented)"}))

@@ -38,12 +38,15 @@ class _Params(ctypes.Structure):
 
 
 def lib():
-    """Load (building if absent) the oracle library."""
+    """Load (building if absent) the oracle library.  With RMHDLB_ORACLE_FMA=1 in the environment the
+    process loads the build with contracted multiply-adds instead, which only measures rounding
+    sensitivity (see build.py)."""
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "liboracle.so")
+        fma = os.environ.get("RMHDLB_ORACLE_FMA") == "1"
+        path = _build.LIB_FMA if fma else _build.LIB
         if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
-            _build.build()
+            _build.build(fma=fma)
         L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         L.rmhdlb_oracle_create.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_void_p)]

@@ -1,7 +1,11 @@
 """Build the oracle shared library (test infrastructure).
 
 Plain gcc, FP64, no contraction of multiply-adds, so the oracle's rounding is
-that of the source as written.
+that of the source as written.  A second build of the same source with
+multiply-adds contracted into fused ones (liboracle_fma.so) only measures the
+oracle's sensitivity to rounding: the difference between the two builds after
+a long run is what a correct implementation that rounds differently (as a GPU
+compiler's contraction does) can leave.
 """
 import os
 import subprocess
@@ -10,16 +14,19 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "rmhdlb_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_FMA = os.path.join(HERE, "liboracle_fma.so")
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11",
-           "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
+def build(verbose: bool = False, fma: bool = False) -> str:
+    out = LIB_FMA if fma else LIB
+    contract = ["-ffp-contract=fast", "-mfma"] if fma else ["-ffp-contract=off"]
+    cmd = ["gcc", "-O2"] + contract + ["-fno-fast-math", "-fPIC", "-shared", "-std=c11",
+                                       "-Wall", "-Wextra", "-o", out + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

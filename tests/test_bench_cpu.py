@@ -38,3 +38,24 @@ def test_traffic_lookup_is_keyed_by_kernel_hash_and_shape():
 def test_tile_text():
     assert bench.tile_text((64, 16, 1)) == "64x2 cells, 16 z-planes per block"
     assert "4 blocks per column" in bench.tile_text((64, 32, 4))
+
+
+def test_rate_fits_recover_their_laws():
+    """The KH study's fits: a pure power law is recovered with its exponent and no residual, a pure
+    1 / ln sigma law has no residual in its own fit and a visible one in the power law, and signs are
+    ignored (the rate at the null is negative in these runs)."""
+    import numpy as np
+    sig = [20.0, 40.0, 60.0, 80.0, 100.0]
+    f = bench.fit_rates(sig, [-0.3 * s ** -0.5 for s in sig])
+    assert abs(f["power_law"]["k"] + 0.5) < 1e-4 and f["power_law"]["max_rel_residual"] < 1e-4
+    assert abs(f["power_law"]["a"] - 0.3) < 1e-9
+    g = bench.fit_rates(sig, [0.1 / np.log(s) for s in sig])
+    assert abs(g["inv_log"]["b"] - 0.1) < 1e-12 and g["inv_log"]["max_rel_residual"] < 1e-12
+    assert g["power_law"]["max_rel_residual"] > 1e-3
+    assert bench.fit_rates(sig[:2], [0.1, 0.2]) is None
+
+
+def test_window_mean():
+    series = [(1.0, 5.0), (2.0, 1.0), (5.0, 2.0), (8.0, 3.0), (9.0, 7.0)]
+    assert bench.window_mean(series) == 2.0
+    assert bench.window_mean([(1.0, 1.0)]) is None
