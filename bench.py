@@ -342,6 +342,7 @@ def timed_form(w, storage, guess, args, stream):
         info["guess_training"] = {"samples": 65536, "iters": 400, "loss_first": float(losses[0]),
                                   "loss_last": float(losses[-1]), "train_s": round(time.perf_counter() - t_tr, 3)}
         info["weights"] = weights
+    g0 = s.moments(fields=())["diag"]["guess_steps"] if guess else 0
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -357,6 +358,10 @@ def timed_form(w, storage, guess, args, stream):
         hist.pop()
     info.update(failed_cells=d["n_failed"], mean_newton_iters=round(d["mean_iters"], 3),
                 newton_hist=hist, guess_fallbacks=d["n_fallback"])
+    if guess:
+        # timed steps that ran the network (the others ran the plain recovery: no cell above the guess's
+        # flow-ratio gate in the step before)
+        info["guess_network_steps"] = f"{d['guess_steps'] - g0} of {args.steps}"
     return ev0.elapsed_time(ev1) / args.steps, wall, s, info
 
 

@@ -167,6 +167,7 @@ typedef struct {
     int64_t n_failed;    /* cells whose recovery failed */
     int64_t n_fallback;  /* cells whose learned guess was rejected (Newton started from T_fl^00) */
     int64_t step;        /* steps taken since rmhdlb_init_fields */
+    int64_t guess_steps; /* of those, steps that ran the learned guess's network (see rmhdlb_set_guess) */
 } rmhdlb_diag;
 
 /* Prescribed fields of a driven face: nx*ny DEVICE values each, x fastest. */
@@ -295,7 +296,13 @@ int rmhdlb_train_guess(rmhdlb_ctx *ctx, const rmhdlb_train_opts *opts, const flo
 int rmhdlb_set_guess_weights(rmhdlb_ctx *ctx, const rmhdlb_guess_weights *w);
 
 /* RMHDLB_GUESS_PLAIN (default) or RMHDLB_GUESS_MLP (needs installed
- * weights, else RMHDLB_EINVAL).  Applies to later steps and moments. */
+ * weights, else RMHDLB_EINVAL).  Applies to later steps and moments.  With
+ * the guess a cell whose flow ratio |S| / T_fl^00 is at most 0.1 still starts
+ * Newton from T_fl^00, and a step runs the network only while the step before
+ * it met a cell above that ratio (enabling the guess, rmhdlb_init_fields and
+ * rmhdlb_set_state open this gate for the next step); the other steps run the
+ * plain recovery in a kernel that carries none of the network's registers.
+ * rmhdlb_diag.guess_steps counts the steps that ran the network. */
 int rmhdlb_set_guess(rmhdlb_ctx *ctx, int32_t mode);
 
 /* The training samples of rmhdlb_train_guess without training: features

@@ -49,6 +49,7 @@ struct rmhdlb_ctx {
     double* force;     // external force density, 3 N doubles, null until set
     double* vmax;      // vmax[0]: largest |beta| of the last forced step; then the per-wavefront partials
     int guess_mode;    // RMHDLB_GUESS_*
+    int64_t* gate;     // the two slots of the learned guess's gate (rmhd::Consts::gflag_rd)
     int64_t step;
     rmhd::StepTuning tune;
 };
@@ -161,7 +162,7 @@ size_t buffer_bytes(const Consts& K, int storage) {
 
 // The device memory of a context: the buffers below, each at a 256-byte
 // aligned offset of one block.
-enum { M_BUF0, M_BUF1, M_SCRATCH, M_PART, M_PART2, M_NULLP, M_FACEB, M_EZ0, M_AUX, M_RESULT, M_COUNT };
+enum { M_BUF0, M_BUF1, M_SCRATCH, M_PART, M_PART2, M_NULLP, M_FACEB, M_EZ0, M_AUX, M_RESULT, M_GATE, M_COUNT };
 
 size_t mem_layout(const Consts& K, int storage, size_t off[M_COUNT]) {
     const size_t nt = (size_t)rmhd::num_tiles(K);
@@ -176,6 +177,7 @@ size_t mem_layout(const Consts& K, int storage, size_t off[M_COUNT]) {
     sz[M_EZ0] = sizeof(double) * (size_t)K.N;
     sz[M_AUX] = sizeof(double) * 4;
     sz[M_RESULT] = sizeof(double) * RESULT_LEN;
+    sz[M_GATE] = sizeof(int64_t) * 3;  // two gate slots, steps that ran the network
     size_t total = 0;
     for (int i = 0; i < M_COUNT; ++i) {
         off[i] = total;
@@ -207,13 +209,13 @@ void pack_tables(const rmhdlb_guess_weights& W, rmhd::GuessTables& T) {
     const float* w = W.w;
     for (int l = 0; l < 64; ++l) {
         const int row = l & 31, h = l >> 5;
-        for (int j = 0; j < 4; ++j) {
-            const int k = 4 * h + j;
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * h + j;
             T.a1[l][j] = (_Float16)(k < MLP_IN ? w[OW1 + row * MLP_IN + k] : 0.0f);
         }
-        for (int s = 0; s < 4; ++s)
-            for (int j = 0; j < 4; ++j) {
-                const int k = 8 * s + 4 * h + j;
+        for (int s = 0; s < 2; ++s)
+            for (int j = 0; j < 8; ++j) {
+                const int k = guess_k(s, j, l);
                 T.a2[l][s][j] = (_Float16)w[OW2 + row * 32 + k];
                 T.a3[l][s][j] = (_Float16)(row < MLP_OUT ? w[OW3 + row * 32 + k] : 0.0f);
             }
@@ -231,6 +233,32 @@ void pack_tables(const rmhdlb_guess_weights& W, rmhd::GuessTables& T) {
         T.mu_x[j] = W.mu_x[j];
         T.inv_sd_x[j] = 1.0f / W.sd_x[j];
     }
+}
+
+// The step's constants with this step's gate slots: read slot cur (written by
+// the previous step), record into the other (record = false: into none).
+rmhd::Consts step_consts(const rmhdlb_ctx* C, bool record) {
+    rmhd::Consts K = C->K;
+    K.gflag_rd = C->gate + C->cur;
+    K.gflag_wr = record ? C->gate + (1 - C->cur) : nullptr;
+    K.gstep = C->step;
+    K.gcount = record ? C->gate + 2 : nullptr;
+    return K;
+}
+
+// Open the gate of the learned guess for the next step (the network runs until
+// a step meets no cell above the flow-ratio gate); with reset, also zero the
+// count of steps that ran it.
+int arm_gate(rmhdlb_ctx* C, bool reset) {
+    int64_t v[3];
+    v[C->cur] = C->step - 1;
+    v[1 - C->cur] = INT64_MIN;
+    v[2] = 0;
+    if (hipMemcpyAsync(C->gate, v, (reset ? 3 : 2) * sizeof(int64_t), hipMemcpyHostToDevice, C->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(C->stream) != hipSuccess)
+        return RMHDLB_EDEVICE;
+    return RMHDLB_OK;
 }
 
 int install_guess(rmhdlb_ctx* C, const rmhdlb_guess_weights& W) {
@@ -353,6 +381,11 @@ int rmhdlb_create(const rmhdlb_params* params, void* hip_stream, rmhdlb_ctx** ou
     C->ez0 = (double*)(base + off[M_EZ0]);
     C->aux = (double*)(base + off[M_AUX]);
     C->result = (double*)(base + off[M_RESULT]);
+    C->gate = (int64_t*)(base + off[M_GATE]);
+    C->K.gflag_rd = nullptr;
+    C->K.gflag_wr = nullptr;
+    C->K.gstep = 0;
+    C->K.gcount = nullptr;
     C->has_state = false;
     C->cur = 0;
     C->step = 0;
@@ -427,7 +460,7 @@ int rmhdlb_init_fields(rmhdlb_ctx* C, const rmhdlb_fields_in* in) {
         return RMHDLB_EDEVICE;  // the force gate starts open
     C->step = 0;
     C->has_state = true;
-    return RMHDLB_OK;
+    return arm_gate(C, true);
 }
 
 int rmhdlb_set_force(rmhdlb_ctx* C, const double* const F[3], double gate) {
@@ -489,8 +522,8 @@ int rmhdlb_step(rmhdlb_ctx* C, int64_t nsteps) {
     if (!C || nsteps < 0) return RMHDLB_EINVAL;
     if (!C->has_state) return RMHDLB_ESTATE;
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = RMHD_DISPATCH(C, launch_step)(C->sb[C->cur], C->sb[1 - C->cur], C->K, C->tune, C->faceB,
-                                                     C->guess_mode ? C->gt : nullptr, C->stream);
+        hipError_t e = RMHD_DISPATCH(C, launch_step)(C->sb[C->cur], C->sb[1 - C->cur], step_consts(C, true), C->tune,
+                                                     C->faceB, C->guess_mode ? C->gt : nullptr, C->stream);
         if (e != hipSuccess) return RMHDLB_EDEVICE;
         C->cur = 1 - C->cur;
         C->step++;
@@ -524,11 +557,13 @@ int rmhdlb_moments(rmhdlb_ctx* C, rmhdlb_fields_out* out, rmhdlb_diag* diag) {
     D.ez0 = C->ez0;
     D.b0 = C->aux;
     D.result = C->result;
-    hipError_t e = RMHD_DISPATCH(C, launch_moments)(C->sb[C->cur], C->K, op, D, C->guess_mode ? C->gt : nullptr,
-                                                    C->stream);
+    hipError_t e = RMHD_DISPATCH(C, launch_moments)(C->sb[C->cur], step_consts(C, false), op, D,
+                                                    C->guess_mode ? C->gt : nullptr, C->stream);
     if (e != hipSuccess) return RMHDLB_EDEVICE;
     double r[RESULT_LEN];
-    if (hipMemcpyAsync(r, C->result, sizeof(r), hipMemcpyDeviceToHost, C->stream) != hipSuccess)
+    int64_t guess_steps = 0;
+    if (hipMemcpyAsync(r, C->result, sizeof(r), hipMemcpyDeviceToHost, C->stream) != hipSuccess ||
+        hipMemcpyAsync(&guess_steps, C->gate + 2, sizeof(int64_t), hipMemcpyDeviceToHost, C->stream) != hipSuccess)
         return RMHDLB_EDEVICE;
     if (hipStreamSynchronize(C->stream) != hipSuccess) return RMHDLB_EDEVICE;
     const int64_t failed = (int64_t)llround(r[8]);
@@ -549,6 +584,7 @@ int rmhdlb_moments(rmhdlb_ctx* C, rmhdlb_fields_out* out, rmhdlb_diag* diag) {
         diag->null_index = (int64_t)llround(r[rmhd::NPART + 2]);
         diag->B0 = r[rmhd::NPART + 3];
         diag->step = C->step;
+        diag->guess_steps = guess_steps;
     }
     return failed ? RMHDLB_ERECOVERY : RMHDLB_OK;
 }
@@ -566,7 +602,7 @@ int rmhdlb_set_guess(rmhdlb_ctx* C, int32_t mode) {
     if (mode == RMHDLB_GUESS_MLP && (C->K.coll || C->K.flux || C->K.forced || C->K.bprev))
         return RMHDLB_EUNSUPPORTED;  // default readings, no force
     C->guess_mode = mode;
-    return RMHDLB_OK;
+    return mode == RMHDLB_GUESS_MLP && C->has_state ? arm_gate(C, false) : RMHDLB_OK;
 }
 
 static int sample_cells(rmhdlb_ctx* C, int ns, double* F, double* T, double* part, double sums[rmhd::SAMPLE_SUMS]) {
@@ -840,7 +876,11 @@ int rmhdlb_autotune(rmhdlb_ctx* C, int32_t* px_out, int32_t* zb_out, int32_t* zg
         for (const rmhd::StepTuning& t : cand) {
             float ms = 0.0f;
             const int rc = time_ms(C->stream, 3, [&]() {
-                return RMHD_DISPATCH(C, launch_step)(C->sb[C->cur], C->sb[1 - C->cur], C->K, t, C->faceB,
+                // the trials read the gate slot of this step and record into the slot this step will record
+                // into, with this step's number and from this step's state: what the real step records
+                rmhd::Consts Kt = step_consts(C, true);
+                Kt.gcount = nullptr;  // trials are not steps
+                return RMHD_DISPATCH(C, launch_step)(C->sb[C->cur], C->sb[1 - C->cur], Kt, t, C->faceB,
                                                      C->guess_mode ? C->gt : nullptr, C->stream);
             }, &ms);
             if (rc != RMHDLB_OK) return rc;
@@ -1203,7 +1243,7 @@ int rmhdlb_set_state(rmhdlb_ctx* C, const double* src) {
     hipError_t e = RMHD_DISPATCH(C, launch_import)(src, C->sb[C->cur], C->K, C->stream);
     if (e != hipSuccess || hipStreamSynchronize(C->stream) != hipSuccess) return RMHDLB_EDEVICE;
     C->has_state = true;
-    return RMHDLB_OK;
+    return C->guess_mode == RMHDLB_GUESS_MLP ? arm_gate(C, false) : RMHDLB_OK;
 }
 
 int rmhdlb_lattice_tables(int32_t* e19, double* w19, int32_t* s24, int32_t* ehat24, int32_t* bhat24) {

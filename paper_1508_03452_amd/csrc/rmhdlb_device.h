@@ -90,6 +90,15 @@ struct Consts {
     const double* force;
     const double* vmax_prev;
     double* vmax_part;   // largest |beta| per wavefront of the step, reduced after it
+    // gate of the learned guess (set per launch): a step runs the network only
+    // when the step before it met a cell whose flow ratio |S| / E_f exceeds the
+    // gate, i.e. when *gflag_rd == gstep - 1; a step that meets one stores its
+    // number gstep in *gflag_wr (null: record nothing).  Two slots, swapped
+    // with the state buffers.
+    const int64_t* gflag_rd;
+    int64_t* gflag_wr;
+    int64_t gstep;
+    int64_t* gcount;     // steps that ran the network (null: not counted)
 };
 
 // Layout of the distributions in a state buffer.  Element indices are
@@ -187,13 +196,15 @@ __device__ __forceinline__ bool solve_shifted_pd(const double Pi[6], double lam,
 // passes the root at most once (from below) and then decreases
 // monotonically to it.  Every Newton step is applied (so lam carries no
 // one-sided bias) until the step is at the rounding floor; beta is then
-// solved at the final lam.  Returns the number of Newton steps.
+// solved at the final lam.  Returns the number of Newton steps.  With SOLVED,
+// beta already holds the solution at lam0 (the first solve is skipped).
+template <bool SOLVED = false>
 __device__ __forceinline__ int newton_from(double Ef, const double S[3], const double Pi[6], double lam0,
                                            double& lam, double beta[3]) {
     lam = lam0;
     int it = 0;
     while (it < 60) {
-        solve_shifted(Pi, lam, S, beta);
+        if (!SOLVED || it > 0) solve_shifted(Pi, lam, S, beta);
         const double phi = lam - Ef + (S[0] * beta[0] + S[1] * beta[1] + S[2] * beta[2]);
         const double dphi = 1.0 - (beta[0] * beta[0] + beta[1] * beta[1] + beta[2] * beta[2]);
         const double d = phi / dphi;
@@ -219,11 +230,10 @@ __device__ __forceinline__ int recover_from_guess(double Ef, const double S[3], 
                                                   double& lam, double beta[3], int& fallback) {
     fallback = lam0 == Ef ? 0 : 1;
     if (lam0 < Ef) {  // false for NaN
-        double y[3];
-        const bool pd = solve_shifted_pd(Pi, lam0, S, y);
-        if (pd && 1.0 - (y[0] * y[0] + y[1] * y[1] + y[2] * y[2]) > 0.0) {
+        const bool pd = solve_shifted_pd(Pi, lam0, S, beta);  // the same solve as Newton's first one
+        if (pd && 1.0 - (beta[0] * beta[0] + beta[1] * beta[1] + beta[2] * beta[2]) > 0.0) {
             fallback = 0;
-            return newton_from(Ef, S, Pi, lam0, lam, beta);
+            return newton_from<true>(Ef, S, Pi, lam0, lam, beta);
         }
     }
     return recover(Ef, S, Pi, lam, beta);

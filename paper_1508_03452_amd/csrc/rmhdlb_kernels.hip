@@ -239,24 +239,41 @@ __device__ __forceinline__ void fluid_tensor(const Consts& K, const CellSol& M, 
 
 // Where the learned guess comes from: none (Newton from E_f), or the
 // network evaluated on the wavefront with two lanes per cell (PAIR) or one
-// lane per cell (SINGLE, two passes of 32 cells).
-enum GuessMode { GUESS_NONE = 0, GUESS_PAIR = 1, GUESS_SINGLE = 2 };
+// lane per cell (SINGLE, two passes of 32 cells); MONITOR: Newton from E_f in
+// a step with the guess enabled whose gate is closed, recording whether the
+// gate opens for the next step.
+enum GuessMode { GUESS_NONE = 0, GUESS_PAIR = 1, GUESS_SINGLE = 2, GUESS_MONITOR = 3 };
 
-// Below this momentum ratio |S| / E_f Newton from E_f converges in one or
-// two steps; such cells take no guess, and a wavefront of only such cells
-// skips the network.
-constexpr double GUESS_MIN_FLOW = 0.02;
+// Below this flow ratio |S| / E_f a cell takes no guess (Newton from E_f needs
+// at most a few steps there, and on the flare box the network saved none for
+// cells between 0.02 and 0.1), a wavefront of only such cells skips the
+// network, and a step that meets no other cell closes the gate for the next.
+#ifndef RMHDLB_GUESS_MIN_FLOW
+#define RMHDLB_GUESS_MIN_FLOW 0.1
+#endif
+constexpr double GUESS_MIN_FLOW = RMHDLB_GUESS_MIN_FLOW;
+
+// Record that this step met a cell above the gate (the lowest such lane of the
+// wavefront stores; skipped once the slot holds this step's number).  Lanes
+// that left the wavefront early do not take part.
+__device__ __forceinline__ void open_gate(const Consts& K, bool moving) {
+    const uint64_t m = __ballot(moving);
+    if (K.gflag_wr && m && (int)(threadIdx.x & 63) == __builtin_ctzll(m) && *K.gflag_wr != K.gstep)
+        *K.gflag_wr = K.gstep;
+}
 
 // Network guess of the eigenvalue for this lane's cell (all lanes of the
 // wavefront call it together).  E_f (no guess) for nearly resting cells; NaN
 // when the predicted |beta| >= 0.999 (those cells fall back to E_f).
 template <int GM>
 __device__ __forceinline__ double guess_lambda(const GuessTables* __restrict__ gt, double Ef, const double S[3],
-                                               const double Pi[6], double N0) {
-    double f[6];
-    mlp_features(Ef, S, Pi, N0, f);
+                                               const double Pi[6], double N0, bool* gate) {
+    double f[6], s;
+    f[0] = flow_ratio(Ef, S, s);
     const bool moving = f[0] > GUESS_MIN_FLOW;
     if (!__any(moving)) return Ef;  // uniform over the wavefront
+    if (gate) *gate = true;
+    mlp_features(Ef, S, Pi, N0, s, f);
     float x[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) x[j] = (float)((f[j] - (double)gt->mu_x[j]) * (double)gt->inv_sd_x[j]);
@@ -281,20 +298,25 @@ __device__ __forceinline__ double guess_lambda(const GuessTables* __restrict__ g
 // M.T0, M.Tab, M.N0, M.Epr, M.B, M.Ep, M.rho_g): fills eps, p, n, gam, beta,
 // E, J, iters, fallback, ok.  Brec is the B of the recovery's T_EM (M.B, or
 // the previous step's B); the Ohm solve always takes M.B.  With a guess mode
-// every lane of the wavefront must call it together.
+// every lane of the wavefront must call it together, and *gate (when given,
+// uniform over the wavefront) is set when a cell of the wavefront lies above
+// the guess's flow-ratio gate.
 template <int GM = GUESS_NONE>
 __device__ __forceinline__ void solve_cell(const Consts& K, CellSol& M, const double (&Brec)[3],
-                                           const GuessTables* __restrict__ gt = nullptr) {
+                                           const GuessTables* __restrict__ gt = nullptr, bool* gate = nullptr) {
     const double c = K.c, c2 = c * c;
     const double* B = M.B;
     double Ef, S[3], Pi[6];
     fluid_tensor(K, M, Brec, Ef, S, Pi);
     double lam;
-    if constexpr (GM == GUESS_NONE) {
+    if constexpr (GM == GUESS_MONITOR)
+        if (gate && __any(S[0] * S[0] + S[1] * S[1] + S[2] * S[2] > (GUESS_MIN_FLOW * Ef) * (GUESS_MIN_FLOW * Ef)))
+            *gate = true;
+    if constexpr (GM == GUESS_NONE || GM == GUESS_MONITOR) {
         M.iters = recover(Ef, S, Pi, lam, M.beta);
         M.fallback = 0;
     } else {
-        const double lam0 = guess_lambda<GM>(gt, Ef, S, Pi, M.N0);
+        const double lam0 = guess_lambda<GM>(gt, Ef, S, Pi, M.N0, gate);
         M.iters = recover_from_guess(Ef, S, Pi, lam0, lam, M.beta, M.fallback);
     }
     const double b2 = M.beta[0] * M.beta[0] + M.beta[1] * M.beta[1] + M.beta[2] * M.beta[2];
@@ -600,7 +622,8 @@ template <bool NT, typename TS, typename TE, typename V, int GM, int VR = 0>
 __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* __restrict__ se, TS* __restrict__ dd,
                                           TE* __restrict__ de, const double* __restrict__ faceB,
                                           const GuessTables* __restrict__ gt, const Consts& K, int cell,
-                                          const Nbr& nb, int h, int x, int y, int z, bool active, double& bmax) {
+                                          const Nbr& nb, int h, int x, int y, int z, bool active, double& bmax,
+                                          bool& gate) {
     // stores of this cell's new state (lanes that only take part in the
     // wavefront's network evaluation store nothing)
     auto put = [&](auto* p, auto v) {
@@ -758,10 +781,10 @@ __device__ __forceinline__ void pair_cell(const TS* __restrict__ sd, const TE* _
         double Bp[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) Bp[a] = ld(se + (int64_t)(3 + a) * S + cell, 0);
-        solve_cell<GM>(K, M, Bp, gt);
+        solve_cell<GM>(K, M, Bp, gt, &gate);
         fe.setup(M.eps, M.p, M.gam, M.beta, M.Ep, Bp, K.c, K.eps0);
     } else {
-        solve_cell<GM>(K, M, M.B, gt);
+        solve_cell<GM>(K, M, M.B, gt, &gate);
         fe.setup(M.eps, M.p, M.gam, M.beta, M.Ep, M.B, K.c, K.eps0);
     }
 
@@ -877,7 +900,8 @@ template <bool NT, typename TS, typename TE, typename V, int GM, int VR = 0>
 __device__ __forceinline__ void quad_cell(const TS* __restrict__ sd, const TE* __restrict__ se, TS* __restrict__ dd,
                                           TE* __restrict__ de, const double* __restrict__ faceB,
                                           const GuessTables* __restrict__ gt, const Consts& K, int cell,
-                                          const Nbr& nb, int x, int y, int z, bool active, double& bmax) {
+                                          const Nbr& nb, int x, int y, int z, bool active, double& bmax,
+                                          bool& gate) {
     auto put = [&](auto* p, auto v) {
         if (active) st<NT>(p, v);
     };
@@ -1025,10 +1049,10 @@ __device__ __forceinline__ void quad_cell(const TS* __restrict__ sd, const TE* _
         double Bp[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) Bp[a] = ld(se + (int64_t)(3 + a) * S + cell, 0);
-        solve_cell<GM>(K, M, Bp, gt);
+        solve_cell<GM>(K, M, Bp, gt, &gate);
         fe.setup(M.eps, M.p, M.gam, M.beta, M.Ep, Bp, K.c, K.eps0);
     } else {
-        solve_cell<GM>(K, M, M.B, gt);
+        solve_cell<GM>(K, M, M.B, gt, &gate);
         fe.setup(M.eps, M.p, M.gam, M.beta, M.Ep, M.B, K.c, K.eps0);
     }
 
@@ -1138,7 +1162,7 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
     const int ybase = ty * PYT * yw + c / PXT;
     // with the force every lane stays (the wavefront's largest |beta| is
     // reduced over all 64 lanes)
-    constexpr bool all_lanes = GM != GUESS_NONE || (VR & 4) != 0;
+    constexpr bool all_lanes = GM == GUESS_PAIR || GM == GUESS_SINGLE || (VR & 4) != 0;
     // row groups of this lane that lie inside the grid (the later groups are further along y)
     int ng = yw;
     if (ybase >= K.ny) ng = 0;
@@ -1150,6 +1174,7 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
     }
     const int z0 = zc * zb * zg, z1 = min(K.nz, z0 + zb * zg);
     double bmax = 0.0;
+    bool gate = false;  // a cell of the walk lay above the guess's gate (uniform over the wavefront)
     // In the forms whose cell code spills (FP64, and FP16 at three waves)
     // the lane's coordinates are made opaque at every plane, so that the x-
     // and y-parts of the neighbour table are recomputed per plane (a few
@@ -1169,12 +1194,13 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
             const Nbr nb = make_nbr<true>(K, xp, yp, z);
             if constexpr (ONE)
                 quad_cell<NT, TS, TE, V, GM, VR>(sd, se, dd, de, faceB, gt, K, cell, nb, xp, yp, z,
-                                                 all_lanes ? active : true, bmax);
+                                                 all_lanes ? active : true, bmax, gate);
             else
                 pair_cell<NT, TS, TE, V, GM, VR>(sd, se, dd, de, faceB, gt, K, cell, nb, hp, xp, yp, z,
-                                                 all_lanes ? active : true, bmax);
+                                                 all_lanes ? active : true, bmax, gate);
         }
     }
+    if constexpr (GM != GUESS_NONE) open_gate(K, gate);
     if constexpr ((VR & 4) != 0) {
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) bmax = fmax(bmax, __shfl_xor(bmax, o, 64));
@@ -1190,6 +1216,15 @@ __global__ __launch_bounds__(PTPB, (fused_waves<TS, GM>())) void k_fused_step(co
                                                         int tiles_x, int ncol, int zb, int zg, int yw, int nblk) {
     const int b = tile_of_block(nblk);
     if (b >= nblk) return;  // uniform over the block
+    // With the guess enabled every step launches the network kernel and the monitor kernel (its own
+    // instantiation, so that it carries none of the network's registers); the one the gate does not
+    // select leaves at once (uniform over the grid).
+    if constexpr (GM == GUESS_MONITOR) {
+        if (*K.gflag_rd == K.gstep - 1) return;
+    } else if constexpr (GM != GUESS_NONE) {
+        if (*K.gflag_rd != K.gstep - 1) return;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && K.gcount) *K.gcount += 1;  // one writer per step
+    }
     fused_block<NT, TS, TE, V, GM, PXT, VR>(sd, se, dd, de, faceB, gt, K, tiles_x, ncol, zb, zg, yw, b);
 }
 
@@ -1352,7 +1387,12 @@ __global__ __launch_bounds__(TPB) void k_moments(const TS* __restrict__ src, con
     const int cell = x + K.nx * (y + K.ny * z);
     const Nbr nb = make_nbr<true>(K, x, y, z);
     Macro M;
-    macroscopic<GM>(src, esrc, faceB, gt, K, cell, nb, x, y, z, M);
+    if constexpr (GM == GUESS_NONE)
+        macroscopic<GM>(src, esrc, faceB, gt, K, cell, nb, x, y, z, M);
+    else if (*K.gflag_rd == K.gstep - 1)  // the guess the next step would take
+        macroscopic<GM>(src, esrc, faceB, gt, K, cell, nb, x, y, z, M);
+    else
+        macroscopic<GUESS_MONITOR>(src, esrc, faceB, gt, K, cell, nb, x, y, z, M);
     if (active) {
         const double c = K.c;
         if (out.n) out.n[cell] = M.n;
@@ -1724,8 +1764,9 @@ __global__ __launch_bounds__(256) void k_guess_samples(const TS* __restrict__ sr
         macroscopic<GUESS_NONE>(src, esrc, faceB, nullptr, K, (int)cell, nb, x, y, z, M);
         double Ef, S[3], Pi[6];
         fluid_tensor(K, M, M.B, Ef, S, Pi);  // the guess is not offered with the previous-B reading
-        double f[6];
-        mlp_features(Ef, S, Pi, M.N0, f);
+        double f[6], sn;
+        f[0] = flow_ratio(Ef, S, sn);
+        mlp_features(Ef, S, Pi, M.N0, sn, f);
         const double t0 = M.eps / Ef;
         const double t1 = sqrt(M.beta[0] * M.beta[0] + M.beta[1] * M.beta[1] + M.beta[2] * M.beta[2]);
         if (M.ok) {
@@ -1856,6 +1897,7 @@ hipError_t launch_step(const StateBuf& src, const StateBuf& dst, const Consts& K
             launch_fused<TS, GUESS_SINGLE, 64>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
         else
             launch_fused<TS, GUESS_PAIR, 64>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
+        launch_fused<TS, GUESS_MONITOR, 64>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);
     }
     else if (tune.px == 32)
         launch_fused<TS, GUESS_NONE, 32>(sd, se, dd, de, faceB, gt, K, zb, zg, yw, s);

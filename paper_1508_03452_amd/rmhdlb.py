@@ -50,7 +50,8 @@ class rmhdlb_diag(ctypes.Structure):
                 ("em_energy", ctypes.c_double), ("max_divB", ctypes.c_double), ("charge", ctypes.c_double),
                 ("mean_iters", ctypes.c_double), ("recon_rate", ctypes.c_double), ("B0", ctypes.c_double),
                 ("null_index", ctypes.c_int64), ("newton_hist", ctypes.c_int64 * 16),
-                ("n_failed", ctypes.c_int64), ("n_fallback", ctypes.c_int64), ("step", ctypes.c_int64)]
+                ("n_failed", ctypes.c_int64), ("n_fallback", ctypes.c_int64), ("step", ctypes.c_int64),
+                ("guess_steps", ctypes.c_int64)]
 
 
 GUESS_PARAMS = 1346
@@ -406,7 +407,7 @@ class Solver:
                                em_energy=d.em_energy, max_divB=d.max_divB, charge=d.charge,
                                mean_iters=d.mean_iters, n_failed=int(d.n_failed), step=int(d.step),
                                recon_rate=d.recon_rate, null_index=int(d.null_index), B0=d.B0,
-                               n_fallback=int(d.n_fallback),
+                               n_fallback=int(d.n_fallback), guess_steps=int(d.guess_steps),
                                newton_hist=np.array(list(d.newton_hist), dtype=np.int64))
         res["rc"] = rc
         return res

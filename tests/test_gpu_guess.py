@@ -156,3 +156,43 @@ def test_learned_guess_gains_on_fast_flows():
     assert errs[worst] <= TOL, (worst, errs[worst])
     assert dg["mean_iters"] <= 0.8 * dp["mean_iters"], (dg["mean_iters"], dp["mean_iters"])
     assert dg["n_fallback"] < 0.05 * w.ncells
+
+
+@pytest.mark.parametrize("storage", ["f64", "f16"])
+def test_guess_gate_closes_on_slow_flows(storage):
+    """On a slow flow (flare box 32 x 32 x 32, drive 0.1c: every cell's |S| / E_f stays below the gate of
+    0.1) the network runs in the first step only (the gate opens when the guess is enabled and closes
+    when a step meets no cell above it); the other steps take the plain recovery, so the state is
+    that of the plain form to rounding (the network and monitor kernels are other instantiations of the
+    same cell code: bitwise in FP16, within the plain parity bound 1e-12 of each state array's scale in
+    FP64, measured 6e-14), and the diagnostics count one network step."""
+    _torch_cuda()
+    w = W.flare(nx=32, ny=32, nz=32, Lz=6.0)
+    s, _, _ = _trained_solver(w, 2, storage)
+    plain = run_gpu(w, 2, storage=storage)
+    s.set_guess(True)
+    s.step(6)
+    plain.step(6)
+    dg = s.moments(fields=())["diag"]
+    assert dg["guess_steps"] == 1 and dg["n_failed"] == 0, dg["guess_steps"]
+    a, b = s.get_state().cpu().numpy(), plain.get_state().cpu().numpy()
+    scale = np.abs(b).reshape(b.shape[0], -1).max(axis=1)
+    gap = (np.abs(a - b).reshape(b.shape[0], -1).max(axis=1) / np.maximum(scale, 1e-300)).max()
+    print(f"[guess] gate closed, {storage}: largest state gap to the plain form {gap:.1e}", flush=True)
+    assert gap <= TOL, gap
+
+
+def test_guess_gate_stays_open_on_fast_flows():
+    """On the KH layer at v0 = 0.4 (|S| / E_f near 0.4 away from the layer) every step runs the network,
+    and init_fields resets the count."""
+    _torch_cuda()
+    w = W.kh(nx=96, ny=160, v0=0.4, ratio=10.0, sigma=1e3)
+    s, _, _ = _trained_solver(w, 3)
+    s.set_guess(True)
+    s.step(5)
+    d = s.moments(fields=())["diag"]
+    assert d["guess_steps"] == 5 and d["step"] == 8, (d["guess_steps"], d["step"])
+    s.init_fields(w.fields)
+    s.step(2)
+    d = s.moments(fields=())["diag"]
+    assert d["guess_steps"] == 2 and d["step"] == 2
