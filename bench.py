@@ -46,7 +46,19 @@ KERNEL_SOURCES = ("paper_1508_03452_amd/csrc/rmhdlb_kernels.hip", "paper_1508_03
 # shape the autotuner picks, and a changed kernel or an unmeasured shape
 # reports null.
 MEASURED_TRAFFIC = {
-    ("flare", "f32", "02ecb1bf1d03", "64,64,4"): 26.42,  # profiles/fused_step_f32_flare256x256x512.md
+    ("flare", "f64", "bdd5290bcdef", "64,32,2"): 65.04,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "bdd5290bcdef", "64,16,4"): 57.76,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "bdd5290bcdef", "64,32,4"): 63.46,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "bdd5290bcdef", "64,64,4"): 67.03,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f16", "bdd5290bcdef", "64,32,2"): 14.11,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16", "bdd5290bcdef", "64,16,4"): 13.81,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16", "bdd5290bcdef", "64,32,4"): 13.89,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16", "bdd5290bcdef", "64,64,4"): 14.85,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16+guess", "bdd5290bcdef", "64,32,2"): 13.78,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "bdd5290bcdef", "64,16,4"): 13.72,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "bdd5290bcdef", "64,32,4"): 13.89,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "bdd5290bcdef", "64,64,4"): 14.79,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f32", "bdd5290bcdef", "64,64,4"): 26.48,  # profiles/fused_step_f32_flare256x256x512.md
 }
 
 

@@ -32,8 +32,10 @@ def test_flare64_against_the_oracle_after_1000_steps():
     open faces elsewhere, sigma = 1e3), 1000 steps on the GPU in every form, against the FP64 oracle's
     fields after the same 1000 steps (tests/golden/flare64_oracle.npz, written by make_flare64.py from
     the oracle alone; six z-planes at every second cell).  FP64 within max(1e-12, 4 s) per field, s the
-    oracle's own one-ulp sensitivity stored with it; FP32, FP16 and FP16 + learned guess within the
-    stated bounds; global energy and mass against the oracle's sums."""
+    oracle's own rounding sensitivity stored with it; FP32, FP16 and FP16 + learned guess within the
+    stated bounds; global energy and mass against the oracle's sums (FP64 within max(1e-12, 4 s) with
+    their own stored sensitivity).  The sensitivity s is the largest gap to the reference oracle run of
+    a run from a density one ulp larger and of the oracle built with fused multiply-adds."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -79,7 +81,8 @@ def test_flare64_against_the_oracle_after_1000_steps():
     tol = {k: max(1e-12, 4 * float(g["sens_" + k])) for k in GOLD_FIELDS}
     bad = {k: (v, tol[k]) for k, v in e.items() if v > tol[k]}
     assert not bad, bad
-    assert de <= 1e-12 and dm <= 1e-12, (de, dm)
+    assert de <= max(1e-12, 4 * float(g["sens_diag_energy"])), (de, float(g["sens_diag_energy"]))
+    assert dm <= max(1e-12, 4 * float(g["sens_diag_mass"])), (dm, float(g["sens_diag_mass"]))
     for name in ("f32", "f16", "f16+guess"):
         e, de, _ = res[name]
         b = FLARE64_TOL[name.split("+")[0]]
