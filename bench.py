@@ -46,19 +46,20 @@ KERNEL_SOURCES = ("paper_1508_03452_amd/csrc/rmhdlb_kernels.hip", "paper_1508_03
 # shape the autotuner picks, and a changed kernel or an unmeasured shape
 # reports null.
 MEASURED_TRAFFIC = {
-    ("flare", "f64", "bdd5290bcdef", "64,32,2"): 65.04,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "bdd5290bcdef", "64,16,4"): 57.76,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "bdd5290bcdef", "64,32,4"): 63.46,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "bdd5290bcdef", "64,64,4"): 67.03,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f16", "bdd5290bcdef", "64,32,2"): 14.11,  # profiles/fused_step_f16_flare256x256x512.md
-    ("flare", "f16", "bdd5290bcdef", "64,16,4"): 13.81,  # profiles/fused_step_f16_flare256x256x512.md
-    ("flare", "f16", "bdd5290bcdef", "64,32,4"): 13.89,  # profiles/fused_step_f16_flare256x256x512.md
-    ("flare", "f16", "bdd5290bcdef", "64,64,4"): 14.85,  # profiles/fused_step_f16_flare256x256x512.md
-    ("flare", "f16+guess", "bdd5290bcdef", "64,32,2"): 13.78,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "bdd5290bcdef", "64,16,4"): 13.72,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "bdd5290bcdef", "64,32,4"): 13.89,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "bdd5290bcdef", "64,64,4"): 14.79,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f32", "bdd5290bcdef", "64,64,4"): 26.48,  # profiles/fused_step_f32_flare256x256x512.md
+    ("flare", "f64", "ef2e71431238", "64,16,4"): 57.79,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "ef2e71431238", "64,32,2"): 64.91,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "ef2e71431238", "64,32,4"): 63.56,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "ef2e71431238", "64,64,4"): 67.17,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f16", "ef2e71431238", "64,16,4"): 12.46,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16", "ef2e71431238", "64,32,2"): 15.28,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16", "ef2e71431238", "64,32,4"): 12.3,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16", "ef2e71431238", "64,64,4"): 12.3,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16+guess", "ef2e71431238", "64,16,4"): 12.48,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "ef2e71431238", "64,32,2"): 15.24,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "ef2e71431238", "64,32,4"): 12.34,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "ef2e71431238", "64,64,4"): 12.36,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f32", "ef2e71431238", "64,16,4"): 26.52,  # profiles/fused_step_f32_flare256x256x512.md
+    ("flare", "f32", "ef2e71431238", "64,64,4"): 26.46,  # profiles/fused_step_f32_flare256x256x512.md
 }
 
 
@@ -183,7 +184,7 @@ def run_sweep(steps, warmup, storage="f32"):
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     info = {"workload": f"batched sweep: {len(specs)} KH slabs, nx, ny in 256..1024, {ncell} cells, "
                         f"sigma 1e2..1e5, one launch per step, hipGraph replays (64 steps per graph)",
-            "storage": storage, "cells": ncell, "tile": f"{px}x{(256 if storage == 'f32' else 128) // px * yw} cells", "waves_per_simd": waves,
+            "storage": storage, "cells": ncell, "tile": f"{px}x{(128 if storage == 'f64' else 256) // px * yw} cells", "waves_per_simd": waves,
             "failed_cells": failed, "wall_s_timed": round(wall, 3),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_fused_batch",
@@ -305,12 +306,12 @@ ALG_BYTES = {"f64": (8, 8), "f32": (4, 4), "f16": (2, 4)}   # (distribution, E_p
 
 
 def tile_text(shape, storage="f64"):
-    """A launch shape in words; a row group has 128 cells with FP64 and FP16 storage (two lanes per cell)
-    and 256 with FP32 (one lane per cell)."""
+    """A launch shape in words; a row group has 128 cells with FP64 storage (two lanes per cell) and 256
+    with FP32 and FP16 (one lane per cell)."""
     px, zb, zg, yw = tuple(shape) + (1,) * (4 - len(shape))
     walk = (f"{zb} z-planes per block" if zg == 1 else
             f"{zg} blocks per column walking chunks of {zg * zb} z-planes interleaved ({zb} planes each)")
-    rows = (256 if storage == "f32" else 128) // px * yw
+    rows = (128 if storage == "f64" else 256) // px * yw
     return f"{px}x{rows} cells, {walk}"
 
 

@@ -337,8 +337,9 @@ int rmhdlb_mlp_eval(const float *w, const float *X, const float *Yt, int32_t n, 
 
 /* ---- launch tuning and batched sweeps --------------------------------------
  * The fused step runs blocks of 256 threads over row groups of px x (R / px)
- * cells, px in {64, 32, 16} (128 too in batches): R = 128 with FP64 and
- * FP16 storage (two lanes per cell), R = 256 with FP32 (one lane per cell);
+ * cells, px in {64, 32, 16} (128 too in batches): R = 128 with FP64
+ * storage (two lanes per cell), R = 256 with FP32 and FP16 (one lane per
+ * cell);
  * a block takes yw such groups stacked along y (a tile of px x (R / px) yw
  * cells) and walks zb z-planes.  With zg > 1 the planes are taken in chunks
  * of zg * zb per column, and the zg blocks of a chunk walk them interleaved
@@ -397,7 +398,7 @@ int rmhdlb_batch_step(rmhdlb_batch *batch, int64_t nsteps);
 
 /* Time the tiles of the batched step (state not advanced) and keep the
  * fastest: px x (R / px) yw cells, R = 128 cells per row group with FP64
- * and FP16 storage (two lanes per cell) and 256 with FP32 (one lane per
+ * storage (two lanes per cell) and 256 with FP32 and FP16 (one lane per
  * cell), so that the shapes 64 x 4, 32 x 8, 128 x 2, 16 x 16 and 64 x 8 are
  * among them for every storage type (eight shapes in all), each with the
  * kernel compiled for 2 and (FP32 storage) 3 waves per SIMD.  Cached per process by storage and the grids

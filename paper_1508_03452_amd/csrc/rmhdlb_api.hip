@@ -148,8 +148,8 @@ size_t dist_elem(int storage) {
     return storage == RMHDLB_STORE_F64 ? 8 : (storage == RMHDLB_STORE_F32 ? 4 : 2);
 }
 size_t efield_elem(int storage) { return storage == RMHDLB_STORE_F64 ? 8 : 4; }
-// The distribution block: 63 arrays of `stride` values in the pair layout (FP64, FP16), 65 in the quad
-// layout (FP32: the rest slot is a quad with two unused values).
+// The distribution block: 63 arrays of `stride` values in the pair layout (FP64), 65 in the quad and
+// double-quad layouts (FP32, FP16: the rest pair takes a quad with two unused values).
 size_t efield_offset(int storage, int64_t stride) {
     const int arrays = rmhd::quad_storage(storage) ? rmhd::QUAD_DIST_ARRAYS : rmhd::PAIR_DIST_ARRAYS;
     const size_t b = (size_t)arrays * (size_t)stride * dist_elem(storage);
@@ -1191,8 +1191,8 @@ int rmhdlb_batch_autotune(rmhdlb_batch* B, int32_t* px_out, int32_t* yw_out, int
     }
     if (!cached) {
         // tiles px x (cells per row group / px) yw, times the occupancy variants of the storage type:
-        // pair layout (FP64, FP16: 128 cells) 64x2, 32x4, 16x8, 64x4, 32x8, 128x2, 16x16, 64x8; quad
-        // layout (FP32: 256 cells) 64x4, 32x8, 16x16, 128x2, 64x8, 32x16, 128x4, 16x32
+        // pair layout (FP64: 128 cells) 64x2, 32x4, 16x8, 64x4, 32x8, 128x2, 16x16, 64x8; quad and
+        // double-quad layouts (FP32, FP16: 256 cells) 64x4, 32x8, 16x16, 128x2, 64x8, 32x16, 128x4, 16x32
         const BatchShape pair_shapes[8] = {{64, 1, 0}, {32, 1, 0}, {16, 1, 0}, {64, 2, 0},
                                            {32, 2, 0}, {128, 2, 0}, {16, 2, 0}, {64, 4, 0}};
         const BatchShape quad_shapes[8] = {{64, 1, 0}, {32, 1, 0}, {16, 1, 0}, {128, 1, 0},

@@ -105,9 +105,8 @@ struct Consts {
 // relative to the buffer's distribution pointer, which sits g0 elements into
 // the buffer (the ghost planes of a driven face take the g0 positions in
 // front of cell 0 of every array; position p = g0 + c of cell c).
-//  - FP64 and FP16 (pair layout): direction i as pairs (f_i, g_i), pair of
-//    cell c at 2 (i S + p); Maxwell population k as its own array at
-//    (38 + k) S + p.
+//  - FP64 (pair layout): direction i as pairs (f_i, g_i), pair of cell c at
+//    2 (i S + p); Maxwell population k as its own array at (38 + k) S + p.
 //  - FP32 (quad layout): direction slot s = 1..9 holds the opposite
 //    directions 2s - 1 (e) and 2s (-e) as quads (f_{2s-1}, g_{2s-1}, f_{2s},
 //    g_{2s}) at 4 (s S + p), slot 0 the rest pair (f_0, g_0, 0, 0); the moving
@@ -115,6 +114,11 @@ struct Consts {
 //    pairs at 40 S + 2 (m S + p), the rest one at 64 S + p.  One lane then
 //    reads both directions of a slot, and both populations of a pair, with one
 //    load per stencil point.
+//  - FP16 (double-quad layout): the quads of two slots side by side in one
+//    16-byte record, record r = 0..3 holding slots 2r + 1 and 2r + 2, record
+//    4 slot 9 and the rest pair (f_0, g_0, 0, 0), at 8 (r S + p); the Maxwell
+//    populations as in the quad layout.  The centre point and the six
+//    Laplacian points of two slots then take one load.
 constexpr int QUAD_SLOTS = 10;           // quad layout: 40 S elements of f and g
 constexpr int QUAD_DIST_ARRAYS = 65;     // quad layout: distribution block of 65 S elements
 constexpr int PAIR_DIST_ARRAYS = 63;     // pair layout: 38 S of f, g and 25 S of h
@@ -130,6 +134,14 @@ __host__ __device__ inline int64_t hrest_quad_index(const Consts& K, int64_t c) 
 // Direction i of the quad layout: its slot and its position (0 or 2) in the quad.
 __host__ __device__ constexpr int quad_slot(int i) { return (i + 1) / 2; }
 __host__ __device__ constexpr int quad_pos(int i) { return (i == 0 || (i & 1)) ? 0 : 2; }
+// Double-quad layout: record r of cell c, and slot s's record and offset (0 or 4) in it.
+constexpr int DQUAD_RECORDS = 5;
+__host__ __device__ inline int64_t dquad_index(const Consts& K, int r, int64_t c) {
+    return 8 * ((int64_t)r * K.stride + c) + 7 * K.g0;
+}
+__host__ __device__ constexpr int dquad_rec(int s) { return s == 0 ? 4 : (s - 1) / 2; }
+__host__ __device__ constexpr int dquad_off(int s) { return s == 0 ? 4 : (s == 9 ? 0 : ((s - 1) & 1) * 4); }
+static_assert(8 * DQUAD_RECORDS == 4 * QUAD_SLOTS, "the Maxwell block follows the same 40 S elements");
 
 // The pairings the quad layout relies on: slot s holds e_{2s-1} and its opposite; the Maxwell
 // populations 2m and 2m + 1 share the streaming offset and have opposite e and b.

@@ -206,10 +206,10 @@ hipError_t launch_face_b(const StateBuf& src, const Consts& K, double* faceB, hi
 // and zg blocks per column and chunk of zg * zb planes: tiles along x,
 // columns, blocks.
 void step_geometry(const Consts& K, int px, int zb, int zg, int yw, int cpb, int& tiles_x, int& ncol, int& nblk);
-// Cells per row group of a fused-step block: 128 in the pair layout (FP64 and FP16 storage, two lanes
-// per cell), 256 in the quad layout (FP32 storage, one lane per cell).
+// Cells per row group of a fused-step block: 128 in the pair layout (FP64 storage, two lanes per cell),
+// 256 in the quad and double-quad layouts (FP32 and FP16 storage, one lane per cell).
 inline int cells_per_block(bool quad) { return quad ? 256 : 128; }
-inline bool quad_storage(int32_t storage) { return storage == RMHDLB_STORE_F32; }
+inline bool quad_storage(int32_t storage) { return storage != RMHDLB_STORE_F64; }
 // One batched step (face pass of the instances that need it, then the fused
 // step of all) reading buffer `parity` of every instance; px the tile width
 // (128, 64, 32, 16), waves the occupancy variant (FP32: 2 or 3).

@@ -82,20 +82,30 @@ __device__ __forceinline__ void st2(T* __restrict__ p, V f, V g) {
         *reinterpret_cast<vec2<T>*>(p) = v;
 }
 
-// FP32 storage uses the quad layout, FP64 and FP16 the pair layout (see
-// rmhdlb_device.h): one lane per cell runs FP32 1.4x faster than two, and
-// FP16 3 % slower (its narrower loads leave fewer to save, and a lane that
-// carries the whole cell holds FP16 to 2 waves per SIMD instead of 3).  Element indices of f_i, g_i and h_k of cell c (c may be a
-// ghost cell of a driven face, down to -g0), for the kernels that read or
-// write single values.
+// FP64 storage uses the pair layout (two lanes per cell), FP32 the quad and
+// FP16 the double-quad layout (one lane per cell; see rmhdlb_device.h).
+// Element indices of f_i, g_i and h_k of cell c (c may be a ghost cell of a
+// driven face, down to -g0), for the kernels that read or write single values.
 template <typename TS>
-constexpr bool quad_layout() {
-    return sizeof(TS) == 4;
+constexpr bool quad_layout() {  // one lane per cell
+    return sizeof(TS) != 8;
+}
+template <typename TS>
+constexpr bool dquad_layout() {
+    return sizeof(TS) == 2;
+}
+// Element index of the quad of slot s of cell c in the quad and double-quad layouts.
+template <typename TS>
+__host__ __device__ __forceinline__ int64_t slot_index(const Consts& K, int s, int64_t c) {
+    if constexpr (dquad_layout<TS>())
+        return dquad_index(K, dquad_rec(s), c) + dquad_off(s);
+    else
+        return quad_index(K, s, c);
 }
 template <typename TS>
 __device__ __forceinline__ int64_t f_at(const Consts& K, int i, int64_t c) {
     if constexpr (quad_layout<TS>())
-        return quad_index(K, quad_slot(i), c) + quad_pos(i);
+        return slot_index<TS>(K, quad_slot(i), c) + quad_pos(i);
     else
         return fg_index(K, i, c);
 }
@@ -579,7 +589,7 @@ constexpr int PTPB = 256;  // threads of a fused-step block: 128 cells, two lane
 #define RMHDLB_WAVES 2
 #endif
 #ifndef RMHDLB_WAVES_F16
-#define RMHDLB_WAVES_F16 3
+#define RMHDLB_WAVES_F16 2
 #endif
 template <typename TS, int GM>
 constexpr int fused_waves() {
@@ -871,6 +881,39 @@ __device__ __forceinline__ vec4<V> ldv4(const T* __restrict__ p, int64_t i) {
     return r;
 }
 
+// 16 bytes of FP16 (two quads) at element i
+template <typename V, typename T>
+__device__ __forceinline__ void ldv8(const T* __restrict__ p, int64_t i, vec4<V>& lo, vec4<V>& hi) {
+    typedef T vec8 __attribute__((ext_vector_type(8)));
+    const vec8 v = *reinterpret_cast<const vec8*>(p + i);
+    lo.x = static_cast<V>(v[0]);
+    lo.y = static_cast<V>(v[1]);
+    lo.z = static_cast<V>(v[2]);
+    lo.w = static_cast<V>(v[3]);
+    hi.x = static_cast<V>(v[4]);
+    hi.y = static_cast<V>(v[5]);
+    hi.z = static_cast<V>(v[6]);
+    hi.w = static_cast<V>(v[7]);
+}
+
+template <bool NT, typename T, typename V>
+__device__ __forceinline__ void st8(T* __restrict__ p, const vec4<V>& lo, const vec4<V>& hi) {
+    typedef T vec8 __attribute__((ext_vector_type(8)));
+    vec8 v;
+    v[0] = static_cast<T>(lo.x);
+    v[1] = static_cast<T>(lo.y);
+    v[2] = static_cast<T>(lo.z);
+    v[3] = static_cast<T>(lo.w);
+    v[4] = static_cast<T>(hi.x);
+    v[5] = static_cast<T>(hi.y);
+    v[6] = static_cast<T>(hi.z);
+    v[7] = static_cast<T>(hi.w);
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, reinterpret_cast<vec8*>(p));
+    else
+        *reinterpret_cast<vec8*>(p) = v;
+}
+
 template <bool NT, typename T, typename V>
 __device__ __forceinline__ void st4(T* __restrict__ p, V a, V b, V c, V d) {
     vec4<T> v;
@@ -889,7 +932,9 @@ __device__ __forceinline__ void st4(T* __restrict__ p, V a, V b, V c, V d) {
 #define RMHDLB_QGROUP 1
 #endif
 
-// The fused step of one cell in one lane (FP32 storage, quad layout):
+// The fused step of one cell in one lane (FP32 storage, quad layout; FP16,
+// double-quad layout, where one load at the centre and at each Laplacian
+// point serves the two slots of a record):
 // slot s = 1..9 carries the opposite directions i0 = 2s - 1 (+e) and
 // i1 = 2s (-e), and one load per point of the link x - 2e .. x + 2e and of the
 // Laplacian serves both; the Maxwell populations 2m, 2m + 1 come from one load
@@ -909,81 +954,156 @@ __device__ __forceinline__ void quad_cell(const TS* __restrict__ sd, const TE* _
     constexpr int CM = VR & 1;
     const V cour = (V)K.cour, kv = (V)K.kv, slope = (VR & 2) ? (V)K.slope : V(0.5);
     V Fv[Q], Gv[Q], Hv[QH + 1];
-    V t00, t0x = 0, t0y = 0, t0z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0, n0;
-    {
-        const vec2<V> fg0 = ldv2<V>(sd, quad_index(K, 0, cell));
-        Fv[0] = fg0.x;
-        Gv[0] = fg0.y;
-        t00 = Fv[0];
-        n0 = Gv[0];
-    }
+    V t00 = 0, t0x = 0, t0y = 0, t0z = 0, txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0, n0 = 0;
     const int lap_xp = nb.at(1, 0, 0), lap_xm = nb.at(-1, 0, 0), lap_yp = nb.at(0, 1, 0), lap_ym = nb.at(0, -1, 0),
               lap_zp = nb.at(0, 0, 1), lap_zm = nb.at(0, 0, -1);
-    static_for<1>([&](auto ic) {
-        constexpr int s = decltype(ic)::value;
-        if constexpr (s <= 9) {
-            constexpr int i0 = 2 * s - 1, i1 = 2 * s;
-            constexpr int ex = EX[i0], ey = EY[i0], ez = EZ[i0];
-            const TS* __restrict__ qa = sd + quad_index(K, s, 0);  // uniform base of slot s
-            auto ldq = [&](int off) { return ldv4<V>(qa, 4 * (int64_t)(cell + off)); };
-            const vec4<V> q0 = ldq(0), qm2 = ldq(nb.at(-2 * ex, -2 * ey, -2 * ez)), qm1 = ldq(nb.at(-ex, -ey, -ez)),
-                          qp1 = ldq(nb.at(ex, ey, ez)), qp2 = ldq(nb.at(2 * ex, 2 * ey, 2 * ez));
-            // the Laplacian's six neighbours (f of both directions); on an axis slot two of them are the
-            // link points x -+ e
-            constexpr bool axis_slot = (ex != 0) + (ey != 0) + (ez != 0) == 1;
-            vec4<V> lxp, lxm, lyp, lym, lzp, lzm;
-            if constexpr (axis_slot && ex != 0) {
-                lxp = qp1;
-                lxm = qm1;
-            } else {
-                lxp = ldq(lap_xp);
-                lxm = ldq(lap_xm);
-            }
-            if constexpr (axis_slot && ey != 0) {
-                lyp = qp1;
-                lym = qm1;
-            } else {
-                lyp = ldq(lap_yp);
-                lym = ldq(lap_ym);
-            }
-            if constexpr (axis_slot && ez != 0) {
-                lzp = qp1;
-                lzm = qm1;
-            } else {
-                lzp = ldq(lap_zp);
-                lzm = ldq(lap_zm);
-            }
-            // +e: upwind stencil x - 2e, x - e, x, x + e; -e: x + 2e, x + e, x, x - e
-            const V lap0 = (lxp.x + lxm.x) + (lyp.x + lym.x) + (lzp.x + lzm.x) - V(6) * q0.x;
-            const V lap1 = (lxp.z + lxm.z) + (lyp.z + lym.z) + (lzp.z + lzm.z) - V(6) * q0.z;
-            const V fv0 = q0.x - cour * ((q0.x + slope * minmod(q0.x - qm1.x, qp1.x - q0.x)) -
-                                         (qm1.x + slope * minmod(qm1.x - qm2.x, q0.x - qm1.x))) + kv * lap0;
-            const V fv1 = q0.z - cour * ((q0.z + slope * minmod(q0.z - qp1.z, qm1.z - q0.z)) -
-                                         (qp1.z + slope * minmod(qp1.z - qp2.z, q0.z - qp1.z))) + kv * lap1;
-            const V gv0 = q0.y - cour * ((q0.y + slope * minmod(q0.y - qm1.y, qp1.y - q0.y)) -
-                                         (qm1.y + slope * minmod(qm1.y - qm2.y, q0.y - qm1.y)));
-            const V gv1 = q0.w - cour * ((q0.w + slope * minmod(q0.w - qp1.w, qm1.w - q0.w)) -
-                                         (qp1.w + slope * minmod(qp1.w - qp2.w, q0.w - qp1.w)));
-            Fv[i0] = fv0;
-            Fv[i1] = fv1;
-            Gv[i0] = gv0;
-            Gv[i1] = gv1;
-            if constexpr (s % RMHDLB_QGROUP == 0 || s == 9)
-                asm volatile("" : "+v"(Fv[i0]), "+v"(Fv[i1]), "+v"(Gv[i0]), "+v"(Gv[i1])::"memory");
-            const V sum = fv0 + fv1, dif = fv0 - fv1;
-            t00 += sum;
-            n0 += gv0 + gv1;
-            if (ex) t0x += ex * dif;
-            if (ey) t0y += ey * dif;
-            if (ez) t0z += ez * dif;
-            if (ex) txx += sum;
-            if (ey) tyy += sum;
-            if (ez) tzz += sum;
-            if (ex * ey) txy += (ex * ey) * sum;
-            if (ex * ez) txz += (ex * ez) * sum;
-            if (ey * ez) tyz += (ey * ez) * sum;
+    // Transport and moments of slot s from its quads at the link points x - 2e .. x + 2e and the
+    // Laplacian's six neighbours.
+    auto transport = [&](auto sc, const vec4<V>& q0, const vec4<V>& qm2, const vec4<V>& qm1, const vec4<V>& qp1,
+                         const vec4<V>& qp2, const vec4<V>& lxp, const vec4<V>& lxm, const vec4<V>& lyp,
+                         const vec4<V>& lym, const vec4<V>& lzp, const vec4<V>& lzm) {
+        constexpr int s = decltype(sc)::value;
+        constexpr int i0 = 2 * s - 1, i1 = 2 * s;
+        constexpr int ex = EX[i0], ey = EY[i0], ez = EZ[i0];
+        // +e: upwind stencil x - 2e, x - e, x, x + e; -e: x + 2e, x + e, x, x - e
+        const V lap0 = (lxp.x + lxm.x) + (lyp.x + lym.x) + (lzp.x + lzm.x) - V(6) * q0.x;
+        const V lap1 = (lxp.z + lxm.z) + (lyp.z + lym.z) + (lzp.z + lzm.z) - V(6) * q0.z;
+        const V fv0 = q0.x - cour * ((q0.x + slope * minmod(q0.x - qm1.x, qp1.x - q0.x)) -
+                                     (qm1.x + slope * minmod(qm1.x - qm2.x, q0.x - qm1.x))) + kv * lap0;
+        const V fv1 = q0.z - cour * ((q0.z + slope * minmod(q0.z - qp1.z, qm1.z - q0.z)) -
+                                     (qp1.z + slope * minmod(qp1.z - qp2.z, q0.z - qp1.z))) + kv * lap1;
+        const V gv0 = q0.y - cour * ((q0.y + slope * minmod(q0.y - qm1.y, qp1.y - q0.y)) -
+                                     (qm1.y + slope * minmod(qm1.y - qm2.y, q0.y - qm1.y)));
+        const V gv1 = q0.w - cour * ((q0.w + slope * minmod(q0.w - qp1.w, qm1.w - q0.w)) -
+                                     (qp1.w + slope * minmod(qp1.w - qp2.w, q0.w - qp1.w)));
+        Fv[i0] = fv0;
+        Fv[i1] = fv1;
+        Gv[i0] = gv0;
+        Gv[i1] = gv1;
+        const V sum = fv0 + fv1, dif = fv0 - fv1;
+        t00 += sum;
+        n0 += gv0 + gv1;
+        if (ex) t0x += ex * dif;
+        if (ey) t0y += ey * dif;
+        if (ez) t0z += ez * dif;
+        if (ex) txx += sum;
+        if (ey) tyy += sum;
+        if (ez) tzz += sum;
+        if (ex * ey) txy += (ex * ey) * sum;
+        if (ex * ez) txz += (ex * ez) * sum;
+        if (ey * ez) tyz += (ey * ez) * sum;
+    };
+    // a slot whose link runs along one axis finds its points x -+ e among the Laplacian's neighbours
+    if constexpr (!dquad_layout<TS>()) {
+        {
+            const vec2<V> fg0 = ldv2<V>(sd, quad_index(K, 0, cell));
+            Fv[0] = fg0.x;
+            Gv[0] = fg0.y;
+            t00 = Fv[0];
+            n0 = Gv[0];
         }
-    });
+        static_for<1>([&](auto ic) {
+            constexpr int s = decltype(ic)::value;
+            if constexpr (s <= 9) {
+                constexpr int i0 = 2 * s - 1;
+                constexpr int ex = EX[i0], ey = EY[i0], ez = EZ[i0];
+                const TS* __restrict__ qa = sd + quad_index(K, s, 0);  // uniform base of slot s
+                auto ldq = [&](int off) { return ldv4<V>(qa, 4 * (int64_t)(cell + off)); };
+                const vec4<V> q0 = ldq(0), qm2 = ldq(nb.at(-2 * ex, -2 * ey, -2 * ez)), qm1 = ldq(nb.at(-ex, -ey, -ez)),
+                              qp1 = ldq(nb.at(ex, ey, ez)), qp2 = ldq(nb.at(2 * ex, 2 * ey, 2 * ez));
+                constexpr bool ax = (ex != 0) + (ey != 0) + (ez != 0) == 1;
+                const vec4<V> lxp = ax && ex ? qp1 : ldq(lap_xp), lxm = ax && ex ? qm1 : ldq(lap_xm);
+                const vec4<V> lyp = ax && ey ? qp1 : ldq(lap_yp), lym = ax && ey ? qm1 : ldq(lap_ym);
+                const vec4<V> lzp = ax && ez ? qp1 : ldq(lap_zp), lzm = ax && ez ? qm1 : ldq(lap_zm);
+                transport(ic, q0, qm2, qm1, qp1, qp2, lxp, lxm, lyp, lym, lzp, lzm);
+                V(&F_)[Q] = Fv;
+                V(&G_)[Q] = Gv;
+                if constexpr (s % RMHDLB_QGROUP == 0 || s == 9)
+                    asm volatile("" : "+v"(F_[i0]), "+v"(F_[i0 + 1]), "+v"(G_[i0]), "+v"(G_[i0 + 1])::"memory");
+            }
+        });
+    } else {
+        // record r: slots a = 2r + 1 and b = 2r + 2 (record 4: slot 9 and the rest pair); the centre and
+        // the Laplacian's points take one 16-byte load for both slots, the link points an 8-byte one
+        static_for<0>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            if constexpr (r < DQUAD_RECORDS) {
+                constexpr int sa = 2 * r + 1, sb = r < 4 ? 2 * r + 2 : 0;
+                const TS* __restrict__ ra = sd + dquad_index(K, r, 0);  // uniform base of record r
+                auto ld8 = [&](int off, vec4<V>& lo, vec4<V>& hi) { ldv8<V>(ra, 8 * (int64_t)(cell + off), lo, hi); };
+                auto ld4 = [&](int off, int half) { return ldv4<V>(ra, 8 * (int64_t)(cell + off) + 4 * half); };
+                vec4<V> ca, cb;
+                ld8(0, ca, cb);
+                vec4<V> xpa, xpb, xma, xmb, ypa, ypb, yma, ymb, zpa, zpb, zma, zmb;
+                if constexpr (sb != 0) {
+                    ld8(lap_xp, xpa, xpb);
+                    ld8(lap_xm, xma, xmb);
+                    ld8(lap_yp, ypa, ypb);
+                    ld8(lap_ym, yma, ymb);
+                    ld8(lap_zp, zpa, zpb);
+                    ld8(lap_zm, zma, zmb);
+                } else {
+                    xpa = ld4(lap_xp, 0);
+                    xma = ld4(lap_xm, 0);
+                    ypa = ld4(lap_yp, 0);
+                    yma = ld4(lap_ym, 0);
+                    zpa = ld4(lap_zp, 0);
+                    zma = ld4(lap_zm, 0);
+                }
+                // the link points of slot s (half h of the record), reusing the Laplacian's on an axis slot
+                auto links = [&](auto sc, int h, const vec4<V>& xp, const vec4<V>& xm, const vec4<V>& yp,
+                                 const vec4<V>& ym, const vec4<V>& zp, const vec4<V>& zm, vec4<V>& qm2, vec4<V>& qm1,
+                                 vec4<V>& qp1, vec4<V>& qp2) {
+                    constexpr int s = decltype(sc)::value;
+                    constexpr int ex = EX[2 * s - 1], ey = EY[2 * s - 1], ez = EZ[2 * s - 1];
+                    constexpr bool ax = (ex != 0) + (ey != 0) + (ez != 0) == 1;
+                    qm2 = ld4(nb.at(-2 * ex, -2 * ey, -2 * ez), h);
+                    qp2 = ld4(nb.at(2 * ex, 2 * ey, 2 * ez), h);
+                    if constexpr (ax && ex == 1) {
+                        qp1 = xp;
+                        qm1 = xm;
+                    } else if constexpr (ax && ex == -1) {
+                        qp1 = xm;
+                        qm1 = xp;
+                    } else if constexpr (ax && ey == 1) {
+                        qp1 = yp;
+                        qm1 = ym;
+                    } else if constexpr (ax && ey == -1) {
+                        qp1 = ym;
+                        qm1 = yp;
+                    } else if constexpr (ax && ez == 1) {
+                        qp1 = zp;
+                        qm1 = zm;
+                    } else if constexpr (ax && ez == -1) {
+                        qp1 = zm;
+                        qm1 = zp;
+                    } else {
+                        qp1 = ld4(nb.at(ex, ey, ez), h);
+                        qm1 = ld4(nb.at(-ex, -ey, -ez), h);
+                    }
+                };
+                vec4<V> am2, am1, ap1, ap2;
+                links(std::integral_constant<int, sa>{}, 0, xpa, xma, ypa, yma, zpa, zma, am2, am1, ap1, ap2);
+                transport(std::integral_constant<int, sa>{}, ca, am2, am1, ap1, ap2, xpa, xma, ypa, yma, zpa, zma);
+                V(&F_)[Q] = Fv;
+                V(&G_)[Q] = Gv;
+                asm volatile("" : "+v"(F_[2 * sa - 1]), "+v"(F_[2 * sa]), "+v"(G_[2 * sa - 1]), "+v"(G_[2 * sa])::"memory");
+                if constexpr (sb != 0) {
+                    vec4<V> bm2, bm1, bp1, bp2;
+                    links(std::integral_constant<int, sb>{}, 1, xpb, xmb, ypb, ymb, zpb, zmb, bm2, bm1, bp1, bp2);
+                    transport(std::integral_constant<int, sb>{}, cb, bm2, bm1, bp1, bp2, xpb, xmb, ypb, ymb, zpb,
+                              zmb);
+                    asm volatile("" : "+v"(F_[2 * sb - 1]), "+v"(F_[2 * sb]), "+v"(G_[2 * sb - 1]),
+                                 "+v"(G_[2 * sb])::"memory");
+                } else {  // the rest pair
+                    Fv[0] = cb.x;
+                    Gv[0] = cb.y;
+                    t00 += Fv[0];
+                    n0 += Gv[0];
+                }
+            }
+        });
+    }
     // stream h (Eq. LB_Maxwell): the pair 2m, 2m + 1 from its common source cell
     V ehx = 0, ehy = 0, ehz = 0, bx = 0, by = 0, bz = 0, hs = 0;
 #pragma unroll
@@ -1074,39 +1194,69 @@ __device__ __forceinline__ void quad_cell(const TS* __restrict__ sd, const TE* _
             fw = fx * M.beta[0] + fy * M.beta[1] + fz * M.beta[2];
         }
     }
+    vec4<V> rest;  // new (f_0, g_0, 0, 0)
     {
         const V q0 = (V)K.fsh[0] - fe.template eq<0>();
         const V geq0 = (V)K.wp[0] * ng * (V(1) - gc3b2);
         V f0n = CM == 0 ? Fv[0] - rate * (Fv[0] + q0) : (Fv[0] - rate * q0) / (V(1) + rate);
         if constexpr ((VR & 4) != 0) f0n += (V)fw;
-        if (active) st2<NT>(dd + quad_index(K, 0, cell), f0n, (Gv[0] + wg * (geq0 - (V)K.gsh[0])) * inv1wg);
+        rest.x = f0n;
+        rest.y = (Gv[0] + wg * (geq0 - (V)K.gsh[0])) * inv1wg;
+        rest.z = V(0);
+        rest.w = V(0);
+        if constexpr (!dquad_layout<TS>())
+            if (active) st2<NT>(dd + quad_index(K, 0, cell), rest.x, rest.y);
     }
     put(dd + hrest_quad_index(K, cell), (V)(2.0 * M.rho) - Hv[QH]);
-    static_for<1>([&](auto ic) {
-        constexpr int s = decltype(ic)::value;
-        if constexpr (s <= 9) {
-            constexpr int i0 = 2 * s - 1, i1 = 2 * s;
-            constexpr int cls = i0 <= 6 ? 1 : 2;
-            const V eb = EX[i0] * bx_ + EY[i0] * by_ + EZ[i0] * bz_;  // e_i0 . beta; -eb for i1
-            const V q_0 = (V)K.fsh[cls] - feq_signed<i0>(fe, V(1));
-            const V q_1 = (V)K.fsh[cls] - feq_signed<i0>(fe, V(-1));
-            const V om0 = rate * (V(1) - V(KAPPA) * eb), om1 = rate * (V(1) + V(KAPPA) * eb);
-            const V ebb = gc2 * eb * eb - gc3b2;
-            const V geq_0 = (V)K.wp[cls] * ng * (V(1) + gc1 * eb + ebb);
-            const V geq_1 = (V)K.wp[cls] * ng * (V(1) - gc1 * eb + ebb);
-            V fn0 = CM == 0 ? Fv[i0] - om0 * (Fv[i0] + q_0) : (Fv[i0] - om0 * q_0) / (V(1) + om0);
-            V fn1 = CM == 0 ? Fv[i1] - om1 * (Fv[i1] + q_1) : (Fv[i1] - om1 * q_1) / (V(1) + om1);
-            if constexpr ((VR & 4) != 0) {
-                constexpr double wcls = cls == 1 ? 99.0 / 722.0 : 9.0 / 361.0;  // D3Q19 weights
-                const double fe_ = (19.0 / 9.0) * wcls / KAPPA * (EX[i0] * fx + EY[i0] * fy + EZ[i0] * fz);
-                fn0 += (V)fe_;
-                fn1 += (V)(-fe_);
-            }
-            if (active)
-                st4<NT>(dd + quad_index(K, s, cell), fn0, (Gv[i0] + wg * (geq_0 - (V)K.gsh[cls])) * inv1wg, fn1,
-                        (Gv[i1] + wg * (geq_1 - (V)K.gsh[cls])) * inv1wg);
+    // the new quad (f, g, f-bar, g-bar) of slot s
+    auto collide = [&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        constexpr int i0 = 2 * s - 1, i1 = 2 * s;
+        constexpr int cls = i0 <= 6 ? 1 : 2;
+        const V eb = EX[i0] * bx_ + EY[i0] * by_ + EZ[i0] * bz_;  // e_i0 . beta; -eb for i1
+        const V q_0 = (V)K.fsh[cls] - feq_signed<i0>(fe, V(1));
+        const V q_1 = (V)K.fsh[cls] - feq_signed<i0>(fe, V(-1));
+        const V om0 = rate * (V(1) - V(KAPPA) * eb), om1 = rate * (V(1) + V(KAPPA) * eb);
+        const V ebb = gc2 * eb * eb - gc3b2;
+        const V geq_0 = (V)K.wp[cls] * ng * (V(1) + gc1 * eb + ebb);
+        const V geq_1 = (V)K.wp[cls] * ng * (V(1) - gc1 * eb + ebb);
+        V fn0 = CM == 0 ? Fv[i0] - om0 * (Fv[i0] + q_0) : (Fv[i0] - om0 * q_0) / (V(1) + om0);
+        V fn1 = CM == 0 ? Fv[i1] - om1 * (Fv[i1] + q_1) : (Fv[i1] - om1 * q_1) / (V(1) + om1);
+        if constexpr ((VR & 4) != 0) {
+            constexpr double wcls = cls == 1 ? 99.0 / 722.0 : 9.0 / 361.0;  // D3Q19 weights
+            const double fe_ = (19.0 / 9.0) * wcls / KAPPA * (EX[i0] * fx + EY[i0] * fy + EZ[i0] * fz);
+            fn0 += (V)fe_;
+            fn1 += (V)(-fe_);
         }
-    });
+        vec4<V> q;
+        q.x = fn0;
+        q.y = (Gv[i0] + wg * (geq_0 - (V)K.gsh[cls])) * inv1wg;
+        q.z = fn1;
+        q.w = (Gv[i1] + wg * (geq_1 - (V)K.gsh[cls])) * inv1wg;
+        return q;
+    };
+    if constexpr (!dquad_layout<TS>()) {
+        static_for<1>([&](auto ic) {
+            constexpr int s = decltype(ic)::value;
+            if constexpr (s <= 9) {
+                const vec4<V> q = collide(ic);
+                if (active) st4<NT>(dd + quad_index(K, s, cell), q.x, q.y, q.z, q.w);
+            }
+        });
+    } else {
+        static_for<0>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            if constexpr (r < DQUAD_RECORDS) {
+                const vec4<V> a = collide(std::integral_constant<int, 2 * r + 1>{});
+                if constexpr (r < 4) {
+                    const vec4<V> b = collide(std::integral_constant<int, 2 * r + 2>{});
+                    if (active) st8<NT>(dd + dquad_index(K, r, cell), a, b);
+                } else {
+                    if (active) st8<NT>(dd + dquad_index(K, r, cell), a, rest);
+                }
+            }
+        });
+    }
     const V cj = (V)(1.0 / (16.0 * 1.4142135623730951 * K.c)), ce = (V)(1.0 / (8.0 * 1.4142135623730951 * K.c));
     const V J0 = (V)M.J[0], J1 = (V)M.J[1], J2 = (V)M.J[2];
     const V E0 = (V)M.E[0], E1 = (V)M.E[1], E2 = (V)M.E[2];
@@ -1146,8 +1296,8 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
                                             TS* __restrict__ dd, TE* __restrict__ de,
                                             const double* __restrict__ faceB, const GuessTables* __restrict__ gt,
                                             const Consts& K, int tiles_x, int ncol, int zb, int zg, int yw, int b) {
-    // pair layout (FP64, FP16): 128 cells per row group, two lanes each; quad layout (FP32): 256 cells,
-    // one lane each
+    // pair layout (FP64): 128 cells per row group, two lanes each; quad and double-quad layouts (FP32,
+    // FP16): 256 cells, one lane each
     constexpr bool ONE = quad_layout<TS>();
     constexpr int PYT = (ONE ? 256 : 128) / PXT;
     const int per = ncol * zg, zc = b / per, r = b % per;
@@ -1175,13 +1325,13 @@ __device__ __forceinline__ void fused_block(const TS* __restrict__ sd, const TE*
     const int z0 = zc * zb * zg, z1 = min(K.nz, z0 + zb * zg);
     double bmax = 0.0;
     bool gate = false;  // a cell of the walk lay above the guess's gate (uniform over the wavefront)
-    // In the forms whose cell code spills (FP64, and FP16 at three waves)
-    // the lane's coordinates are made opaque at every plane, so that the x-
-    // and y-parts of the neighbour table are recomputed per plane (a few
-    // integer operations) instead of being kept across the walk and spilled:
-    // that took 11 scratch reloads per plane out of the plain FP16 loop and
-    // 7 out of the FP64 one.  FP32 does not spill and keeps them (recomputing
-    // them there measured 6 % slower).
+    // In FP64 and FP16 the lane's coordinates are made opaque at every plane,
+    // so that the x- and y-parts of the neighbour table are recomputed per
+    // plane (a few integer operations) instead of being kept across the walk:
+    // in FP64, whose cell code is at the register limit, that took 7 scratch
+    // reloads per plane out of the loop; in FP16 (double-quad layout) it is
+    // 0.4-1.2 % faster.  FP32 keeps them (recomputing them there measured 6 %
+    // slower).
     constexpr bool opaque = sizeof(TS) != 4;
     const int groups = all_lanes ? yw : ng;
     for (int z = z0 + zoff; z < z1; z += zg) {

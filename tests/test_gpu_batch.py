@@ -168,7 +168,7 @@ def test_batch_rejects_mixed_parity_and_autotunes():
     b.close()
 
 
-# the batch tuner's tiles (px, yw) of both layouts: px x (R / px) yw cells, R = 128 (FP64, FP16), 256 (FP32)
+# the batch tuner's tiles (px, yw) of both layouts: px x (R / px) yw cells, R = 128 (FP64), 256 (FP32, FP16)
 BATCH_TILES = ((64, 1), (32, 1), (16, 1), (128, 1), (64, 2), (32, 2), (128, 2), (16, 2), (64, 4))
 
 
