@@ -471,25 +471,25 @@ def _sub_state(state, shape, cx, cy, cz, r=2):
     return state[:, iz][:, :, iy][:, :, :, ix], (len(ix), len(iy), len(iz))
 
 
-@pytest.mark.parametrize("name", ["kh", "flare"])
-def test_full_size_sampled_cells_one_step(name):
+@pytest.mark.parametrize("name,prefix", [("kh", 3), ("flare", 3), ("kh", 199), ("flare", 199)])
+def test_full_size_sampled_cells_one_step(name, prefix):
     """At the full benchmark sizes (KH slab 1024x2048x1, flare box 256x256x512)
-    and the benchmark's launch configuration: take the GPU state after a few
-    steps, cut the stencil neighbourhood of sampled interior cells, advance it
-    one step with the oracle, and compare the sampled cells' new state with the
-    GPU's own next step."""
+    and the benchmark's launch configuration: take the GPU state after 3 or 199
+    steps (the KH slab's 200-step prefix), cut the stencil neighbourhood of
+    sampled interior cells, advance it one step with the oracle, and compare the
+    sampled cells' new state with the GPU's own next step."""
     torch = _torch_cuda()
     w = W.kh() if name == "kh" else W.flare()
     s = run_gpu(w, 0)
     shape = s.autotune()   # the launch shape bench.py times (the state is not advanced)
-    print(f"[parity] {name} full size, autotuned shape {shape}", flush=True)
-    s.step(3)
+    print(f"[parity] {name} full size, autotuned shape {shape}, after {prefix} steps", flush=True)
+    s.step(prefix)
     st = s.get_state()
     s.step(1)
     st1 = s.get_state()
-    # the same four steps in the default shape (one block per column walk of
-    # 4 planes): the launch shape changes the order of work, not one bit
-    d = run_gpu(w, 4)
+    # the same steps in the default shape (one block per column walk of 4
+    # planes): the launch shape changes the order of work, not one bit
+    d = run_gpu(w, prefix + 1)
     assert torch.equal(d.get_state(), st1)
     d.close()
     del d
@@ -515,8 +515,54 @@ def test_full_size_sampled_cells_one_step(name):
         for sl in (slice(0, 19), slice(19, 38), slice(38, 63), slice(63, 66)):
             scale = max(np.abs(ref[sl]).max(), 1e-3 * field_scale(w))
             worst = max(worst, np.abs(got[sl] - ref[sl]).max() / scale)
-    print(f"[parity] {name} full-size sampled-cell worst {worst:.2e}", flush=True)
+    print(f"[parity] {name} full-size sampled-cell worst {worst:.2e} after {prefix} steps", flush=True)
     assert worst <= TOL
+
+
+# One step of a reduced storage form from its own state, against the FP64 oracle's step from the same
+# (widened) state, per state group relative to the group's largest value: the form's arithmetic and
+# the rounding of the stored deviations in that one step: a few units of the storage's rounding
+# (FP32 6e-8, FP16 4.9e-4 of the stored deviation).  Measured on the KH slab and the flare box: FP32
+# 2.1e-7, FP16 5.6e-4.
+ONE_STEP_TOL = {"f32": 1e-6, "f16": 2e-3}
+
+
+@pytest.mark.parametrize("name,storage", [("kh", "f32"), ("kh", "f16"), ("flare", "f32"), ("flare", "f16")])
+def test_full_size_sampled_cells_one_step_reduced_forms(name, storage):
+    """The FP32 and FP16 forms at the full benchmark sizes in their tuned launch shapes (quad and
+    double-quad layouts, one lane per cell): sampled interior cells after 3 steps, one step by the
+    oracle from the form's own state against the form's next step."""
+    torch = _torch_cuda()
+    w = W.kh() if name == "kh" else W.flare()
+    s = run_gpu(w, 0, storage=storage)
+    shape = s.autotune()
+    s.step(3)
+    st = s.get_state()
+    s.step(1)
+    st1 = s.get_state()
+    rng = np.random.default_rng(12)
+    nx, ny, nz = w.shape
+    worst = {g: 0.0 for g in ("F", "G", "h", "E")}
+    for _ in range(24):
+        cx = int(rng.integers(3, nx - 3))
+        cy = int(rng.integers(3, ny - 3))
+        cz = int(rng.integers(3, nz - 3)) if nz > 6 else 0
+        ix = np.arange(cx - 2, cx + 3)
+        iy = np.arange(cy - 2, cy + 3)
+        iz = np.arange(cz - 2, cz + 3) if nz > 1 else np.array([0])
+        sub = st[:, torch.as_tensor(iz, device="cuda")][:, :, torch.as_tensor(iy, device="cuda")][
+            :, :, :, torch.as_tensor(ix, device="cuda")].cpu().numpy()
+        o = oracle.Oracle((5, 5, len(iz)), (("periodic", "periodic"),) * 3, **w.params)
+        o.set_state(np.ascontiguousarray(sub))
+        o.step(1)
+        got = st1[:, cz, cy, cx].cpu().numpy()
+        ref = o.get_state()[:, len(iz) // 2, 2, 2]
+        for g, sl in (("F", slice(0, 19)), ("G", slice(19, 38)), ("h", slice(38, 63)), ("E", slice(63, 66))):
+            scale = max(np.abs(ref[sl]).max(), 1e-3 * field_scale(w))
+            worst[g] = max(worst[g], float(np.abs(got[sl] - ref[sl]).max() / scale))
+    print(f"[parity] {name} {storage} full size, shape {shape}, one step from its own state: " +
+          " ".join(f"{g} {v:.1e}" for g, v in worst.items()), flush=True)
+    assert max(worst.values()) <= ONE_STEP_TOL[storage], worst
 
 
 @pytest.mark.parametrize("divb_fix", [0, 1])
