@@ -92,6 +92,11 @@ def parse():
                          "of uneven sizes stepped as one batch; khsweep: not a timing but the reconnection "
                          "study of the KH set-up in the paper's units, the rate at the null against sigma "
                          "(one JSON line with the series and the fits)")
+    ap.add_argument("--kh-v0", type=float, default=0.2, help="kh: shear speed v0 (units of c)")
+    ap.add_argument("--kh-ratio", type=float, default=10.0, help="kh: density ratio across the layer")
+    ap.add_argument("--kh-sigma", type=float, default=1e3, help="kh: conductivity")
+    ap.add_argument("--collision", type=int, default=0, choices=[0, 1],
+                    help="history runs: the f collision (0 explicit, 1 the paper's printed form)")
     ap.add_argument("--sigmas", default="20,40,60,80,100", help="khsweep: the conductivities")
     ap.add_argument("--kh-u0", type=float, default=0.2, help="khsweep: shear speed U0 in units of c")
     ap.add_argument("--kh-dn", type=float, default=1.8, help="khsweep: density jump across the layer")
@@ -424,8 +429,8 @@ def history_main(args):
     from paper_1508_03452_amd import workloads as W
     from paper_1508_03452_amd.rmhdlb import Solver
     torch.cuda.set_device(0)
-    w = W.flare() if args.workload == "flare" else W.kh()
-    s = Solver(w.shape, w.bc, storage=args.storage, **w.params)
+    w = W.flare() if args.workload == "flare" else W.kh(v0=args.kh_v0, ratio=args.kh_ratio, sigma=args.kh_sigma)
+    s = Solver(w.shape, w.bc, storage=args.storage, **dict(w.params, collision=args.collision))
     s.init_fields(w.fields)
     if w.driven is not None:
         s.set_driven_face(w.driven)
@@ -451,7 +456,9 @@ def history_main(args):
         del m, B, u
         if d["n_failed"]:
             break
-    print(json.dumps({"workload": args.workload, "shape": list(w.shape), "storage": args.storage,
+    wl = (args.workload if args.workload == "flare" else
+          f"kh v0={args.kh_v0:g} ratio={args.kh_ratio:g} sigma={args.kh_sigma:g}") + f", collision {args.collision}"
+    print(json.dumps({"workload": wl, "shape": list(w.shape), "storage": args.storage,
                       "launch_shape": list(shape), "steps_run": done, "every": args.history, "history": hist}),
           flush=True)
 
@@ -557,7 +564,7 @@ def main():
     import torch
     from paper_1508_03452_amd import workloads as W
     torch.cuda.set_device(0)
-    w = W.flare() if args.workload == "flare" else W.kh()
+    w = W.flare() if args.workload == "flare" else W.kh(v0=args.kh_v0, ratio=args.kh_ratio, sigma=args.kh_sigma)
     ncell = w.ncells
     stream = torch.cuda.current_stream()
     # the headline form (plain FP64 unless --storage says otherwise)
@@ -584,7 +591,8 @@ def main():
         "config": {"workload": (f"flare-like 3-D box {w.shape[0]}x{w.shape[1]}x{w.shape[2]}, sigma=1e3, "
                                 f"driven shearing bottom face, open faces elsewhere"
                                 if args.workload == "flare" else
-                                f"KH shear layer {w.shape[0]}x{w.shape[1]}x{w.shape[2]}, v0=0.2, ratio 10, sigma=1e3"),
+                                f"KH shear layer {w.shape[0]}x{w.shape[1]}x{w.shape[2]}, v0={args.kh_v0:g}, "
+                                f"ratio {args.kh_ratio:g}, sigma={args.kh_sigma:g}"),
                    "storage": args.storage, "cells": ncell,
                    "recovery": "Newton from the learned guess" if args.guess else "plain Newton",
                    "arithmetic": "f64" if args.storage == "f64" else "f32 (recovery and Ohm solve in f64)",

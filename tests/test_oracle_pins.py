@@ -941,3 +941,40 @@ def test_null_point_ties_go_to_the_lowest_index():
     d = o.diagnostics()
     assert d["null_index"] == 2 * 6
     assert np.isnan(d["recon_rate"]) and d["B0"] == 0.0
+
+
+def _moving_conductor(ux, sigma, N=32, seed=11):
+    """Uniform periodic N x N x 1 state, n = 0.18, p = 1, u = (ux, 0, 0), B = E = 0, with a seeded
+    out-of-plane field B_z of 1e-8 (divergence-free: it varies in x and y only)."""
+    grid = (1, N, N)
+    z = np.zeros(grid)
+    Bz = 1e-8 * np.random.default_rng(seed).standard_normal(grid)
+    o = oracle.Oracle((N, N, 1), W.PERIODIC3, sigma=sigma)
+    o.init(dict(n=np.full(grid, 0.18), p=np.ones(grid), u=(np.full(grid, ux), z.copy(), z.copy()),
+                E=(z.copy(), z.copy(), z.copy()), B=(z.copy(), z.copy(), Bz), rho_c=None))
+    return o
+
+
+def _bz_rate(o, t0, t1):
+    o.step(t0)
+    a = np.abs(o.moments()["Bz"]).max()
+    o.step(t1 - t0)
+    m = o.moments()
+    assert m["n_failed"] == 0
+    return np.log(np.abs(m["Bz"]).max() / a) / (t1 - t0)
+
+
+def test_out_of_plane_mode_of_a_moving_conductor_grows():
+    """Characterises a limitation of the scheme as read (not a property the paper states).  In a
+    conductor moving at u = 0.2c through the lattice (c = dx = 1) the out-of-plane mode B_z, E_x, E_y
+    grows from any seed: at sigma = 1e3 by about 0.0047 per step, with E_y close to the ideal u_x B_z.
+    The Maxwell populations relax with tau_h = 1/2, a reflection about h_eq that damps nothing, so in
+    the ideal-Ohm limit B_z is carried by the flow without dissipation.  Without conduction (sigma = 0)
+    the convection current rho u alone (Reading R20) drives the same mode, about 0.04 per step.  The same
+    state at rest keeps the seed (no growth)."""
+    rate = _bz_rate(_moving_conductor(-0.2, 1e3), 800, 1600)
+    assert 0.003 < rate < 0.007
+    vac = _bz_rate(_moving_conductor(-0.2, 0.0), 200, 400)
+    assert 0.03 < vac < 0.05
+    rest = _bz_rate(_moving_conductor(0.0, 1e3), 400, 800)
+    assert rest < 5e-4
