@@ -11,7 +11,9 @@ launched on.  The headline value is the plain FP64 form; the same box is then
 timed in the mixed + learned form (FP16-shifted storage, learned recovery
 guess trained untimed on the box) and reported beside it with its speed-up,
 and once more in FP16 storage without the guess (mixed_plain), which shows
-whether the network pays for itself on this workload.
+whether the network pays for itself on this workload.  per_gpu_share: the
+plain FP64 step on one GPU's share of an 8-way slab decomposition along z
+(the bottom 64 planes), beside the halo bytes such a slab would exchange.
 
 roofline: algorithmic HBM bytes of one step (read + write of the 66 state
 values per cell) divided by the measured average step duration, against the
@@ -325,6 +327,33 @@ def alg_bytes_per_step(storage, ncell, b_prev=False):
     values with the previous-B reading: 69 values, 1104 B per cell in FP64)."""
     dist_b, e_b = ALG_BYTES[storage]
     return 2 * (63 * dist_b + (6 if b_prev else 3) * e_b) * ncell
+
+
+def share_form(w, args, stream, parts=8):
+    """One GPU's share of a slab decomposition of the flare box along z into `parts` slabs: the bottom
+    nz/parts planes at the same cell spacing, plain FP64, its cut face open in place of the halo planes
+    a neighbour would send.  Reports the step time beside the halo a slab would exchange per step
+    (values per face cell: the F and G of the 10 directions with a z component at 2 layers, the other
+    8 moving F for the Laplacian's layer, the 8 entering h* and E) over one xGMI link per neighbour."""
+    import torch
+    from paper_1508_03452_amd import workloads as W
+    nx, ny, nz = w.shape
+    ws = W.flare(nx=nx, ny=ny, nz=nz // parts, Lz=12.0 / parts)
+    ms, _, s, info = timed_form(ws, "f64", False, args, stream)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    n = ws.ncells
+    a = alg_bytes_per_step("f64", n) / (ms * 1e-3) / 1e9
+    halo_values = 10 * 2 * 2 + 8 + 8 + 3
+    face_bytes = halo_values * nx * ny * 8
+    return {"shape": list(ws.shape), "cells": n, "parts": parts, "storage": "f64",
+            "value": round(n / (ms * 1e-3) / 1e6, 2), "unit": "MLUPS", "ms_per_step": round(ms, 4),
+            "roofline": {"achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(a / HBM_PEAK_GBS, 4)},
+            "tile": info["tile"], "launch_shape": info["launch_shape"],
+            "halo_bytes_per_face": face_bytes,
+            "halo_ms_per_face_at_153_GBps": round(face_bytes / 153e9 * 1e3, 4)}
 
 
 def timed_form(w, storage, guess, args, stream):
@@ -650,6 +679,8 @@ def main():
         mlups_s, ms_s, info_s = run_sweep(args.steps, args.warmup)
         out["sweep"] = {"value": round(mlups_s, 2), "unit": "MLUPS", "ms_per_step": round(ms_s, 4),
                         "steps": args.steps, **info_s}
+    if not args.single_form and args.workload == "flare":
+        out["per_gpu_share"] = share_form(w, args, stream)
     out["copy_probe_gbs"] = copy_probe_gbs(stream)
     del w.fields
     if not args.no_cpu_baseline:
