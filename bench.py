@@ -186,6 +186,15 @@ def run_sweep(steps, warmup, storage="f32"):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1) / steps
+    # the same steps in persistent mode (one cooperative launch, grid barriers between the steps)
+    b.set_persistent(True)
+    torch.cuda.synchronize()
+    ev0.record(st)
+    b.step(steps)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    ms_persistent = ev0.elapsed_time(ev1) / steps
+    b.set_persistent(False)
     failed = sum(inst.moments(fields=())["diag"]["n_failed"] for inst in b.instances)
     alg_bytes = alg_bytes_per_step(storage, ncell)
     achieved = alg_bytes / (ms * 1e-3) / 1e9
@@ -193,6 +202,7 @@ def run_sweep(steps, warmup, storage="f32"):
                         f"sigma 1e2..1e5, one launch per step, hipGraph replays (64 steps per graph)",
             "storage": storage, "cells": ncell, "tile": f"{px}x{(128 if storage == 'f64' else 256) // px * yw} cells", "waves_per_simd": waves,
             "failed_cells": failed, "wall_s_timed": round(wall, 3),
+            "persistent_ms_per_step": round(ms_persistent, 4),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_fused_batch",
                          "alg_bytes_per_launch": alg_bytes}}
@@ -205,8 +215,9 @@ def run_sweep(steps, warmup, storage="f32"):
 def launch_modes(storage="f32", steps=128):
     """Step cadence of a batch of small slabs (64 KH slabs of 64..192 cells a side, 1.1 M cells), where
     the cost of launching shows: one eager launch per step (rmhdlb_batch_step with one step), replays
-    of the 2-step graph and replays of the 64-step graph, each over the same `steps` steps on the same
-    batch (ms per step from HIP events on the batch's stream)."""
+    of the 2-step graph, replays of the 64-step graph and persistent mode (all `steps` steps in one
+    cooperative launch), each over the same `steps` steps on the same batch (ms per step from HIP
+    events on the batch's stream)."""
     import torch
     from paper_1508_03452_amd import workloads as W
     from paper_1508_03452_amd.rmhdlb import Batch
@@ -231,6 +242,8 @@ def launch_modes(storage="f32", steps=128):
     out = {"workload": f"{len(specs)} KH slabs, nx, ny in 64..192, {sum(sp['nx'] * sp['ny'] for sp in specs)} "
                        f"cells, {storage}", "steps": steps,
            "ms_per_step": {"eager": timed(1), "graph_2_steps": timed(2), "graph_64_steps": timed(64)}}
+    b.set_persistent(True)
+    out["ms_per_step"]["persistent"] = timed(steps)
     b.close()
     del b
     torch.cuda.empty_cache()

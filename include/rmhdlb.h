@@ -393,7 +393,8 @@ rmhdlb_ctx *rmhdlb_batch_instance(rmhdlb_batch *batch, int32_t i);
  * else RMHDLB_ESTATE.  Steps are replayed from hipGraphs captured on the
  * batch's stream (64 steps per graph, then 2, then one eager launch); a graph
  * is captured again whenever the launch geometry changed (an instance's
- * tuning, the batch's tile shape). */
+ * tuning, the batch's tile shape).  In persistent mode
+ * (rmhdlb_batch_set_persistent) the call is one cooperative launch instead. */
 int rmhdlb_batch_step(rmhdlb_batch *batch, int64_t nsteps);
 
 /* Time the tiles of the batched step (state not advanced) and keep the
@@ -409,6 +410,22 @@ int rmhdlb_batch_autotune(rmhdlb_batch *batch, int32_t *px, int32_t *yw, int32_t
 /* Set the batch's tile directly: px in {128, 64, 32, 16}, 1 <= yw <= 8,
  * waves 2, or 3 with FP32 storage (RMHDLB_EINVAL otherwise). */
 int rmhdlb_batch_set_tuning(rmhdlb_batch *batch, int32_t px, int32_t yw, int32_t waves);
+
+/* Launch mode of rmhdlb_batch_step (Sec. III step, run over many instances).
+ * on = 0 (the default): one launch per step, replayed from hipGraphs.  on = 1:
+ * each call runs its nsteps steps in one cooperative launch of a persistent
+ * kernel whose blocks (as many as are resident at once, a multiple of 8) take
+ * the tiles of a step in turn and meet at a grid barrier before the next step
+ * (and after the face pass when an instance adjusts its open faces); the
+ * batch's tile shape and waves apply, and the states are bitwise those of
+ * mode 0.  The launch needs all of its blocks resident together: work on
+ * other streams delays it but ends by itself, while two persistent runs
+ * overlapping on one device could each hold part of it and wait for the
+ * other, so a caller runs one at a time per device.  RMHDLB_EINVAL for on
+ * outside {0, 1}, RMHDLB_EUNSUPPORTED when the
+ * device cannot launch cooperatively; a failed launch makes
+ * rmhdlb_batch_step return RMHDLB_EDEVICE. */
+int rmhdlb_batch_set_persistent(rmhdlb_batch *batch, int32_t on);
 
 /* Release the batch and its instances.  NULL is accepted. */
 int rmhdlb_batch_destroy(rmhdlb_batch *batch);

@@ -952,6 +952,8 @@ struct rmhdlb_batch {
     rmhd::BatchInst* dev;
     int total_blocks;
     int64_t total_face;
+    int persistent;            // rmhdlb_batch_step: 1 = one cooperative launch per call
+    int* next;                 // the persistent kernel's tile counters (after the instance table)
     hipGraphExec_t exec_long;  // GRAPH_LONG steps from parity 0, or null
     hipGraphExec_t exec_pair;  // two steps from parity 0, or null
     BatchGeom graph_geom;      // the geometry both graphs were captured with
@@ -1011,6 +1013,20 @@ hipError_t batch_launch(rmhdlb_batch* B, int parity) {
         default:
             return rmhd::launch_batch<_Float16>(B->dev, B->n, B->total_blocks, B->total_face, B->px, B->waves,
                                                 parity, B->stream);
+    }
+}
+
+hipError_t batch_launch_persistent(rmhdlb_batch* B, int parity, int nsteps) {
+    switch (B->storage) {
+        case RMHDLB_STORE_F64:
+            return rmhd::launch_batch_persistent<double>(B->dev, B->n, B->total_blocks, B->total_face, B->px,
+                                                         B->waves, parity, nsteps, B->next, B->stream);
+        case RMHDLB_STORE_F32:
+            return rmhd::launch_batch_persistent<float>(B->dev, B->n, B->total_blocks, B->total_face, B->px,
+                                                        B->waves, parity, nsteps, B->next, B->stream);
+        default:
+            return rmhd::launch_batch_persistent<_Float16>(B->dev, B->n, B->total_blocks, B->total_face, B->px,
+                                                           B->waves, parity, nsteps, B->next, B->stream);
     }
 }
 
@@ -1083,7 +1099,9 @@ int rmhdlb_batch_create(const rmhdlb_params* params, int32_t n, void* hip_stream
     B->px = 64;
     B->yw = 1;
     B->waves = 2;
+    B->persistent = 0;
     B->dev = nullptr;
+    B->next = nullptr;
     B->exec_long = B->exec_pair = nullptr;
     B->total_blocks = 0;
     B->total_face = 0;
@@ -1091,7 +1109,9 @@ int rmhdlb_batch_create(const rmhdlb_params* params, int32_t n, void* hip_stream
     B->host.resize(n);
     int rc = RMHDLB_OK;
     for (int i = 0; i < n && rc == RMHDLB_OK; ++i) rc = rmhdlb_create(&params[i], hip_stream, &B->ctx[i]);
-    if (rc == RMHDLB_OK && hipMalloc((void**)&B->dev, sizeof(rmhd::BatchInst) * n) != hipSuccess) {
+    // the instance table, then the persistent kernel's 16 tile counters
+    const size_t table = (sizeof(rmhd::BatchInst) * n + 255) / 256 * 256;
+    if (rc == RMHDLB_OK && hipMalloc((void**)&B->dev, table + 16 * sizeof(int)) != hipSuccess) {
         B->dev = nullptr;
         rc = RMHDLB_ENOMEM;
     }
@@ -1099,6 +1119,7 @@ int rmhdlb_batch_create(const rmhdlb_params* params, int32_t n, void* hip_stream
         rmhdlb_batch_destroy(B);
         return rc;
     }
+    B->next = reinterpret_cast<int*>(reinterpret_cast<char*>(B->dev) + table);
     *out = B;
     return RMHDLB_OK;
 }
@@ -1130,6 +1151,19 @@ int rmhdlb_batch_step(rmhdlb_batch* B, int64_t nsteps) {
         B->graph_geom = batch_geom(B);
     }
     int parity = B->ctx[0]->cur;
+    if (B->persistent) {
+        for (int64_t done = 0; done < nsteps;) {
+            const int chunk = (int)std::min<int64_t>(nsteps - done, 1 << 30);
+            if (batch_launch_persistent(B, parity, chunk) != hipSuccess) return RMHDLB_EDEVICE;
+            parity = (parity + chunk) & 1;
+            done += chunk;
+        }
+        for (rmhdlb_ctx* C : B->ctx) {
+            C->cur = parity;
+            C->step += nsteps;
+        }
+        return RMHDLB_OK;
+    }
     int64_t left = nsteps;
     if (parity == 1) {
         if (batch_launch(B, 1) != hipSuccess) return RMHDLB_EDEVICE;
@@ -1158,6 +1192,19 @@ int rmhdlb_batch_step(rmhdlb_batch* B, int64_t nsteps) {
         C->cur = parity;
         C->step += nsteps;
     }
+    return RMHDLB_OK;
+}
+
+int rmhdlb_batch_set_persistent(rmhdlb_batch* B, int32_t on) {
+    if (!B || (on != 0 && on != 1)) return RMHDLB_EINVAL;
+    if (on) {
+        int dev = 0, coop = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess)
+            return RMHDLB_EDEVICE;
+        if (!coop) return RMHDLB_EUNSUPPORTED;
+    }
+    B->persistent = on;
     return RMHDLB_OK;
 }
 

@@ -216,6 +216,12 @@ inline bool quad_storage(int32_t storage) { return storage != RMHDLB_STORE_F64; 
 template <typename TS>
 hipError_t launch_batch(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face, int px, int waves,
                         int parity, hipStream_t s);
+// nsteps batched steps in one cooperative launch of the persistent batch
+// kernel (grid barriers between the steps), starting from buffer `parity`;
+// next: 16 ints of device memory for its tile counters (cleared here).
+template <typename TS>
+hipError_t launch_batch_persistent(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face, int px,
+                                   int waves, int parity, int nsteps, int* next, hipStream_t s);
 template <typename TS>
 hipError_t launch_guess_samples(const StateBuf& src, const Consts& K, double* faceB, int ns, double* F, double* T,
                                 double* part, double* result, hipStream_t s);

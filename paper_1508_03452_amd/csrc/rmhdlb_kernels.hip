@@ -3,13 +3,16 @@
 //
 // Layout in HBM: structure of arrays, x fastest.  A state buffer holds the
 // distributions F[0..18], G[0..18], h*[0..24] of storage type TS, interleaved
-// as (f_i, g_i) pairs (FP64 and FP16, 63 arrays) or as quads of opposite
-// directions (FP32, 65 arrays; the layouts are described in rmhdlb_device.h),
+// as (f_i, g_i) pairs (FP64, 63 arrays), as quads of opposite directions
+// (FP32, 65 arrays) or as records of two such quads (FP16, 65 arrays; the
+// layouts are described in rmhdlb_device.h),
 // then (256-byte aligned) the 3 E_prev arrays of type TE (TS, or FP32 when TS
 // is FP16); two buffers, read one and write the other.  The stored state is post-collision.  On the FP32 and FP16
 // storage paths F and G are stored as deviations from w_i E_ref and
 // w'_i N_ref (references from the initial fields) and the step runs in FP32
 // arithmetic, with the recovery and the Ohm solve in FP64.
+#include <hip/hip_cooperative_groups.h>
+
 #include "rmhdlb_device.h"
 #include "rmhdlb_internal.h"
 #include "rmhdlb_mlp.h"
@@ -1484,6 +1487,67 @@ __global__ __launch_bounds__(256) void k_face_b_batch(const BatchInst* __restric
     face_b_cell((const TS*)B.dist[parity], B.K, B.faceB, g - B.face0);
 }
 
+// Persistent batched run: nsteps steps in one cooperative launch whose grid
+// (a multiple of 8) is no larger than the blocks resident at once.  The tiles
+// of a step are dealt as k_fused_batch deals its blocks: XCD x (blocks g with
+// g % 8 == x, as the hardware deals blocks to XCDs) runs the contiguous tile
+// range [x P, (x + 1) P), and its blocks take the next tile of that range
+// from a counter, in order and as they become free (each block takes its
+// next one while its current one runs), so that the tiles in flight
+// together stay neighbours.  next holds two sets of 8 counters, zero
+// at launch: step k counts in set k % 2, and the first block of each group
+// clears its counter of the other set (last used in step k - 1, whose fetches
+// all ended before the barrier).  All blocks meet at a grid barrier after
+// each step (the next one reads what it wrote) and, with the open-face
+// adjustment, after the face pass that precedes each step.  Every block runs
+// every phase and reaches every barrier: no thread leaves the kernel early,
+// and a fetch loop ends once its counter passes P.
+template <bool NT, typename TS, typename TE, typename V, int PXT, int WV>
+__global__ __launch_bounds__(PTPB, WV) void k_fused_batch_persistent(const BatchInst* __restrict__ I, int ninst,
+                                                                     int total, int64_t total_face, int parity0,
+                                                                     int nsteps, int* __restrict__ next) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    __shared__ int tile_sh;
+    const int P = (total + 7) / 8;
+    const int x = blockIdx.x % 8;
+    for (int k = 0; k < nsteps; ++k) {
+        const int parity = (parity0 + k) & 1;
+        if (total_face > 0) {
+            for (int64_t g = (int64_t)blockIdx.x * PTPB + threadIdx.x; g < total_face;
+                 g += (int64_t)gridDim.x * PTPB) {
+                const int i = find_instance(ninst, g, [&](int j) { return I[j].face0; });
+                if (I[i].K.divb) face_b_cell((const TS*)I[i].dist[parity], I[i].K, I[i].faceB, g - I[i].face0);
+            }
+            grid.sync();
+        }
+        int* cnt = next + (k & 1) * 8 + x;
+        if (blockIdx.x < 8 && threadIdx.x == 0) atomicExch(next + ((k + 1) & 1) * 8 + x, 0);
+        // the next tile is taken while the current one runs, so the counter's round trip is hidden
+        if (threadIdx.x == 0) tile_sh = atomicAdd(cnt, 1);
+        __syncthreads();
+        int j = tile_sh;
+        __syncthreads();
+        while (j < P) {  // j is uniform over the block
+            int nj = 0;
+            if (threadIdx.x == 0) nj = atomicAdd(cnt, 1);
+            const int b = x * P + j;
+            if (b < total) {
+                const int i = find_instance(ninst, b, [&](int jj) { return I[jj].blk0; });
+                const BatchInst& B = I[i];
+                fused_block<NT, TS, TE, V, GUESS_NONE, PXT>(
+                    (const TS*)B.dist[parity], (const TE*)B.efield[parity], (TS*)B.dist[1 - parity],
+                    (TE*)B.efield[1 - parity], B.faceB, nullptr, B.K, B.tiles_x, B.ncol, B.zb, 1, B.yw,
+                    (int)(b - B.blk0));
+            }
+            if (threadIdx.x == 0) tile_sh = nj;
+            __syncthreads();
+            j = tile_sh;
+            __syncthreads();
+        }
+        grid.sync();
+    }
+}
+
 // Deterministic (key, index) minimum, ties to the lower index; NaN keys never win.
 __device__ __forceinline__ void argmin_merge(double& k, double& i, double k2, double i2) {
     if (k2 < k || (k2 == k && i2 < i)) {
@@ -2098,6 +2162,62 @@ hipError_t launch_batch(const BatchInst* dev, int ninst, int total_blocks, int64
     return hipGetLastError();
 }
 
+// Clears the persistent run's 16 tile counters (a kernel, not a memset node,
+// should a caller capture the step).
+__global__ void k_zero16(int* __restrict__ p) {
+    if (threadIdx.x < 16) p[threadIdx.x] = 0;
+}
+
+// The persistent run's grid: the blocks resident at once (occupancy of this
+// instantiation times the compute units), rounded down to a multiple of 8 and
+// at most the rounded tile range.  The cooperative launch refuses a grid that
+// cannot be resident as a whole, so the grid barriers always complete.
+template <typename TS, int PXT, int WV>
+static hipError_t launch_persistent_fused(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face,
+                                          int parity, int nsteps, int* next, hipStream_t s) {
+    using TE = typename StoreTypes<TS>::E;
+    using V = typename StoreTypes<TS>::V;
+    const void* kern = reinterpret_cast<const void*>(&k_fused_batch_persistent<true, TS, TE, V, PXT, WV>);
+    int dev_id = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev_id);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, PTPB, 0);
+    if (e != hipSuccess) return e;
+    const int range = (total_blocks + 7) / 8 * 8;
+    const int resident = per_cu * cus / 8 * 8;
+    const int grid = resident < range ? resident : range;
+    if (grid < 8) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_zero16, dim3(1), dim3(64), 0, s, next);
+    void* args[] = {(void*)&dev, (void*)&ninst, (void*)&total_blocks, (void*)&total_face, (void*)&parity,
+                    (void*)&nsteps, (void*)&next};
+    return hipLaunchCooperativeKernel(kern, dim3(grid), dim3(PTPB), args, 0, s);
+}
+
+template <typename TS, int WV>
+static hipError_t launch_persistent_px(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face, int px,
+                                       int parity, int nsteps, int* next, hipStream_t s) {
+    if (px == 128)
+        return launch_persistent_fused<TS, 128, WV>(dev, ninst, total_blocks, total_face, parity, nsteps, next, s);
+    if (px == 32)
+        return launch_persistent_fused<TS, 32, WV>(dev, ninst, total_blocks, total_face, parity, nsteps, next, s);
+    if (px == 16)
+        return launch_persistent_fused<TS, 16, WV>(dev, ninst, total_blocks, total_face, parity, nsteps, next, s);
+    return launch_persistent_fused<TS, 64, WV>(dev, ninst, total_blocks, total_face, parity, nsteps, next, s);
+}
+
+template <typename TS>
+hipError_t launch_batch_persistent(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face, int px,
+                                   int waves, int parity, int nsteps, int* next, hipStream_t s) {
+    if constexpr (sizeof(TS) == 4) {
+        if (waves == 3)
+            return launch_persistent_px<TS, 3>(dev, ninst, total_blocks, total_face, px, parity, nsteps, next, s);
+        return launch_persistent_px<TS, 2>(dev, ninst, total_blocks, total_face, px, parity, nsteps, next, s);
+    } else {
+        return launch_persistent_px<TS, fused_waves<TS, 0>()>(dev, ninst, total_blocks, total_face, px, parity,
+                                                               nsteps, next, s);
+    }
+}
+
 template <typename TS>
 hipError_t launch_moments(const StateBuf& src, const Consts& K, const OutPtrs& out, const DiagBufs& D,
                           const GuessTables* gt, hipStream_t s) {
@@ -2205,6 +2325,8 @@ hipError_t launch_guess_samples(const StateBuf& src, const Consts& K, double* fa
     template hipError_t launch_init<TS>(const InPtrs&, const Consts&, double*, const StateBuf&, hipStream_t);         \
     template hipError_t launch_ghost<TS>(const FacePtrs&, const Consts&, const StateBuf&, hipStream_t);               \
     template hipError_t launch_batch<TS>(const BatchInst*, int, int, int64_t, int, int, int, hipStream_t);            \
+    template hipError_t launch_batch_persistent<TS>(const BatchInst*, int, int, int64_t, int, int, int, int, int*,   \
+                                                    hipStream_t);                                                     \
     template hipError_t launch_guess_samples<TS>(const StateBuf&, const Consts&, double*, int, double*, double*,      \
                                                  double*, double*, hipStream_t);                                      \
     template hipError_t launch_export<TS>(const StateBuf&, double*, const Consts&, hipStream_t);                      \

@@ -76,7 +76,7 @@ SYMBOLS = ("rmhdlb_create", "rmhdlb_init_fields", "rmhdlb_step", "rmhdlb_moments
            "rmhdlb_set_driven_face", "rmhdlb_train_guess", "rmhdlb_set_guess_weights", "rmhdlb_set_guess",
            "rmhdlb_guess_samples", "rmhdlb_mlp_eval", "rmhdlb_autotune", "rmhdlb_set_tuning", "rmhdlb_set_force",
            "rmhdlb_batch_create", "rmhdlb_batch_instance", "rmhdlb_batch_step", "rmhdlb_batch_autotune",
-           "rmhdlb_batch_set_tuning", "rmhdlb_batch_destroy", "rmhdlb_workspace_bytes",
+           "rmhdlb_batch_set_tuning", "rmhdlb_batch_set_persistent", "rmhdlb_batch_destroy", "rmhdlb_workspace_bytes",
            "rmhdlb_guess_samples_noalloc", "rmhdlb_device_copy")
 
 _LIB = None
@@ -126,6 +126,7 @@ def load():
     L.rmhdlb_batch_step.argtypes = [vp, ctypes.c_int64]
     L.rmhdlb_batch_autotune.argtypes = [vp, ip32, ip32, ip32]
     L.rmhdlb_batch_set_tuning.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.rmhdlb_batch_set_persistent.argtypes = [vp, ctypes.c_int32]
     L.rmhdlb_batch_destroy.argtypes = [vp]
     L.rmhdlb_device_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     _LIB = L
@@ -465,6 +466,10 @@ class Batch:
 
     def set_tuning(self, px, yw=1, waves=2):
         _check(load().rmhdlb_batch_set_tuning(self._h, int(px), int(yw), int(waves)), "rmhdlb_batch_set_tuning")
+
+    def set_persistent(self, on=True):
+        """Step each call in one cooperative launch of the persistent kernel (on) or by graph replays (off)."""
+        _check(load().rmhdlb_batch_set_persistent(self._h, 1 if on else 0), "rmhdlb_batch_set_persistent")
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -251,3 +251,69 @@ def test_batched_sweep_instances_against_the_oracle():
               f"state {max(serr.values()):.1e}", flush=True)
         assert errs[worst] <= 1e-12 and max(serr.values()) <= 1e-12, (w.shape, errs[worst], serr)
     b.close()
+
+
+def _sync():
+    """The graph-replay batch finishes before the persistent one starts: a cooperative launch needs all
+    of its blocks resident together, so the two are not left to overlap on the device."""
+    import torch
+    torch.cuda.synchronize()
+
+
+def _pair_batches(ws, storage, waves=2):
+    """The same instances as two batches on their own streams: graph replays, and persistent mode."""
+    torch = _torch_cuda()
+    g = _batch(ws, storage, torch.cuda.Stream())
+    p = _batch(ws, storage, torch.cuda.Stream())
+    for b in (g, p):
+        b.set_tuning(64, 1, waves)
+    p.set_persistent(True)
+    return g, p
+
+
+def _assert_batches_equal(g, p, steps):
+    import torch
+    torch.cuda.synchronize()
+    for sg, sp in zip(g.instances, p.instances):
+        assert np.array_equal(_state(sg), _state(sp), equal_nan=True)
+        assert sp.moments(fields=())["diag"]["step"] == steps
+
+
+@pytest.mark.parametrize("storage,waves", [("f64", 2), ("f32", 2), ("f32", 3), ("f16", 2)])
+def test_persistent_batch_matches_graph_replays(storage, waves):
+    """Persistent mode (one cooperative launch per call, grid barriers between the steps) against graph
+    replays, bit for bit: six KH slabs of 384-512 x 256-320 cells, about 3,800 tiles, more than the
+    blocks resident at once, so that every block takes several tiles per step; calls of 1, 6 and 5
+    steps start from both buffer parities."""
+    rng = np.random.default_rng(11)
+    ws = [W.kh(nx=int(rng.choice([384, 448, 512])), ny=int(rng.choice([256, 320])), v0=float(rng.uniform(0.05, 0.4)),
+               ratio=float(rng.uniform(1, 10)), sigma=float(10 ** rng.uniform(2, 4)), seed=20 + i) for i in range(6)]
+    print(f"[batch] persistent {storage} waves {waves}: {sum(w.ncells for w in ws)} cells", flush=True)
+    g, p = _pair_batches(ws, storage, waves)
+    done = 0
+    for k in (1, 6, 5):
+        g.step(k)
+        _sync()
+        p.step(k)
+        done += k
+        _assert_batches_equal(g, p, done)
+    g.close()
+    p.close()
+
+
+def test_persistent_batch_with_the_open_face_adjustment():
+    """An instance with the open-face div B adjustment makes the persistent kernel run the face pass
+    (its own phase and grid barrier) before each step: uneven slabs, the 3-D open box and a KH slab with
+    the adjustment on, 7 steps in calls of 3 and 4, against graph replays bit for bit."""
+    ws = _sweep_workloads(n=3, seed=12)
+    kh = W.kh(nx=96, ny=64, v0=0.2, ratio=4.0, sigma=1e3, seed=5)
+    kh.params = dict(kh.params, divb_fix=1)
+    ws.append(kh)
+    g, p = _pair_batches(ws, "f32")
+    for k in (3, 4):
+        g.step(k)
+        _sync()
+        p.step(k)
+    _assert_batches_equal(g, p, 7)
+    g.close()
+    p.close()
