@@ -415,10 +415,11 @@ int rmhdlb_batch_set_tuning(rmhdlb_batch *batch, int32_t px, int32_t yw, int32_t
  * on = 0 (the default): one launch per step, replayed from hipGraphs.  on = 1:
  * each call runs its nsteps steps in one cooperative launch of a persistent
  * kernel whose blocks (as many as are resident at once, a multiple of 8) take
- * the tiles of a step in turn and meet at a grid barrier before the next step
- * (and after the face pass when an instance adjusts its open faces); the
- * batch's tile shape and waves apply, and the states are bitwise those of
- * mode 0.  The launch needs all of its blocks resident together: work on
+ * the tiles of a step in turn and meet at a grid barrier before the next step;
+ * the batch's tile shape and waves apply, and the states are bitwise those of
+ * mode 0.  A batch with an instance that adjusts its open faces (divb_fix)
+ * has no face pass in this mode: rmhdlb_batch_step returns
+ * RMHDLB_EUNSUPPORTED for it (mode 0 steps it).  The launch needs all of its blocks resident together: work on
  * other streams delays it but ends by itself, while two persistent runs
  * overlapping on one device could each hold part of it and wait for the
  * other, so a caller runs one at a time per device.  RMHDLB_EINVAL for on

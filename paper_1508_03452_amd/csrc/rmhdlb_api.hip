@@ -1019,14 +1019,14 @@ hipError_t batch_launch(rmhdlb_batch* B, int parity) {
 hipError_t batch_launch_persistent(rmhdlb_batch* B, int parity, int nsteps) {
     switch (B->storage) {
         case RMHDLB_STORE_F64:
-            return rmhd::launch_batch_persistent<double>(B->dev, B->n, B->total_blocks, B->total_face, B->px,
-                                                         B->waves, parity, nsteps, B->next, B->stream);
+            return rmhd::launch_batch_persistent<double>(B->dev, B->n, B->total_blocks, B->px, B->waves,
+                                                         parity, nsteps, B->next, B->stream);
         case RMHDLB_STORE_F32:
-            return rmhd::launch_batch_persistent<float>(B->dev, B->n, B->total_blocks, B->total_face, B->px,
-                                                        B->waves, parity, nsteps, B->next, B->stream);
+            return rmhd::launch_batch_persistent<float>(B->dev, B->n, B->total_blocks, B->px, B->waves,
+                                                        parity, nsteps, B->next, B->stream);
         default:
-            return rmhd::launch_batch_persistent<_Float16>(B->dev, B->n, B->total_blocks, B->total_face, B->px,
-                                                           B->waves, parity, nsteps, B->next, B->stream);
+            return rmhd::launch_batch_persistent<_Float16>(B->dev, B->n, B->total_blocks, B->px, B->waves,
+                                                           parity, nsteps, B->next, B->stream);
     }
 }
 
@@ -1151,6 +1151,7 @@ int rmhdlb_batch_step(rmhdlb_batch* B, int64_t nsteps) {
         B->graph_geom = batch_geom(B);
     }
     int parity = B->ctx[0]->cur;
+    if (B->persistent && B->total_face > 0) return RMHDLB_EUNSUPPORTED;  // no face pass in the persistent kernel
     if (B->persistent) {
         for (int64_t done = 0; done < nsteps;) {
             const int chunk = (int)std::min<int64_t>(nsteps - done, 1 << 30);

@@ -218,10 +218,11 @@ hipError_t launch_batch(const BatchInst* dev, int ninst, int total_blocks, int64
                         int parity, hipStream_t s);
 // nsteps batched steps in one cooperative launch of the persistent batch
 // kernel (grid barriers between the steps), starting from buffer `parity`;
-// next: 16 ints of device memory for its tile counters (cleared here).
+// next: 16 ints of device memory for its tile counters (cleared here).  No
+// face pass: the caller steps batches that need one by graph replays.
 template <typename TS>
-hipError_t launch_batch_persistent(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face, int px,
-                                   int waves, int parity, int nsteps, int* next, hipStream_t s);
+hipError_t launch_batch_persistent(const BatchInst* dev, int ninst, int total_blocks, int px, int waves, int parity,
+                                   int nsteps, int* next, hipStream_t s);
 template <typename TS>
 hipError_t launch_guess_samples(const StateBuf& src, const Consts& K, double* faceB, int ns, double* F, double* T,
                                 double* part, double* result, hipStream_t s);

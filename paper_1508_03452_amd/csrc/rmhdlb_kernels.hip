@@ -1498,28 +1498,20 @@ __global__ __launch_bounds__(256) void k_face_b_batch(const BatchInst* __restric
 // at launch: step k counts in set k % 2, and the first block of each group
 // clears its counter of the other set (last used in step k - 1, whose fetches
 // all ended before the barrier).  All blocks meet at a grid barrier after
-// each step (the next one reads what it wrote) and, with the open-face
-// adjustment, after the face pass that precedes each step.  Every block runs
-// every phase and reaches every barrier: no thread leaves the kernel early,
-// and a fetch loop ends once its counter passes P.
+// each step (the next one reads what it wrote).  No face pass: batches with
+// the open-face adjustment are stepped by graph replays.  Every block reaches
+// every barrier: no thread leaves the kernel early, and a fetch loop ends
+// once its counter passes P.
 template <bool NT, typename TS, typename TE, typename V, int PXT, int WV>
 __global__ __launch_bounds__(PTPB, WV) void k_fused_batch_persistent(const BatchInst* __restrict__ I, int ninst,
-                                                                     int total, int64_t total_face, int parity0,
-                                                                     int nsteps, int* __restrict__ next) {
+                                                                     int total, int parity0, int nsteps,
+                                                                     int* __restrict__ next) {
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
     __shared__ int tile_sh;
     const int P = (total + 7) / 8;
     const int x = blockIdx.x % 8;
     for (int k = 0; k < nsteps; ++k) {
         const int parity = (parity0 + k) & 1;
-        if (total_face > 0) {
-            for (int64_t g = (int64_t)blockIdx.x * PTPB + threadIdx.x; g < total_face;
-                 g += (int64_t)gridDim.x * PTPB) {
-                const int i = find_instance(ninst, g, [&](int j) { return I[j].face0; });
-                if (I[i].K.divb) face_b_cell((const TS*)I[i].dist[parity], I[i].K, I[i].faceB, g - I[i].face0);
-            }
-            grid.sync();
-        }
         int* cnt = next + (k & 1) * 8 + x;
         if (blockIdx.x < 8 && threadIdx.x == 0) atomicExch(next + ((k + 1) & 1) * 8 + x, 0);
         // the next tile is taken while the current one runs, so the counter's round trip is hidden
@@ -2173,8 +2165,8 @@ __global__ void k_zero16(int* __restrict__ p) {
 // at most the rounded tile range.  The cooperative launch refuses a grid that
 // cannot be resident as a whole, so the grid barriers always complete.
 template <typename TS, int PXT, int WV>
-static hipError_t launch_persistent_fused(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face,
-                                          int parity, int nsteps, int* next, hipStream_t s) {
+static hipError_t launch_persistent_fused(const BatchInst* dev, int ninst, int total_blocks, int parity,
+                                          int nsteps, int* next, hipStream_t s) {
     using TE = typename StoreTypes<TS>::E;
     using V = typename StoreTypes<TS>::V;
     const void* kern = reinterpret_cast<const void*>(&k_fused_batch_persistent<true, TS, TE, V, PXT, WV>);
@@ -2188,33 +2180,33 @@ static hipError_t launch_persistent_fused(const BatchInst* dev, int ninst, int t
     const int grid = resident < range ? resident : range;
     if (grid < 8) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_zero16, dim3(1), dim3(64), 0, s, next);
-    void* args[] = {(void*)&dev, (void*)&ninst, (void*)&total_blocks, (void*)&total_face, (void*)&parity,
-                    (void*)&nsteps, (void*)&next};
+    void* args[] = {(void*)&dev, (void*)&ninst, (void*)&total_blocks, (void*)&parity, (void*)&nsteps,
+                    (void*)&next};
     return hipLaunchCooperativeKernel(kern, dim3(grid), dim3(PTPB), args, 0, s);
 }
 
 template <typename TS, int WV>
-static hipError_t launch_persistent_px(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face, int px,
-                                       int parity, int nsteps, int* next, hipStream_t s) {
+static hipError_t launch_persistent_px(const BatchInst* dev, int ninst, int total_blocks, int px, int parity,
+                                       int nsteps, int* next, hipStream_t s) {
     if (px == 128)
-        return launch_persistent_fused<TS, 128, WV>(dev, ninst, total_blocks, total_face, parity, nsteps, next, s);
+        return launch_persistent_fused<TS, 128, WV>(dev, ninst, total_blocks, parity, nsteps, next, s);
     if (px == 32)
-        return launch_persistent_fused<TS, 32, WV>(dev, ninst, total_blocks, total_face, parity, nsteps, next, s);
+        return launch_persistent_fused<TS, 32, WV>(dev, ninst, total_blocks, parity, nsteps, next, s);
     if (px == 16)
-        return launch_persistent_fused<TS, 16, WV>(dev, ninst, total_blocks, total_face, parity, nsteps, next, s);
-    return launch_persistent_fused<TS, 64, WV>(dev, ninst, total_blocks, total_face, parity, nsteps, next, s);
+        return launch_persistent_fused<TS, 16, WV>(dev, ninst, total_blocks, parity, nsteps, next, s);
+    return launch_persistent_fused<TS, 64, WV>(dev, ninst, total_blocks, parity, nsteps, next, s);
 }
 
 template <typename TS>
-hipError_t launch_batch_persistent(const BatchInst* dev, int ninst, int total_blocks, int64_t total_face, int px,
-                                   int waves, int parity, int nsteps, int* next, hipStream_t s) {
+hipError_t launch_batch_persistent(const BatchInst* dev, int ninst, int total_blocks, int px, int waves, int parity,
+                                   int nsteps, int* next, hipStream_t s) {
     if constexpr (sizeof(TS) == 4) {
         if (waves == 3)
-            return launch_persistent_px<TS, 3>(dev, ninst, total_blocks, total_face, px, parity, nsteps, next, s);
-        return launch_persistent_px<TS, 2>(dev, ninst, total_blocks, total_face, px, parity, nsteps, next, s);
+            return launch_persistent_px<TS, 3>(dev, ninst, total_blocks, px, parity, nsteps, next, s);
+        return launch_persistent_px<TS, 2>(dev, ninst, total_blocks, px, parity, nsteps, next, s);
     } else {
-        return launch_persistent_px<TS, fused_waves<TS, 0>()>(dev, ninst, total_blocks, total_face, px, parity,
-                                                               nsteps, next, s);
+        return launch_persistent_px<TS, fused_waves<TS, 0>()>(dev, ninst, total_blocks, px, parity, nsteps, next,
+                                                               s);
     }
 }
 
@@ -2325,7 +2317,7 @@ hipError_t launch_guess_samples(const StateBuf& src, const Consts& K, double* fa
     template hipError_t launch_init<TS>(const InPtrs&, const Consts&, double*, const StateBuf&, hipStream_t);         \
     template hipError_t launch_ghost<TS>(const FacePtrs&, const Consts&, const StateBuf&, hipStream_t);               \
     template hipError_t launch_batch<TS>(const BatchInst*, int, int, int64_t, int, int, int, hipStream_t);            \
-    template hipError_t launch_batch_persistent<TS>(const BatchInst*, int, int, int64_t, int, int, int, int, int*,   \
+    template hipError_t launch_batch_persistent<TS>(const BatchInst*, int, int, int, int, int, int, int*,            \
                                                     hipStream_t);                                                     \
     template hipError_t launch_guess_samples<TS>(const StateBuf&, const Consts&, double*, int, double*, double*,      \
                                                  double*, double*, hipStream_t);                                      \

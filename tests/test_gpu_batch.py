@@ -301,6 +301,9 @@ def test_persistent_batch_matches_graph_replays(storage, waves):
     p.close()
 
 
+@pytest.mark.skip(reason="a GPU memory fault (aperture violation) was reported during this test with a per-wavefront "
+                         "variant of the persistent kernel; its cause was not found, so the variant was removed and the "
+                         "persistent kernel's face pass switched off (persistent mode refuses such batches)")
 def test_persistent_batch_with_the_open_face_adjustment():
     """An instance with the open-face div B adjustment makes the persistent kernel run the face pass
     (its own phase and grid barrier) before each step: uneven slabs, the 3-D open box and a KH slab with
@@ -317,3 +320,23 @@ def test_persistent_batch_with_the_open_face_adjustment():
     _assert_batches_equal(g, p, 7)
     g.close()
     p.close()
+
+
+def test_persistent_mode_refuses_the_face_pass():
+    """A batch with an instance that adjusts its open faces has no face pass in persistent mode: the step is
+    refused before any launch (RMHDLB_EUNSUPPORTED), the state is left alone, and graph replays step it."""
+    torch = _torch_cuda()
+    from paper_1508_03452_amd.rmhdlb import RmhdlbError
+    kh = W.kh(nx=96, ny=64, v0=0.2, ratio=4.0, sigma=1e3, seed=5)
+    kh.params = dict(kh.params, divb_fix=1)
+    b = _batch([kh], "f32", torch.cuda.Stream())
+    before = _state(b.instances[0])
+    b.set_persistent(True)
+    with pytest.raises(RmhdlbError):
+        b.step(2)
+    assert np.array_equal(before, _state(b.instances[0]))
+    b.set_persistent(False)
+    b.step(2)
+    torch.cuda.synchronize()
+    assert b.instances[0].moments(fields=())["diag"]["step"] == 2
+    b.close()
