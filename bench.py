@@ -48,20 +48,20 @@ KERNEL_SOURCES = ("paper_1508_03452_amd/csrc/rmhdlb_kernels.hip", "paper_1508_03
 # shape the autotuner picks, and a changed kernel or an unmeasured shape
 # reports null.
 MEASURED_TRAFFIC = {
-    ("flare", "f64", "f54c840ac4f6", "64,16,4"): 57.9,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "f54c840ac4f6", "64,32,2"): 64.77,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "f54c840ac4f6", "64,32,4"): 63.58,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f64", "f54c840ac4f6", "64,64,4"): 67.08,  # profiles/fused_step_f64_flare256x256x512.md
-    ("flare", "f16", "f54c840ac4f6", "64,16,4"): 12.45,  # profiles/fused_step_f16_flare256x256x512.md
-    ("flare", "f16", "f54c840ac4f6", "64,32,2"): 15.28,  # profiles/fused_step_f16_flare256x256x512.md
-    ("flare", "f16", "f54c840ac4f6", "64,32,4"): 12.29,  # profiles/fused_step_f16_flare256x256x512.md
-    ("flare", "f16", "f54c840ac4f6", "64,64,4"): 12.32,  # profiles/fused_step_f16_flare256x256x512.md
-    ("flare", "f16+guess", "f54c840ac4f6", "64,16,4"): 12.48,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "f54c840ac4f6", "64,32,2"): 15.26,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "f54c840ac4f6", "64,32,4"): 12.35,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f16+guess", "f54c840ac4f6", "64,64,4"): 12.36,  # profiles/fused_step_f16g_flare256x256x512.md
-    ("flare", "f32", "f54c840ac4f6", "64,16,4"): 26.57,  # profiles/fused_step_f32_flare256x256x512.md
-    ("flare", "f32", "f54c840ac4f6", "64,64,4"): 26.43,  # profiles/fused_step_f32_flare256x256x512.md
+    ("flare", "f64", "f3d6a751689c", "64,16,4"): 57.59,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "f3d6a751689c", "64,32,2"): 65.17,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "f3d6a751689c", "64,32,4"): 63.5,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f64", "f3d6a751689c", "64,64,4"): 66.93,  # profiles/fused_step_f64_flare256x256x512.md
+    ("flare", "f16", "f3d6a751689c", "64,16,4"): 12.44,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16", "f3d6a751689c", "64,32,2"): 15.33,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16", "f3d6a751689c", "64,32,4"): 12.3,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16", "f3d6a751689c", "64,64,4"): 12.31,  # profiles/fused_step_f16_flare256x256x512.md
+    ("flare", "f16+guess", "f3d6a751689c", "64,16,4"): 12.47,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "f3d6a751689c", "64,32,2"): 15.26,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "f3d6a751689c", "64,32,4"): 12.34,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f16+guess", "f3d6a751689c", "64,64,4"): 12.36,  # profiles/fused_step_f16g_flare256x256x512.md
+    ("flare", "f32", "f3d6a751689c", "64,16,4"): 26.65,  # profiles/fused_step_f32_flare256x256x512.md
+    ("flare", "f32", "f3d6a751689c", "64,64,4"): 26.49,  # profiles/fused_step_f32_flare256x256x512.md
 }
 
 
