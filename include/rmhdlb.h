@@ -185,7 +185,8 @@ typedef struct rmhdlb_ctx rmhdlb_ctx; /* opaque, owned by the library */
 size_t rmhdlb_workspace_bytes(const rmhdlb_params *params);
 
 /* Create a solver.  Validates *params (RMHDLB_EINVAL, also for a workspace
- * smaller than rmhdlb_workspace_bytes or not 256-byte aligned; tau_h != 1/2
+ * smaller than rmhdlb_workspace_bytes or not 256-byte aligned, and for a grid
+ * of 2^30 cells or more, since cell indices are 32-bit; tau_h != 1/2
  * gives RMHDLB_EUNSUPPORTED), takes its device memory from params->workspace
  * or allocates it on the current HIP device (RMHDLB_ENOMEM), clears it on
  * `hip_stream` (a hipStream_t, may be NULL) and keeps that stream.  On

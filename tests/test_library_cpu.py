@@ -107,6 +107,15 @@ def test_workspace_bytes():
     assert R.workspace_bytes(R.make_params((0, 4, 4))) == 0
 
 
+def test_grid_beyond_32_bit_cell_indices_is_rejected():
+    """Cell indices (and the pair layout's lane index, cell + stride) are 32-bit: grids of 2^30 cells or more
+    are refused (workspace query 0), the largest grid below that is accepted and sized in 64-bit bytes
+    (about 300 GB for 1024 x 1024 x 1023 cells in FP16, more than one GPU holds)."""
+    assert R.workspace_bytes(R.make_params((1024, 1024, 1024), storage="f16")) == 0
+    big = R.workspace_bytes(R.make_params((1024, 1024, 1023), storage="f16"))
+    assert big > 2 * 138 * 1024 * 1024 * 1023
+
+
 @pytest.mark.parametrize("short,offset", [(1, 0), (0, 8)])
 def test_workspace_too_small_or_misaligned_is_rejected(short, offset):
     """A caller workspace below rmhdlb_workspace_bytes, or not 256-byte aligned, is refused before any
