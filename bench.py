@@ -418,6 +418,10 @@ def timed_form(w, storage, guess, args, stream):
         hist.pop()
     info.update(failed_cells=d["n_failed"], mean_newton_iters=round(d["mean_iters"], 3),
                 newton_hist=hist, guess_fallbacks=d["n_fallback"])
+    # the diagnostics after the timed steps (the reconnection rate R = delta E_z / B0 at the null of the band
+    # around y = 0 is the KH slab's observable)
+    info["diagnostics"] = {k: (None if not np.isfinite(d[k]) else float(f"{d[k]:.6g}"))
+                           for k in ("energy", "mass", "em_energy", "max_divB", "charge", "recon_rate")}
     if guess:
         # timed steps that ran the network (the others ran the plain recovery: no cell above the guess's
         # flow-ratio gate in the step before)
