@@ -420,11 +420,10 @@ int rmhdlb_batch_set_tuning(rmhdlb_batch *batch, int32_t px, int32_t yw, int32_t
  * the batch's tile shape and waves apply, and the states are bitwise those of
  * mode 0.  A batch with an instance that adjusts its open faces (divb_fix)
  * has no face pass in this mode: rmhdlb_batch_step returns
- * RMHDLB_EUNSUPPORTED for it (mode 0 steps it).  The launch needs all of its blocks resident together: work on
- * other streams delays it but ends by itself, while two persistent runs
- * overlapping on one device could each hold part of it and wait for the
- * other, so a caller runs one at a time per device.  RMHDLB_EINVAL for on
- * outside {0, 1}, RMHDLB_EUNSUPPORTED when the
+ * RMHDLB_EUNSUPPORTED for it (mode 0 steps it).  The launch needs all of
+ * its blocks resident together, so a caller starts it with no other kernels
+ * in flight on the device (synchronise first) and runs one at a time per
+ * device.  RMHDLB_EINVAL for on outside {0, 1}, RMHDLB_EUNSUPPORTED when the
  * device cannot launch cooperatively; a failed launch makes
  * rmhdlb_batch_step return RMHDLB_EDEVICE. */
 int rmhdlb_batch_set_persistent(rmhdlb_batch *batch, int32_t on);
