@@ -146,12 +146,16 @@ def cpu_baseline(budget_s):
         rates.append(w.ncells * steps / el / 1e6)
         total_steps += steps
         total_s += el
-    model = "unknown CPU"
+    model, mhz = "unknown CPU", None
     try:
         with open("/proc/cpuinfo") as fh:
-            model = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
-    except (OSError, StopIteration):
+            lines = fh.readlines()
+        model = next(l.split(":", 1)[1].strip() for l in lines if l.startswith("model name"))
+        mhz = next(float(l.split(":", 1)[1]) for l in lines if l.startswith("cpu MHz"))
+    except (OSError, StopIteration, ValueError):
         pass
+    if mhz:
+        model += f", {mhz:.0f} MHz"
     return {"value": sorted(rates)[1], "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"flare generator at 64x64x32 ({w.ncells} cells), median of 3 runs "
                       f"({total_steps} steps, {total_s:.1f} s in all), single-threaded FP64 C oracle: "
