@@ -346,6 +346,13 @@ def alg_bytes_per_step(storage, ncell, b_prev=False):
     return 2 * (63 * dist_b + (6 if b_prev else 3) * e_b) * ncell
 
 
+def halo_values_per_face_cell():
+    """Values a slab's neighbour needs per face cell and step (z-slabs): the F and G of the 10 directions
+    with a z component at 2 layers (the link stencil reaches x - 2e), the other 8 moving F for the
+    Laplacian's layer, the 8 h* entering across the face and E for the Gauss charge."""
+    return 10 * 2 * 2 + 8 + 8 + 3
+
+
 def share_form(w, args, stream, parts=8):
     """One GPU's share of a slab decomposition of the flare box along z into `parts` slabs: the bottom
     nz/parts planes at the same cell spacing, plain FP64, its cut face open in place of the halo planes
@@ -362,8 +369,7 @@ def share_form(w, args, stream, parts=8):
     torch.cuda.empty_cache()
     n = ws.ncells
     a = alg_bytes_per_step("f64", n) / (ms * 1e-3) / 1e9
-    halo_values = 10 * 2 * 2 + 8 + 8 + 3
-    face_bytes = halo_values * nx * ny * 8
+    face_bytes = halo_values_per_face_cell() * nx * ny * 8
     return {"shape": list(ws.shape), "cells": n, "parts": parts, "storage": "f64",
             "value": round(n / (ms * 1e-3) / 1e6, 2), "unit": "MLUPS", "ms_per_step": round(ms, 4),
             "roofline": {"achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
