@@ -390,10 +390,12 @@ def test_alfven_wave_500_steps():
     check_case(W.alfven(), 500, conditioned=True, symmetric=True)
 
 
-def test_alfven_wave_of_the_paper():
+@pytest.mark.parametrize("steps", [283, 425])
+def test_alfven_wave_of_the_paper(steps):
     """The paper's Alfven set-up: 400 cells on [-1, 1] (dx = 0.005), open ends, sigma = 1e5, initial
-    charge from Gauss's law, to t = 1 (283 steps); conditioning-derived bound (stiff Ohm coupling)."""
-    check_case(W.alfven_box(), 283, conditioned=True, symmetric=True)
+    charge from Gauss's law, to the two times it is compared at, t = 1 and 1.5 (283 and 425 steps);
+    conditioning-derived bound (stiff Ohm coupling)."""
+    check_case(W.alfven_box(), steps, conditioned=True, symmetric=True)
 
 
 @pytest.mark.parametrize("sigma", [100.0, 50.0])
