@@ -434,8 +434,9 @@ class Solver:
 
 class Batch:
     """Independent instances stepped together (one launch per step over all of them, replayed from hipGraphs
-    on a non-default stream).  specs: list of (shape, bc, params dict); each instance's device memory is a
-    torch tensor unless workspace="library"."""
+    on a non-default stream; or, after set_persistent(), each call's steps in one cooperative launch).
+    specs: list of (shape, bc, params dict); each instance's device memory is a torch tensor unless
+    workspace="library"."""
 
     def __init__(self, specs, storage="f32", stream=None, workspace="torch"):
         import torch
