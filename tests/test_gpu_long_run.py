@@ -1,6 +1,7 @@
 """Long runs on the GPU through the C ABI, against the oracle: the 64^3 instance of the flare box (driven
 bottom face, open faces elsewhere) after 1000 steps in every storage form, the current sheet at its
-stated 4000 steps, and the paper's supersonic KH and forced flare set-ups.
+stated 4000 steps, and the paper's supersonic KH and forced flare set-ups; and the reduced forms on the
+full KH slab after its 200-step prefix against the FP64 path.
 
 The flare box's flow amplifies rounding about a million-fold over 1000 steps (the oracle's own one-ulp
 sensitivity is stored with its fields), so the plain FP64 path agrees with the oracle to that
@@ -254,3 +255,50 @@ def _sheet_class(k):
     if k == "rho_c":
         return "rho_c"
     return "B" if k[0] == "B" and len(k) == 2 else "primary"
+
+
+# Stated bounds of the reduced forms on the full KH slab after its 200-step prefix, against the FP64
+# path (which the parity tests check against the oracle on sampled cells after the same prefix);
+# measured: FP32 fluid <= 2.8e-5, E_z 1.3e-5, B 7.2e-5, J_z 3.5e-4, energy 2.4e-8; FP16 fluid <= 3.1e-3,
+# E_z 5.9e-3, B 0.13, J_z 0.56, energy 4.9e-5 (relative to the field scale 0.1; the velocity error of the
+# storage enters B through E = -u x B at sigma = 1e3).
+KH200_TOL = {"f32": {"fluid": 2e-4, "E": 2e-4, "B": 1e-3, "J": 5e-3, "energy": 1e-6},
+             "f16": {"fluid": 1e-2, "E": 2e-2, "B": 0.3, "J": 1.0, "energy": 5e-4}}
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_kh_slab_reduced_forms_after_the_200_step_prefix(storage):
+    """The KH slab (1024 x 2048, v0 = 0.2, density ratio 10, sigma = 1e3) for 200 steps in a reduced
+    storage form beside the FP64 path: per field max |form - FP64| / max(max |FP64|, floor) (floors c for
+    u, the field scale 0.1 for E, B and J) and the total energy, within the stated bounds."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1508_03452_amd.rmhdlb import Solver
+    w = W.kh()
+    keep = ("n", "p", "ux", "uy", "Ez", "Bx", "By", "Jz")
+
+    def run(st):
+        s = Solver(w.shape, w.bc, storage=st, **w.params)
+        s.init_fields(w.fields)
+        s.step(200)
+        m = s.moments(fields=keep)
+        out = {k: m[k].cpu().numpy() for k in keep}
+        e = m["diag"]["energy"]
+        s.close()
+        return out, e
+
+    print(f"[long] KH slab 1024x2048, 200 steps, {storage} against FP64", flush=True)
+    ref, e_ref = run("f64")
+    got, e_got = run(storage)
+    tol = KH200_TOL[storage]
+    errs = {}
+    for k in keep:
+        floor = 1.0 if k[0] == "u" else (0.1 if k[0] in "EBJ" else 1e-300)
+        errs[k] = float(np.abs(got[k] - ref[k]).max() / max(np.abs(ref[k]).max(), floor))
+    errs["energy"] = abs(e_got - e_ref) / abs(e_ref)
+    print("[long] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    group = {"n": "fluid", "p": "fluid", "ux": "fluid", "uy": "fluid", "Ez": "E", "Bx": "B", "By": "B", "Jz": "J",
+             "energy": "energy"}
+    for k, v in errs.items():
+        assert np.isfinite(v) and v <= tol[group[k]], (k, v)
